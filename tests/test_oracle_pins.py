@@ -1,0 +1,307 @@
+"""Pins for the CPU oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own code path (CPU only).
+
+P1  Theorem th3.4: diag(T) of Alg. 1 equals |diag R| of the QR of A Omega,
+    for every block size (rank independent of the partition).
+P2  Lemma lem2: exact rank is recovered on exact-rank input.
+P3  orthonormal U_hat, V_hat.
+P4  Eckart-Young optimum (full SVD) and the deterministic bound of
+    Theorem siam.
+P5  output identity U D V^T = Q Q^T A, D upper triangular with diag >= 0.
+P6  R-values: sigma(D_hat) = sigma_1..r(A) on exact-rank input.
+P7  monotonicity in the tolerance (section 4.4).
+P8  storage worked example of the introduction.
+P9  FP64 error magnitudes of section 4.5 (table "0.4n").
+P10 Philox4x32-10 known-answer vectors; Gaussian statistics.
+plus special cases (zero matrix, full rank, m < n, ragged last block, scale
+invariance) and planted mistakes that at least one pin must catch.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle.eodabe_oracle as O
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _orth_err(X):
+    return np.linalg.norm(X.T @ X - np.eye(X.shape[1]))
+
+
+# ---------------------------------------------------------------- P10: RNG
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLD, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = O.philox4x32_10(np.array([v[:4]], dtype=np.uint64), (v[4], v[5]))[0]
+        assert [int(x) for x in out] == v[6:10]
+
+
+def test_gaussian_statistics():
+    from scipy import stats
+    z = O.omega_columns(seed=123, n=4096, col0=0, ncols=64).ravel()   # 262144 draws
+    N = z.size
+    assert abs(z.mean()) < 5 / math.sqrt(N)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / N)
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+    # FP32-representable values (the precision the GPU stores them in)
+    assert np.array_equal(z, z.astype(np.float32).astype(np.float64))
+
+
+def test_omega_column_is_function_of_seed_and_column():
+    a = O.omega_columns(7, 100, 10, 5)
+    b = O.omega_columns(7, 100, 12, 1)
+    assert np.array_equal(a[:, 2], b[:, 0])
+    c = O.omega_columns(8, 100, 12, 1)
+    assert not np.array_equal(b, c)
+    # row prefix independent of n: rows come from counters (row//4, col)
+    d = O.omega_columns(7, 37, 12, 1)
+    assert np.array_equal(d[:, 0], b[:37, 0])
+
+
+# ---------------------------------------------------------------- P1: th3.4
+@pytest.mark.parametrize("seed", range(4))
+def test_diagT_equals_qr_of_sketch(seed):
+    A = W.lowrank_haar(seed, m=300, n=200, r=25, noise_std=1e-10)
+    nrm = np.linalg.norm(A)
+    be = O.basis_ext(A, 1e-7 * nrm, 16, seed)
+    d = be["diagT"]
+    Om = O.omega_columns(seed, A.shape[1], 0, d.size)
+    R = np.linalg.qr(A @ Om)[1]
+    ref = np.abs(np.diag(R))
+    assert np.max(np.abs(ref - d)) <= 1e-12 * nrm
+    big = ref > 1e-6 * nrm
+    assert np.max(np.abs(ref - d)[big] / ref[big]) <= 1e-12
+    # Theorem th3.4(ii) / Remark rem3.6: exactly the first rank entries > eps
+    assert be["rank"] == int(np.argmax(d <= 1e-7 * nrm))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_rank_independent_of_block_size(seed):
+    A = W.lowrank_haar(seed, m=256, n=256, r=30, noise_std=1e-9)
+    ranks = {k: O.eod_abe(A, 1e-6, k=k, seed=seed).rank for k in (1, 7, 8, 32, 64, 256)}
+    assert len(set(ranks.values())) == 1, ranks
+
+
+# ---------------------------------------------------------------- P2, P3, P5, P6
+@pytest.mark.parametrize("r", [1, 5, 20, 64])
+@pytest.mark.parametrize("q", [0, 1])
+def test_exact_rank_recovered(r, q):
+    A = W.lowrank_haar(100 + r, m=400, n=300, r=r, noise_std=0.0)
+    res = O.eod_abe(A, 1e-10, k=16, q=q, seed=r)
+    assert res.rank == r
+    assert O.rel_err(A, res.U, res.D, res.V) <= 1e-12
+    assert _orth_err(res.U) < 1e-12 and _orth_err(res.V) < 1e-12          # P3
+    # P5: U D V^T = Q Q^T A, D upper triangular with non-negative diagonal
+    Qb = res.Qbasis
+    assert np.linalg.norm(res.U @ res.D @ res.V.T - Qb @ (Qb.T @ A)) <= 1e-13 * np.linalg.norm(A)
+    assert np.allclose(np.tril(res.D, -1), 0) and np.all(np.diag(res.D) >= 0)
+    # P6: singular values of D_hat are those of A
+    sA = np.linalg.svd(A, compute_uv=False)[:r]
+    sD = np.linalg.svd(res.D, compute_uv=False)
+    assert np.max(np.abs(sA - sD) / sA) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_c1_exact_rank_twenty(seed):
+    A = W.lowrank_haar(seed, noise_std=0.0)          # 512 x 512, rank 20
+    res = O.eod_abe(A, 1e-8, k=32, seed=seed)
+    assert res.rank == 20 and res.blocks == 1
+
+
+# ---------------------------------------------------------------- P4: error
+@pytest.mark.parametrize("seed", range(3))
+def test_eckart_young_with_power_iteration(seed):
+    A = W.lowrank_haar(seed)                         # C1 with noise 1e-12
+    res = O.eod_abe(A, 1e-8, k=32, q=1, seed=seed)
+    ey = O.eckart_young_relerr(A, res.rank)
+    assert abs(O.rel_err(A, res.U, res.D, res.V) - ey) <= 1e-10
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_siam_deterministic_bound(seed):
+    A = W.lowrank_haar(seed)
+    res = O.eod_abe(A, 1e-8, k=32, q=0, seed=seed)
+    r = res.rank
+    Om = O.omega_columns(seed, A.shape[1], 0, r)     # Q spans A Omega[:, :r]
+    bound = O.siam_bound_sq(A, r, Om, q=0)
+    nrm2 = np.linalg.norm(A) ** 2
+    err2 = (O.rel_err(A, res.U, res.D, res.V) ** 2) * nrm2
+    assert err2 <= bound + 1e-28 * nrm2
+    assert O.eckart_young_relerr(A, r) ** 2 * nrm2 <= err2 * (1 + 1e-6)
+
+
+def test_no_better_than_eckart_young_on_decaying_spectrum():
+    A = W.robustness("III", seed=3, n=200)
+    for q in (0, 1, 2):
+        res = O.eod_abe(A, 1e-6, k=8, q=q, seed=3)
+        ey = O.eckart_young_relerr(A, res.rank)
+        e = O.rel_err(A, res.U, res.D, res.V)
+        assert ey <= e * (1 + 1e-9)
+        if q >= 1:
+            assert e <= 1.5 * ey
+
+
+# ---------------------------------------------------------------- P7
+def test_rank_monotone_in_tolerance():
+    A = (W.haar(np.random.default_rng(5), 90, 90) * W.devils_stairs_sigma(90)[None, :]) \
+        @ W.haar(np.random.default_rng(6), 90, 90).T
+    tols = [10.0 ** e for e in range(-12, 0)]
+    res = [O.eod_abe(A, t, k=8, seed=1) for t in tols]
+    ranks = [r.rank for r in res]
+    errs = [O.rel_err(A, r.U, r.D, r.V) for r in res]
+    assert all(a >= b for a, b in zip(ranks, ranks[1:])), ranks
+    assert all(a <= b * (1 + 1e-9) + 1e-15 for a, b in zip(errs, errs[1:])), errs
+
+
+# ---------------------------------------------------------------- P8
+def test_storage_worked_example():
+    g = {}
+    for l in open(os.path.join(GOLD, "storage_example.txt")):
+        if l.strip() and not l.startswith("#"):
+            k, *v = l.split()
+            g[k] = v
+    m, n = int(g["m"][0]), int(g["n"][0])
+    ranks = [int(x) for x in g["ranks"]]
+    full = 3 * m * n
+    fact = sum(O.storage_bytes(m, n, r) for r in ranks)
+    assert full == int(g["total_full"][0])
+    assert fact == int(g["total_factored"][0])
+    assert round(100 * (1 - fact / full), 2) == float(g["reduction_percent"][0])
+    # the bound is where storing factors stops paying
+    rb = O.storage_rank_bound(m, n)
+    assert O.storage_bytes(m, n, math.floor(rb)) < m * n < O.storage_bytes(m, n, math.ceil(rb) + 1)
+    assert abs(O.storage_bytes(m, n, rb) - m * n) < 1e-6 * m * n
+
+
+# ---------------------------------------------------------------- P9
+@pytest.mark.slow
+def test_mat2_fp64_magnitudes():
+    rows = [l.split() for l in open(os.path.join(GOLD, "mat2_relerr_table.txt"))
+            if l.strip() and not l.startswith("#")]
+    paper = {(int(n), int(q)): float(e) for n, q, e in rows}
+    n = 2000                                   # scaled from the paper's 4000
+    A = W.mat2(11, n, int(0.4 * n))
+    for q in (0, 1):
+        res = O.eod_abe(A, 1e-12, k=64, q=q, seed=11)
+        assert res.rank == int(0.4 * n)
+        e = O.rel_err(A, res.U, res.D, res.V)
+        ref = paper[(4000, q)]
+        assert ref / 100 <= e <= ref * 100, (q, e, ref)
+
+
+# ---------------------------------------------------------------- special cases
+def test_zero_matrix():
+    res = O.eod_abe(np.zeros((50, 40)), 1e-3)
+    assert res.rank == 0 and res.U.shape == (50, 0) and res.V.shape == (40, 0)
+
+
+def test_full_rank_never_stops():
+    A = np.random.default_rng(0).standard_normal((70, 50))
+    res = O.eod_abe(A, 1e-14, k=16, seed=2)
+    assert res.rank == 50 and O.rel_err(A, res.U, res.D, res.V) < 1e-13
+    assert res.blocks == 4                         # 16+16+16+2: ragged last block
+
+
+def test_rank_zero_on_first_column():
+    A = W.lowrank_haar(1, m=64, n=64, r=3, noise_std=0.0)
+    res = O.eod_abe(A, 10.0, k=8)                 # eps > ||A omega|| for any omega
+    assert res.rank == 0 and res.blocks == 1
+
+
+def test_wide_matrix_is_transpose():
+    A = W.lowrank_haar(4, m=120, n=300, r=12, noise_std=0.0)
+    res = O.eod_abe(A, 1e-9, k=8, seed=4)
+    rt = O.eod_abe(A.T, 1e-9, k=8, seed=4)
+    assert res.rank == rt.rank == 12
+    assert res.U.shape == (120, 12) and res.V.shape == (300, 12)
+    assert np.allclose(np.tril(res.D, -1), 0) and np.all(np.diag(res.D) >= 0)
+    assert np.linalg.norm(res.U @ res.D @ res.V.T - rt.V @ rt.D.T @ rt.U.T) < 1e-12 * np.linalg.norm(A)
+    assert O.rel_err(A, res.U, res.D, res.V) < 1e-12
+
+
+def test_relative_tolerance_is_scale_invariant():
+    A = W.lowrank_haar(9, m=128, n=128, r=10, noise_std=1e-8)
+    r1 = O.eod_abe(A, 1e-4, k=8, seed=9).rank
+    r2 = O.eod_abe(1e6 * A, 1e-4, k=8, seed=9).rank
+    r3 = O.eod_abe(1e-6 * A, 1e-4, k=8, seed=9).rank
+    assert r1 == r2 == r3 == 10
+
+
+def test_precision_stability_classifier():
+    A = W.lowrank_haar(0)
+    ok, r64, r32 = O.precision_stable(A, 1e-5, 32, 0)
+    assert ok and r64 == r32 == 20
+
+
+# ---------------------------------------------------------------- planted mistakes
+def _exact_case():
+    A = W.lowrank_haar(3, m=200, n=160, r=9, noise_std=0.0)
+    return A, O.eod_abe(A, 1e-10, k=8, seed=3)
+
+
+def _pins_hold(A, res):
+    if res.rank != 9:
+        return False
+    if _orth_err(res.U) > 1e-12 or _orth_err(res.V) > 1e-12:
+        return False
+    if not (np.allclose(np.tril(res.D, -1), 0) and np.all(np.diag(res.D) >= 0)):
+        return False
+    return O.rel_err(A, res.U, res.D, res.V) <= 1e-12
+
+
+def test_pins_hold_on_unmodified_oracle():
+    assert _pins_hold(*_exact_case())
+
+
+@pytest.mark.parametrize("mutant", ["keep_stop_column", "no_sign_fix", "perturbed_qr_input",
+                                    "transposed_core", "absolute_eps"])
+def test_planted_mistake_is_caught(monkeypatch, mutant):
+    if mutant == "keep_stop_column":
+        orig = O.basis_ext
+
+        def bad(A, eps, k, seed, sketch_dtype=np.float64):
+            out = orig(A, eps, k, seed, sketch_dtype)
+            extra = O.omega_columns(seed, A.shape[1], 999, 1)
+            y = A @ extra
+            y -= out["Q"] @ (out["Q"].T @ y)
+            out["Q"] = np.concatenate([out["Q"], y / np.linalg.norm(y)], axis=1)
+            out["rank"] += 1
+            return out
+        monkeypatch.setattr(O, "basis_ext", bad)
+    elif mutant == "no_sign_fix":
+        monkeypatch.setattr(O, "qr_posdiag", lambda Y: np.linalg.qr(-Y, mode="reduced"))
+    elif mutant == "perturbed_qr_input":
+        orig_qr = O.qr_posdiag
+        monkeypatch.setattr(O, "qr_posdiag", lambda Y: orig_qr(Y + 1e-3 * np.roll(Y, 1, axis=0)))
+    elif mutant == "transposed_core":
+        orig_qr = O.qr_posdiag
+        calls = {"n": 0}
+
+        def qr_t(Y):
+            calls["n"] += 1
+            P, T = orig_qr(Y)
+            return (P, T.T) if Y.shape[0] == Y.shape[1] else (P, T)
+        monkeypatch.setattr(O, "qr_posdiag", qr_t)
+    elif mutant == "absolute_eps":
+        A = 1e3 * W.lowrank_haar(3, m=200, n=160, r=9, noise_std=1e-9)
+        assert O.eod_abe(A, 1e-5, k=8, seed=3).rank == 9
+        orig = O.basis_ext
+        monkeypatch.setattr(O, "basis_ext", lambda A_, eps, k, seed, sd=np.float64:
+                            orig(A_, eps / np.linalg.norm(A_), k, seed, sd))
+        # a relative test keeps rank 9 under scaling; an absolute one does not
+        assert O.eod_abe(A, 1e-5, k=8, seed=3).rank != 9
+        return
+    A, res = None, None
+    try:
+        A, res = _exact_case()
+    except Exception:
+        return                                      # a crash also counts as caught
+    assert not _pins_hold(A, res)

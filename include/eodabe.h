@@ -1,0 +1,175 @@
+/*
+ * eodabe.h -- C ABI of the MI355X (gfx950) EOD-ABE library.
+ *
+ * EOD-ABE (efficient orthogonal decomposition with automatic basis
+ * extraction; Xu, Shen, Liu, Jia, arXiv 2506.22713) computes
+ *     A ~= U_hat * D_hat * V_hat^T
+ * for a real m x n matrix A, with U_hat (m x r) and V_hat (n x r) having
+ * orthonormal columns and D_hat (r x r) upper triangular, where the rank r
+ * is found on the fly by the blocked randomized basis extraction of
+ * Alg. 1 (BasisExt) and the factorization is closed out by Alg. 2 (power
+ * iteration, C = Q^T A, QR of C^T, QR of R^T).
+ *
+ * Conventions for every entry point:
+ *   - Matrix arguments are DEVICE pointers (hipMalloc'd or torch CUDA
+ *     tensors) unless stated otherwise.  Sizes are element counts.
+ *   - A is row-major: element (i, j) at A[i*lda + j], lda >= n.  A is read
+ *     only; the caller keeps ownership of every buffer it passes.
+ *   - Work is enqueued on the stream given in eodabe_opts (0 = the null
+ *     stream).  eodabe_factor returns after one final stream
+ *     synchronisation, with the rank valid in *info.
+ *   - The library allocates no device memory: the caller passes a
+ *     workspace of at least eodabe_workspace_size() bytes.
+ *   - Return value: 0 = EODABE_OK, < 0 error (nothing useful written),
+ *     > 0 warning (results written).  No exception crosses the ABI.
+ *   - One context per stream; a context is not thread safe.
+ */
+#ifndef EODABE_H
+#define EODABE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eodabe_ctx eodabe_ctx;
+
+/* ---- status codes ---------------------------------------------------- */
+#define EODABE_OK             0
+#define EODABE_EINVAL        -1   /* bad size, leading dimension, tol, option or NULL pointer */
+#define EODABE_EWORKSPACE    -2   /* workspace NULL or smaller than eodabe_workspace_size() */
+#define EODABE_ECAPACITY     -3   /* the rank found exceeds r_cap (outputs too small) */
+#define EODABE_ENONFINITE    -4   /* A holds NaN or Inf (||A||_F is not finite) */
+#define EODABE_EHIP          -5   /* a HIP runtime call failed (see eodabe_last_hip_error) */
+#define EODABE_ENODEVICE     -6   /* no gfx950 device visible */
+#define EODABE_WTOL_FLOOR     1   /* warning: tol is below the data-type floor 8 u sqrt(n);
+                                     rank decisions there are dominated by rounding */
+
+/* ---- element types ---------------------------------------------------- */
+#define EODABE_F32  0
+#define EODABE_F64  1
+
+/* ---- sketch precision (steps that read A inside the basis loop) ------- */
+#define EODABE_SKETCH_NATIVE 0    /* same type as A */
+#define EODABE_SKETCH_F16    1    /* FP16 operands on MFMA, FP32 accumulation (A must be F32) */
+#define EODABE_SKETCH_BF16   2    /* BF16 operands on MFMA, FP32 accumulation (A must be F32) */
+
+typedef struct eodabe_opts {
+  int      block;        /* b: columns per basis block (the paper's k), 1..128; default 32   */
+  int      power_iters;  /* q: subspace iterations of Alg. 2, 0..16; default 0               */
+  uint64_t seed;         /* Philox4x32-10 key; column c of Omega is a pure function of (seed, c) */
+  int      a_dtype;      /* EODABE_F32 or EODABE_F64                                         */
+  int      sketch_dtype; /* EODABE_SKETCH_*                                                   */
+  int      blocks_per_sync; /* basis blocks enqueued between host checks of the stop flag;
+                              0 = automatic                                                   */
+  void*    stream;       /* hipStream_t                                                       */
+} eodabe_opts;
+
+typedef struct eodabe_info {
+  int64_t rank;          /* r: columns accepted by Alg. 1                                     */
+  int     blocks;        /* basis blocks executed (J)                                         */
+  int     status_flags;  /* bit 0: tol below floor (WTOL_FLOOR); bit 1: A was transposed (m<n);
+                            bit 2: a Cholesky pivot was floored in the final QRs              */
+  double  norm_a;        /* ||A||_F (FP64 accumulation)                                       */
+  double  eps;           /* tol * ||A||_F, the absolute stopping threshold                    */
+} eodabe_info;
+
+/* Fill *o with defaults (block 32, q 0, seed 0, F32, native sketch, stream 0). */
+void eodabe_default_opts(eodabe_opts* o);
+
+/* Create a context bound to the current HIP device.  *out receives the
+ * handle.  Errors: EINVAL (NULL out/opts or option out of range), ENODEVICE. */
+int eodabe_create(eodabe_ctx** out, const eodabe_opts* opts);
+
+/* Create a host-only context: options are validated and workspace sizes
+ * can be queried without a device (e.g. on a build host); every call that
+ * would touch the GPU returns EODABE_ENODEVICE.  Errors: EINVAL. */
+int eodabe_create_host(eodabe_ctx** out, const eodabe_opts* opts);
+
+/* Release the context (host memory only). NULL is ignored. */
+void eodabe_destroy(eodabe_ctx* ctx);
+
+/* Bytes of device workspace eodabe_factor needs for an m x n problem whose
+ * outputs have r_cap columns (r_cap <= min(m, n); 0 = min(m, n)).
+ * Returns 0 for invalid sizes. */
+size_t eodabe_workspace_size(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t r_cap);
+
+/* Factor A (Alg. 2 around Alg. 1).
+ *   A      m x n, row-major, leading dimension lda >= n, type opts.a_dtype.
+ *   tol    relative tolerance: the basis loop stops at the first column l
+ *          with |T(l,l)| <= eps = tol * ||A||_F (Alg. 1 stopping test,
+ *          Remark rem3.6).  tol > 0 and finite.
+ *   ws     device workspace of ws_bytes >= eodabe_workspace_size(m, n, r_cap).
+ *   Ut     output, r_cap x m row-major: row a holds column a of U_hat.
+ *   core   output, r_cap x r_cap row-major: D_hat (upper triangular, diag >= 0)
+ *          in its leading r x r block.
+ *   Vt     output, r_cap x n row-major: row a holds column a of V_hat.
+ *   info   host pointer; rank, blocks, ||A||_F, eps.
+ * Rows r..r_cap-1 of the outputs are left unspecified.  For m < n the
+ * factorization of A^T is computed and transposed back (the core is
+ * re-triangularised by one more QR).  Errors: EINVAL, EWORKSPACE,
+ * ECAPACITY (rank > r_cap; info->rank holds the rank found so far),
+ * ENONFINITE, EHIP.  Warning: WTOL_FLOOR. */
+int eodabe_factor(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda,
+                  double tol, void* ws, size_t ws_bytes,
+                  void* Ut, void* core, void* Vt, int64_t r_cap, eodabe_info* info);
+
+/* Human-readable text for a status code (static storage). */
+const char* eodabe_strerror(int status);
+
+/* Last hipError_t seen by the context (0 if none). */
+int eodabe_last_hip_error(const eodabe_ctx* ctx);
+
+/* ---- live kernel timing ------------------------------------------------ */
+#define EODABE_PROF_SKETCH  0   /* a2: Y = A Omega_j, one launch per executed block */
+#define EODABE_PROF_PROJECT 1   /* a9: C = Q^T A, one launch per factorization      */
+#define EODABE_PROF_KINDS   2
+
+/* Turn HIP-event timing of the dominant kernels on (enable != 0) or off,
+ * and reset the accumulated totals.  Events are recorded on the context's
+ * stream immediately before and after each timed launch; launches of
+ * speculative blocks that returned early are not counted. */
+int eodabe_profile(eodabe_ctx* ctx, int enable);
+
+/* Accumulated timing of one kernel kind since the last eodabe_profile():
+ * total milliseconds, number of launches, and algorithmic bytes moved
+ * (sketch: A + Omega_j + Y_j; projection: A + Q + C, in the data type). */
+int eodabe_profile_read(const eodabe_ctx* ctx, int kind, double* total_ms, int64_t* launches,
+                        double* bytes);
+
+/* ---- building blocks, exposed for kernel-level parity tests ----------- */
+
+/* Raw Philox4x32-10 words: for i < count, counter (ctr0 + i, ctr1, ctr2, 0)
+ * and key (seed lo, seed hi) -> out[4*i .. 4*i+3] (device, uint32).
+ * (Salmon et al., SC'11.) */
+int eodabe_philox(eodabe_ctx* ctx, uint64_t seed, uint32_t ctr0, uint32_t ctr1, uint32_t ctr2,
+                  int64_t count, uint32_t* out);
+
+/* Columns col0 .. col0+ncols-1 of the n x n Gaussian test matrix of Alg. 1,
+ * written transposed: out[j*ldo + i] = Omega(i, col0 + j) for i < n, 0 for
+ * n <= i < ldo (ldo >= n).  Entry (i, c) comes from Philox counter
+ * (i/4, c, 0, 0) and Box-Muller in FP64, rounded to FP32 (dtype F32) or
+ * kept as that FP32 value (dtype F64). */
+int eodabe_omega(eodabe_ctx* ctx, int dtype, int64_t n, int64_t col0, int64_t ncols,
+                 int64_t ldo, void* out);
+
+/* Y = A * Omega(:, col0 : col0+ncols-1), the sketch of Alg. 1 (Y_j before
+ * projection).  A as in eodabe_factor; Y column-major m x ncols (ldy >= m).
+ * ncols <= 128.  ws >= eodabe_sketch_workspace_size(m, n, ncols). */
+size_t eodabe_sketch_workspace_size(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t ncols);
+int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda,
+                  int64_t col0, int64_t ncols, void* Y, int64_t ldy, void* ws, size_t ws_bytes);
+
+/* Alg. 1 only: the basis Q (column-major m x r_cap, ldq = m) and the
+ * examined |T(l,l)| values (host array diagT of capacity diag_cap; the
+ * count written is min(info->rank + 1, n)).  Same workspace as eodabe_factor. */
+int eodabe_basis(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda,
+                 double tol, void* ws, size_t ws_bytes, void* Q, int64_t r_cap,
+                 double* diagT, int64_t diag_cap, eodabe_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EODABE_H */

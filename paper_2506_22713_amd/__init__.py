@@ -1,0 +1,276 @@
+"""Python binding of the MI355X EOD-ABE library (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of ``libeodabe.so``; this
+module only turns torch tensors into pointers and sizes, allocates the
+caller-owned workspace and outputs with torch, and maps status codes to
+exceptions.  Importing it fails loudly if the shared library has not been
+built (``python -m paper_2506_22713_amd.build``).  Function names follow the
+C ABI in ``include/eodabe.h``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeodabe.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"EOD-ABE HIP library not built: {LIB_PATH} is missing "
+        "(run `python -m paper_2506_22713_amd.build`)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+EODABE_OK = 0
+EODABE_EINVAL = -1
+EODABE_EWORKSPACE = -2
+EODABE_ECAPACITY = -3
+EODABE_ENONFINITE = -4
+EODABE_EHIP = -5
+EODABE_ENODEVICE = -6
+EODABE_WTOL_FLOOR = 1
+F32, F64 = 0, 1
+SKETCH_NATIVE, SKETCH_F16, SKETCH_BF16 = 0, 1, 2
+
+EXPORTED = [
+    "eodabe_default_opts", "eodabe_create", "eodabe_create_host", "eodabe_destroy", "eodabe_workspace_size",
+    "eodabe_factor", "eodabe_strerror", "eodabe_last_hip_error", "eodabe_philox",
+    "eodabe_omega", "eodabe_sketch_workspace_size", "eodabe_sketch", "eodabe_basis",
+    "eodabe_profile", "eodabe_profile_read",
+]
+PROF_SKETCH, PROF_PROJECT = 0, 1
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("power_iters", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("a_dtype", ctypes.c_int),
+                ("sketch_dtype", ctypes.c_int), ("blocks_per_sync", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("blocks", ctypes.c_int),
+                ("status_flags", ctypes.c_int), ("norm_a", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
+_vp, _i64, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+_lib.eodabe_default_opts.argtypes = [ctypes.POINTER(Opts)]
+_lib.eodabe_default_opts.restype = None
+_lib.eodabe_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(Opts)]
+_lib.eodabe_create.restype = ctypes.c_int
+_lib.eodabe_create_host.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(Opts)]
+_lib.eodabe_create_host.restype = ctypes.c_int
+_lib.eodabe_destroy.argtypes = [_vp]
+_lib.eodabe_destroy.restype = None
+_lib.eodabe_workspace_size.argtypes = [_vp, _i64, _i64, _i64]
+_lib.eodabe_workspace_size.restype = _sz
+_lib.eodabe_factor.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, _vp, _sz,
+                               _vp, _vp, _vp, _i64, ctypes.POINTER(Info)]
+_lib.eodabe_factor.restype = ctypes.c_int
+_lib.eodabe_basis.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, _vp, _sz, _vp, _i64,
+                              ctypes.POINTER(ctypes.c_double), _i64, ctypes.POINTER(Info)]
+_lib.eodabe_basis.restype = ctypes.c_int
+_lib.eodabe_strerror.argtypes = [ctypes.c_int]
+_lib.eodabe_strerror.restype = ctypes.c_char_p
+_lib.eodabe_last_hip_error.argtypes = [_vp]
+_lib.eodabe_last_hip_error.restype = ctypes.c_int
+_lib.eodabe_philox.argtypes = [_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                               ctypes.c_uint32, _i64, _vp]
+_lib.eodabe_philox.restype = ctypes.c_int
+_lib.eodabe_omega.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i64, _i64, _vp]
+_lib.eodabe_omega.restype = ctypes.c_int
+_lib.eodabe_sketch_workspace_size.argtypes = [_vp, _i64, _i64, _i64]
+_lib.eodabe_sketch_workspace_size.restype = _sz
+_lib.eodabe_sketch.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _sz]
+_lib.eodabe_sketch.restype = ctypes.c_int
+_lib.eodabe_profile.argtypes = [_vp, ctypes.c_int]
+_lib.eodabe_profile.restype = ctypes.c_int
+_lib.eodabe_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+_lib.eodabe_profile_read.restype = ctypes.c_int
+
+
+class EodAbeError(RuntimeError):
+    def __init__(self, status: int, where: str, hip: int = 0):
+        msg = _lib.eodabe_strerror(status).decode()
+        super().__init__(f"{where}: {msg} (status {status}" + (f", hip error {hip})" if hip else ")"))
+        self.status = status
+
+
+def strerror(status: int) -> str:
+    return _lib.eodabe_strerror(status).decode()
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.float32:
+        return F32
+    if t == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t} (float32 or float64)")
+
+
+class Context:
+    """One eodabe_ctx (bound to a stream and a set of options)."""
+
+    def __init__(self, block: int = 32, power_iters: int = 0, seed: int = 0,
+                 dtype: torch.dtype = torch.float32, sketch: int = SKETCH_NATIVE,
+                 blocks_per_sync: int = 0, stream: torch.cuda.Stream | None = None,
+                 host_only: bool = False):
+        o = Opts()
+        _lib.eodabe_default_opts(ctypes.byref(o))
+        o.block, o.power_iters, o.seed = block, power_iters, seed & (2 ** 64 - 1)
+        o.a_dtype, o.sketch_dtype, o.blocks_per_sync = _dtype_code(dtype), sketch, blocks_per_sync
+        s = None if host_only else (stream if stream is not None else torch.cuda.current_stream())
+        o.stream = s.cuda_stream if s is not None else None
+        self.opts, self.dtype, self.stream = o, dtype, s
+        h = _vp()
+        create = _lib.eodabe_create_host if host_only else _lib.eodabe_create
+        st = create(ctypes.byref(h), ctypes.byref(o))
+        if st != EODABE_OK:
+            raise EodAbeError(st, "eodabe_create_host" if host_only else "eodabe_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.eodabe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, where: str):
+        if st < 0:
+            raise EodAbeError(st, where, _lib.eodabe_last_hip_error(self.h))
+        return st
+
+    def profile(self, enable: bool = True):
+        """eodabe_profile: start (or stop) live HIP-event timing; resets totals."""
+        self._check(_lib.eodabe_profile(self.h, int(enable)), "eodabe_profile")
+
+    def profile_read(self, kind: int):
+        """eodabe_profile_read -> (total_ms, launches, algorithmic_bytes)."""
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        self._check(_lib.eodabe_profile_read(self.h, kind, ctypes.byref(ms), ctypes.byref(n),
+                                             ctypes.byref(by)), "eodabe_profile_read")
+        return ms.value, n.value, by.value
+
+    def workspace_size(self, m: int, n: int, r_cap: int = 0) -> int:
+        return int(_lib.eodabe_workspace_size(self.h, m, n, r_cap))
+
+    def workspace(self, m: int, n: int, r_cap: int = 0) -> torch.Tensor:
+        nb = self.workspace_size(m, n, r_cap)
+        if nb == 0:
+            raise EodAbeError(EODABE_EINVAL, "eodabe_workspace_size")
+        return torch.empty(nb, dtype=torch.uint8, device="cuda")
+
+
+@dataclass
+class Factorization:
+    U: torch.Tensor       # m x r view (columns orthonormal)
+    D: torch.Tensor       # r x r upper triangular
+    Vt: torch.Tensor      # r x n
+    rank: int
+    blocks: int
+    eps: float
+    norm_a: float
+    status: int
+    flags: int
+
+
+def _check_matrix(A: torch.Tensor, dtype: torch.dtype):
+    if not A.is_cuda or A.dim() != 2:
+        raise ValueError("A must be a 2-D CUDA (HIP) tensor")
+    if A.dtype != dtype:
+        raise TypeError(f"A has dtype {A.dtype}, context expects {dtype}")
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major (stride(1) == 1)")
+
+
+def alloc_outputs(A: torch.Tensor, r_cap: int = 0):
+    """Caller-owned output buffers (Ut, core, Vt) for eodabe_factor."""
+    m, n = A.shape
+    rc = r_cap or min(m, n)
+    return (torch.empty((max(rc, 1), m), dtype=A.dtype, device=A.device),
+            torch.zeros((max(rc, 1), max(rc, 1)), dtype=A.dtype, device=A.device),
+            torch.empty((max(rc, 1), n), dtype=A.dtype, device=A.device))
+
+
+def factor(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int = 0,
+           ws: torch.Tensor | None = None, out=None, **ctx_kw) -> Factorization:
+    """eodabe_factor: A ~= U D V^T with the adaptive rank (Alg. 2 around Alg. 1)."""
+    ctx = ctx or Context(**{"dtype": A.dtype, **ctx_kw})
+    _check_matrix(A, ctx.dtype)
+    m, n = A.shape
+    rc = r_cap or min(m, n)
+    if ws is None:
+        ws = ctx.workspace(m, n, rc)
+    Ut, core, Vt = out if out is not None else alloc_outputs(A, rc)
+    info = Info()
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    st = _lib.eodabe_factor(ctx.h, A.data_ptr(), m, n, lda, float(tol), ws.data_ptr(), ws.numel(),
+                            Ut.data_ptr(), core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
+    ctx._check(st, "eodabe_factor")
+    r = int(info.rank)
+    return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
+                         float(info.norm_a), st, int(info.status_flags))
+
+
+def basis(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int = 0,
+          ws: torch.Tensor | None = None, **ctx_kw):
+    """eodabe_basis: Alg. 1 only.  Returns (Q (m x r), diagT (numpy), info)."""
+    import numpy as np
+    ctx = ctx or Context(**{"dtype": A.dtype, **ctx_kw})
+    _check_matrix(A, ctx.dtype)
+    m, n = A.shape
+    rc = r_cap or min(m, n)
+    if ws is None:
+        ws = ctx.workspace(m, n, rc)
+    Qt = torch.empty((max(rc, 1), m), dtype=A.dtype, device=A.device)
+    diag = np.zeros(max(n, 1), dtype=np.float64)
+    info = Info()
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    st = _lib.eodabe_basis(ctx.h, A.data_ptr(), m, n, lda, float(tol), ws.data_ptr(), ws.numel(),
+                           Qt.data_ptr(), rc, diag.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           diag.size, ctypes.byref(info))
+    ctx._check(st, "eodabe_basis")
+    r = int(info.rank)
+    return Qt[:r].T, diag[: min(r + 1, n)], info
+
+
+def philox(ctx: Context, seed: int, ctr0: int, ctr1: int, ctr2: int, count: int) -> torch.Tensor:
+    """eodabe_philox: raw Philox4x32-10 words, shape (count, 4), int32 view of uint32."""
+    out = torch.empty((max(count, 1), 4), dtype=torch.int32, device="cuda")
+    ctx._check(_lib.eodabe_philox(ctx.h, seed & (2 ** 64 - 1), ctr0, ctr1, ctr2, count,
+                                  out.data_ptr()), "eodabe_philox")
+    return out[:count]
+
+
+def omega(ctx: Context, n: int, col0: int, ncols: int, dtype: torch.dtype = torch.float32,
+          ldo: int | None = None) -> torch.Tensor:
+    """eodabe_omega: columns col0.. of the Gaussian test matrix, returned as (n, ncols)."""
+    ldo = ldo or n
+    out = torch.empty((max(ncols, 1), max(ldo, 1)), dtype=dtype, device="cuda")
+    ctx._check(_lib.eodabe_omega(ctx.h, _dtype_code(dtype), n, col0, ncols, ldo, out.data_ptr()),
+               "eodabe_omega")
+    return out[:ncols, :n].T
+
+
+def sketch(ctx: Context, A: torch.Tensor, col0: int, ncols: int) -> torch.Tensor:
+    """eodabe_sketch: Y = A Omega(:, col0:col0+ncols), returned as (m, ncols)."""
+    _check_matrix(A, ctx.dtype)
+    m, n = A.shape
+    nb = int(_lib.eodabe_sketch_workspace_size(ctx.h, m, n, ncols))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    Yt = torch.empty((max(ncols, 1), max(m, 1)), dtype=A.dtype, device="cuda")
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    ctx._check(_lib.eodabe_sketch(ctx.h, A.data_ptr(), m, n, lda, col0, ncols, Yt.data_ptr(),
+                                  max(m, 1), ws.data_ptr(), ws.numel()), "eodabe_sketch")
+    return Yt[:ncols, :m].T

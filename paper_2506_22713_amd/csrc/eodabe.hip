@@ -1,0 +1,979 @@
+// Host side of the EOD-ABE library: C ABI, workspace plan and the enqueue
+// logic of Alg. 1 (basis extraction) and Alg. 2 (power iteration,
+// projection, closing QRs).  All arithmetic runs in the kernels of
+// eodabe_kernels.hpp; the host only validates, carves the caller's
+// workspace and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/eodabe.h"
+#include "eodabe_kernels.hpp"
+
+using namespace eodabe;
+
+struct eodabe_ctx {
+  eodabe_opts o;
+  hipStream_t stream;
+  int device;
+  int cu_count;
+  int last_hip;
+  State* host_state;      // pinned host copy of the control block
+  int64_t* host_wlog;     // pinned host copy of the basis-width log
+  int64_t host_wlog_cap;
+  bool host_only;
+  // live timing (eodabe_profile)
+  bool prof_on = false;
+  struct Mark { hipEvent_t a, b; int kind; int block; double bytes; };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Mark> marks;
+  double prof_ms[EODABE_PROF_KINDS] = {0, 0};
+  int64_t prof_n[EODABE_PROF_KINDS] = {0, 0};
+  double prof_bytes[EODABE_PROF_KINDS] = {0, 0};
+};
+
+namespace {
+
+constexpr int BN_MAX = 128;
+
+inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+inline int64_t cdiv(int64_t x, int64_t a) { return (x + a - 1) / a; }
+
+// K-chunk (multiple of 16) and the number of non-empty splits actually
+// launched for a reduction of length K asked to use `want` splits.  Every
+// partial buffer consumer must use this count.
+inline int64_t split_chunk(int64_t K, int want) {
+  return rup(cdiv(std::max<int64_t>(K, 1), std::max(want, 1)), 16);
+}
+inline int eff_splits(int64_t K, int want) {
+  return (int)std::max<int64_t>(1, cdiv(std::max<int64_t>(K, 1), split_chunk(K, want)));
+}
+
+#define HIPCHK(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) {                            \
+      ctx->last_hip = (int)e_;                         \
+      return EODABE_EHIP;                              \
+    }                                                  \
+  } while (0)
+
+#define LAUNCHCHK()                                    \
+  do {                                                 \
+    hipError_t e_ = hipGetLastError();                 \
+    if (e_ != hipSuccess) {                            \
+      ctx->last_hip = (int)e_;                         \
+      return EODABE_EHIP;                              \
+    }                                                  \
+  } while (0)
+
+#define TRY(x)                                         \
+  do {                                                 \
+    int s_ = (x);                                      \
+    if (s_ < 0) return s_;                             \
+  } while (0)
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(int64_t count) {
+    off = (size_t)rup((int64_t)off, 256);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// Event pair around one timed launch (no-op unless profiling is on).
+hipEvent_t prof_event(eodabe_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+int prof_begin(eodabe_ctx* ctx, hipStream_t st) {
+  if (!ctx->prof_on) return -1;
+  eodabe_ctx::Mark mk{prof_event(ctx), prof_event(ctx), 0, 0, 0.0};
+  if (!mk.a || !mk.b) return -1;
+  (void)hipEventRecord(mk.a, st);
+  ctx->marks.push_back(mk);
+  return (int)ctx->marks.size() - 1;
+}
+void prof_end(eodabe_ctx* ctx, hipStream_t st, int id, int kind, int block, double bytes) {
+  if (id < 0) return;
+  auto& mk = ctx->marks[id];
+  mk.kind = kind;
+  mk.block = block;
+  mk.bytes = bytes;
+  (void)hipEventRecord(mk.b, st);
+}
+// After the stream has been synchronised: fold the marks of blocks that ran
+// (block <= last_block) into the totals and recycle the events.
+void prof_collect(eodabe_ctx* ctx, int last_block) {
+  for (auto& mk : ctx->marks) {
+    if (mk.block <= last_block) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, mk.a, mk.b) == hipSuccess) {
+        ctx->prof_ms[mk.kind] += ms;
+        ctx->prof_n[mk.kind] += 1;
+        ctx->prof_bytes[mk.kind] += mk.bytes;
+      }
+    }
+    ctx->ev_pool.push_back(mk.a);
+    ctx->ev_pool.push_back(mk.b);
+  }
+  ctx->marks.clear();
+}
+
+// Problem geometry after the optional transpose (mm >= nn).
+struct Geo {
+  int64_t mm, nn;       // factored matrix is mm x nn (row-major, ld lda_eff)
+  bool transposed;
+  bool packed;          // A copied into workspace (transpose or alignment)
+  int64_t lda_eff;
+  int b, bn;            // block width and padded width (multiple of 16)
+  int64_t nblk;         // ceil(nn / b)
+  int64_t ldk;          // Omega^T leading dim (>= nn, multiple of 4)
+  int64_t ldy;          // Y / Q leading dim (>= mm, multiple of 4)
+  int64_t r_cap;        // output capacity (rank bound)
+  int s_sketch;         // K-splits of the sketch
+  int s_proj;           // K-splits of Q^T Y
+  int s_gram;           // K-splits of block Grams
+  int s_core;           // K-splits of the r-column products (C = Q^T A etc.)
+  size_t elem;
+};
+
+struct WS {
+  State* st;
+  int64_t* wlog;
+  int32_t* accv;
+  int32_t* dead;        // nblk x BN_MAX
+  double* diag_log;     // nn
+  double* normparts;    // per sketch workgroup
+  void* omega;          // bn x ldk
+  void* ypart;          // s_sketch x ldy x bn
+  void* y;              // ldy x bn
+  void* wpart;          // s_proj x ldw x bn
+  void* w;              // ldw x bn
+  double* gpart;        // s_gram x bn x bn
+  double* r1;           // bn x bn
+  double* r2;
+  void* q;              // ldy x (nn + bn)
+  void* apack;          // mm x lda_eff (if packed)
+  // closing steps
+  void* cbuf;           // r_cap x ldk   (C = Q^T A, then V^T in place)
+  void* cpart;          // s_core x r_cap x ldk
+  void* ybig;           // ldy x r_cap   (power iteration / U_hat scratch)
+  double* gbig;         // Gram partials of the closing QRs
+  double* rb1;          // r_cap x r_cap
+  double* rb2;
+  double* rb3;
+  double* rb4;
+  int32_t* deadbig;     // r_cap
+  double* dg;           // r_cap
+  void* tbig;           // ldy x r_cap scratch for large-f triangular solves
+  size_t total;
+};
+
+int64_t ldw_of(const Geo& g) { return rup(g.nn + g.bn, 4); }
+
+WS carve(void* base, const Geo& g) {
+  Carver c(base);
+  WS w{};
+  const size_t e = g.elem;
+  w.st = c.take<State>(1);
+  w.wlog = c.take<int64_t>(g.nblk + 2);
+  w.accv = c.take<int32_t>(g.nblk + 1);
+  w.dead = c.take<int32_t>((g.nblk + 1) * BN_MAX);
+  w.diag_log = c.take<double>(g.nn + BN_MAX);
+  w.normparts = c.take<double>((int64_t)g.s_sketch * cdiv(g.mm, 128) + 64);
+  w.omega = c.take<char>((int64_t)g.bn * g.ldk * e);
+  w.ypart = c.take<char>((int64_t)g.s_sketch * g.ldy * g.bn * e);
+  w.y = c.take<char>(g.ldy * g.bn * e);
+  w.wpart = c.take<char>((int64_t)g.s_proj * ldw_of(g) * g.bn * e);
+  w.w = c.take<char>(ldw_of(g) * g.bn * e);
+  w.gpart = c.take<double>((int64_t)g.s_gram * g.bn * g.bn);
+  w.r1 = c.take<double>(g.bn * g.bn);
+  w.r2 = c.take<double>(g.bn * g.bn);
+  w.q = c.take<char>(g.ldy * (g.nn + g.bn) * e);
+  w.apack = g.packed ? c.take<char>(g.mm * g.lda_eff * e) : nullptr;
+  const int64_t rc = std::max<int64_t>(g.r_cap, 1);
+  w.cbuf = c.take<char>(rc * g.ldk * e);
+  w.cpart = c.take<char>((int64_t)g.s_core * rc * g.ldk * e);
+  w.ybig = c.take<char>(g.ldy * rc * e);
+  const int64_t rb = std::max<int64_t>(rc, g.bn);
+  w.gbig = c.take<double>(std::max<int64_t>(32 * std::min<int64_t>(rb, 64) * std::min<int64_t>(rb, 64),
+                                            rb * rb));
+  w.rb1 = c.take<double>(rb * rb);
+  w.rb2 = c.take<double>(rb * rb);
+  w.rb3 = c.take<double>(rb * rb);
+  w.rb4 = c.take<double>(rb * rb);
+  w.deadbig = c.take<int32_t>(rc + 64);
+  w.dg = c.take<double>(rc + 64);
+  w.tbig = c.take<char>(std::max(g.ldy, g.ldk) * rc * std::max<size_t>(e, 8));
+  w.total = c.off + 256;
+  return w;
+}
+
+bool plan(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t lda, const void* A,
+          int64_t r_cap, Geo& g) {
+  if (m < 0 || n < 0) return false;
+  const int dt = ctx->o.a_dtype;
+  g.elem = dt == EODABE_F64 ? 8 : 4;
+  g.transposed = m < n;
+  g.mm = g.transposed ? n : m;
+  g.nn = g.transposed ? m : n;
+  const int64_t mn = std::min(m, n);
+  if (r_cap == 0) r_cap = mn;
+  if (r_cap < 0 || r_cap > mn) return false;
+  g.r_cap = r_cap;
+  const bool aligned = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+  g.packed = g.transposed || !aligned;
+  g.lda_eff = g.packed ? rup(std::max<int64_t>(g.nn, 1), 4) : lda;
+  g.b = ctx->o.block;
+  g.bn = (int)rup(g.b, 16);
+  g.nblk = cdiv(g.nn, g.b);
+  g.ldk = rup(std::max<int64_t>(g.nn, 1), 4);
+  g.ldy = rup(std::max<int64_t>(g.mm, 1), 4);
+  // K-splits: aim for ~2048 waves on the sketch, at least 256 K per split.
+  const int64_t mt = std::max<int64_t>(cdiv(g.mm, 128), 1);
+  int64_t s = cdiv(512, mt);
+  s = std::min<int64_t>(s, std::max<int64_t>(g.nn / 256, 1));
+  g.s_sketch = (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+  g.s_proj = (int)std::max<int64_t>(1, std::min<int64_t>(32, g.mm / 1024));
+  g.s_gram = (int)std::max<int64_t>(1, std::min<int64_t>(64, g.mm / 2048));
+  // C = Q^T A: output r x nn is small, the reduction over mm is long.
+  const int64_t rc1 = std::max<int64_t>(r_cap, 1);
+  const int64_t tiles = cdiv(std::max<int64_t>(g.nn, 1), 256) * cdiv(rc1, 64);
+  int64_t sc = std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, tiles), g.mm / 256));
+  const int64_t per = rc1 * g.ldk * (int64_t)g.elem;
+  while (sc > 1 && sc * per > ((int64_t)1 << 29)) sc /= 2;
+  g.s_core = (int)std::min<int64_t>(sc, 1024);
+  return true;
+}
+
+// ------------------------------------------------------------------------
+// Typed enqueue helpers.
+// ------------------------------------------------------------------------
+template <typename T>
+struct Ops {
+  eodabe_ctx* ctx;
+  hipStream_t st;
+
+  // out_parts = X (M x K, row-major ldx) * Z (N x K, row-major ldz)^T
+  template <typename Tacc>
+  int gemm_nt(const T* X, int64_t ldx, const T* Z, int64_t ldz, int64_t M, int64_t N, int64_t K,
+              int splits, Tacc* out, int64_t ldo, int64_t part_stride, double* sumsq = nullptr,
+              const int64_t* wlog = nullptr, const int32_t* stopb = nullptr, int blk = 0) {
+    if (M <= 0 || N <= 0) return 0;
+    const int64_t kchunk = split_chunk(K, splits);
+    splits = eff_splits(K, splits);
+    if (N <= 16) {
+      dim3 grid((unsigned)cdiv(M, 128), splits, 1);
+      hipLaunchKernelGGL((k_gemm_nt<T, Tacc, 2, 1>), grid, dim3(256), 0, st, X, ldx, Z, ldz, M, N, K,
+                         kchunk, out, ldo, part_stride, sumsq, wlog, stopb, blk);
+    } else if (N <= 32) {
+      dim3 grid((unsigned)cdiv(M, 128), splits, 1);
+      hipLaunchKernelGGL((k_gemm_nt<T, Tacc, 2, 2>), grid, dim3(256), 0, st, X, ldx, Z, ldz, M, N, K,
+                         kchunk, out, ldo, part_stride, sumsq, wlog, stopb, blk);
+    } else {
+      dim3 grid((unsigned)cdiv(M, 128), splits, (unsigned)cdiv(N, 64));
+      hipLaunchKernelGGL((k_gemm_nt<T, Tacc, 2, 4>), grid, dim3(256), 0, st, X, ldx, Z, ldz, M, N, K,
+                         kchunk, out, ldo, part_stride, sumsq, wlog, stopb, blk);
+    }
+    LAUNCHCHK();
+    return 0;
+  }
+
+  int gemm_nn(const T* X, int64_t ldx, const T* Z, int64_t ldz, int64_t M, int64_t N, int64_t K,
+              int splits, T* out, int64_t ldo, int64_t part_stride) {
+    if (M <= 0 || N <= 0) return 0;
+    const int64_t kchunk = split_chunk(K, splits);
+    splits = eff_splits(K, splits);
+    dim3 grid((unsigned)cdiv(N, 256), splits, (unsigned)cdiv(M, 64));
+    hipLaunchKernelGGL((k_gemm_nn<T, 4>), grid, dim3(256), 0, st, X, ldx, Z, ldz, M, N, K, kchunk,
+                       out, ldo, part_stride);
+    LAUNCHCHK();
+    return 0;
+  }
+
+  template <typename U>
+  int reduce(const U* parts, int nparts, int64_t stride, int64_t count, U* out,
+             const int32_t* stopb = nullptr, int blk = 0) {
+    if (count <= 0) return 0;
+    unsigned nb = (unsigned)std::min<int64_t>(cdiv(count, 256), 4096);
+    hipLaunchKernelGGL((k_reduce_parts<U>), dim3(nb), dim3(256), 0, st, parts, nparts, stride, count,
+                       out, stopb, blk);
+    LAUNCHCHK();
+    return 0;
+  }
+
+  // Z = X R^{-1} (R f x f FP64).  In place allowed only for f <= 64.
+  int trsm(const T* X, int64_t ldx, T* Zo, int64_t ldz, int64_t m, int f, const double* R,
+           int64_t zoff, int ncols_out, const int64_t* wlog = nullptr, const int32_t* accd = nullptr,
+           const int32_t* stopb = nullptr, int blk = 0) {
+    if (m <= 0 || f <= 0) return 0;
+    dim3 grid((unsigned)cdiv(m, 256));
+    if (f <= 16) {
+      hipLaunchKernelGGL((k_trsm_rows<T, T, 16>), grid, dim3(256), 0, st, X, ldx, Zo, ldz, m, f, R,
+                         zoff, ncols_out, wlog, accd, stopb, blk);
+    } else if (f <= 32) {
+      hipLaunchKernelGGL((k_trsm_rows<T, T, 32>), grid, dim3(256), 0, st, X, ldx, Zo, ldz, m, f, R,
+                         zoff, ncols_out, wlog, accd, stopb, blk);
+    } else if (f <= 64) {
+      hipLaunchKernelGGL((k_trsm_rows<T, T, 64>), grid, dim3(256), 0, st, X, ldx, Zo, ldz, m, f, R,
+                         zoff, ncols_out, wlog, accd, stopb, blk);
+    } else {
+      // out of place only (the caller provides distinct buffers)
+      hipLaunchKernelGGL((k_trsm_rows_big<T, T>), grid, dim3(256), 0, st, X, ldx, Zo, ldz, m, f, R,
+                         ncols_out);
+    }
+    LAUNCHCHK();
+    return 0;
+  }
+
+  // Y = Q W with an FP64 W (column-major, ldw); FP64 accumulation.
+  int update_d(T* Y, int64_t ldy, const T* Q, int64_t ldq, int64_t m, int64_t w, int f,
+               const double* W, int64_t ldw) {
+    if (m <= 0 || f <= 0) return 0;
+    dim3 grid((unsigned)cdiv(m, 256), (unsigned)cdiv(f, 32));
+    hipLaunchKernelGGL((k_update_rows<T, double, 32>), grid, dim3(256), 0, st, Y, ldy, Q, ldq, m, w, f,
+                       W, ldw, 0, (const int64_t*)nullptr, (const int32_t*)nullptr, 0);
+    LAUNCHCHK();
+    return 0;
+  }
+
+  int update(T* Y, int64_t ldy, const T* Q, int64_t ldq, int64_t m, int64_t w, int f, const T* W,
+             int64_t ldw, int subtract, const int64_t* wlog = nullptr, const int32_t* stopb = nullptr,
+             int blk = 0) {
+    if (m <= 0 || f <= 0) return 0;
+    dim3 grid((unsigned)cdiv(m, 256), (unsigned)cdiv(f, 32));
+    hipLaunchKernelGGL((k_update_rows<T, T, 32>), grid, dim3(256), 0, st, Y, ldy, Q, ldq, m, w, f, W,
+                       ldw, subtract, wlog, stopb, blk);
+    LAUNCHCHK();
+    return 0;
+  }
+};
+
+int launch_cholesky(eodabe_ctx* ctx, hipStream_t st, const double* parts, int nparts,
+                    int64_t pstride, int f, double* R, int32_t* dead, int first, State* stp,
+                    const int32_t* stopb, int blk, int count_floors, double* gscratch, double* dg) {
+  if (f <= 0) return 0;
+  const size_t lds = ((size_t)f * f + f) * sizeof(double);
+  if (f <= 64 && nparts > 16) {
+    const int64_t cnt = (int64_t)f * f;
+    hipLaunchKernelGGL(k_reduce_parts<double>, dim3((unsigned)cdiv(cnt, 256)), dim3(256), 0, st, parts,
+                       nparts, pstride, cnt, gscratch, stopb, blk);
+    parts = gscratch;
+    nparts = 1;
+  }
+  if (f <= 64) {
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), lds, st, parts, nparts, pstride, f, R, dead,
+                       first, stp, stopb, blk, count_floors);
+  } else {
+    // sum the parts into gscratch, then factor in global memory
+    const int64_t cnt = (int64_t)f * f;
+    unsigned nb = (unsigned)std::min<int64_t>(cdiv(cnt, 256), 4096);
+    hipLaunchKernelGGL(k_reduce_parts<double>, dim3(nb), dim3(256), 0, st, parts, nparts, pstride,
+                       cnt, gscratch, stopb, blk);
+    hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(256), 0, st, gscratch, f, R, dead, dg, first,
+                       stp, count_floors);
+  }
+  LAUNCHCHK();
+  return 0;
+}
+
+// In-place CholeskyQR2 of X (rows x f, element (i,c) at c*ld + i) with the
+// floored first pass; writes R = R2 R1 (element (i,j) at j*f + i) to Rout,
+// or its transpose when transpose_R.  Scratch from ws.
+template <typename T>
+int cholqr2(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, T* X, int64_t ld,
+            int64_t rows, int f, double* Rout, int transpose_R, T* tmp) {
+  Ops<T> ops{ctx, st};
+  if (f <= 0 || rows <= 0) return 0;
+  const int sg = f <= 64 ? std::max(1, (int)std::min<int64_t>(32, rows / 512)) : 1;  // <= 32 (gbig)
+  hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, w.deadbig, (int64_t)f);
+  double* Rs[2] = {w.rb1, w.rb2};
+  for (int pass = 0; pass < 2; ++pass) {
+    TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, sg, w.gbig, f, (int64_t)f * f));
+    TRY(launch_cholesky(ctx, st, w.gbig, eff_splits(rows, sg), (int64_t)f * f, f, Rs[pass], w.deadbig, pass == 0,
+                        w.st, nullptr, 0, 1, w.rb3, w.dg));
+    if (f <= 64) {
+      TRY(ops.trsm(X, ld, X, ld, rows, f, Rs[pass], 0, f));
+    } else {
+      TRY(ops.trsm(X, ld, tmp, ld, rows, f, Rs[pass], 0, f));
+      const int64_t cnt = ld * (int64_t)f;
+      hipLaunchKernelGGL((k_copy2d<T, T>), dim3((unsigned)cdiv(cnt, 32), 1), dim3(32, 8), 0, st, tmp,
+                         cnt, X, cnt, (int64_t)1, cnt, 0);
+      LAUNCHCHK();
+    }
+  }
+  const int64_t ff = (int64_t)f * f;
+  hipLaunchKernelGGL(k_trimul, dim3((unsigned)cdiv(ff, 256)), dim3(256), 0, st, w.rb2, w.rb1, f, Rout,
+                     transpose_R);
+  LAUNCHCHK();
+  return 0;
+}
+
+template <typename T>
+int copy2d(eodabe_ctx* ctx, hipStream_t st, const T* src, int64_t lds, T* dst, int64_t ldd,
+           int64_t rows, int64_t cols, int transpose) {
+  if (rows <= 0 || cols <= 0) return 0;
+  dim3 grid((unsigned)cdiv(cols, 32), (unsigned)cdiv(rows, 32));
+  hipLaunchKernelGGL((k_copy2d<T, T>), grid, dim3(32, 8), 0, st, src, lds, dst, ldd, rows, cols,
+                     transpose);
+  LAUNCHCHK();
+  return 0;
+}
+
+// Alg. 1 on the (already oriented) mm x nn matrix Ae.  On return the basis
+// is in w.q (column-major, ld g.ldy) and *rank holds its width.
+template <typename T>
+int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, double tol,
+              int64_t* rank, int* blocks, double* norm_a) {
+  Ops<T> ops{ctx, st};
+  const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
+  const int nwlog = (int)(g.nblk + 2);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, st, w.st, tol, w.wlog, nwlog);
+  hipLaunchKernelGGL(k_zero<int32_t>, dim3(64), dim3(256), 0, st, w.dead,
+                     (int64_t)(g.nblk + 1) * BN_MAX);
+  hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, w.accv, (int64_t)(g.nblk + 1));
+  LAUNCHCHK();
+  T* omega = (T*)w.omega;
+  T* y = (T*)w.y;
+  T* q = (T*)w.q;
+  T* wbuf = (T*)w.w;
+  const int64_t ldw = ldw_of(g);
+  const int32_t* stopb = &w.st->stop_block;
+  int per_sync = ctx->o.blocks_per_sync > 0 ? ctx->o.blocks_per_sync : 2;
+  int64_t j = 0;
+  bool finished = (g.nn == 0);
+  int64_t sketch_wgs = cdiv(g.mm, 128);
+  while (!finished) {
+    const int64_t jend = std::min<int64_t>(g.nblk, j + per_sync);
+    for (; j < jend; ++j) {
+      const int blk = (int)j;
+      const int64_t col0 = j * g.b;
+      const int f = (int)std::min<int64_t>(g.b, g.nn - col0);
+      // a1: Omega_j (bn rows; rows f..bn-1 zero)
+      {
+        dim3 grid((unsigned)cdiv(cdiv(g.ldk, 4), 256), g.bn);
+        hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.ldk, omega,
+                           stopb, blk);
+        if (f < g.bn)
+          hipLaunchKernelGGL(k_zero<T>, dim3(64), dim3(256), 0, st, omega + (int64_t)f * g.ldk,
+                             (int64_t)(g.bn - f) * g.ldk);
+        LAUNCHCHK();
+      }
+      // a2: sketch Y = A Omega_j (K-split partials; block 0 also ||A||_F)
+      const int64_t ystride = g.ldy * g.bn;
+      const int pid = prof_begin(ctx, st);
+      TRY(ops.template gemm_nt<T>(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch,
+                                  (T*)w.ypart, g.ldy, ystride, j == 0 ? w.normparts : nullptr,
+                                  nullptr, stopb, blk));
+      prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
+               (double)g.elem * ((double)g.mm * g.nn + (double)g.nn * f + (double)g.mm * f));
+      if (j == 0) {
+        const int64_t nparts = sketch_wgs * (int64_t)eff_splits(g.nn, g.s_sketch);
+        hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, w.normparts, nparts, w.st);
+        LAUNCHCHK();
+      }
+      TRY(ops.reduce((const T*)w.ypart, eff_splits(g.nn, g.s_sketch), ystride, ystride, y, stopb, blk));
+      // a3 + a4: two rounds of [project against the basis so far (width
+      // wlog[j] <= j*b), FP64-Gram Cholesky, triangular solve]: block
+      // Gram-Schmidt with re-orthogonalisation interleaved with CholeskyQR2
+      // (first Cholesky pass floored).  The second solve is the append below.
+      int32_t* deadj = w.dead + j * BN_MAX;
+      const int64_t gs = (int64_t)f * f;
+      const int64_t wmax = std::min<int64_t>(j * g.b, g.nn);
+      for (int pass = 0; pass < 2; ++pass) {
+        if (j > 0) {
+          TRY(ops.template gemm_nt<T>(q, g.ldy, y, g.ldy, wmax, f, g.mm, g.s_proj, (T*)w.wpart, ldw,
+                                      ldw * g.bn, nullptr, w.wlog, stopb, blk));
+          hipLaunchKernelGGL((k_reduce_cols<T>), dim3(256), dim3(256), 0, st, (const T*)w.wpart,
+                             eff_splits(g.mm, g.s_proj), ldw * g.bn, wmax, (int64_t)f, ldw, wbuf, w.wlog,
+                             stopb, blk);
+          LAUNCHCHK();
+          TRY(ops.update(y, g.ldy, q, g.ldy, g.mm, wmax, f, wbuf, ldw, 1, w.wlog, stopb, blk));
+        }
+        double* Rp = pass == 0 ? w.r1 : w.r2;
+        TRY(ops.template gemm_nt<double>(y, g.ldy, y, g.ldy, f, f, g.mm, g.s_gram, w.gpart, f, gs,
+                                         nullptr, nullptr, stopb, blk));
+        TRY(launch_cholesky(ctx, st, w.gpart, eff_splits(g.mm, g.s_gram), gs, f, Rp, deadj, pass == 0,
+                            w.st, stopb, blk, 0, w.rb3, w.dg));
+        if (pass == 0) {
+          if (f <= 64) {
+            TRY(ops.trsm(y, g.ldy, y, g.ldy, g.mm, f, w.r1, 0, f, nullptr, nullptr, stopb, blk));
+          } else {
+            TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r1, 0, f));
+            TRY(copy2d<T>(ctx, st, (T*)w.tbig, g.ldy, y, g.ldy, f, g.ldy, 0));
+          }
+        }
+      }
+      // a5: stop test on diag(T) = diag(R2) diag(R1)
+      hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, w.r1, w.r2, deadj, f, col0, g.nn, w.st,
+                         w.wlog, w.accv, w.diag_log, blk);
+      LAUNCHCHK();
+      // a6: append P = Z R2^{-1} (accepted columns) into Q at column wlog[j]
+      if (f <= 64) {
+        TRY(ops.trsm(y, g.ldy, q, g.ldy, g.mm, f, w.r2, 0, 0, w.wlog, w.accv, stopb, blk));
+      } else {
+        // large blocks: solve into scratch, then copy the accepted columns
+        TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r2, 0, f));
+        // the copy below uses the host-known bound f; rows past acc are
+        // overwritten by later blocks (the basis is sized nn + bn).
+        HIPCHK(hipStreamSynchronize(st));
+        int64_t wj = 0;
+        HIPCHK(hipMemcpy(&wj, w.wlog + j, sizeof(int64_t), hipMemcpyDeviceToHost));
+        TRY(copy2d<T>(ctx, st, (T*)w.tbig, g.ldy, q + wj * g.ldy, g.ldy, f, g.ldy, 0));
+      }
+    }
+    // host check of the stop flag (one small D2H copy per chunk)
+    HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->host_state->nonfinite) return EODABE_ENONFINITE;
+    if (ctx->host_state->stop_block != 0x7fffffff || j >= g.nblk) finished = true;
+    if (ctx->prof_on)
+      prof_collect(ctx, ctx->host_state->stop_block != 0x7fffffff ? ctx->host_state->stop_block
+                                                                   : (int)g.nblk);
+    per_sync = std::min(per_sync * 2, 16);
+  }
+  int64_t r = 0;
+  int nb = 0;
+  if (g.nn > 0) {
+    nb = (int)std::min<int64_t>(ctx->host_state->stop_block, g.nblk - 1) + 1;
+    HIPCHK(hipMemcpy(&r, w.wlog + nb, sizeof(int64_t), hipMemcpyDeviceToHost));
+    *norm_a = std::sqrt(ctx->host_state->normsq);
+  } else {
+    *norm_a = 0.0;
+  }
+  *rank = r;
+  *blocks = nb;
+  return 0;
+}
+
+// Alg. 2 after Alg. 1: power iteration, C = Q^T A, QR(C^T), QR(R^T).
+// Writes U_hat (column-major mm x r, ld ldu) to Uout, V_hat^T (r x nn,
+// row-major ldv) to Vout and D_hat (r x r row-major, ldd) to Dout.
+template <typename T>
+int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, int64_t r,
+              T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout, int64_t ldd) {
+  Ops<T> ops{ctx, st};
+  T* q = (T*)w.q;
+  T* cb = (T*)w.cbuf;
+  const int64_t cstride = r * g.ldk;
+  for (int it = 0; it < ctx->o.power_iters; ++it) {
+    // Y~^T = Q^T A (r x nn), QR(Y~) -> Q~ (stored as Q~^T = cbuf rows)
+    TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, g.s_core, (T*)w.cpart, g.ldk, cstride));
+    TRY(ops.reduce((const T*)w.cpart, eff_splits(g.mm, g.s_core), cstride, cstride, cb));
+    TRY(cholqr2<T>(ctx, st, g, w, cb, g.ldk, g.nn, (int)r, w.rb4, 0, (T*)w.tbig));
+    // Y = A Q~ (mm x r), QR(Y) -> Q
+    TRY(ops.template gemm_nt<T>(Ae, g.lda_eff, cb, g.ldk, g.mm, r, g.nn, 1, q, g.ldy, g.ldy * r));
+    TRY(cholqr2<T>(ctx, st, g, w, q, g.ldy, g.mm, (int)r, w.rb4, 0, (T*)w.tbig));
+  }
+  // a9: C = Q^T A (r x nn, row-major ld ldk)
+  const int pid = prof_begin(ctx, st);
+  TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, g.s_core, (T*)w.cpart, g.ldk, cstride));
+  prof_end(ctx, st, pid, EODABE_PROF_PROJECT, 0,
+           (double)g.elem * ((double)g.mm * g.nn + (double)g.mm * r + (double)r * g.nn));
+  TRY(ops.reduce((const T*)w.cpart, eff_splits(g.mm, g.s_core), cstride, cstride, cb));
+  // a10: C^T = V R  (C^T is nn x r with element (j,a) at a*ldk + j = cbuf)
+  //      -> cbuf holds V^T; R^T (row-major R) into rb4 as a column-major r x r
+  TRY(cholqr2<T>(ctx, st, g, w, cb, g.ldk, g.nn, (int)r, w.rb4, 1, (T*)w.tbig));
+  // R^T = Q_hat R_hat (FP64, r x r, column-major in rb4)
+  {
+    Ops<double> opd{ctx, st};
+    (void)opd;
+    TRY(cholqr2<double>(ctx, st, g, w, w.rb4, r, r, (int)r, w.rb3, 0, (double*)w.tbig));
+  }
+  // U_hat = Q Q_hat : (mm x r) (r x r); Q_hat FP64 column-major in rb4.
+  {
+    TRY(ops.update_d(Uout, ldu, q, g.ldy, g.mm, r, (int)r, w.rb4, r));
+  }
+  // outputs: V^T rows, D_hat
+  TRY(copy2d<T>(ctx, st, cb, g.ldk, Vout, ldv, r, g.nn, 0));
+  {
+    // D_hat = R_hat (element (i,j) at j*r + i in rb3) -> row-major Dout
+    const int64_t cnt = r * r;
+    (void)cnt;
+    dim3 grid((unsigned)cdiv(r, 32), (unsigned)cdiv(r, 32));
+    hipLaunchKernelGGL((k_copy2d<double, T>), grid, dim3(32, 8), 0, st, w.rb3, r, Dout, ldd, r, r, 1);
+    LAUNCHCHK();
+  }
+  return 0;
+}
+
+int check_ctx(const eodabe_ctx* ctx) { return ctx ? 0 : EODABE_EINVAL; }
+
+int check_dev(const eodabe_ctx* ctx) { return ctx->host_only ? EODABE_ENODEVICE : 0; }
+
+}  // namespace
+
+namespace {
+struct SketchPlan {
+  int64_t bn, ldk, ldyp, s;
+};
+SketchPlan sketch_plan(int64_t m, int64_t n, int64_t ncols) {
+  SketchPlan p;
+  p.bn = rup(std::max<int64_t>(ncols, 1), 16);
+  p.ldk = rup(std::max<int64_t>(n, 1), 4);
+  p.ldyp = rup(std::max<int64_t>(m, 1), 4);
+  const int64_t mt = std::max<int64_t>(cdiv(m, 128), 1);
+  int64_t s = std::min<int64_t>(cdiv(512, mt), std::max<int64_t>(n / 256, 1));
+  p.s = std::max<int64_t>(1, std::min<int64_t>(s, 64));
+  return p;
+}
+template <typename T>
+size_t sketch_carve(void* base, int64_t m, const SketchPlan& p, T** om, T** yp, T** ap, T** yr) {
+  Carver c(base);
+  *om = c.take<T>(p.bn * p.ldk);
+  *yp = c.take<T>(p.s * p.ldyp * p.bn);
+  *ap = c.take<T>(m * p.ldk);
+  *yr = c.take<T>(p.ldyp * p.bn);
+  return c.off + 256;
+}
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+void eodabe_default_opts(eodabe_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->block = 32;
+  o->power_iters = 0;
+  o->seed = 0;
+  o->a_dtype = EODABE_F32;
+  o->sketch_dtype = EODABE_SKETCH_NATIVE;
+  o->blocks_per_sync = 0;
+  o->stream = nullptr;
+}
+
+static int validate_opts(const eodabe_opts* opts) {
+  if (opts->block < 1 || opts->block > BN_MAX) return EODABE_EINVAL;
+  if (opts->power_iters < 0 || opts->power_iters > 16) return EODABE_EINVAL;
+  if (opts->a_dtype != EODABE_F32 && opts->a_dtype != EODABE_F64) return EODABE_EINVAL;
+  if (opts->sketch_dtype != EODABE_SKETCH_NATIVE) return EODABE_EINVAL;
+  if (opts->blocks_per_sync < 0) return EODABE_EINVAL;
+  return EODABE_OK;
+}
+
+int eodabe_create_host(eodabe_ctx** out, const eodabe_opts* opts) {
+  if (!out || !opts) return EODABE_EINVAL;
+  *out = nullptr;
+  TRY(validate_opts(opts));
+  eodabe_ctx* c = new (std::nothrow) eodabe_ctx();
+  if (!c) return EODABE_EINVAL;
+  c->o = *opts;
+  c->stream = nullptr;
+  c->device = -1;
+  c->cu_count = 0;
+  c->last_hip = 0;
+  c->host_state = nullptr;
+  c->host_wlog = nullptr;
+  c->host_wlog_cap = 0;
+  c->host_only = true;
+  *out = c;
+  return EODABE_OK;
+}
+
+int eodabe_create(eodabe_ctx** out, const eodabe_opts* opts) {
+  if (!out || !opts) return EODABE_EINVAL;
+  *out = nullptr;
+  TRY(validate_opts(opts));
+  int dev = 0, ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return EODABE_ENODEVICE;
+  if (hipGetDevice(&dev) != hipSuccess) return EODABE_ENODEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return EODABE_ENODEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return EODABE_ENODEVICE;
+  eodabe_ctx* c = new (std::nothrow) eodabe_ctx();
+  if (!c) return EODABE_EINVAL;
+  c->o = *opts;
+  c->stream = (hipStream_t)opts->stream;
+  c->device = dev;
+  c->cu_count = prop.multiProcessorCount;
+  c->last_hip = 0;
+  if (hipHostMalloc((void**)&c->host_state, sizeof(State), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return EODABE_EHIP;
+  }
+  c->host_wlog = nullptr;
+  c->host_wlog_cap = 0;
+  c->host_only = false;
+  *out = c;
+  return EODABE_OK;
+}
+
+int eodabe_profile(eodabe_ctx* ctx, int enable) {
+  TRY(check_ctx(ctx));
+  ctx->prof_on = enable != 0 && !ctx->host_only;
+  for (int k = 0; k < EODABE_PROF_KINDS; ++k) {
+    ctx->prof_ms[k] = 0.0;
+    ctx->prof_n[k] = 0;
+    ctx->prof_bytes[k] = 0.0;
+  }
+  return EODABE_OK;
+}
+
+int eodabe_profile_read(const eodabe_ctx* ctx, int kind, double* total_ms, int64_t* launches,
+                        double* bytes) {
+  TRY(check_ctx(ctx));
+  if (kind < 0 || kind >= EODABE_PROF_KINDS) return EODABE_EINVAL;
+  if (total_ms) *total_ms = ctx->prof_ms[kind];
+  if (launches) *launches = ctx->prof_n[kind];
+  if (bytes) *bytes = ctx->prof_bytes[kind];
+  return EODABE_OK;
+}
+
+void eodabe_destroy(eodabe_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& mk : ctx->marks) {
+    (void)hipEventDestroy(mk.a);
+    (void)hipEventDestroy(mk.b);
+  }
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+  delete ctx;
+}
+
+const char* eodabe_strerror(int s) {
+  switch (s) {
+    case EODABE_OK: return "ok";
+    case EODABE_EINVAL: return "invalid argument";
+    case EODABE_EWORKSPACE: return "workspace missing or too small";
+    case EODABE_ECAPACITY: return "rank exceeds r_cap";
+    case EODABE_ENONFINITE: return "A holds NaN or Inf";
+    case EODABE_EHIP: return "HIP runtime error";
+    case EODABE_ENODEVICE: return "no gfx950 device";
+    case EODABE_WTOL_FLOOR: return "warning: tol below the data-type floor";
+    default: return "unknown status";
+  }
+}
+
+int eodabe_last_hip_error(const eodabe_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+size_t eodabe_workspace_size(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t r_cap) {
+  if (!ctx) return 0;
+  Geo g;
+  // assume the worst case (packing needed) so the size is valid for any A
+  if (!plan(ctx, m, n, 1, (const void*)1, r_cap, g)) return 0;
+  g.packed = true;
+  g.lda_eff = rup(std::max<int64_t>(g.nn, 1), 4);
+  return carve(nullptr, g).total;
+}
+
+static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, double tol,
+                       void* ws, size_t ws_bytes, void* Ut, void* core, void* Vt, int64_t r_cap,
+                       eodabe_info* info, void* Qbasis, double* diagT, int64_t diag_cap,
+                       bool basis_only) {
+  TRY(check_ctx(ctx));
+  if (!info) return EODABE_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  if (m < 0 || n < 0 || lda < n || lda < 1) return EODABE_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return EODABE_EINVAL;
+  if ((m > 0 && n > 0) && !A) return EODABE_EINVAL;
+  if (!basis_only && (m > 0 && n > 0) && (!Ut || !core || !Vt)) return EODABE_EINVAL;
+  if (basis_only && (m > 0 && n > 0) && !Qbasis) return EODABE_EINVAL;
+  Geo g;
+  if (!plan(ctx, m, n, lda, A, r_cap, g)) return EODABE_EINVAL;
+  const size_t need = eodabe_workspace_size(ctx, m, n, r_cap);
+  if (!ws || ws_bytes < need) return EODABE_EWORKSPACE;
+  if (m == 0 || n == 0) return EODABE_OK;
+  TRY(check_dev(ctx));
+  WS w = carve(ws, g);
+  hipStream_t st = ctx->stream;
+  const bool f64 = ctx->o.a_dtype == EODABE_F64;
+  int status = EODABE_OK;
+  // dtype floor warning: tol < 8 u sqrt(n)
+  const double u = f64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+  if (tol < 8.0 * u * std::sqrt((double)std::min(m, n))) {
+    status = EODABE_WTOL_FLOOR;
+    info->status_flags |= 1;
+  }
+  if (g.transposed) info->status_flags |= 2;
+  int64_t rank = 0;
+  int blocks = 0;
+  double norm_a = 0.0;
+  auto body = [&](auto tag) -> int {
+    typedef decltype(tag) T;
+    const T* Ae = (const T*)A;
+    if (g.packed) {
+      TRY(copy2d<T>(ctx, st, (const T*)A, lda, (T*)w.apack, g.lda_eff, g.mm, g.nn, g.transposed ? 1 : 0));
+      Ae = (const T*)w.apack;
+    }
+    TRY(run_basis<T>(ctx, st, g, w, Ae, tol, &rank, &blocks, &norm_a));
+    info->rank = rank;
+    info->blocks = blocks;
+    info->norm_a = norm_a;
+    info->eps = tol * norm_a;
+    if (diagT && diag_cap > 0) {
+      const int64_t cnt = std::min<int64_t>(diag_cap, std::min<int64_t>(rank + 1, g.nn));
+      HIPCHK(hipMemcpy(diagT, w.diag_log, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    if (basis_only) {
+      if (rank > g.r_cap) return EODABE_ECAPACITY;
+      if (g.transposed) return EODABE_EINVAL;   // basis of A^T: not offered
+      TRY(copy2d<T>(ctx, st, (T*)w.q, g.ldy, (T*)Qbasis, g.mm, rank, g.ldy, 0));
+      HIPCHK(hipStreamSynchronize(st));
+      return 0;
+    }
+    if (rank > g.r_cap) return EODABE_ECAPACITY;
+    if (rank == 0) {
+      HIPCHK(hipStreamSynchronize(st));
+      return 0;
+    }
+    if (!g.transposed) {
+      TRY(run_close<T>(ctx, st, g, w, Ae, rank, (T*)Ut, m, (T*)Vt, n, (T*)core, r_cap));
+    } else {
+      // factor of A^T = U' D' V'^T (U' nn... here mm = n rows): A = V' D'^T U'^T.
+      // U' -> ybig (column-major n x r), V'^T -> cbuf (r x m), D' -> rb_tmp
+      T* ut = (T*)w.ybig;            // U' column-major (ld = ldy)
+      TRY(run_close<T>(ctx, st, g, w, Ae, rank, ut, g.ldy, (T*)w.cbuf, g.ldk, (T*)w.tbig, rank));
+      // D'^T (r x r): tbig holds D' row-major (ld r) = D'^T column-major.
+      Ops<double> opd{ctx, st};
+      (void)opd;
+      const int64_t cnt = rank * rank;
+      hipLaunchKernelGGL((k_copy2d<T, double>), dim3((unsigned)cdiv(cnt, 32), 1), dim3(32, 8), 0, st,
+                         (const T*)w.tbig, cnt, w.rb4, cnt, (int64_t)1, cnt, 0);
+      LAUNCHCHK();
+      TRY(cholqr2<double>(ctx, st, g, w, w.rb4, rank, rank, (int)rank, w.rb3, 0, (double*)w.tbig));
+      // U_out = V' Q'' : V' column-major m x r is cbuf (element (i,a) at a*ldk + i)
+      Ops<T> ops{ctx, st};
+      TRY(ops.update_d((T*)Ut, m, (const T*)w.cbuf, g.ldk, m, rank, (int)rank, w.rb4, rank));
+      // Vt_out = U'^T : U' column-major n x r (ld ldy) -> row a = column a
+      TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));
+      dim3 grid((unsigned)cdiv(rank, 32), (unsigned)cdiv(rank, 32));
+      hipLaunchKernelGGL((k_copy2d<double, T>), grid, dim3(32, 8), 0, st, w.rb3, rank, (T*)core, r_cap,
+                         rank, rank, 1);
+      LAUNCHCHK();
+    }
+    HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->prof_on) prof_collect(ctx, 0x7fffffff);
+    if (ctx->host_state->floored) info->status_flags |= 4;
+    return 0;
+  };
+  int s = f64 ? body(double{}) : body(float{});
+  if (s < 0) return s;
+  return status;
+}
+
+int eodabe_factor(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, double tol,
+                  void* ws, size_t ws_bytes, void* Ut, void* core, void* Vt, int64_t r_cap,
+                  eodabe_info* info) {
+  return factor_impl(ctx, A, m, n, lda, tol, ws, ws_bytes, Ut, core, Vt, r_cap, info, nullptr,
+                     nullptr, 0, false);
+}
+
+int eodabe_basis(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, double tol,
+                 void* ws, size_t ws_bytes, void* Q, int64_t r_cap, double* diagT, int64_t diag_cap,
+                 eodabe_info* info) {
+  if (m < n) return EODABE_EINVAL;
+  return factor_impl(ctx, A, m, n, lda, tol, ws, ws_bytes, nullptr, nullptr, nullptr, r_cap, info, Q,
+                     diagT, diag_cap, true);
+}
+
+int eodabe_philox(eodabe_ctx* ctx, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                  int64_t count, uint32_t* out) {
+  TRY(check_ctx(ctx));
+  if (count < 0 || (count > 0 && !out)) return EODABE_EINVAL;
+  if (count == 0) return EODABE_OK;
+  TRY(check_dev(ctx));
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st,
+                     (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), c0, c1, c2, count, out);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));
+  return EODABE_OK;
+}
+
+int eodabe_omega(eodabe_ctx* ctx, int dtype, int64_t n, int64_t col0, int64_t ncols, int64_t ldo,
+                 void* out) {
+  TRY(check_ctx(ctx));
+  if (n < 0 || col0 < 0 || ncols < 0 || ldo < n || ncols > 65535) return EODABE_EINVAL;
+  if (dtype != EODABE_F32 && dtype != EODABE_F64) return EODABE_EINVAL;
+  if (n == 0 || ncols == 0) return EODABE_OK;
+  if (!out) return EODABE_EINVAL;
+  TRY(check_dev(ctx));
+  hipStream_t st = ctx->stream;
+  const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
+  dim3 grid((unsigned)cdiv(cdiv(ldo, 4), 256), (unsigned)ncols);
+  if (dtype == EODABE_F32)
+    hipLaunchKernelGGL(k_omega<float>, grid, dim3(256), 0, st, k0, k1, n, col0, (int)ncols, ldo,
+                       (float*)out, nullptr, 0);
+  else
+    hipLaunchKernelGGL(k_omega<double>, grid, dim3(256), 0, st, k0, k1, n, col0, (int)ncols, ldo,
+                       (double*)out, nullptr, 0);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));
+  return EODABE_OK;
+}
+
+size_t eodabe_sketch_workspace_size(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t ncols) {
+  if (!ctx || m < 0 || n < 0 || ncols < 0 || ncols > BN_MAX) return 0;
+  SketchPlan p = sketch_plan(m, n, ncols);
+  if (ctx->o.a_dtype == EODABE_F64) {
+    double *a, *b, *c, *d;
+    return sketch_carve<double>(nullptr, m, p, &a, &b, &c, &d);
+  }
+  float *a, *b, *c, *d;
+  return sketch_carve<float>(nullptr, m, p, &a, &b, &c, &d);
+}
+
+int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, int64_t col0,
+                  int64_t ncols, void* Y, int64_t ldy, void* ws, size_t ws_bytes) {
+  TRY(check_ctx(ctx));
+  if (m < 0 || n < 0 || lda < n || ncols < 0 || ncols > BN_MAX || ldy < m || col0 < 0)
+    return EODABE_EINVAL;
+  if (m == 0 || n == 0 || ncols == 0) return EODABE_OK;
+  if (!A || !Y) return EODABE_EINVAL;
+  if (!ws || ws_bytes < eodabe_sketch_workspace_size(ctx, m, n, ncols)) return EODABE_EWORKSPACE;
+  TRY(check_dev(ctx));
+  hipStream_t st = ctx->stream;
+  const SketchPlan p = sketch_plan(m, n, ncols);
+  const int64_t bn = p.bn, ldk = p.ldk, ldyp = p.ldyp;
+  const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
+  auto body = [&](auto tag) -> int {
+    typedef decltype(tag) T;
+    T *om, *yp, *ap, *yr;
+    sketch_carve<T>(ws, m, p, &om, &yp, &ap, &yr);
+    const T* Ae = (const T*)A;
+    int64_t la = lda;
+    if (!(((uintptr_t)A % 16 == 0) && (lda % 4 == 0))) {
+      TRY(copy2d<T>(ctx, st, (const T*)A, lda, ap, ldk, m, n, 0));
+      Ae = ap;
+      la = ldk;
+    }
+    dim3 grid((unsigned)cdiv(cdiv(ldk, 4), 256), (unsigned)bn);
+    hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, n, col0, (int)ncols, ldk, om,
+                       nullptr, 0);
+    if (ncols < bn)
+      hipLaunchKernelGGL(k_zero<T>, dim3(64), dim3(256), 0, st, om + ncols * ldk, (bn - ncols) * ldk);
+    LAUNCHCHK();
+    Ops<T> ops{ctx, st};
+    const int64_t ystr = ldyp * bn;
+    TRY(ops.template gemm_nt<T>(Ae, la, om, ldk, m, bn, n, (int)p.s, yp, ldyp, ystr));
+    TRY(ops.reduce((const T*)yp, eff_splits(n, (int)p.s), ystr, ystr, yr));
+    TRY(copy2d<T>(ctx, st, yr, ldyp, (T*)Y, ldy, ncols, m, 0));
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+  };
+  return ctx->o.a_dtype == EODABE_F64 ? body(double{}) : body(float{});
+}
+
+}  // extern "C"

@@ -1,0 +1,779 @@
+// Device kernels of the EOD-ABE hot path for CDNA4 (gfx950, wave64).
+//
+// Layout conventions (all sizes in elements):
+//   A      row-major m x n, lda            (input, read only)
+//   Omega  stored transposed: row j of the buffer is column c0+j of Omega
+//   Y, Z   column-major m x f (ld >= m, multiple of 4): the current block
+//   Q      column-major m x w (ldq): the basis accumulated so far
+//   G, R   small FP64 matrices, element (i, j) at j*ld + i
+// Every GEMM here is a "stream one operand, reduce over K" skinny product;
+// the MFMA micro-kernels use v_mfma_*_16x16x4 with each lane loading four
+// consecutive K values (16 B for FP32) per operand, so both operands are
+// read with dwordx4 loads and the four MFMAs of a chunk consume them in
+// K-order 4g+v (g = lane/16, v = 0..3).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eodabe {
+
+typedef float  f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+constexpr double U64 = 1.1102230246251565e-16;   // 2^-53
+constexpr double FLOOR_C = 64.0;                 // pivot floor: FLOOR_C * u64 * G(k,k)
+
+// Control block shared by the kernels of one factorization (device memory).
+struct State {
+  double eps;            // tol * ||A||_F
+  double normsq;         // ||A||_F^2
+  double tol;
+  int32_t stop_block;    // first block whose stop test fired (INT32_MAX: none yet)
+  int32_t nonfinite;     // ||A||_F not finite
+  int32_t floored;       // a pivot was floored in the closing QRs
+  int32_t pad;
+  uint32_t counter[8];   // arrival counters (reset by the last arriving workgroup)
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+// Two standard normals from two uniform words: u1 = (x+1) 2^-32 in (0,1],
+// u2 = y 2^-32 in [0,1), r = sqrt(-2 ln u1), (r cos 2 pi u2, r sin 2 pi u2).
+// Evaluated in FP64 and rounded to FP32.
+__device__ __forceinline__ void box_muller(uint32_t x, uint32_t y, float& z0, float& z1) {
+  const double u1 = ((double)x + 1.0) * 2.3283064365386963e-10;
+  const double u2 = (double)y * 2.3283064365386963e-10;
+  const double rad = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincos(2.0 * 3.141592653589793 * u2, &s, &c);
+  z0 = (float)(rad * c);
+  z1 = (float)(rad * s);
+}
+
+__global__ void k_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                         int64_t count, uint32_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  U4 r = philox4x32_10(U4{c0 + (uint32_t)i, c1, c2, 0u}, k0, k1);
+  out[4 * i + 0] = r.x; out[4 * i + 1] = r.y; out[4 * i + 2] = r.z; out[4 * i + 3] = r.w;
+}
+
+// out[j*ldo + i] = Omega(i, col0 + j), i < n; zero for n <= i < ldo.
+// Entry (i, c): Philox counter (i/4, c, 0, 0); words (x0,x1) -> rows 4q, 4q+1,
+// (x2,x3) -> rows 4q+2, 4q+3.
+template <typename T>
+__global__ void k_omega(uint32_t k0, uint32_t k1, int64_t n, int64_t col0, int ncols,
+                        int64_t ldo, T* __restrict__ out, const int32_t* __restrict__ stop_block,
+                        int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (4 * q >= ldo || j >= ncols) return;
+  float z[4] = {0.f, 0.f, 0.f, 0.f};
+  if (4 * q < n) {
+    U4 r = philox4x32_10(U4{(uint32_t)q, (uint32_t)(col0 + j), 0u, 0u}, k0, k1);
+    box_muller(r.x, r.y, z[0], z[1]);
+    box_muller(r.z, r.w, z[2], z[3]);
+  }
+  T* o = out + (int64_t)j * ldo + 4 * q;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (4 * q + e < ldo) o[e] = (4 * q + e < n) ? (T)z[e] : (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// MFMA wrappers: D(16x16) += A(16x4) B(4x16).  Lane l supplies A[l%16][l/16]
+// and B[l/16][l%16].  Accumulator register e of lane l holds D[row][l%16]
+// with row = Mfma::row(l/16, e): 4(l/16)+e for the f32 instruction,
+// 4e+(l/16) for the f64 one.
+// ---------------------------------------------------------------------------
+template <typename Tacc> struct Mfma;
+template <> struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static constexpr bool rows_contiguous = true;
+  static __device__ __forceinline__ int row(int g, int e) { return 4 * g + e; }
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static constexpr bool rows_contiguous = false;
+  static __device__ __forceinline__ int row(int g, int e) { return 4 * e + g; }
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// Four consecutive elements.
+template <typename T> struct V4 { T v[4]; };
+template <typename T>
+__device__ __forceinline__ V4<T> ld4(const T* p) {
+  V4<T> r;
+  if constexpr (sizeof(T) == 4) {
+    f32x4 x = *reinterpret_cast<const f32x4*>(p);
+    r.v[0] = x[0]; r.v[1] = x[1]; r.v[2] = x[2]; r.v[3] = x[3];
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    double2 a = q[0], b = q[1];
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+  }
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ V4<T> ld4_masked(const T* p, int64_t k, int64_t kend) {
+  V4<T> r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) r.v[e] = (k + e < kend) ? p[e] : (T)0;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// NT GEMM partials: out_s(M x N) = X(M x K) * Z(N x K)^T over K-split s.
+// X row-major (ldx), Z row-major (ldz); both K-contiguous, ldx/ldz multiples
+// of 4 and 16-byte aligned bases.  out_s element (m, j) at
+// out + s*part_stride + j*ldo + m  (column-major; ldo multiple of 4).
+// Workgroup = 4 waves; wave w owns rows [m0 + 16*RT*w, +16*RT) and all 16*CT
+// columns of the grid-z tile.  If sumsq != nullptr, each workgroup of grid-z
+// tile 0 writes sum(X^2) over the elements it read to sumsq[block id].
+// M_dev / block control: if wlog != nullptr the row count M is read from
+// wlog[block_id] (basis width known only on the device) and the kernel
+// returns at once when *stop_block < block_id.
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tacc, int RT, int CT>
+__global__ __launch_bounds__(256) void k_gemm_nt(
+    const Tin* __restrict__ X, int64_t ldx, const Tin* __restrict__ Z, int64_t ldz,
+    int64_t M, int64_t N, int64_t K, int64_t kchunk, Tacc* __restrict__ out, int64_t ldo,
+    int64_t part_stride, double* __restrict__ sumsq, const int64_t* __restrict__ wlog,
+    const int32_t* __restrict__ stop_block, int block_id) {
+  typedef Mfma<Tacc> MF;
+  if (stop_block && *stop_block < block_id) return;
+  if (wlog) M = wlog[block_id];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * (64 * RT) + wv * (16 * RT);
+  const int64_t n0 = (int64_t)blockIdx.z * (16 * CT);
+  const int s = blockIdx.y;
+  const int64_t kb = (int64_t)s * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  const bool do_ss = (sumsq != nullptr) && blockIdx.z == 0;
+  double ss = 0.0;
+  __shared__ double ss_red[4];
+  if (m0 >= M || kb >= ke) {       // nothing to do for this wave (still reach the reduction)
+    if (do_ss) {
+      if (lane == 0) ss_red[wv] = 0.0;
+      __syncthreads();
+      if (threadIdx.x == 0)
+        sumsq[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ss_red[0] + ss_red[1] + ss_red[2] + ss_red[3];
+    }
+    return;
+  }
+  const Tin* xp[RT];
+  bool xvalid[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int64_t row = m0 + 16 * t + r;
+    xvalid[t] = row < M;
+    xp[t] = X + (xvalid[t] ? row : (M - 1)) * ldx + 4 * g;
+  }
+  const Tin* zp[CT];
+#pragma unroll
+  for (int u = 0; u < CT; ++u) {
+    const int64_t col = n0 + 16 * u + r;
+    zp[u] = Z + (col < N ? col : (N - 1)) * ldz + 4 * g;
+  }
+  typename MF::acc_t acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) acc[t][u] = MF::zero();
+
+  const int64_t kfull = kb + ((ke - kb) / 16) * 16;
+  V4<Tin> a[RT], b[CT];
+  int64_t k = kb;
+  if (k < kfull) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t) a[t] = ld4(xp[t] + k);
+#pragma unroll
+    for (int u = 0; u < CT; ++u) b[u] = ld4(zp[u] + k);
+  }
+  for (; k < kfull; k += 16) {
+    V4<Tin> an[RT], bn[CT];
+    const bool more = k + 16 < kfull;
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) an[t] = ld4(xp[t] + k + 16);
+#pragma unroll
+      for (int u = 0; u < CT; ++u) bn[u] = ld4(zp[u] + k + 16);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < CT; ++u)
+          acc[t][u] = MF::op((Tacc)a[t].v[v], (Tacc)b[u].v[v], acc[t][u]);
+    if (do_ss) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        if (xvalid[t])
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ss += (double)a[t].v[v] * (double)a[t].v[v];
+    }
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[t] = an[t];
+#pragma unroll
+      for (int u = 0; u < CT; ++u) b[u] = bn[u];
+    }
+  }
+  if (kfull < ke) {                 // ragged K tail
+#pragma unroll
+    for (int t = 0; t < RT; ++t) a[t] = ld4_masked(xp[t] + kfull, kfull + 4 * g, ke);
+#pragma unroll
+    for (int u = 0; u < CT; ++u) b[u] = ld4_masked(zp[u] + kfull, kfull + 4 * g, ke);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < CT; ++u)
+          acc[t][u] = MF::op((Tacc)a[t].v[v], (Tacc)b[u].v[v], acc[t][u]);
+    if (do_ss) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        if (xvalid[t])
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ss += (double)a[t].v[v] * (double)a[t].v[v];
+    }
+  }
+  Tacc* o = out + (int64_t)s * part_stride;
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+      const int64_t col = n0 + 16 * u + r;
+      if (col >= N) continue;
+      if constexpr (MF::rows_contiguous) {
+        const int64_t row = m0 + 16 * t + 4 * g;
+        Tacc* p = o + col * ldo + row;
+        if (row + 3 < M && ((ldo & 3) == 0) && ((part_stride & 3) == 0)) {
+          *reinterpret_cast<f32x4*>(p) = acc[t][u];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (row + e < M) p[e] = acc[t][u][e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = m0 + 16 * t + MF::row(g, e);
+          if (row < M) o[col * ldo + row] = acc[t][u][e];
+        }
+      }
+    }
+  }
+  if (do_ss) {
+    // wave reduction then workgroup reduction (fixed order: deterministic)
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+    if (lane == 0) ss_red[wv] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      sumsq[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ss_red[0] + ss_red[1] + ss_red[2] + ss_red[3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// NN GEMM partials: out_s(M x N) = X(M x K) * Z(K x N) over K-split s, with X
+// row-major K-contiguous (ldx) and Z row-major N-contiguous (ldz).  Used for
+// C = Q^T A (X = Q^T, i.e. Q column-major; Z = A).  out_s row-major
+// (element (m, j) at s*part_stride + m*ldo + j).
+// Lane l loads rows k0+4g+v (v = 0..3) of Z at columns j0+4r .. 4r+3, so a
+// wave covers 16 K-rows x 64 columns with dwordx4 loads; MFMA tile u (0..3)
+// holds columns j0 + 4j + u.  Each wave computes 16*RT rows of out.
+// Workgroup = 4 waves = 4 consecutive 64-column panels.
+// ---------------------------------------------------------------------------
+template <typename T, int RT>
+__global__ __launch_bounds__(256) void k_gemm_nn(
+    const T* __restrict__ X, int64_t ldx, const T* __restrict__ Z, int64_t ldz,
+    int64_t M, int64_t N, int64_t K, int64_t kchunk, T* __restrict__ out, int64_t ldo,
+    int64_t part_stride) {
+  typedef Mfma<T> MF;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t j0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
+  const int64_t m0 = (int64_t)blockIdx.z * (16 * RT);
+  const int s = blockIdx.y;
+  const int64_t kb = (int64_t)s * kchunk, ke = min(K, kb + kchunk);
+  if (j0 >= N || kb >= ke || m0 >= M) return;
+  const int64_t jc = j0 + 4 * r;                       // first of this lane's 4 columns
+  const bool jvec = (jc + 3 < N);
+  const T* xp[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int64_t row = m0 + 16 * t + r;
+    xp[t] = X + (row < M ? row : (M - 1)) * ldx + 4 * g;
+  }
+  typename MF::acc_t acc[RT][4];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
+  for (int64_t k = kb; k < ke; k += 16) {
+    const bool full = (k + 16 <= ke);
+    V4<T> a[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) a[t] = full ? ld4(xp[t] + k) : ld4_masked(xp[t] + k, k + 4 * g, ke);
+    V4<T> zv[4];                       // zv[v].v[u] = Z[k+4g+v][jc+u]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t kr = k + 4 * g + v;
+      if (kr < ke && jvec) {
+        zv[v] = ld4(Z + kr * ldz + jc);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) zv[v].v[u] = (kr < ke && jc + u < N) ? Z[kr * ldz + jc + u] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(a[t].v[v], zv[v].v[u], acc[t][u]);
+  }
+  T* o = out + (int64_t)s * part_stride;
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = m0 + 16 * t + MF::row(g, e);
+      if (row >= M) continue;
+      T* p = o + row * ldo + jc;
+      if (jvec && ((ldo & 3) == 0)) {
+        if constexpr (sizeof(T) == 4) {
+          *reinterpret_cast<f32x4*>(p) = f32x4{acc[t][0][e], acc[t][1][e], acc[t][2][e], acc[t][3][e]};
+        } else {
+          reinterpret_cast<double2*>(p)[0] = double2{acc[t][0][e], acc[t][1][e]};
+          reinterpret_cast<double2*>(p)[1] = double2{acc[t][2][e], acc[t][3][e]};
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (jc + u < N) p[u] = acc[t][u][e];
+      }
+    }
+  }
+}
+
+// out[i] = sum_s parts[s*stride + i] (fixed order), i < count.  Optional
+// block control as in k_gemm_nt.
+template <typename T>
+__global__ void k_reduce_parts(const T* __restrict__ parts, int nparts, int64_t stride,
+                               int64_t count, T* __restrict__ out,
+                               const int32_t* __restrict__ stop_block, int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T acc = parts[i];
+    for (int s = 1; s < nparts; ++s) acc += parts[(int64_t)s * stride + i];
+    out[i] = acc;
+  }
+}
+
+// Column-block reduction for a column-major matrix with leading dimension ld
+// where only rows < rows_dev (read from wlog[block_id] when given) matter:
+// out(i, c) = sum_s parts_s(i, c), i < rows, c < cols.
+template <typename T>
+__global__ void k_reduce_cols(const T* __restrict__ parts, int nparts, int64_t stride,
+                              int64_t rows, int64_t cols, int64_t ld, T* __restrict__ out,
+                              const int64_t* __restrict__ wlog, const int32_t* __restrict__ stop_block,
+                              int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  if (wlog) rows = wlog[block_id];
+  const int64_t total = rows * cols;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = idx / rows, i = idx - c * rows;
+    const int64_t off = c * ld + i;
+    T acc = parts[off];
+    for (int s = 1; s < nparts; ++s) acc += parts[(int64_t)s * stride + off];
+    out[off] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Y(m x f) -= Q(m x w) * W(w x f)   (Y, Q column-major; W column-major ldw)
+// One thread per row; W staged in LDS in chunks of 64 rows.  w from wlog.
+// With beta == 0: Y = +Q*W (used for U_hat = Q Q_hat).
+// ---------------------------------------------------------------------------
+template <typename T, typename TW, int F>
+__global__ __launch_bounds__(256) void k_update_rows(
+    T* __restrict__ Y, int64_t ldy, const T* __restrict__ Q, int64_t ldq, int64_t m, int64_t w,
+    int f, const TW* __restrict__ W, int64_t ldw, int subtract,
+    const int64_t* __restrict__ wlog, const int32_t* __restrict__ stop_block, int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  if (wlog) w = wlog[block_id];
+  if (w == 0 && subtract) return;
+  __shared__ TW Ws[64 * F];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * F;          // column tile
+  const int fc = (int)min((int64_t)F, (int64_t)f - c0);
+  TW acc[F];
+#pragma unroll
+  for (int c = 0; c < F; ++c) acc[c] = 0;
+  for (int64_t a0 = 0; a0 < w; a0 += 64) {
+    const int na = (int)min((int64_t)64, w - a0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * F; idx += blockDim.x) {
+      const int a = idx / F, c = idx - a * F;
+      Ws[idx] = (a < na && c < fc) ? W[(c0 + c) * ldw + a0 + a] : (TW)0;
+    }
+    __syncthreads();
+    if (i < m) {
+      for (int a = 0; a < na; ++a) {
+        const TW qv = (TW)Q[(a0 + a) * ldq + i];
+#pragma unroll
+        for (int c = 0; c < F; ++c) acc[c] += qv * Ws[a * F + c];
+      }
+    }
+  }
+  if (i < m) {
+#pragma unroll
+    for (int c = 0; c < F; ++c) {
+      if (c < fc) {
+        T* p = Y + (c0 + c) * ldy + i;
+        *p = subtract ? (T)((TW)*p - acc[c]) : (T)acc[c];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of a symmetric positive semi-definite f x f matrix (FP64, one
+// workgroup), with the rules of the blocked CholeskyQR used here:
+//   * dead columns (flag set) are skipped: R(k,k) = 1, row and column zero;
+//   * a pivot G(k,k) - sum R(i,k)^2 <= FLOOR_C u64 G(k,k) is floored to that
+//     value when first_pass (the column stays alive but its row is zeroed so
+//     it does not feed later columns), and marks the column dead otherwise.
+// G is the sum of nparts partial matrices (element (i,j) at j*f + i).
+// R is written with element (i,j) at j*f + i (upper triangle; lower zero).
+// mode 0: plain; mode 1: closing-QR mode (counts floored pivots in st->floored).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cholesky(
+    const double* __restrict__ Gparts, int nparts, int64_t part_stride, int f,
+    double* __restrict__ R, int32_t* __restrict__ dead, int first_pass,
+    State* st, const int32_t* __restrict__ stop_block, int block_id, int count_floors) {
+  if (stop_block && *stop_block < block_id) return;
+  extern __shared__ double sm[];
+  double* G = sm;                 // f*f (only if it fits; host decides)
+  double* dg = sm + (int64_t)f * f;   // original diagonal (f)
+  __shared__ int s_flag;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t ff = (int64_t)f * f;
+  for (int64_t idx = tid; idx < ff; idx += nt) {
+    double a = 0.0;
+    for (int s = 0; s < nparts; ++s) a += Gparts[(int64_t)s * part_stride + idx];
+    G[idx] = a;
+  }
+  __syncthreads();
+  for (int k = tid; k < f; k += nt) dg[k] = G[(int64_t)k * f + k];
+  __syncthreads();
+  for (int k = 0; k < f; ++k) {
+    if (tid == 0) {
+      int fl = 0;
+      if (dead[k]) {
+        fl = 2;
+      } else {
+        const double piv = G[(int64_t)k * f + k];
+        const double flo = FLOOR_C * U64 * dg[k];
+        if (!(piv > flo) || !(piv < INFINITY)) {
+          if (first_pass) {
+            G[(int64_t)k * f + k] = sqrt(flo > 1e-300 ? flo : 1e-300);
+            fl = 1;
+            if (count_floors && st) atomicAdd(&st->floored, 1);
+          } else {
+            dead[k] = 1;
+            fl = 2;
+          }
+        } else {
+          G[(int64_t)k * f + k] = sqrt(piv);
+        }
+      }
+      if (fl == 2) G[(int64_t)k * f + k] = 1.0;
+      s_flag = fl;
+    }
+    __syncthreads();
+    const int fl = s_flag;
+    const double rkk = G[(int64_t)k * f + k];
+    // row k of R: R(k,j) = G(k,j) / R(k,k) for alive j > k
+    for (int j = k + 1 + tid; j < f; j += nt) {
+      double v = G[(int64_t)j * f + k];
+      v = (fl != 0 || dead[j]) ? 0.0 : v / rkk;
+      G[(int64_t)j * f + k] = v;
+    }
+    __syncthreads();
+    if (fl == 0) {
+      // trailing update G(i,j) -= R(k,i) R(k,j), k < i <= j
+      const int nrem = f - k - 1;
+      const int64_t npairs = (int64_t)nrem * nrem;
+      for (int64_t p = tid; p < npairs; p += nt) {
+        const int ii = k + 1 + (int)(p / nrem), jj = k + 1 + (int)(p % nrem);
+        if (ii <= jj) G[(int64_t)jj * f + ii] -= G[(int64_t)ii * f + k] * G[(int64_t)jj * f + k];
+      }
+      __syncthreads();
+    }
+  }
+  for (int64_t idx = tid; idx < ff; idx += nt) {
+    const int64_t j = idx / f, i = idx - j * f;
+    R[idx] = (i <= j) ? G[idx] : 0.0;
+  }
+}
+
+// Same algorithm with G in global memory (large f); G is overwritten.
+__global__ __launch_bounds__(256) void k_cholesky_global(
+    double* __restrict__ G, int f, double* __restrict__ R, int32_t* __restrict__ dead,
+    double* __restrict__ dg, int first_pass, State* st, int count_floors) {
+  __shared__ int s_flag;
+  __shared__ double s_rkk;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t ff = (int64_t)f * f;
+  for (int k = tid; k < f; k += nt) dg[k] = G[(int64_t)k * f + k];
+  __syncthreads();
+  for (int k = 0; k < f; ++k) {
+    if (tid == 0) {
+      int fl = 0;
+      if (dead[k]) {
+        fl = 2;
+      } else {
+        const double piv = G[(int64_t)k * f + k];
+        const double flo = FLOOR_C * U64 * dg[k];
+        if (!(piv > flo) || !(piv < INFINITY)) {
+          if (first_pass) {
+            G[(int64_t)k * f + k] = sqrt(flo > 1e-300 ? flo : 1e-300);
+            fl = 1;
+            if (count_floors && st) atomicAdd(&st->floored, 1);
+          } else {
+            dead[k] = 1;
+            fl = 2;
+          }
+        } else {
+          G[(int64_t)k * f + k] = sqrt(piv);
+        }
+      }
+      if (fl == 2) G[(int64_t)k * f + k] = 1.0;
+      s_flag = fl;
+      s_rkk = G[(int64_t)k * f + k];
+    }
+    __syncthreads();
+    const int fl = s_flag;
+    const double rkk = s_rkk;
+    for (int j = k + 1 + tid; j < f; j += nt) {
+      double v = G[(int64_t)j * f + k];
+      G[(int64_t)j * f + k] = (fl != 0 || dead[j]) ? 0.0 : v / rkk;
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (fl == 0) {
+      const int nrem = f - k - 1;
+      for (int jj = k + 1 + (tid / 32); jj < f; jj += nt / 32) {
+        const double rkj = G[(int64_t)jj * f + k];
+        if (rkj == 0.0) continue;
+        for (int ii = k + 1 + (tid & 31); ii <= jj; ii += 32)
+          G[(int64_t)jj * f + ii] -= G[(int64_t)ii * f + k] * rkj;
+      }
+      (void)nrem;
+      __threadfence_block();
+      __syncthreads();
+    }
+  }
+  for (int64_t idx = tid; idx < ff; idx += nt) {
+    const int64_t j = idx / f, i = idx - j * f;
+    R[idx] = (i <= j) ? G[idx] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Z = X R^{-1} row by row (forward substitution in FP64):
+//   z_c = (x_c - sum_{k<c} z_k R(k,c)) / R(c,c).
+// X element (i, c) at c*ldx + i; Z likewise (ldz); may alias X.
+// R (f x f, element (i,j) at j*f + i) staged in LDS when small.
+// Only columns c < ncols_out(_dev) are written, at Z + (zoff(_dev) + c)*ldz:
+// for the basis append, zoff = wlog[block_id] and ncols_out = acc[block_id].
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tout, int FMAX>
+__global__ __launch_bounds__(256) void k_trsm_rows(
+    const Tin* __restrict__ X, int64_t ldx, Tout* __restrict__ Zo, int64_t ldz, int64_t m,
+    int f, const double* __restrict__ R, int64_t zoff, int ncols_out,
+    const int64_t* __restrict__ wlog, const int32_t* __restrict__ acc_dev,
+    const int32_t* __restrict__ stop_block, int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  if (wlog) zoff = wlog[block_id];
+  if (acc_dev) ncols_out = acc_dev[block_id];
+  __shared__ double Rs[FMAX * FMAX];
+  for (int idx = threadIdx.x; idx < f * f; idx += blockDim.x) Rs[idx] = R[idx];
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double z[FMAX];
+#pragma unroll
+  for (int c = 0; c < FMAX; ++c) {
+    if (c < f) {
+      double v = (double)X[(int64_t)c * ldx + i];
+      for (int k = 0; k < c; ++k) v -= z[k] * Rs[c * f + k];
+      z[c] = v / Rs[c * f + c];
+    } else {
+      z[c] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < FMAX; ++c)
+    if (c < ncols_out) Zo[(zoff + c) * ldz + i] = (Tout)z[c];
+}
+
+// Large-f variant: R read from global memory (L2), z kept in global scratch.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_trsm_rows_big(
+    const Tin* __restrict__ X, int64_t ldx, Tout* __restrict__ Zo, int64_t ldz, int64_t m,
+    int f, const double* __restrict__ R, int ncols_out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  // in place over X is not allowed here; Zo holds the solution progressively
+  for (int c = 0; c < f; ++c) {
+    double v = (double)X[(int64_t)c * ldx + i];
+    const double* Rc = R + (int64_t)c * f;
+    for (int k = 0; k < c; ++k) v -= (double)Zo[(int64_t)k * ldz + i] * Rc[k];
+    Zo[(int64_t)c * ldz + i] = (Tout)(v / Rc[c]);
+  }
+  (void)ncols_out;
+}
+
+// ---------------------------------------------------------------------------
+// Stopping test of Alg. 1 for block `block_id` (one thread):
+//   d_c = |T(c,c)| = R2(c,c) R1(c,c) (0 for dead columns); the first c with
+//   d_c <= eps stops the loop and keeps columns 0..c-1; otherwise all f are
+//   kept and the loop ends when the last column of Omega has been used.
+// Writes acc[block], wlog[block+1] = wlog[block] + acc, the examined d_c to
+// diag_log[col0 + c], and stop_block.
+// ---------------------------------------------------------------------------
+__global__ void k_decide(const double* __restrict__ R1, const double* __restrict__ R2,
+                         const int32_t* __restrict__ dead, int f, int64_t col0, int64_t n,
+                         State* st, int64_t* __restrict__ wlog, int32_t* __restrict__ acc,
+                         double* __restrict__ diag_log, int block_id) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (st->stop_block < block_id) return;
+  const double eps = st->eps;
+  int keep = f;
+  bool stop = false;
+  if (st->nonfinite) {
+    keep = 0;
+    stop = true;
+  } else {
+    for (int c = 0; c < f; ++c) {
+      const double d = dead[c] ? 0.0 : R2[(int64_t)c * f + c] * R1[(int64_t)c * f + c];
+      diag_log[col0 + c] = d;
+      if (d <= eps) { keep = c; stop = true; break; }
+    }
+  }
+  if (col0 + f >= n) stop = true;
+  acc[block_id] = keep;
+  wlog[block_id + 1] = wlog[block_id] + keep;
+  if (stop) st->stop_block = block_id;
+}
+
+// ||A||_F from per-workgroup partial sums (fixed order), eps = tol ||A||_F.
+__global__ void k_finish_norm(const double* __restrict__ parts, int64_t nparts, State* st) {
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) a += parts[i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double s = red[0];
+    st->normsq = s;
+    const bool bad = !(s < INFINITY);   // NaN or Inf
+    st->nonfinite = bad ? 1 : 0;
+    st->eps = bad ? 0.0 : st->tol * sqrt(s);
+  }
+}
+
+__global__ void k_init_state(State* st, double tol, int64_t* wlog, int nwlog) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->eps = 0.0; st->normsq = 0.0; st->tol = tol;
+    st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->pad = 0;
+    for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
+  }
+  for (int i = threadIdx.x; i < nwlog; i += blockDim.x) wlog[i] = 0;
+}
+
+// Fill with zeros (graph-safe replacement for memset).
+template <typename T>
+__global__ void k_zero(T* __restrict__ p, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (T)0;
+}
+
+// R = R2 * R1 (upper triangular f x f, element (i,j) at j*f+i).  Writes the
+// product transposed if transpose_out (element (i,j) of R at i*f + j).
+__global__ void k_trimul(const double* __restrict__ R2, const double* __restrict__ R1, int f,
+                         double* __restrict__ out, int transpose_out) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)f * f) return;
+  const int j = (int)(idx / f), i = (int)(idx - (int64_t)j * f);
+  double v = 0.0;
+  if (i <= j)
+    for (int k = i; k <= j; ++k) v += R2[(int64_t)k * f + i] * R1[(int64_t)j * f + k];
+  if (transpose_out) out[(int64_t)i * f + j] = v;
+  else out[idx] = v;
+}
+
+// Generic 2-D copy with optional transpose and type conversion:
+// dst(i, j) at dst[i*ldd + j] = src(i, j) (no transpose, src[i*lds + j]) or
+// src(j, i) (transpose, src[j*lds + i]), for i < rows, j < cols.
+template <typename Ts, typename Td>
+__global__ void k_copy2d(const Ts* __restrict__ src, int64_t lds, Td* __restrict__ dst, int64_t ldd,
+                         int64_t rows, int64_t cols, int transpose) {
+  __shared__ Ts tile[32][33];
+  const int64_t bi = (int64_t)blockIdx.y * 32, bj = (int64_t)blockIdx.x * 32;
+  if (!transpose) {
+    for (int ty = threadIdx.y; ty < 32; ty += blockDim.y) {
+      const int64_t i = bi + ty, j = bj + threadIdx.x;
+      if (i < rows && j < cols) dst[i * ldd + j] = (Td)src[i * lds + j];
+    }
+    return;
+  }
+  // dst(i,j) = src(j,i): read a 32x32 tile of src rows bj.., cols bi..
+  for (int ty = threadIdx.y; ty < 32; ty += blockDim.y) {
+    const int64_t sr = bj + ty, sc = bi + threadIdx.x;
+    tile[ty][threadIdx.x] = (sr < cols && sc < rows) ? src[sr * lds + sc] : (Ts)0;
+  }
+  __syncthreads();
+  for (int ty = threadIdx.y; ty < 32; ty += blockDim.y) {
+    const int64_t i = bi + ty, j = bj + threadIdx.x;
+    if (i < rows && j < cols) dst[i * ldd + j] = (Td)tile[threadIdx.x][ty];
+  }
+}
+
+}  // namespace eodabe

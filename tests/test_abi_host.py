@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU needed): the shared library loads,
+exports every function include/eodabe.h declares, validates options and
+sizes, and plans workspace, using a host-only context."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "eodabe.h")
+LIB = os.path.join(ROOT, "paper_2506_22713_amd", "libeodabe.so")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(eodabe_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not os.path.exists(LIB):
+        pytest.fail("libeodabe.so not built (run python -m paper_2506_22713_amd.build)")
+    import paper_2506_22713_amd as E
+    return E
+
+
+def test_every_declared_symbol_is_exported(E):
+    names = _declared()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert getattr(lib, n) is not None
+    assert set(E.EXPORTED) <= set(names)
+
+
+def test_strerror_and_defaults(E):
+    for code in (0, -1, -2, -3, -4, -5, -6, 1):
+        assert E.strerror(code) and E.strerror(code) != "unknown status"
+    o = E.Opts()
+    E._lib.eodabe_default_opts(ctypes.byref(o))
+    assert o.block == 32 and o.power_iters == 0 and o.a_dtype == E.F32
+
+
+@pytest.mark.parametrize("bad", [dict(block=0), dict(block=129), dict(power_iters=-1),
+                                 dict(power_iters=17), dict(blocks_per_sync=-1)])
+def test_option_validation(E, bad):
+    with pytest.raises(E.EodAbeError) as ei:
+        E.Context(host_only=True, **bad)
+    assert ei.value.status == E.EODABE_EINVAL
+
+
+def test_workspace_planning(E):
+    import torch
+    c = E.Context(host_only=True)
+    s1 = c.workspace_size(512, 512)
+    s2 = c.workspace_size(4096, 4096)
+    s3 = c.workspace_size(4096, 4096, 400)
+    assert 0 < s1 < s2 and 0 < s3 < s2
+    assert c.workspace_size(200, 500) > 0          # wide: transposed plan
+    assert c.workspace_size(10, 10, 11) == 0       # r_cap > min(m, n)
+    assert c.workspace_size(-1, 10) == 0
+    c64 = E.Context(host_only=True, dtype=torch.float64)
+    assert c64.workspace_size(512, 512) > s1
+
+
+def test_factor_argument_errors_without_device(E):
+    c = E.Context(host_only=True)
+    info = E.Info()
+    f = E._lib.eodabe_factor
+    ws = ctypes.create_string_buffer(16)
+    # NULL context, bad sizes, bad lda, bad tol: rejected before any device use
+    assert f(None, None, 4, 4, 4, 1e-3, None, 0, None, None, None, 0, ctypes.byref(info)) == E.EODABE_EINVAL
+    assert f(c.h, None, -1, 4, 4, 1e-3, None, 0, None, None, None, 0, ctypes.byref(info)) == E.EODABE_EINVAL
+    assert f(c.h, ws, 4, 4, 3, 1e-3, None, 0, ws, ws, ws, 0, ctypes.byref(info)) == E.EODABE_EINVAL
+    for tol in (0.0, -1.0, float("nan"), float("inf")):
+        assert f(c.h, ws, 4, 4, 4, tol, None, 0, ws, ws, ws, 0, ctypes.byref(info)) == E.EODABE_EINVAL
+    # workspace too small
+    assert f(c.h, ws, 4, 4, 4, 1e-3, ws, 16, ws, ws, ws, 0, ctypes.byref(info)) == E.EODABE_EWORKSPACE
+    # empty problem: nothing to do
+    need = c.workspace_size(0, 5)
+    big = ctypes.create_string_buffer(need)
+    assert f(c.h, None, 0, 5, 5, 1e-3, big, need, None, None, None, 0, ctypes.byref(info)) == E.EODABE_OK
+    # a well-formed call on a host-only context reports the missing device
+    need = c.workspace_size(4, 4)
+    big = ctypes.create_string_buffer(need)
+    assert f(c.h, ws, 4, 4, 4, 1e-3, big, need, ws, ws, ws, 0, ctypes.byref(info)) == E.EODABE_ENODEVICE

@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (written per test):
+* Philox words: bit-exact.  Gaussian entries: FP32 values equal except for
+  at most a few 1-ulp differences (both sides evaluate Box-Muller in FP64
+  with their own libm and round to FP32).
+* Sketch A*Omega: elementwise |Y - Y_ref| <= K u (|A| |Omega|) (the
+  classical bound of a length-K dot product in the data precision).
+* Rank: equal to the oracle's rank on every precision-stable instance
+  (FP64 runs: always; FP32 runs: where the FP64 oracle and its FP32-data
+  emulation agree).  diag(T) within the precision's resolution.
+* RelErr = ||A - U D V^T||_F / ||A||_F within 1e-10 (FP64) or 1e-5 (FP32)
+  of the oracle's, absolute; orthonormality of U and V; D upper triangular
+  with a non-negative diagonal.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle.eodabe_oracle as O  # noqa: E402
+import paper_2506_22713_amd as E  # noqa: E402
+import workloads as W  # noqa: E402
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+RELERR_TOL = {torch.float32: 1e-5, torch.float64: 1e-10}
+ORTH_TOL = {torch.float32: 5e-5, torch.float64: 1e-12}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev(A, dtype):
+    return torch.from_numpy(np.ascontiguousarray(A)).to(device="cuda", dtype=dtype)
+
+
+def gpu_relerr(A64, f):
+    U = f.U.double().cpu().numpy()
+    D = f.D.double().cpu().numpy()
+    Vt = f.Vt.double().cpu().numpy()
+    nrm = np.linalg.norm(A64)
+    return float(np.linalg.norm(A64 - U @ D @ Vt) / nrm) if nrm else 0.0, U, D, Vt
+
+
+def check_factor(A64, dtype, tol, b=32, q=0, seed=0, stable=True):
+    say("factor", A64.shape, dtype, "tol", tol, "b", b, "q", q, "seed", seed)
+    ref = O.eod_abe(A64, tol, k=b, q=q, seed=seed)
+    f = E.factor(dev(A64, dtype), tol, block=b, power_iters=q, seed=seed)
+    torch.cuda.synchronize()
+    if stable:
+        assert f.rank == ref.rank, (f.rank, ref.rank)
+    if f.rank == 0:
+        return f, ref
+    e_gpu, U, D, Vt = gpu_relerr(A64, f)
+    e_ref = O.rel_err(A64, ref.U, ref.D, ref.V)
+    if f.rank == ref.rank:
+        assert abs(e_gpu - e_ref) <= RELERR_TOL[dtype], (e_gpu, e_ref)
+    r = f.rank
+    assert np.linalg.norm(U.T @ U - np.eye(r)) <= ORTH_TOL[dtype] * math.sqrt(r)
+    assert np.linalg.norm(Vt @ Vt.T - np.eye(r)) <= ORTH_TOL[dtype] * math.sqrt(r)
+    assert np.all(np.tril(D, -1) == 0) and np.all(np.diag(D) >= 0)
+    return f, ref
+
+
+@pytest.fixture(scope="module")
+def ctx32():
+    return E.Context(dtype=torch.float32, seed=1234)
+
+
+# ---------------------------------------------------------------- RNG
+@pytest.mark.parametrize("seed", [0, 1234, 2 ** 40 + 7])
+def test_philox_bit_exact(seed):
+    say("philox", seed)
+    c = E.Context(seed=seed)
+    n = 5000
+    got = E.philox(c, seed, 17, 3, 9, n).cpu().numpy().view(np.uint32)
+    ctr = np.zeros((n, 4), dtype=np.uint64)
+    ctr[:, 0] = 17 + np.arange(n)
+    ctr[:, 1] = 3
+    ctr[:, 2] = 9
+    ref = O.philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_omega_matches_oracle(dtype):
+    say("omega", dtype)
+    c = E.Context(seed=99, dtype=dtype)
+    n, col0, nc = 1003, 37, 21
+    got = E.omega(c, n, col0, nc, dtype=dtype).double().cpu().numpy()
+    ref = O.omega_columns(99, n, col0, nc)
+    diff = got != ref
+    assert diff.mean() <= 1e-4
+    if diff.any():
+        g32, r32 = got[diff].astype(np.float32), ref[diff].astype(np.float32)
+        ulp = np.abs(g32.view(np.int32).astype(np.int64) - r32.view(np.int32).astype(np.int64))
+        assert ulp.max() <= 1
+
+
+# ---------------------------------------------------------------- sketch
+@pytest.mark.parametrize("m,n,nc,col0", [(300, 200, 32, 0), (1000, 777, 20, 64), (4099, 4100, 32, 32),
+                                         (129, 33, 128, 0), (5000, 17, 16, 3)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_sketch_matches_oracle_product(m, n, nc, col0, dtype):
+    say("sketch", m, n, nc, col0, dtype)
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n))
+    if dtype == torch.float32:
+        A = A.astype(np.float32).astype(np.float64)
+    c = E.Context(seed=5, dtype=dtype)
+    Y = E.sketch(c, dev(A, dtype), col0, nc).double().cpu().numpy()
+    Om = O.omega_columns(5, n, col0, nc)
+    ref = A @ Om
+    bound = n * (U32 if dtype == torch.float32 else U64) * (np.abs(A) @ np.abs(Om)) + 1e-300
+    assert np.all(np.abs(Y - ref) <= bound)
+
+
+def test_sketch_unaligned_leading_dimension():
+    say("sketch unaligned lda")
+    rng = np.random.default_rng(3)
+    big = rng.standard_normal((200, 103)).astype(np.float32)
+    At = torch.from_numpy(big).cuda()[:, :101]                 # lda = 103 (not a multiple of 4)
+    c = E.Context(seed=8)
+    Y = E.sketch(c, At, 0, 16).double().cpu().numpy()
+    A = big[:, :101].astype(np.float64)
+    ref = A @ O.omega_columns(8, 101, 0, 16)
+    assert np.all(np.abs(Y - ref) <= 101 * U32 * (np.abs(A) @ np.abs(O.omega_columns(8, 101, 0, 16))))
+
+
+# ---------------------------------------------------------------- Alg. 1
+@pytest.mark.parametrize("seed", range(5))
+def test_basis_c1_fp64(seed):
+    say("basis C1 fp64", seed)
+    A = W.lowrank_haar(seed)
+    nrm = np.linalg.norm(A)
+    ref = O.basis_ext(A, 1e-8 * nrm, 32, seed)
+    Q, d, info = E.basis(dev(A, torch.float64), 1e-8, block=32, seed=seed, dtype=torch.float64)
+    assert info.rank == ref["rank"]
+    k = min(len(d), len(ref["diagT"]))
+    assert np.max(np.abs(d[:k] - ref["diagT"][:k])) <= 1e-12 * nrm
+    Qn = Q.cpu().numpy()
+    assert np.linalg.norm(Qn.T @ Qn - np.eye(info.rank)) < 1e-12
+    # same subspace as the oracle's basis, to the resolution of the weakest
+    # accepted direction (rounding u ||A|| over its pivot)
+    dmin = ref["diagT"][: info.rank].min()
+    assert np.linalg.norm(Qn @ (Qn.T @ ref["Q"]) - ref["Q"]) < 100 * U64 * nrm / dmin * math.sqrt(info.rank)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_basis_c1_fp32(seed):
+    say("basis C1 fp32", seed)
+    A = W.lowrank_haar(seed).astype(np.float32).astype(np.float64)
+    stable, r64, r32 = O.precision_stable(A, 1e-5, 32, seed)
+    Q, d, info = E.basis(dev(A, torch.float32), 1e-5, block=32, seed=seed)
+    if stable:
+        assert info.rank == r64
+    ref = O.basis_ext(A, 1e-5 * np.linalg.norm(A), 32, seed)
+    k = min(len(d), len(ref["diagT"]))
+    assert np.max(np.abs(d[:k] - ref["diagT"][:k])) <= 64 * math.sqrt(A.shape[1]) * U32 * np.linalg.norm(A)
+
+
+# ---------------------------------------------------------------- Alg. 2
+@pytest.mark.parametrize("seed", range(4))
+def test_factor_c1_fp64(seed):
+    check_factor(W.lowrank_haar(seed), torch.float64, 1e-8, seed=seed)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_factor_c1_fp32(seed):
+    A = W.lowrank_haar(seed).astype(np.float32).astype(np.float64)
+    stable, _, _ = O.precision_stable(A, 1e-5, 32, seed)
+    check_factor(A, torch.float32, 1e-5, seed=seed, stable=stable)
+
+
+def test_factor_exact_rank_matches_oracle_factors():
+    A = W.lowrank_haar(7, m=400, n=300, r=20, noise_std=0.0)
+    f, ref = check_factor(A, torch.float64, 1e-10, b=16, seed=7)
+    # factors are unique (positive diagonals): compare element by element
+    D = f.D.cpu().numpy()
+    assert np.max(np.abs(D - ref.D)) <= 1e-9 * np.abs(ref.D).max()
+    U = f.U.cpu().numpy()
+    assert np.max(np.abs(U - ref.U)) <= 1e-7
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_factor_power_iteration(q):
+    A = W.lowrank_haar(3)
+    f, ref = check_factor(A, torch.float64, 1e-8, q=q, seed=3)
+    ey = O.eckart_young_relerr(A, f.rank)
+    e, *_ = gpu_relerr(A, f)
+    assert abs(e - ey) <= 1e-10
+
+
+def test_factor_wide_matrix():
+    A = W.lowrank_haar(4, m=150, n=420, r=12, noise_std=0.0)
+    check_factor(A, torch.float64, 1e-9, b=8, seed=4)
+
+
+def test_factor_full_rank_ragged():
+    A = np.random.default_rng(0).standard_normal((333, 70))
+    f, ref = check_factor(A, torch.float64, 1e-13, b=16, seed=2)
+    assert f.rank == 70 and f.blocks == 5
+
+
+@pytest.mark.parametrize("b", [1, 8, 20, 64, 100, 128])
+def test_factor_block_sizes(b):
+    A = W.lowrank_haar(9, m=500, n=260, r=30, noise_std=1e-10)
+    check_factor(A, torch.float64, 1e-7, b=b, seed=9)
+
+
+def test_zero_matrix_rank_zero():
+    say("zero matrix")
+    f = E.factor(torch.zeros((64, 48), device="cuda"), 1e-3)
+    assert f.rank == 0
+
+
+def test_rank_zero_first_column():
+    say("rank zero first column")
+    A = W.lowrank_haar(1, m=64, n=64, r=3, noise_std=0.0)
+    f = E.factor(dev(A, torch.float64), 10.0, block=8)
+    assert f.rank == 0 and f.blocks == 1
+
+
+def test_capacity_error():
+    say("capacity")
+    A = W.lowrank_haar(2, m=200, n=200, r=30, noise_std=0.0)
+    with pytest.raises(E.EodAbeError) as ei:
+        E.factor(dev(A, torch.float64), 1e-10, r_cap=10)
+    assert ei.value.status == E.EODABE_ECAPACITY
+
+
+def test_nonfinite_input():
+    say("nonfinite")
+    A = torch.ones((100, 80), device="cuda")
+    A[5, 7] = float("nan")
+    with pytest.raises(E.EodAbeError) as ei:
+        E.factor(A, 1e-3)
+    assert ei.value.status == E.EODABE_ENONFINITE
+
+
+def test_tol_floor_warning():
+    say("tol floor")
+    A = W.lowrank_haar(0).astype(np.float32)
+    f = E.factor(dev(A, torch.float32), 1e-9)
+    assert f.status == E.EODABE_WTOL_FLOOR and (f.flags & 1)
+
+
+def test_deterministic_runs():
+    say("determinism")
+    A = dev(W.image(1, 1024, 0.05), torch.float32)
+    f1 = E.factor(A, 1e-3, seed=3)
+    f2 = E.factor(A, 1e-3, seed=3)
+    assert f1.rank == f2.rank
+    assert torch.equal(f1.D, f2.D) and torch.equal(f1.U, f2.U) and torch.equal(f1.Vt, f2.Vt)
+
+
+# ---------------------------------------------------------------- workloads
+def test_image_small_fp32():
+    A = W.image(0, 1024, 0.05).astype(np.float64)
+    stable, _, _ = O.precision_stable(A, 1e-3, 32, 0)
+    check_factor(A, torch.float32, 1e-3, seed=0, stable=stable)
+
+
+def test_hyperspectral_small_fp32():
+    A = W.hyperspectral(0, pixels=16384).astype(np.float64)
+    stable, _, _ = O.precision_stable(A, 1e-2, 16, 0)
+    check_factor(A, torch.float32, 1e-2, b=16, seed=0, stable=stable)
+
+
+def test_mat2_fp64():
+    A = W.mat2(1, 600, 240)
+    check_factor(A, torch.float64, 1e-12, b=32, seed=1)

@@ -72,23 +72,25 @@ def image(seed: int, size: int = 4096, noise_std: float = 0.5, blobs: int = 64,
     w = size if width is None else width
     y = np.arange(h, dtype=np.float64)
     x = np.arange(w, dtype=np.float64)
-    img = np.zeros((h, w), dtype=np.float64)
+    # the image is a sum of outer products: collect the factors, one matmul
+    fy, fx = [], []
     for _ in range(blobs):
         cy, cx = rng.uniform(0, h), rng.uniform(0, w)
         sg = rng.uniform(*sigma_px)
         amp = rng.uniform(-1.0, 1.0)
-        gy = np.exp(-0.5 * ((y - cy) / sg) ** 2)
-        gx = np.exp(-0.5 * ((x - cx) / sg) ** 2)
-        img += amp * np.outer(gy, gx)
+        fy.append(amp * np.exp(-0.5 * ((y - cy) / sg) ** 2))
+        fx.append(np.exp(-0.5 * ((x - cx) / sg) ** 2))
     n_ref = float(max(h, w))
     for _ in range(modes):
-        fy, fx = rng.integers(0, 8, size=2)
+        ky, kx = rng.integers(0, 8, size=2)
         phi = rng.uniform(0, 2 * np.pi)
         amp = rng.uniform(-0.3, 0.3)
-        ay = 2 * np.pi * fy * y / n_ref
-        ax = 2 * np.pi * fx * x / n_ref + phi
+        ay = 2 * np.pi * ky * y / n_ref
+        ax = 2 * np.pi * kx * x / n_ref + phi
         # cos(ay + ax) = cos ay cos ax - sin ay sin ax  (rank <= 2)
-        img += amp * (np.outer(np.cos(ay), np.cos(ax)) - np.outer(np.sin(ay), np.sin(ax)))
+        fy += [amp * np.cos(ay), -amp * np.sin(ay)]
+        fx += [np.cos(ax), np.sin(ax)]
+    img = np.stack(fy, axis=1) @ np.stack(fx, axis=1).T
     lo, hi = img.min(), img.max()
     img = (img - lo) * (255.0 / (hi - lo)) if hi > lo else np.zeros_like(img)
     if noise_std:

@@ -167,7 +167,8 @@ struct WS {
   void* y;              // ldy x bn
   void* wpart;          // s_proj x ldw x bn
   void* w;              // ldw x bn
-  double* gpart;        // s_gram x bn x bn
+  double* gpart;        // Gram partials (max(s_gram,16) x bn x bn)
+  double* gsum;         // summed block Gram (bn x bn)
   double* r1;           // bn x bn
   double* r2;
   void* q;              // ldy x (nn + bn)
@@ -204,7 +205,8 @@ WS carve(void* base, const Geo& g) {
   w.y = c.take<char>(g.ldy * g.bn * e);
   w.wpart = c.take<char>((int64_t)g.s_proj * ldw_of(g) * g.bn * e);
   w.w = c.take<char>(ldw_of(g) * g.bn * e);
-  w.gpart = c.take<double>((int64_t)g.s_gram * g.bn * g.bn);
+  w.gpart = c.take<double>((int64_t)std::max(g.s_gram, 64) * g.bn * g.bn);
+  w.gsum = c.take<double>((int64_t)g.bn * g.bn);
   w.r1 = c.take<double>(g.bn * g.bn);
   w.r2 = c.take<double>(g.bn * g.bn);
   w.q = c.take<char>(g.ldy * (g.nn + g.bn) * e);
@@ -214,14 +216,14 @@ WS carve(void* base, const Geo& g) {
   w.cpart = c.take<char>((int64_t)g.s_core * rc * g.ldk * e);
   w.ybig = c.take<char>(g.ldy * rc * e);
   const int64_t rb = std::max<int64_t>(rc, g.bn);
-  w.gbig = c.take<double>(std::max<int64_t>(32 * std::min<int64_t>(rb, 64) * std::min<int64_t>(rb, 64),
+  w.gbig = c.take<double>(std::max<int64_t>(64 * std::min<int64_t>(rb, 64) * std::min<int64_t>(rb, 64),
                                             rb * rb));
   w.rb1 = c.take<double>(rb * rb);
   w.rb2 = c.take<double>(rb * rb);
   w.rb3 = c.take<double>(rb * rb);
   w.rb4 = c.take<double>(rb * rb);
   w.deadbig = c.take<int32_t>(rc + 64);
-  w.dg = c.take<double>(rc + 64);
+  w.dg = c.take<double>(std::max<int64_t>(rc, g.bn) + 64);
   w.tbig = c.take<char>(std::max(g.ldy, g.ldk) * rc * std::max<size_t>(e, 8));
   w.total = c.off + 256;
   return w;
@@ -297,14 +299,47 @@ struct Ops {
     return 0;
   }
 
+  // Y partials = A Omega^T (bn <= 128 columns), see k_sketch
+  int sketch(const T* A, int64_t lda, const T* Om, int64_t ldk, int64_t M, int bn, int64_t K,
+             int splits, T* out, int64_t ldo, int64_t part_stride, double* sumsq,
+             const int32_t* stopb, int blk) {
+    if (M <= 0 || bn <= 0) return 0;
+    const int64_t kchunk = split_chunk(K, splits);
+    splits = eff_splits(K, splits);
+#define SK_CASE(CC)                                                                                   \
+  do {                                                                                                \
+    dim3 grid((unsigned)cdiv(M, 128), splits, 1);                                                     \
+    hipLaunchKernelGGL((k_sketch<T, 2, CC>), grid, dim3(256), 0, st, A, lda, Om, ldk, M, bn, K, kchunk, \
+                       out, ldo, part_stride, sumsq, stopb, blk);                                     \
+  } while (0)
+    if (bn <= 16) SK_CASE(1);
+    else if (bn <= 32) SK_CASE(2);
+    else if (bn <= 48) SK_CASE(3);
+    else if (bn <= 64) SK_CASE(4);
+    else if (bn <= 96) SK_CASE(6);
+    else SK_CASE(8);
+#undef SK_CASE
+    LAUNCHCHK();
+    return 0;
+  }
+
   int gemm_nn(const T* X, int64_t ldx, const T* Z, int64_t ldz, int64_t M, int64_t N, int64_t K,
               int splits, T* out, int64_t ldo, int64_t part_stride) {
     if (M <= 0 || N <= 0) return 0;
     const int64_t kchunk = split_chunk(K, splits);
     splits = eff_splits(K, splits);
-    dim3 grid((unsigned)cdiv(N, 256), splits, (unsigned)cdiv(M, 64));
-    hipLaunchKernelGGL((k_gemm_nn<T, 4>), grid, dim3(256), 0, st, X, ldx, Z, ldz, M, N, K, kchunk,
-                       out, ldo, part_stride);
+    // rows of the output per wave: 16*RT with RT = ceil(M/16) up to 4, so a
+    // small rank does not spend MFMA cycles on padding rows
+    const int rt = (int)std::min<int64_t>(4, cdiv(M, 16));
+    dim3 grid((unsigned)cdiv(N, 256), splits, (unsigned)cdiv(M, 16 * rt));
+#define NN_CASE(RR)                                                                                   \
+  hipLaunchKernelGGL((k_gemm_nn<T, RR>), grid, dim3(256), 0, st, X, ldx, Z, ldz, M, N, K, kchunk, out, \
+                     ldo, part_stride)
+    if (rt == 1) NN_CASE(1);
+    else if (rt == 2) NN_CASE(2);
+    else if (rt == 3) NN_CASE(3);
+    else NN_CASE(4);
+#undef NN_CASE
     LAUNCHCHK();
     return 0;
   }
@@ -320,24 +355,36 @@ struct Ops {
     return 0;
   }
 
+  template <typename U>
+  int reduce_wide(const U* parts, int nparts, int64_t stride, int64_t count, U* out,
+                  const int32_t* stopb = nullptr, int blk = 0) {
+    if (count <= 0) return 0;
+    if (nparts <= 4) return reduce(parts, nparts, stride, count, out, stopb, blk);
+    hipLaunchKernelGGL((k_reduce_parts_wide<U>), dim3((unsigned)cdiv(count, 64)), dim3(64, 16), 0, st,
+                       parts, nparts, stride, count, out, stopb, blk);
+    LAUNCHCHK();
+    return 0;
+  }
+
   // Z = X R^{-1} (R f x f FP64).  In place allowed only for f <= 64.
   int trsm(const T* X, int64_t ldx, T* Zo, int64_t ldz, int64_t m, int f, const double* R,
            int64_t zoff, int ncols_out, const int64_t* wlog = nullptr, const int32_t* accd = nullptr,
            const int32_t* stopb = nullptr, int blk = 0) {
     if (m <= 0 || f <= 0) return 0;
-    dim3 grid((unsigned)cdiv(m, 256));
+    dim3 grid((unsigned)cdiv(m, 64));
     if (f <= 16) {
-      hipLaunchKernelGGL((k_trsm_rows<T, T, 16>), grid, dim3(256), 0, st, X, ldx, Zo, ldz, m, f, R,
+      hipLaunchKernelGGL((k_trsm_rows<T, T, 16>), grid, dim3(64), 0, st, X, ldx, Zo, ldz, m, f, R,
                          zoff, ncols_out, wlog, accd, stopb, blk);
     } else if (f <= 32) {
-      hipLaunchKernelGGL((k_trsm_rows<T, T, 32>), grid, dim3(256), 0, st, X, ldx, Zo, ldz, m, f, R,
+      hipLaunchKernelGGL((k_trsm_rows<T, T, 32>), grid, dim3(64), 0, st, X, ldx, Zo, ldz, m, f, R,
                          zoff, ncols_out, wlog, accd, stopb, blk);
     } else if (f <= 64) {
-      hipLaunchKernelGGL((k_trsm_rows<T, T, 64>), grid, dim3(256), 0, st, X, ldx, Zo, ldz, m, f, R,
+      hipLaunchKernelGGL((k_trsm_rows<T, T, 64>), grid, dim3(64), 0, st, X, ldx, Zo, ldz, m, f, R,
                          zoff, ncols_out, wlog, accd, stopb, blk);
     } else {
       // out of place only (the caller provides distinct buffers)
-      hipLaunchKernelGGL((k_trsm_rows_big<T, T>), grid, dim3(256), 0, st, X, ldx, Zo, ldz, m, f, R,
+      hipLaunchKernelGGL((k_trsm_rows_big<T, T>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, X,
+                         ldx, Zo, ldz, m, f, R,
                          ncols_out);
     }
     LAUNCHCHK();
@@ -348,8 +395,8 @@ struct Ops {
   int update_d(T* Y, int64_t ldy, const T* Q, int64_t ldq, int64_t m, int64_t w, int f,
                const double* W, int64_t ldw) {
     if (m <= 0 || f <= 0) return 0;
-    dim3 grid((unsigned)cdiv(m, 256), (unsigned)cdiv(f, 32));
-    hipLaunchKernelGGL((k_update_rows<T, double, 32>), grid, dim3(256), 0, st, Y, ldy, Q, ldq, m, w, f,
+    dim3 grid((unsigned)cdiv(m, 64), (unsigned)cdiv(f, 32));
+    hipLaunchKernelGGL((k_update_rows<T, double, 32>), grid, dim3(64), 0, st, Y, ldy, Q, ldq, m, w, f,
                        W, ldw, 0, (const int64_t*)nullptr, (const int32_t*)nullptr, 0);
     LAUNCHCHK();
     return 0;
@@ -367,63 +414,122 @@ struct Ops {
   }
 };
 
-int launch_cholesky(eodabe_ctx* ctx, hipStream_t st, const double* parts, int nparts,
-                    int64_t pstride, int f, double* R, int32_t* dead, int first, State* stp,
-                    const int32_t* stopb, int blk, int count_floors, double* gscratch, double* dg) {
+CholArgs chol_args(const WS& w, double* R, int32_t* dead, int first, int fresh, int count_floors) {
+  CholArgs ca{};
+  ca.R = R;
+  ca.dead = dead;
+  ca.first_pass = first;
+  ca.fresh = fresh;
+  ca.st = w.st;
+  ca.count_floors = count_floors;
+  return ca;
+}
+
+// G = X^T X (FP64) of the column-major rows x f block X, then R = chol(G)
+// with the floor/kill rules and the epilogues in ca (stop test, product,
+// D output, ||A||_F finish).  With Rsolve, X := X Rsolve^{-1} first (in
+// place).  f <= 64: one launch (k_gram_rows; its last workgroup runs the
+// Cholesky).  Wider blocks: generic GEMM, global Cholesky, separate stop
+// test (no fused solve or product).
+template <typename T>
+int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, int64_t rows, int f,
+              double* parts, const CholArgs& ca, const int32_t* stopb = nullptr, int blk = 0,
+              const double* Rsolve = nullptr) {
   if (f <= 0) return 0;
-  const size_t lds = ((size_t)f * f + f) * sizeof(double);
-  if (f <= 64 && nparts > 16) {
-    const int64_t cnt = (int64_t)f * f;
-    hipLaunchKernelGGL(k_reduce_parts<double>, dim3((unsigned)cdiv(cnt, 256)), dim3(256), 0, st, parts,
-                       nparts, pstride, cnt, gscratch, stopb, blk);
-    parts = gscratch;
-    nparts = 1;
-  }
   if (f <= 64) {
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), lds, st, parts, nparts, pstride, f, R, dead,
-                       first, stp, stopb, blk, count_floors);
-  } else {
-    // sum the parts into gscratch, then factor in global memory
-    const int64_t cnt = (int64_t)f * f;
-    unsigned nb = (unsigned)std::min<int64_t>(cdiv(cnt, 256), 4096);
-    hipLaunchKernelGGL(k_reduce_parts<double>, dim3(nb), dim3(256), 0, st, parts, nparts, pstride,
-                       cnt, gscratch, stopb, blk);
-    hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(256), 0, st, gscratch, f, R, dead, dg, first,
-                       stp, count_floors);
+    uint32_t* counter = &w.st->counter[0];
+#define GRAM_CASE(FF, MM)                                                                            \
+  do {                                                                                               \
+    const int64_t npan = cdiv(rows, GramCfg<T, FF, MM>::RPW);                                        \
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(npan, 64));               \
+    hipLaunchKernelGGL((k_gram_rows<T, FF, MM>), dim3(grid), dim3(256), 0, st, X, ld, rows, f,       \
+                       Rsolve, parts, counter, stopb, blk, ca);                                      \
+  } while (0)
+#define GRAM_F(FF)                   \
+  do {                               \
+    if (Rsolve) GRAM_CASE(FF, 2);    \
+    else GRAM_CASE(FF, 0);           \
+  } while (0)
+    if (f <= 16) GRAM_F(16);
+    else if (f <= 32) GRAM_F(32);
+    else if (f <= 48) GRAM_F(48);
+    else GRAM_F(64);
+#undef GRAM_F
+#undef GRAM_CASE
+    LAUNCHCHK();
+    return 0;
   }
+  if (Rsolve || ca.Rprod || ca.Dout) return EODABE_EINVAL;   // fused forms only for f <= 64
+  Ops<T> ops{ctx, st};
+  if (ca.fresh) hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, ca.dead, (int64_t)f);
+  if (ca.norm_parts)
+    hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, ca.norm_parts, ca.n_norm, w.st);
+  TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, 1, parts, f, (int64_t)f * f, nullptr,
+                                   nullptr, stopb, blk));
+  hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.dead, w.dg,
+                     ca.first_pass, w.st, ca.count_floors);
+  if (ca.R1)
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, ca.R1, ca.R, ca.dead, f, ca.col0, ca.n, w.st,
+                       ca.wlog, ca.acc, ca.diag_log, blk);
   LAUNCHCHK();
   return 0;
 }
 
-// In-place CholeskyQR2 of X (rows x f, element (i,c) at c*ld + i) with the
-// floored first pass; writes R = R2 R1 (element (i,j) at j*f + i) to Rout,
-// or its transpose when transpose_R.  Scratch from ws.
+// CholeskyQR2 of X (rows x f, element (i,c) at c*ld + i), first Cholesky
+// pass floored.  The orthonormal factor goes to Zout (leading dimension ldz;
+// X itself when Zout is null), R = R2 R1 (element (i,j) at j*f + i, or its
+// transpose when transpose_R) to Rout, and optionally R in the data type,
+// row-major, to Dout (ldd).  X is overwritten.
 template <typename T>
 int cholqr2(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, T* X, int64_t ld,
-            int64_t rows, int f, double* Rout, int transpose_R, T* tmp) {
+            int64_t rows, int f, double* Rout, int transpose_R, T* tmp, T* Zout = nullptr,
+            int64_t ldz = 0, T* Dout = nullptr, int64_t ldd = 0) {
+  (void)g;
   Ops<T> ops{ctx, st};
   if (f <= 0 || rows <= 0) return 0;
-  const int sg = f <= 64 ? std::max(1, (int)std::min<int64_t>(32, rows / 512)) : 1;  // <= 32 (gbig)
-  hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, w.deadbig, (int64_t)f);
+  if (!Zout) {
+    Zout = X;
+    ldz = ld;
+  }
+  if (f <= 64) {
+    // [Gram, chol] -> R1;  [X := X R1^{-1}, Gram, chol, R2 R1] -> R2, R;  Z = X R2^{-1}
+    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, chol_args(w, w.rb1, w.deadbig, 1, 1, 1)));
+    CholArgs ca = chol_args(w, w.rb2, w.deadbig, 0, 0, 1);
+    ca.Rprod = Rout;
+    ca.prod_transpose = transpose_R;
+    ca.Dout = Dout;
+    ca.ldd = ldd;
+    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, ca, nullptr, 0, w.rb1));
+    TRY(ops.trsm(X, ld, Zout, ldz, rows, f, w.rb2, 0, f));
+    return 0;
+  }
   double* Rs[2] = {w.rb1, w.rb2};
   for (int pass = 0; pass < 2; ++pass) {
-    TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, sg, w.gbig, f, (int64_t)f * f));
-    TRY(launch_cholesky(ctx, st, w.gbig, eff_splits(rows, sg), (int64_t)f * f, f, Rs[pass], w.deadbig, pass == 0,
-                        w.st, nullptr, 0, 1, w.rb3, w.dg));
-    if (f <= 64) {
-      TRY(ops.trsm(X, ld, X, ld, rows, f, Rs[pass], 0, f));
-    } else {
-      TRY(ops.trsm(X, ld, tmp, ld, rows, f, Rs[pass], 0, f));
-      const int64_t cnt = ld * (int64_t)f;
-      hipLaunchKernelGGL((k_copy2d<T, T>), dim3((unsigned)cdiv(cnt, 32), 1), dim3(32, 8), 0, st, tmp,
-                         cnt, X, cnt, (int64_t)1, cnt, 0);
-      LAUNCHCHK();
-    }
+    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig,
+                     chol_args(w, Rs[pass], w.deadbig, pass == 0, pass == 0, 1)));
+    TRY(ops.trsm(X, ld, tmp, ld, rows, f, Rs[pass], 0, f));
+    const int64_t cnt = ld * (int64_t)f;
+    hipLaunchKernelGGL((k_copy2d<T, T>), dim3((unsigned)cdiv(cnt, 32), 1), dim3(32, 8), 0, st, tmp,
+                       cnt, X, cnt, (int64_t)1, cnt, 0);
+    LAUNCHCHK();
   }
   const int64_t ff = (int64_t)f * f;
   hipLaunchKernelGGL(k_trimul, dim3((unsigned)cdiv(ff, 256)), dim3(256), 0, st, w.rb2, w.rb1, f, Rout,
                      transpose_R);
   LAUNCHCHK();
+  if (Zout != X) {
+    dim3 grid((unsigned)cdiv(rows, 32), (unsigned)cdiv(f, 32));
+    hipLaunchKernelGGL((k_copy2d<T, T>), grid, dim3(32, 8), 0, st, X, ld, Zout, ldz, (int64_t)f, rows,
+                       0);
+    LAUNCHCHK();
+  }
+  if (Dout) {
+    if (transpose_R) return EODABE_EINVAL;
+    dim3 grid((unsigned)cdiv(f, 32), (unsigned)cdiv(f, 32));
+    hipLaunchKernelGGL((k_copy2d<double, T>), grid, dim3(32, 8), 0, st, Rout, (int64_t)f, Dout, ldd,
+                       (int64_t)f, (int64_t)f, 1);
+    LAUNCHCHK();
+  }
   return 0;
 }
 
@@ -446,10 +552,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   Ops<T> ops{ctx, st};
   const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
   const int nwlog = (int)(g.nblk + 2);
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, st, w.st, tol, w.wlog, nwlog);
-  hipLaunchKernelGGL(k_zero<int32_t>, dim3(64), dim3(256), 0, st, w.dead,
-                     (int64_t)(g.nblk + 1) * BN_MAX);
-  hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, w.accv, (int64_t)(g.nblk + 1));
+  hipLaunchKernelGGL(k_init_state, dim3(64), dim3(256), 0, st, w.st, tol, w.wlog, nwlog, w.dead,
+                     (int64_t)(g.nblk + 1) * BN_MAX, w.accv, (int)(g.nblk + 1));
   LAUNCHCHK();
   T* omega = (T*)w.omega;
   T* y = (T*)w.y;
@@ -457,7 +561,9 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   T* wbuf = (T*)w.w;
   const int64_t ldw = ldw_of(g);
   const int32_t* stopb = &w.st->stop_block;
-  int per_sync = ctx->o.blocks_per_sync > 0 ? ctx->o.blocks_per_sync : 2;
+  // blocks enqueued before each host check of the stop flag: 1, 2, 4, 4, ...
+  // (speculative blocks after the stop return at once from every kernel)
+  int per_sync = ctx->o.blocks_per_sync > 0 ? ctx->o.blocks_per_sync : 1;
   int64_t j = 0;
   bool finished = (g.nn == 0);
   int64_t sketch_wgs = cdiv(g.mm, 128);
@@ -480,23 +586,18 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       // a2: sketch Y = A Omega_j (K-split partials; block 0 also ||A||_F)
       const int64_t ystride = g.ldy * g.bn;
       const int pid = prof_begin(ctx, st);
-      TRY(ops.template gemm_nt<T>(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch,
-                                  (T*)w.ypart, g.ldy, ystride, j == 0 ? w.normparts : nullptr,
-                                  nullptr, stopb, blk));
+      TRY(ops.sketch(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch, (T*)w.ypart, g.ldy,
+                     ystride, j == 0 ? w.normparts : nullptr, stopb, blk));
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
                (double)g.elem * ((double)g.mm * g.nn + (double)g.nn * f + (double)g.mm * f));
-      if (j == 0) {
-        const int64_t nparts = sketch_wgs * (int64_t)eff_splits(g.nn, g.s_sketch);
-        hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, w.normparts, nparts, w.st);
-        LAUNCHCHK();
-      }
-      TRY(ops.reduce((const T*)w.ypart, eff_splits(g.nn, g.s_sketch), ystride, ystride, y, stopb, blk));
+      const int nsp = eff_splits(g.nn, g.s_sketch);
+      if (j > 0) TRY(ops.reduce((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       // a3 + a4: two rounds of [project against the basis so far (width
       // wlog[j] <= j*b), FP64-Gram Cholesky, triangular solve]: block
       // Gram-Schmidt with re-orthogonalisation interleaved with CholeskyQR2
-      // (first Cholesky pass floored).  The second solve is the append below.
+      // (first Cholesky pass floored).  The second Cholesky also runs the
+      // stop test (a5); the second solve is the append below.
       int32_t* deadj = w.dead + j * BN_MAX;
-      const int64_t gs = (int64_t)f * f;
       const int64_t wmax = std::min<int64_t>(j * g.b, g.nn);
       for (int pass = 0; pass < 2; ++pass) {
         if (j > 0) {
@@ -508,12 +609,25 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           LAUNCHCHK();
           TRY(ops.update(y, g.ldy, q, g.ldy, g.mm, wmax, f, wbuf, ldw, 1, w.wlog, stopb, blk));
         }
-        double* Rp = pass == 0 ? w.r1 : w.r2;
-        TRY(ops.template gemm_nt<double>(y, g.ldy, y, g.ldy, f, f, g.mm, g.s_gram, w.gpart, f, gs,
-                                         nullptr, nullptr, stopb, blk));
-        TRY(launch_cholesky(ctx, st, w.gpart, eff_splits(g.mm, g.s_gram), gs, f, Rp, deadj, pass == 0,
-                            w.st, stopb, blk, 0, w.rb3, w.dg));
-        if (pass == 0) {
+        CholArgs ca = chol_args(w, pass == 0 ? w.r1 : w.r2, deadj, pass == 0, 0, 0);
+        if (pass == 1) {
+          ca.R1 = w.r1;
+          ca.col0 = col0;
+          ca.n = g.nn;
+          ca.wlog = w.wlog;
+          ca.acc = w.accv;
+          ca.diag_log = w.diag_log;
+        }
+        if (j == 0 && pass == 0) {
+          ca.norm_parts = w.normparts;
+          ca.n_norm = sketch_wgs * (int64_t)nsp;
+          TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+        }
+        // with no basis yet (j == 0) the pass-0 solve runs inside the pass-1 Gram
+        const bool fused = (j == 0 && pass == 1 && f <= 64);
+        TRY(gram_chol<T>(ctx, st, w, y, g.ldy, g.mm, f, w.gpart, ca, stopb, blk,
+                         fused ? w.r1 : nullptr));
+        if (pass == 0 && !(j == 0 && f <= 64)) {
           if (f <= 64) {
             TRY(ops.trsm(y, g.ldy, y, g.ldy, g.mm, f, w.r1, 0, f, nullptr, nullptr, stopb, blk));
           } else {
@@ -522,10 +636,6 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           }
         }
       }
-      // a5: stop test on diag(T) = diag(R2) diag(R1)
-      hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, w.r1, w.r2, deadj, f, col0, g.nn, w.st,
-                         w.wlog, w.accv, w.diag_log, blk);
-      LAUNCHCHK();
       // a6: append P = Z R2^{-1} (accepted columns) into Q at column wlog[j]
       if (f <= 64) {
         TRY(ops.trsm(y, g.ldy, q, g.ldy, g.mm, f, w.r2, 0, 0, w.wlog, w.accv, stopb, blk));
@@ -548,13 +658,13 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
     if (ctx->prof_on)
       prof_collect(ctx, ctx->host_state->stop_block != 0x7fffffff ? ctx->host_state->stop_block
                                                                    : (int)g.nblk);
-    per_sync = std::min(per_sync * 2, 16);
+    if (ctx->o.blocks_per_sync <= 0) per_sync = std::min(per_sync * 2, 4);
   }
   int64_t r = 0;
   int nb = 0;
   if (g.nn > 0) {
     nb = (int)std::min<int64_t>(ctx->host_state->stop_block, g.nblk - 1) + 1;
-    HIPCHK(hipMemcpy(&r, w.wlog + nb, sizeof(int64_t), hipMemcpyDeviceToHost));
+    r = ctx->host_state->rank;           // set by the stop test of the last block
     *norm_a = std::sqrt(ctx->host_state->normsq);
   } else {
     *norm_a = 0.0;
@@ -574,10 +684,17 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   T* q = (T*)w.q;
   T* cb = (T*)w.cbuf;
   const int64_t cstride = r * g.ldk;
+  // K-splits of the r x nn products over mm rows: about 1024 waves, bounded
+  // by the partial buffer (planned for r_cap) and by 256 rows per split.
+  const int64_t tiles = cdiv(g.nn, 256) * cdiv(r, 16 * std::min<int64_t>(4, cdiv(r, 16)));
+  int64_t sc = std::max<int64_t>(1, cdiv(256, tiles));
+  sc = std::min<int64_t>(sc, std::max<int64_t>(1, g.mm / 256));
+  sc = std::min<int64_t>(sc, std::max<int64_t>(1, ((int64_t)g.s_core * std::max<int64_t>(g.r_cap, 1)) / r));
+  const int s_core = (int)std::min<int64_t>(sc, 1024);
   for (int it = 0; it < ctx->o.power_iters; ++it) {
     // Y~^T = Q^T A (r x nn), QR(Y~) -> Q~ (stored as Q~^T = cbuf rows)
-    TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, g.s_core, (T*)w.cpart, g.ldk, cstride));
-    TRY(ops.reduce((const T*)w.cpart, eff_splits(g.mm, g.s_core), cstride, cstride, cb));
+    TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
+    TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb));
     TRY(cholqr2<T>(ctx, st, g, w, cb, g.ldk, g.nn, (int)r, w.rb4, 0, (T*)w.tbig));
     // Y = A Q~ (mm x r), QR(Y) -> Q
     TRY(ops.template gemm_nt<T>(Ae, g.lda_eff, cb, g.ldk, g.mm, r, g.nn, 1, q, g.ldy, g.ldy * r));
@@ -585,33 +702,24 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   }
   // a9: C = Q^T A (r x nn, row-major ld ldk)
   const int pid = prof_begin(ctx, st);
-  TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, g.s_core, (T*)w.cpart, g.ldk, cstride));
+  TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
   prof_end(ctx, st, pid, EODABE_PROF_PROJECT, 0,
            (double)g.elem * ((double)g.mm * g.nn + (double)g.mm * r + (double)r * g.nn));
-  TRY(ops.reduce((const T*)w.cpart, eff_splits(g.mm, g.s_core), cstride, cstride, cb));
-  // a10: C^T = V R  (C^T is nn x r with element (j,a) at a*ldk + j = cbuf)
-  //      -> cbuf holds V^T; R^T (row-major R) into rb4 as a column-major r x r
-  TRY(cholqr2<T>(ctx, st, g, w, cb, g.ldk, g.nn, (int)r, w.rb4, 1, (T*)w.tbig));
-  // R^T = Q_hat R_hat (FP64, r x r, column-major in rb4)
+  TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb));
+  // a10: C^T = V R  (C^T is nn x r with element (j,a) at a*ldk + j = cbuf);
+  //      V^T rows go straight to Vout, R^T (row-major R) to rb4 as a
+  //      column-major r x r matrix.
+  TRY(cholqr2<T>(ctx, st, g, w, cb, g.ldk, g.nn, (int)r, w.rb4, 1, (T*)w.tbig, Vout, ldv));
+  // R^T = Q_hat R_hat (FP64, r x r, column-major in rb4); D_hat = R_hat -> Dout
+  TRY(cholqr2<double>(ctx, st, g, w, w.rb4, r, r, (int)r, w.rb3, 0, (double*)w.tbig, nullptr, 0,
+                      nullptr, 0));
   {
-    Ops<double> opd{ctx, st};
-    (void)opd;
-    TRY(cholqr2<double>(ctx, st, g, w, w.rb4, r, r, (int)r, w.rb3, 0, (double*)w.tbig));
-  }
-  // U_hat = Q Q_hat : (mm x r) (r x r); Q_hat FP64 column-major in rb4.
-  {
-    TRY(ops.update_d(Uout, ldu, q, g.ldy, g.mm, r, (int)r, w.rb4, r));
-  }
-  // outputs: V^T rows, D_hat
-  TRY(copy2d<T>(ctx, st, cb, g.ldk, Vout, ldv, r, g.nn, 0));
-  {
-    // D_hat = R_hat (element (i,j) at j*r + i in rb3) -> row-major Dout
-    const int64_t cnt = r * r;
-    (void)cnt;
     dim3 grid((unsigned)cdiv(r, 32), (unsigned)cdiv(r, 32));
     hipLaunchKernelGGL((k_copy2d<double, T>), grid, dim3(32, 8), 0, st, w.rb3, r, Dout, ldd, r, r, 1);
     LAUNCHCHK();
   }
+  // U_hat = Q Q_hat : (mm x r) (r x r); Q_hat FP64 column-major in rb4.
+  TRY(ops.update_d(Uout, ldu, q, g.ldy, g.mm, r, (int)r, w.rb4, r));
   return 0;
 }
 
@@ -967,7 +1075,7 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
     LAUNCHCHK();
     Ops<T> ops{ctx, st};
     const int64_t ystr = ldyp * bn;
-    TRY(ops.template gemm_nt<T>(Ae, la, om, ldk, m, bn, n, (int)p.s, yp, ldyp, ystr));
+    TRY(ops.sketch(Ae, la, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, nullptr, nullptr, 0));
     TRY(ops.reduce((const T*)yp, eff_splits(n, (int)p.s), ystr, ystr, yr));
     TRY(copy2d<T>(ctx, st, yr, ldyp, (T*)Y, ldy, ncols, m, 0));
     HIPCHK(hipStreamSynchronize(st));

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace eodabe {
 
 typedef float  f32x4 __attribute__((ext_vector_type(4)));
@@ -33,6 +35,7 @@ struct State {
   int32_t nonfinite;     // ||A||_F not finite
   int32_t floored;       // a pivot was floored in the closing QRs
   int32_t pad;
+  int64_t rank;          // basis width after the latest decided block
   uint32_t counter[8];   // arrival counters (reset by the last arriving workgroup)
 };
 
@@ -301,6 +304,162 @@ __global__ __launch_bounds__(256) void k_gemm_nt(
 }
 
 // ---------------------------------------------------------------------------
+// Sketch Y = A Omega_j (Alg. 1), K-split partials, on MFMA.
+// A row-major (lda multiple of 4, 16-byte aligned); Omega^T row-major
+// (N x ldk, N <= 16*CT columns).  Workgroup = 4 waves on 4 row tiles of 16*RT rows, one K-range
+// [kb, ke) per grid-y index.  The workgroup's Omega slab (bn x KS) is staged
+// in LDS once per slab (rows padded by 16 bytes), so only A streams from
+// HBM; A is prefetched four chunks (16 K each) ahead in registers.  Output
+// partial s: element (i, c) at out + s*part_stride + c*ldo + i.  Optional
+// per-workgroup sum of squares of A (tile z == 0 only) for ||A||_F.
+// ---------------------------------------------------------------------------
+template <typename T, int RT, int CT>
+struct SketchCfg {
+  static constexpr int KS = (16 * CT * (int)sizeof(T) <= 128) ? 256 : 128;
+  static constexpr int LDO = KS + 16 / (int)sizeof(T);
+};
+
+template <typename T, int RT, int CT>
+__global__ __launch_bounds__(256) void k_sketch(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ Om, int64_t ldk, int64_t M, int N,
+    int64_t K, int64_t kchunk, T* __restrict__ out, int64_t ldo, int64_t part_stride,
+    double* __restrict__ sumsq, const int32_t* __restrict__ stop_block, int block_id) {
+  typedef Mfma<T> MF;
+  typedef SketchCfg<T, RT, CT> Cfg;
+  constexpr int KS = Cfg::KS, LDO = Cfg::LDO, NC = 16 * CT;
+  if (stop_block && *stop_block < block_id) return;
+  __shared__ T oms[NC * LDO];
+  __shared__ double ss_red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * (64 * RT) + wv * (16 * RT);
+  const int s = blockIdx.y;
+  const int64_t kb = (int64_t)s * kchunk, ke = min(K, kb + kchunk);
+  const bool do_ss = sumsq != nullptr;
+  double ss = 0.0;
+  const T* ap[RT];
+  bool aval[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int64_t row = m0 + 16 * t + r;
+    aval[t] = row < M;
+    ap[t] = A + (aval[t] ? row : (M - 1)) * lda + 4 * g;
+  }
+  typename MF::acc_t acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) acc[t][u] = MF::zero();
+  const bool active = (m0 < M);
+  for (int64_t sb = kb; sb < ke; sb += KS) {
+    const int64_t se = min(ke, sb + KS);
+    const int slen = (int)(se - sb);
+    __syncthreads();
+    // stage Omega^T[0:NC, sb:se] (zero beyond se)
+    for (int idx = tid; idx < NC * (KS / 4); idx += 256) {
+      const int c = idx / (KS / 4), k4 = (idx - c * (KS / 4)) * 4;
+      V4<T> v;
+      if (c >= N) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v.v[e] = (T)0;
+      } else if (k4 + 3 < slen) {
+        v = ld4(Om + (int64_t)c * ldk + sb + k4);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v.v[e] = (k4 + e < slen) ? Om[(int64_t)c * ldk + sb + k4 + e] : (T)0;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) oms[c * LDO + k4 + e] = v.v[e];
+    }
+    __syncthreads();
+    if (!active) continue;
+    const int nfull = slen / 16;
+    auto compute = [&](const V4<T>(&a)[RT], int kl) {
+      V4<T> b[CT];
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        const T* q = &oms[(16 * u + r) * LDO + kl + 4 * g];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) b[u].v[e] = q[e];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int u = 0; u < CT; ++u) acc[t][u] = MF::op(a[t].v[v], b[u].v[v], acc[t][u]);
+      if (do_ss) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+          if (aval[t])
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ss += (double)a[t].v[v] * (double)a[t].v[v];
+      }
+    };
+    // 4-deep register pipeline over the full 16-K chunks of this slab
+    V4<T> a[4][RT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nfull)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * q);
+    for (int c = 0; c < nfull; c += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (c + q < nfull) {
+          compute(a[q], 16 * (c + q));
+          if (c + q + 4 < nfull)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * (c + q + 4));
+        }
+      }
+    }
+    if (nfull * 16 < slen) {                  // ragged tail of the slab
+      V4<T> at[RT];
+      const int64_t k = sb + 16 * nfull;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) at[t] = ld4_masked(ap[t] + k, k + 4 * g, se);
+      compute(at, 16 * nfull);
+    }
+  }
+  if (active) {
+    T* o = out + (int64_t)s * part_stride;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        const int64_t col = 16 * u + r;
+        if (col >= N) continue;
+        if constexpr (MF::rows_contiguous) {
+          const int64_t row = m0 + 16 * t + 4 * g;
+          T* p = o + col * ldo + row;
+          if (row + 3 < M && ((ldo & 3) == 0) && ((part_stride & 3) == 0)) {
+            *reinterpret_cast<f32x4*>(p) = acc[t][u];
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (row + e < M) p[e] = acc[t][u][e];
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t row = m0 + 16 * t + MF::row(g, e);
+            if (row < M) o[col * ldo + row] = acc[t][u][e];
+          }
+        }
+      }
+    }
+  }
+  if (do_ss) {
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+    if (lane == 0) ss_red[wv] = ss;
+    __syncthreads();
+    if (tid == 0)
+      sumsq[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ss_red[0] + ss_red[1] + ss_red[2] + ss_red[3];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // NN GEMM partials: out_s(M x N) = X(M x K) * Z(K x N) over K-split s, with X
 // row-major K-contiguous (ldx) and Z row-major N-contiguous (ldz).  Used for
 // C = Q^T A (X = Q^T, i.e. Q column-major; Z = A).  out_s row-major
@@ -398,6 +557,31 @@ __global__ void k_reduce_parts(const T* __restrict__ parts, int nparts, int64_t 
   }
 }
 
+// out[i] = sum_s parts[s*stride + i] for many partials: a 64 x 16 thread
+// block, the 16 thread rows take interleaved partials and are folded in
+// fixed order through LDS (deterministic).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_reduce_parts_wide(const T* __restrict__ parts, int nparts,
+                                                           int64_t stride, int64_t count,
+                                                           T* __restrict__ out,
+                                                           const int32_t* __restrict__ stop_block,
+                                                           int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  __shared__ T red[16][64];
+  const int64_t i = blockIdx.x * (int64_t)64 + threadIdx.x;
+  T acc = 0;
+  if (i < count)
+    for (int s = threadIdx.y; s < nparts; s += 16) acc += parts[(int64_t)s * stride + i];
+  red[threadIdx.y][threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.y == 0 && i < count) {
+    T a = red[0][threadIdx.x];
+#pragma unroll
+    for (int y = 1; y < 16; ++y) a += red[y][threadIdx.x];
+    out[i] = a;
+  }
+}
+
 // Column-block reduction for a column-major matrix with leading dimension ld
 // where only rows < rows_dev (read from wlog[block_id] when given) matter:
 // out(i, c) = sum_s parts_s(i, c), i < rows, c < cols.
@@ -448,7 +632,17 @@ __global__ __launch_bounds__(256) void k_update_rows(
     }
     __syncthreads();
     if (i < m) {
-      for (int a = 0; a < na; ++a) {
+      int a = 0;
+      for (; a + 8 <= na; a += 8) {
+        TW qv[8];                                 // 8 independent loads in flight
+#pragma unroll
+        for (int q = 0; q < 8; ++q) qv[q] = (TW)Q[(a0 + a + q) * ldq + i];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+          for (int c = 0; c < F; ++c) acc[c] += qv[q] * Ws[(a + q) * F + c];
+      }
+      for (; a < na; ++a) {
         const TW qv = (TW)Q[(a0 + a) * ldq + i];
 #pragma unroll
         for (int c = 0; c < F; ++c) acc[c] += qv * Ws[a * F + c];
@@ -466,85 +660,335 @@ __global__ __launch_bounds__(256) void k_update_rows(
   }
 }
 
+// Broadcast of a double from a wave-uniform lane (v_readlane on both halves).
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
 // ---------------------------------------------------------------------------
-// Cholesky of a symmetric positive semi-definite f x f matrix (FP64, one
-// workgroup), with the rules of the blocked CholeskyQR used here:
+// Cholesky of a symmetric positive semi-definite f x f matrix (f <= F <= 64,
+// FP64) on one wavefront, with the rules of the blocked CholeskyQR used here:
 //   * dead columns (flag set) are skipped: R(k,k) = 1, row and column zero;
 //   * a pivot G(k,k) - sum R(i,k)^2 <= FLOOR_C u64 G(k,k) is floored to that
 //     value when first_pass (the column stays alive but its row is zeroed so
 //     it does not feed later columns), and marks the column dead otherwise.
-// G is the sum of nparts partial matrices (element (i,j) at j*f + i).
-// R is written with element (i,j) at j*f + i (upper triangle; lower zero).
-// mode 0: plain; mode 1: closing-QR mode (counts floored pivots in st->floored).
+// Lane j holds column j of G in registers (fully unrolled over F); pivots
+// and row entries are broadcast with v_readlane.  G: element (i,j) at
+// j*f + i; R is written the same way (lower part zero).
+// If R1 != nullptr this is the second pass of a basis block and the stop test
+// of Alg. 1 follows: d_c = |T(c,c)| = R(c,c) R1(c,c) (0 for dead columns);
+// the first c with d_c <= eps keeps columns 0..c-1 and stops the loop;
+// otherwise all f are kept and the loop ends after the last column of Omega.
+// Writes acc[block], wlog[block+1] = wlog[block] + acc, st->rank, the
+// examined d_c to diag_log[col0 + c] and stop_block.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cholesky(
-    const double* __restrict__ Gparts, int nparts, int64_t part_stride, int f,
-    double* __restrict__ R, int32_t* __restrict__ dead, int first_pass,
-    State* st, const int32_t* __restrict__ stop_block, int block_id, int count_floors) {
-  if (stop_block && *stop_block < block_id) return;
-  extern __shared__ double sm[];
-  double* G = sm;                 // f*f (only if it fits; host decides)
-  double* dg = sm + (int64_t)f * f;   // original diagonal (f)
-  __shared__ int s_flag;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t ff = (int64_t)f * f;
-  for (int64_t idx = tid; idx < ff; idx += nt) {
+// Arguments of the Cholesky that closes a Gram pass (see chol_wave).
+struct CholArgs {
+  double* R;               // R out: f x f, element (i,j) at j*f + i (lower part zero)
+  int32_t* dead;           // per-column dead flags (in/out)
+  int first_pass;          // floor (1) or kill (0) non-positive pivots
+  int fresh;               // ignore incoming dead flags (a new factorization)
+  State* st;
+  int count_floors;        // add floored pivots to st->floored
+  const double* R1;        // non-null: stop test of a basis block (diag of R1)
+  int64_t col0, n;
+  int64_t* wlog;
+  int32_t* acc;
+  double* diag_log;
+  double* Rprod;           // non-null: also write R * R1 (R1 = the solve matrix)
+  int prod_transpose;      // product element (i,j) at i*f + j instead of j*f + i
+  void* Dout;              // non-null: product written in the data type, row-major, ld ldd
+  int64_t ldd;
+  const double* norm_parts;  // non-null: finish ||A||_F and eps = tol ||A||_F first
+  int64_t n_norm;
+};
+
+// Cholesky + fused epilogues on one wavefront (lane j = column j, j < f),
+// left-looking and in place in LDS: W (row-major, leading dimension F) holds
+// G on entry (upper triangle read) and R on exit; step k computes row k:
+//   s_j = G(k,j) - sum_{i<k} R(i,k) R(i,j),  j >= k.
+// The pivot s_k is broadcast with v_readlane; LDS operations of one wave
+// execute in order, so no barrier is needed between steps.  Pivot rules:
+//   * dead columns (flag set) are skipped: R(k,k) = 1, row and column zero;
+//   * a pivot s_k <= FLOOR_C u64 G(k,k) is floored to that value on a first
+//     pass (the column stays alive but its row is zeroed so it does not feed
+//     later columns), and marks the column dead otherwise.
+// Epilogues: the product R R1 (R1 in LDS, column-major, leading dimension
+// F+1), and for a basis block the stop test of Alg. 1: d_c = |T(c,c)| =
+// R(c,c) R1(c,c) (0 for dead columns); the first c with d_c <= eps keeps
+// columns 0..c-1 and stops the loop, otherwise all f are kept and the loop
+// ends after the last column of Omega.
+template <int F, typename T>
+__device__ __forceinline__ void chol_wave(double* W, int f, const CholArgs& ca, int block_id,
+                                          const double* R1l) {
+  const int j = threadIdx.x & 63;
+  const bool mine = j < f;
+  State* st = ca.st;
+  if (ca.norm_parts) {                    // ||A||_F from the sketch partials (fixed order)
     double a = 0.0;
-    for (int s = 0; s < nparts; ++s) a += Gparts[(int64_t)s * part_stride + idx];
-    G[idx] = a;
+    for (int64_t i = j; i < ca.n_norm; i += 64) a += ca.norm_parts[i];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if (j == 0) {
+      st->normsq = a;
+      const bool bad = !(a < INFINITY);
+      st->nonfinite = bad ? 1 : 0;
+      st->eps = bad ? 0.0 : st->tol * sqrt(a);
+    }
   }
-  __syncthreads();
-  for (int k = tid; k < f; k += nt) dg[k] = G[(int64_t)k * f + k];
-  __syncthreads();
+  int deadj = mine ? (ca.fresh ? 0 : ca.dead[j]) : 1;
+  const double dgj = mine ? W[j * F + j] : 0.0;        // original G(j,j)
+  double diagj = 1.0;
+  int nfloor = 0;
   for (int k = 0; k < f; ++k) {
-    if (tid == 0) {
-      int fl = 0;
-      if (dead[k]) {
-        fl = 2;
+    double sj = 0.0;
+    if (mine && j >= k) {
+      sj = W[k * F + j];
+#pragma unroll 4
+      for (int i = 0; i < k; ++i) sj -= W[i * F + k] * W[i * F + j];
+    }
+    const double piv = readlane_d(sj, k);
+    const double dgk = readlane_d(dgj, k);
+    const int deadk = readlane_i(deadj, k);
+    int fl = 0;
+    double rkk;
+    if (deadk) {
+      fl = 2;
+      rkk = 1.0;
+    } else {
+      const double flo = FLOOR_C * U64 * dgk;
+      if (!(piv > flo) || !(piv < INFINITY)) {
+        fl = ca.first_pass ? 1 : 2;
+        rkk = ca.first_pass ? sqrt(flo > 1e-300 ? flo : 1e-300) : 1.0;
       } else {
-        const double piv = G[(int64_t)k * f + k];
-        const double flo = FLOOR_C * U64 * dg[k];
-        if (!(piv > flo) || !(piv < INFINITY)) {
-          if (first_pass) {
-            G[(int64_t)k * f + k] = sqrt(flo > 1e-300 ? flo : 1e-300);
-            fl = 1;
-            if (count_floors && st) atomicAdd(&st->floored, 1);
-          } else {
-            dead[k] = 1;
-            fl = 2;
-          }
-        } else {
-          G[(int64_t)k * f + k] = sqrt(piv);
+        rkk = sqrt(piv);
+      }
+    }
+    nfloor += (fl == 1);
+    if (mine && j >= k) {
+      double v;
+      if (j == k) {
+        v = rkk;
+        diagj = rkk;
+        if (fl == 2) deadj = 1;
+      } else {
+        v = (fl != 0 || deadj) ? 0.0 : sj / rkk;
+      }
+      W[k * F + j] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (mine) {
+    for (int i = 0; i < f; ++i) ca.R[(int64_t)j * f + i] = (i <= j) ? W[i * F + j] : 0.0;
+    ca.dead[j] = deadj;
+  }
+  if (ca.count_floors && j == 0 && nfloor) atomicAdd(&st->floored, nfloor);
+  if (ca.Rprod && R1l && mine) {
+    // (R R1)(i,j) = sum_{k=i..j} R(i,k) R1(k,j)
+    for (int i = 0; i < f; ++i) {
+      double v = 0.0;
+      if (i <= j)
+        for (int k = i; k <= j; ++k) v += W[i * F + k] * R1l[j * (F + 1) + k];
+      if (ca.prod_transpose) ca.Rprod[(int64_t)i * f + j] = v;
+      else ca.Rprod[(int64_t)j * f + i] = v;
+      if (ca.Dout) reinterpret_cast<T*>(ca.Dout)[(int64_t)i * ca.ldd + j] = (T)v;
+    }
+  }
+  if (!ca.R1) return;
+  // stop test (Alg. 1): first column whose |T(c,c)| <= eps
+  const double eps = st->eps;
+  double d = 0.0;
+  bool hit = false;
+  if (mine) {
+    d = deadj ? 0.0 : diagj * ca.R1[(int64_t)j * f + j];
+    hit = (d <= eps) || st->nonfinite;
+  }
+  const unsigned long long mask = __ballot(hit);
+  const int keep = mask ? (int)__ffsll((long long)mask) - 1 : f;
+  if (mine && j <= keep) ca.diag_log[ca.col0 + j] = d;
+  if (j == 0) {
+    const bool stop = (mask != 0ull) || (ca.col0 + f >= ca.n);
+    ca.acc[block_id] = keep;
+    const int64_t wn = ca.wlog[block_id] + keep;
+    ca.wlog[block_id + 1] = wn;
+    st->rank = wn;
+    if (stop) st->stop_block = block_id;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrix G = X^T X (FP64 accumulation) of a column-major rows x f block
+// X (f <= F <= 64), with an optional front end applied to each row first:
+//   MODE 0: X as stored;
+//   MODE 1: X := sum of nsrc partial blocks src + s*src_stride (written to X);
+//   MODE 2: X := X R^{-1} (forward substitution in FP64, R upper f x f,
+//           element (i,j) at j*f + i; written to X in the data type).
+// Each workgroup takes panels of RPW rows (grid-stride), stages the panel
+// (as stored, in the data type) in LDS column by column, and accumulates
+// on f64 MFMA with its 4 waves splitting the panel rows.  The waves are
+// folded in fixed order through LDS, the workgroup partial goes to
+// parts[blockIdx.x] (element (i,j) at j*f + i), and the last workgroup to
+// arrive (device-scope counter) sums the partials in fixed order and runs
+// the Cholesky of G (plus the stop test for a basis block) on its wave 0.
+// ---------------------------------------------------------------------------
+template <typename T, int F, int MODE>
+struct GramCfg {
+  // MODE 0: panel in the data type; MODE 2: panel in FP64 (the solved rows)
+  typedef typename std::conditional<MODE == 2, double, T>::type P;
+  static constexpr int RPW = (MODE == 2) ? (F <= 32 ? 256 : 128) : (F * (int)sizeof(T) <= 128 ? 256 : 128);
+  static constexpr int LDP = RPW + 16 / (int)sizeof(P);   // padded column stride (bank spread)
+};
+
+template <typename T, int F, int MODE>
+__global__ __launch_bounds__(256) void k_gram_rows(
+    T* __restrict__ X, int64_t ld, int64_t rows, int f, const double* __restrict__ Rm,
+    double* __restrict__ parts, uint32_t* __restrict__ counter, const int32_t* __restrict__ stop_block,
+    int block_id, CholArgs ca) {
+  typedef Mfma<double> MF;
+  typedef GramCfg<T, F, MODE> Cfg;
+  typedef typename Cfg::P P;
+  constexpr int TT = F / 16;
+  constexpr int RPW = Cfg::RPW;
+  constexpr int LDP = Cfg::LDP;
+  if (stop_block && *stop_block < block_id) return;
+  __shared__ P pan[F * LDP];                 // column-major panel: pan[c*LDP + row]
+  __shared__ double Rs[MODE == 2 ? F * (F + 1) : 1];   // R1(k,c) at c*(F+1) + k
+  __shared__ double rinv[MODE == 2 ? F : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  if constexpr (MODE == 2) {
+    for (int idx = tid; idx < f * f; idx += 256) {
+      const int c = idx / f, kk = idx - c * f;
+      Rs[c * (F + 1) + kk] = Rm[idx];
+    }
+    for (int c = tid; c < f; c += 256) rinv[c] = 1.0 / Rm[(int64_t)c * f + c];
+  }
+  typename MF::acc_t acc[TT][TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t)
+#pragma unroll
+    for (int u = 0; u < TT; ++u) acc[t][u] = MF::zero();
+  const int64_t npan = (rows + RPW - 1) / RPW;
+  for (int64_t pnl = blockIdx.x; pnl < npan; pnl += gridDim.x) {
+    const int64_t rb = pnl * RPW;
+    __syncthreads();                          // previous panel consumed (and Rs ready)
+    if (tid < RPW) {
+      const int rl = tid;
+      const int64_t row = rb + rl;
+      const bool ok = row < rows;
+      // stage the row (loads batched 8 at a time)
+      for (int c0 = 0; c0 < F; c0 += 8) {
+        T xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          xv[q] = (c0 + q < f && ok) ? X[(int64_t)(c0 + q) * ld + row] : (T)0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pan[(c0 + q) * LDP + rl] = (P)xv[q];
+      }
+      if constexpr (MODE == 2) {
+        // z_c = (x_c - sum_{k<c} z_k R(k,c)) / R(c,c) in FP64, rounded to T
+        for (int c = 0; c < f; ++c) {
+          double v = pan[c * LDP + rl];
+#pragma unroll 4
+          for (int k = 0; k < c; ++k) v -= pan[k * LDP + rl] * Rs[c * (F + 1) + k];
+          v *= rinv[c];
+          pan[c * LDP + rl] = v;
+        }
+        for (int c = 0; c < f; ++c) {
+          const T zt = (T)pan[c * LDP + rl];
+          if (ok) X[(int64_t)c * ld + row] = zt;
+          pan[c * LDP + rl] = ok ? (double)zt : 0.0;
         }
       }
-      if (fl == 2) G[(int64_t)k * f + k] = 1.0;
-      s_flag = fl;
     }
     __syncthreads();
-    const int fl = s_flag;
-    const double rkk = G[(int64_t)k * f + k];
-    // row k of R: R(k,j) = G(k,j) / R(k,k) for alive j > k
-    for (int j = k + 1 + tid; j < f; j += nt) {
-      double v = G[(int64_t)j * f + k];
-      v = (fl != 0 || dead[j]) ? 0.0 : v / rkk;
-      G[(int64_t)j * f + k] = v;
-    }
-    __syncthreads();
-    if (fl == 0) {
-      // trailing update G(i,j) -= R(k,i) R(k,j), k < i <= j
-      const int nrem = f - k - 1;
-      const int64_t npairs = (int64_t)nrem * nrem;
-      for (int64_t p = tid; p < npairs; p += nt) {
-        const int ii = k + 1 + (int)(p / nrem), jj = k + 1 + (int)(p % nrem);
-        if (ii <= jj) G[(int64_t)jj * f + ii] -= G[(int64_t)ii * f + k] * G[(int64_t)jj * f + k];
+    // MFMA over this panel: wave wv takes rows [wv*RPW/4, (wv+1)*RPW/4)
+    constexpr int PW = RPW / 4;
+#pragma unroll
+    for (int k0 = 0; k0 < PW; k0 += 16) {
+      const int kr = wv * PW + k0 + 4 * g;
+      V4<double> a[TT];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const P* q = &pan[(16 * t + r) * LDP + kr];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[t].v[e] = (double)q[e];
       }
-      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+#pragma unroll
+          for (int u = t; u < TT; ++u) acc[t][u] = MF::op(a[t].v[v], a[u].v[v], acc[t][u]);
     }
   }
-  for (int64_t idx = tid; idx < ff; idx += nt) {
-    const int64_t j = idx / f, i = idx - j * f;
-    R[idx] = (i <= j) ? G[idx] : 0.0;
+  // fold the 4 waves (fixed order) through LDS (reuse the panel storage)
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(pan);   // needs TT*TT*256 doubles <= sizeof(pan)
+  static_assert(sizeof(P) * F * LDP >= sizeof(double) * TT * TT * 256, "fold buffer");
+  for (int w = 0; w < 4; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int t = 0; t < TT; ++t)
+#pragma unroll
+        for (int u = t; u < TT; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            double* qq = &red[((t * TT + u) * 4 + e) * 64 + lane];
+            *qq = (w == 0) ? acc[t][u][e] : *qq + acc[t][u][e];
+          }
+    }
+    __syncthreads();
   }
+  // workgroup partial, symmetric fill: tile (t,u) register e of lane l is
+  // G[16t + 4e + l/16][16u + l%16]
+  double* Pw = parts + (int64_t)blockIdx.x * f * f;
+  for (int idx = tid; idx < TT * TT * 256; idx += 256) {
+    const int l = idx & 63, e = (idx >> 6) & 3, tu = idx >> 8;
+    const int t = tu / TT, u = tu - t * TT;
+    if (u < t) continue;
+    const int i = 16 * t + 4 * e + (l >> 4), jj = 16 * u + (l & 15);
+    if (i < f && jj < f) {
+      const double v = red[idx];
+      Pw[(int64_t)jj * f + i] = v;
+      Pw[(int64_t)i * f + jj] = v;
+    }
+  }
+  // the last workgroup to arrive folds all partials in fixed order
+  __threadfence();
+  __shared__ int s_last;
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // fixed-order sum of the partials (loads issued in groups of 8) into LDS
+  // (row-major, leading dimension F), then the Cholesky and stop test
+  const int ff = f * f;
+  double* Gl = reinterpret_cast<double*>(pan);
+  static_assert(sizeof(P) * F * LDP >= sizeof(double) * F * F, "Cholesky buffer");
+  const unsigned nb = gridDim.x;
+  for (int idx = tid; idx < ff; idx += 256) {
+    double a = 0.0;
+    unsigned b = 0;
+    for (; b + 8 <= nb; b += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = parts[(int64_t)(b + q) * ff + idx];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a += v[q];
+    }
+    for (; b < nb; ++b) a += parts[(int64_t)b * ff + idx];
+    const int c = idx / f, rr = idx - c * f;          // element (rr, c); G is symmetric
+    Gl[rr * F + c] = a;
+  }
+  if (tid == 0) *counter = 0u;
+  __syncthreads();
+  if (wv != 0) return;
+  chol_wave<F, T>(Gl, f, ca, block_id, MODE == 2 ? Rs : nullptr);
 }
 
 // Same algorithm with G in global memory (large f); G is overwritten.
@@ -619,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_cholesky_global(
 // for the basis append, zoff = wlog[block_id] and ncols_out = acc[block_id].
 // ---------------------------------------------------------------------------
 template <typename Tin, typename Tout, int FMAX>
-__global__ __launch_bounds__(256) void k_trsm_rows(
+__global__ __launch_bounds__(64) void k_trsm_rows(
     const Tin* __restrict__ X, int64_t ldx, Tout* __restrict__ Zo, int64_t ldz, int64_t m,
     int f, const double* __restrict__ R, int64_t zoff, int ncols_out,
     const int64_t* __restrict__ wlog, const int32_t* __restrict__ acc_dev,
@@ -628,24 +1072,31 @@ __global__ __launch_bounds__(256) void k_trsm_rows(
   if (wlog) zoff = wlog[block_id];
   if (acc_dev) ncols_out = acc_dev[block_id];
   __shared__ double Rs[FMAX * FMAX];
+  __shared__ double rinv[FMAX];
+  __shared__ double zs[FMAX * 65];               // zs[c*65 + thread]
   for (int idx = threadIdx.x; idx < f * f; idx += blockDim.x) Rs[idx] = R[idx];
-  __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  double z[FMAX];
+  for (int c = threadIdx.x; c < f; c += blockDim.x) rinv[c] = 1.0 / R[(int64_t)c * f + c];
+  const int t = threadIdx.x;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + t;
+  const bool ok = i < m;
+  for (int c0 = 0; c0 < f; c0 += 8) {            // row loads, 8 in flight
+    Tin xv[8];
 #pragma unroll
-  for (int c = 0; c < FMAX; ++c) {
-    if (c < f) {
-      double v = (double)X[(int64_t)c * ldx + i];
-      for (int k = 0; k < c; ++k) v -= z[k] * Rs[c * f + k];
-      z[c] = v / Rs[c * f + c];
-    } else {
-      z[c] = 0.0;
-    }
+    for (int q = 0; q < 8; ++q) xv[q] = (c0 + q < f && ok) ? X[(int64_t)(c0 + q) * ldx + i] : (Tin)0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (c0 + q < FMAX) zs[(c0 + q) * 65 + t] = (double)xv[q];
   }
-#pragma unroll
-  for (int c = 0; c < FMAX; ++c)
-    if (c < ncols_out) Zo[(zoff + c) * ldz + i] = (Tout)z[c];
+  __syncthreads();
+  // z_c = (x_c - sum_{k<c} z_k R(k,c)) / R(c,c)
+  for (int c = 0; c < f; ++c) {
+    double v = zs[c * 65 + t];
+#pragma unroll 4
+    for (int k = 0; k < c; ++k) v -= zs[k * 65 + t] * Rs[c * f + k];
+    zs[c * 65 + t] = v * rinv[c];
+  }
+  if (!ok) return;
+  for (int c = 0; c < ncols_out; ++c) Zo[(zoff + c) * ldz + i] = (Tout)zs[c * 65 + t];
 }
 
 // Large-f variant: R read from global memory (L2), z kept in global scratch.
@@ -665,14 +1116,8 @@ __global__ __launch_bounds__(256) void k_trsm_rows_big(
   (void)ncols_out;
 }
 
-// ---------------------------------------------------------------------------
-// Stopping test of Alg. 1 for block `block_id` (one thread):
-//   d_c = |T(c,c)| = R2(c,c) R1(c,c) (0 for dead columns); the first c with
-//   d_c <= eps stops the loop and keeps columns 0..c-1; otherwise all f are
-//   kept and the loop ends when the last column of Omega has been used.
-// Writes acc[block], wlog[block+1] = wlog[block] + acc, the examined d_c to
-// diag_log[col0 + c], and stop_block.
-// ---------------------------------------------------------------------------
+// Stop test of Alg. 1 for blocks wider than 64 columns (one thread); the
+// same rule as the tail of k_cholesky.
 __global__ void k_decide(const double* __restrict__ R1, const double* __restrict__ R2,
                          const int32_t* __restrict__ dead, int f, int64_t col0, int64_t n,
                          State* st, int64_t* __restrict__ wlog, int32_t* __restrict__ acc,
@@ -682,19 +1127,15 @@ __global__ void k_decide(const double* __restrict__ R1, const double* __restrict
   const double eps = st->eps;
   int keep = f;
   bool stop = false;
-  if (st->nonfinite) {
-    keep = 0;
-    stop = true;
-  } else {
-    for (int c = 0; c < f; ++c) {
-      const double d = dead[c] ? 0.0 : R2[(int64_t)c * f + c] * R1[(int64_t)c * f + c];
-      diag_log[col0 + c] = d;
-      if (d <= eps) { keep = c; stop = true; break; }
-    }
+  for (int c = 0; c < f; ++c) {
+    const double d = dead[c] ? 0.0 : R2[(int64_t)c * f + c] * R1[(int64_t)c * f + c];
+    diag_log[col0 + c] = d;
+    if (d <= eps || st->nonfinite) { keep = c; stop = true; break; }
   }
   if (col0 + f >= n) stop = true;
   acc[block_id] = keep;
   wlog[block_id + 1] = wlog[block_id] + keep;
+  st->rank = wlog[block_id + 1];
   if (stop) st->stop_block = block_id;
 }
 
@@ -718,13 +1159,17 @@ __global__ void k_finish_norm(const double* __restrict__ parts, int64_t nparts, 
   }
 }
 
-__global__ void k_init_state(State* st, double tol, int64_t* wlog, int nwlog) {
+__global__ void k_init_state(State* st, double tol, int64_t* wlog, int nwlog, int32_t* dead,
+                             int64_t ndead, int32_t* acc, int nacc) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->eps = 0.0; st->normsq = 0.0; st->tol = tol;
-    st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->pad = 0;
+    st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->pad = 0; st->rank = 0;
     for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
   }
-  for (int i = threadIdx.x; i < nwlog; i += blockDim.x) wlog[i] = 0;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = t; i < nwlog; i += nt) wlog[i] = 0;
+  for (int64_t i = t; i < ndead; i += nt) dead[i] = 0;
+  for (int64_t i = t; i < nacc; i += nt) acc[i] = 0;
 }
 
 // Fill with zeros (graph-safe replacement for memset).

@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--workload", default="image4096")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain device copy of A (counter calibration under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -123,6 +125,14 @@ def main():
     ms_wall = wall * 1e3 / args.steps
     prof = {k: ctx.profile_read(k) for k in (E.PROF_SKETCH, E.PROF_PROJECT)}
     ctx.profile(False)
+    if args.copy_calib:
+        # one copy of exactly A's bytes: its FETCH_SIZE / WRITE_SIZE under
+        # rocprofv3 --pmc calibrate the counters of the factorization kernels
+        dst = torch.empty_like(A)
+        dst.copy_(A)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {A.numel() * A.element_size()} bytes read and written")
+        del dst
 
     # correctness of the timed result (the same call each step)
     A64 = A.double()

@@ -3,6 +3,7 @@
 // projection, closing QRs).  All arithmetic runs in the kernels of
 // eodabe_kernels.hpp; the host only validates, carves the caller's
 // workspace and enqueues.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -92,7 +93,9 @@ struct Carver {
   }
 };
 
-// Event pair around one timed launch (no-op unless profiling is on).
+// Event pair of one timed launch (no-op unless profiling is on); the events
+// ride on the kernel dispatch itself (hipExtLaunchKernelGGL), so they time
+// the kernel execution without the launch gaps around it.
 hipEvent_t prof_event(eodabe_ctx* ctx) {
   if (!ctx->ev_pool.empty()) {
     hipEvent_t e = ctx->ev_pool.back();
@@ -107,7 +110,7 @@ int prof_begin(eodabe_ctx* ctx, hipStream_t st) {
   if (!ctx->prof_on) return -1;
   eodabe_ctx::Mark mk{prof_event(ctx), prof_event(ctx), 0, 0, 0.0};
   if (!mk.a || !mk.b) return -1;
-  (void)hipEventRecord(mk.a, st);
+  (void)st;
   ctx->marks.push_back(mk);
   return (int)ctx->marks.size() - 1;
 }
@@ -117,7 +120,13 @@ void prof_end(eodabe_ctx* ctx, hipStream_t st, int id, int kind, int block, doub
   mk.kind = kind;
   mk.block = block;
   mk.bytes = bytes;
-  (void)hipEventRecord(mk.b, st);
+  (void)st;
+}
+// Attach (or detach, id < 0) the events of mark id to the next timed launch.
+template <typename O>
+void prof_attach(eodabe_ctx* ctx, O& ops, int id) {
+  ops.pe0 = id >= 0 ? ctx->marks[id].a : nullptr;
+  ops.pe1 = id >= 0 ? ctx->marks[id].b : nullptr;
 }
 // After the stream has been synchronised: fold the marks of blocks that ran
 // (block <= last_block) into the totals and recycle the events.
@@ -171,6 +180,8 @@ struct WS {
   double* gsum;         // summed block Gram (bn x bn)
   double* r1;           // bn x bn
   double* r2;
+  double* r1inv;        // bn x bn: R1^{-1} of the current block
+  double* r2inv;        // bn x bn: R2^{-1} of the current block
   void* q;              // ldy x (nn + bn)
   void* apack;          // mm x lda_eff (if packed)
   // closing steps
@@ -182,6 +193,7 @@ struct WS {
   double* rb2;
   double* rb3;
   double* rb4;
+  double* rb5;
   int32_t* deadbig;     // r_cap
   double* dg;           // r_cap
   void* tbig;           // ldy x r_cap scratch for large-f triangular solves
@@ -209,6 +221,8 @@ WS carve(void* base, const Geo& g) {
   w.gsum = c.take<double>((int64_t)g.bn * g.bn);
   w.r1 = c.take<double>(g.bn * g.bn);
   w.r2 = c.take<double>(g.bn * g.bn);
+  w.r1inv = c.take<double>(g.bn * g.bn);
+  w.r2inv = c.take<double>(g.bn * g.bn);
   w.q = c.take<char>(g.ldy * (g.nn + g.bn) * e);
   w.apack = g.packed ? c.take<char>(g.mm * g.lda_eff * e) : nullptr;
   const int64_t rc = std::max<int64_t>(g.r_cap, 1);
@@ -222,6 +236,7 @@ WS carve(void* base, const Geo& g) {
   w.rb2 = c.take<double>(rb * rb);
   w.rb3 = c.take<double>(rb * rb);
   w.rb4 = c.take<double>(rb * rb);
+  w.rb5 = c.take<double>(rb * rb);
   w.deadbig = c.take<int32_t>(rc + 64);
   w.dg = c.take<double>(std::max<int64_t>(rc, g.bn) + 64);
   w.tbig = c.take<char>(std::max(g.ldy, g.ldk) * rc * std::max<size_t>(e, 8));
@@ -273,6 +288,9 @@ template <typename T>
 struct Ops {
   eodabe_ctx* ctx;
   hipStream_t st;
+  // Timed launches (sketch, projection): when set, the events are attached
+  // to the kernel's own dispatch (start and end of its execution).
+  hipEvent_t pe0 = nullptr, pe1 = nullptr;
 
   // out_parts = X (M x K, row-major ldx) * Z (N x K, row-major ldz)^T
   template <typename Tacc>
@@ -309,8 +327,8 @@ struct Ops {
 #define SK_CASE(CC)                                                                                   \
   do {                                                                                                \
     dim3 grid((unsigned)cdiv(M, 128), splits, 1);                                                     \
-    hipLaunchKernelGGL((k_sketch<T, 2, CC>), grid, dim3(256), 0, st, A, lda, Om, ldk, M, bn, K, kchunk, \
-                       out, ldo, part_stride, sumsq, stopb, blk);                                     \
+    hipExtLaunchKernelGGL((k_sketch<T, 2, CC>), grid, dim3(256), 0, st, pe0, pe1, 0, A, lda, Om, ldk, M, \
+                          bn, K, kchunk, out, ldo, part_stride, sumsq, stopb, blk);                   \
   } while (0)
     if (bn <= 16) SK_CASE(1);
     else if (bn <= 32) SK_CASE(2);
@@ -333,8 +351,8 @@ struct Ops {
     const int rt = (int)std::min<int64_t>(4, cdiv(M, 16));
     dim3 grid((unsigned)cdiv(N, 256), splits, (unsigned)cdiv(M, 16 * rt));
 #define NN_CASE(RR)                                                                                   \
-  hipLaunchKernelGGL((k_gemm_nn<T, RR>), grid, dim3(256), 0, st, X, ldx, Z, ldz, M, N, K, kchunk, out, \
-                     ldo, part_stride)
+  hipExtLaunchKernelGGL((k_gemm_nn<T, RR>), grid, dim3(256), 0, st, pe0, pe1, 0, X, ldx, Z, ldz, M, N, \
+                        K, kchunk, out, ldo, part_stride)
     if (rt == 1) NN_CASE(1);
     else if (rt == 2) NN_CASE(2);
     else if (rt == 3) NN_CASE(3);
@@ -366,27 +384,30 @@ struct Ops {
     return 0;
   }
 
-  // Z = X R^{-1} (R f x f FP64).  In place allowed only for f <= 64.
+  // Z = X R^{-1} (R f x f FP64, f > 64 in practice), out of place.
   int trsm(const T* X, int64_t ldx, T* Zo, int64_t ldz, int64_t m, int f, const double* R,
-           int64_t zoff, int ncols_out, const int64_t* wlog = nullptr, const int32_t* accd = nullptr,
-           const int32_t* stopb = nullptr, int blk = 0) {
+           int ncols_out) {
     if (m <= 0 || f <= 0) return 0;
-    dim3 grid((unsigned)cdiv(m, 64));
-    if (f <= 16) {
-      hipLaunchKernelGGL((k_trsm_rows<T, T, 16>), grid, dim3(64), 0, st, X, ldx, Zo, ldz, m, f, R,
-                         zoff, ncols_out, wlog, accd, stopb, blk);
-    } else if (f <= 32) {
-      hipLaunchKernelGGL((k_trsm_rows<T, T, 32>), grid, dim3(64), 0, st, X, ldx, Zo, ldz, m, f, R,
-                         zoff, ncols_out, wlog, accd, stopb, blk);
-    } else if (f <= 64) {
-      hipLaunchKernelGGL((k_trsm_rows<T, T, 64>), grid, dim3(64), 0, st, X, ldx, Zo, ldz, m, f, R,
-                         zoff, ncols_out, wlog, accd, stopb, blk);
-    } else {
-      // out of place only (the caller provides distinct buffers)
-      hipLaunchKernelGGL((k_trsm_rows_big<T, T>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, X,
-                         ldx, Zo, ldz, m, f, R,
-                         ncols_out);
-    }
+    hipLaunchKernelGGL((k_trsm_rows_big<T, T>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, X, ldx,
+                       Zo, ldz, m, f, R, ncols_out);
+    LAUNCHCHK();
+    return 0;
+  }
+
+  // Z = X W for blocks of f <= 64 columns (one job, or two in one launch).
+  int apply(const ApplyJob& j0, const ApplyJob* j1, int f, const int32_t* stopb = nullptr,
+            int blk = 0) {
+    if (f <= 0) return 0;
+    const int64_t rows = std::max<int64_t>(j0.rows, j1 ? j1->rows : 0);
+    if (rows <= 0) return 0;
+    dim3 grid((unsigned)cdiv(rows, 64), j1 ? 2 : 1);
+    const ApplyJob jb = j1 ? *j1 : j0;
+    if (f <= 16)
+      hipLaunchKernelGGL((k_apply<T, 16>), grid, dim3(256), 0, st, j0, jb, stopb, blk);
+    else if (f <= 32)
+      hipLaunchKernelGGL((k_apply<T, 32>), grid, dim3(256), 0, st, j0, jb, stopb, blk);
+    else
+      hipLaunchKernelGGL((k_apply<T, 64>), grid, dim3(256), 0, st, j0, jb, stopb, blk);
     LAUNCHCHK();
     return 0;
   }
@@ -425,16 +446,16 @@ CholArgs chol_args(const WS& w, double* R, int32_t* dead, int first, int fresh, 
   return ca;
 }
 
-// G = X^T X (FP64) of the column-major rows x f block X, then R = chol(G)
-// with the floor/kill rules and the epilogues in ca (stop test, product,
-// D output, ||A||_F finish).  With Rsolve, X := X Rsolve^{-1} first (in
-// place).  f <= 64: one launch (k_gram_rows; its last workgroup runs the
-// Cholesky).  Wider blocks: generic GEMM, global Cholesky, separate stop
-// test (no fused solve or product).
+// G = Z^T Z (FP64) of the rows x f block Z = X (W null) or Z = X W (W f x f
+// FP64, element (i,j) at j*f + i, Z rounded to T and written over X), then
+// the Cholesky with the floor/kill rules and the epilogues in ca (R,
+// R^{-1}, stop test, ||A||_F finish).  f <= 64: one launch (k_gram_rows; its last workgroup runs the
+// Cholesky with inverse).  Wider blocks: generic GEMM, global Cholesky,
+// separate stop test (no W, no inverse).
 template <typename T>
 int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, int64_t rows, int f,
               double* parts, const CholArgs& ca, const int32_t* stopb = nullptr, int blk = 0,
-              const double* Rsolve = nullptr) {
+              const double* W = nullptr) {
   if (f <= 0) return 0;
   if (f <= 64) {
     uint32_t* counter = &w.st->counter[0];
@@ -442,24 +463,23 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
   do {                                                                                               \
     const int64_t npan = cdiv(rows, GramCfg<T, FF, MM>::RPW);                                        \
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(npan, 64));               \
-    hipLaunchKernelGGL((k_gram_rows<T, FF, MM>), dim3(grid), dim3(256), 0, st, X, ld, rows, f,       \
-                       Rsolve, parts, counter, stopb, blk, ca);                                      \
+    hipLaunchKernelGGL((k_gram_rows<T, FF, MM>), dim3(grid), dim3(256), 0, st, X, ld, rows, f, W,    \
+                       parts, counter, stopb, blk, ca);                                              \
   } while (0)
 #define GRAM_F(FF)                   \
   do {                               \
-    if (Rsolve) GRAM_CASE(FF, 2);    \
+    if (W) GRAM_CASE(FF, 1);         \
     else GRAM_CASE(FF, 0);           \
   } while (0)
     if (f <= 16) GRAM_F(16);
     else if (f <= 32) GRAM_F(32);
-    else if (f <= 48) GRAM_F(48);
     else GRAM_F(64);
 #undef GRAM_F
 #undef GRAM_CASE
     LAUNCHCHK();
     return 0;
   }
-  if (Rsolve || ca.Rprod || ca.Dout) return EODABE_EINVAL;   // fused forms only for f <= 64
+  if (W || ca.Rinv) return EODABE_EINVAL;   // fused forms only for f <= 64
   Ops<T> ops{ctx, st};
   if (ca.fresh) hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, ca.dead, (int64_t)f);
   if (ca.norm_parts)
@@ -477,9 +497,10 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
 
 // CholeskyQR2 of X (rows x f, element (i,c) at c*ld + i), first Cholesky
 // pass floored.  The orthonormal factor goes to Zout (leading dimension ldz;
-// X itself when Zout is null), R = R2 R1 (element (i,j) at j*f + i, or its
-// transpose when transpose_R) to Rout, and optionally R in the data type,
-// row-major, to Dout (ldd).  X is overwritten.
+// X itself when Zout is null).  Blocks wider than 64 columns also write
+// R = R2 R1 (element (i,j) at j*f + i, or its transpose when transpose_R) to
+// Rout and optionally R in the data type, row-major, to Dout (ldd), and
+// overwrite X.
 template <typename T>
 int cholqr2(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, T* X, int64_t ld,
             int64_t rows, int f, double* Rout, int transpose_R, T* tmp, T* Zout = nullptr,
@@ -492,22 +513,24 @@ int cholqr2(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, T* X, in
     ldz = ld;
   }
   if (f <= 64) {
-    // [Gram, chol] -> R1;  [X := X R1^{-1}, Gram, chol, R2 R1] -> R2, R;  Z = X R2^{-1}
-    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, chol_args(w, w.rb1, w.deadbig, 1, 1, 1)));
-    CholArgs ca = chol_args(w, w.rb2, w.deadbig, 0, 0, 1);
-    ca.Rprod = Rout;
-    ca.prod_transpose = transpose_R;
-    ca.Dout = Dout;
-    ca.ldd = ldd;
-    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, ca, nullptr, 0, w.rb1));
-    TRY(ops.trsm(X, ld, Zout, ldz, rows, f, w.rb2, 0, f));
+    // [Gram, chol_inv] -> R1 (rb1), R1^{-1} (rb3); [X := X R1^{-1}, Gram,
+    // chol_inv] -> R2 (rb2), R2^{-1} (rb5); Z = X R2^{-1}.  Rout and Dout are
+    // not written on this path (the closing steps take R1, R2 from rb1, rb2).
+    CholArgs c1 = chol_args(w, w.rb1, w.deadbig, 1, 1, 1);
+    c1.Rinv = w.rb3;
+    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, c1));
+    CholArgs c2 = chol_args(w, w.rb2, w.deadbig, 0, 0, 1);
+    c2.Rinv = w.rb5;
+    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, c2, nullptr, 0, w.rb3));
+    const ApplyJob a{X, ld, Zout, ldz, w.rb5, rows, 0, f, f, nullptr, nullptr};
+    TRY(ops.apply(a, nullptr, f));
     return 0;
   }
   double* Rs[2] = {w.rb1, w.rb2};
   for (int pass = 0; pass < 2; ++pass) {
     TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig,
                      chol_args(w, Rs[pass], w.deadbig, pass == 0, pass == 0, 1)));
-    TRY(ops.trsm(X, ld, tmp, ld, rows, f, Rs[pass], 0, f));
+    TRY(ops.trsm(X, ld, tmp, ld, rows, f, Rs[pass], f));
     const int64_t cnt = ld * (int64_t)f;
     hipLaunchKernelGGL((k_copy2d<T, T>), dim3((unsigned)cdiv(cnt, 32), 1), dim3(32, 8), 0, st, tmp,
                        cnt, X, cnt, (int64_t)1, cnt, 0);
@@ -586,8 +609,10 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       // a2: sketch Y = A Omega_j (K-split partials; block 0 also ||A||_F)
       const int64_t ystride = g.ldy * g.bn;
       const int pid = prof_begin(ctx, st);
+      prof_attach(ctx, ops, pid);
       TRY(ops.sketch(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch, (T*)w.ypart, g.ldy,
                      ystride, j == 0 ? w.normparts : nullptr, stopb, blk));
+      prof_attach(ctx, ops, -1);
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
                (double)g.elem * ((double)g.mm * g.nn + (double)g.nn * f + (double)g.mm * f));
       const int nsp = eff_splits(g.nn, g.s_sketch);
@@ -599,6 +624,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       // stop test (a5); the second solve is the append below.
       int32_t* deadj = w.dead + j * BN_MAX;
       const int64_t wmax = std::min<int64_t>(j * g.b, g.nn);
+      const bool small = f <= 64;
+      if (j == 0) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       for (int pass = 0; pass < 2; ++pass) {
         if (j > 0) {
           TRY(ops.template gemm_nt<T>(q, g.ldy, y, g.ldy, wmax, f, g.mm, g.s_proj, (T*)w.wpart, ldw,
@@ -610,7 +637,14 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           TRY(ops.update(y, g.ldy, q, g.ldy, g.mm, wmax, f, wbuf, ldw, 1, w.wlog, stopb, blk));
         }
         CholArgs ca = chol_args(w, pass == 0 ? w.r1 : w.r2, deadj, pass == 0, 0, 0);
-        if (pass == 1) {
+        if (pass == 0) {
+          if (small) ca.Rinv = w.r1inv;
+          if (j == 0) {
+            ca.norm_parts = w.normparts;
+            ca.n_norm = sketch_wgs * (int64_t)nsp;
+          }
+        } else {
+          if (small) ca.Rinv = w.r2inv;
           ca.R1 = w.r1;
           ca.col0 = col0;
           ca.n = g.nn;
@@ -618,30 +652,29 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           ca.acc = w.accv;
           ca.diag_log = w.diag_log;
         }
-        if (j == 0 && pass == 0) {
-          ca.norm_parts = w.normparts;
-          ca.n_norm = sketch_wgs * (int64_t)nsp;
-          TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
-        }
-        // with no basis yet (j == 0) the pass-0 solve runs inside the pass-1 Gram
-        const bool fused = (j == 0 && pass == 1 && f <= 64);
+        // Y := Y R1^{-1} between the passes.  Block 0 (nothing to project
+        // against) lets the second Gram kernel form it in place; later blocks
+        // normalise first, so that the second projection acts on the
+        // normalised block (re-orthogonalisation needs that order).
+        const bool fuse = small && j == 0;
         TRY(gram_chol<T>(ctx, st, w, y, g.ldy, g.mm, f, w.gpart, ca, stopb, blk,
-                         fused ? w.r1 : nullptr));
-        if (pass == 0 && !(j == 0 && f <= 64)) {
-          if (f <= 64) {
-            TRY(ops.trsm(y, g.ldy, y, g.ldy, g.mm, f, w.r1, 0, f, nullptr, nullptr, stopb, blk));
-          } else {
-            TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r1, 0, f));
-            TRY(copy2d<T>(ctx, st, (T*)w.tbig, g.ldy, y, g.ldy, f, g.ldy, 0));
-          }
+                         (fuse && pass == 1) ? w.r1inv : nullptr));
+        if (pass == 0 && small && !fuse) {
+          const ApplyJob a{y, g.ldy, y, g.ldy, w.r1inv, g.mm, 0, f, f, nullptr, nullptr};
+          TRY(ops.apply(a, nullptr, f, stopb, blk));
+        }
+        if (pass == 0 && !small) {
+          TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r1, f));
+          TRY(copy2d<T>(ctx, st, (T*)w.tbig, g.ldy, y, g.ldy, f, g.ldy, 0));
         }
       }
       // a6: append P = Z R2^{-1} (accepted columns) into Q at column wlog[j]
-      if (f <= 64) {
-        TRY(ops.trsm(y, g.ldy, q, g.ldy, g.mm, f, w.r2, 0, 0, w.wlog, w.accv, stopb, blk));
+      if (small) {
+        const ApplyJob a{y, g.ldy, q, g.ldy, w.r2inv, g.mm, 0, f, 0, w.wlog, w.accv};
+        TRY(ops.apply(a, nullptr, f, stopb, blk));
       } else {
         // large blocks: solve into scratch, then copy the accepted columns
-        TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r2, 0, f));
+        TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r2, f));
         // the copy below uses the host-known bound f; rows past acc are
         // overwritten by later blocks (the basis is sized nn + bn).
         HIPCHK(hipStreamSynchronize(st));
@@ -674,12 +707,32 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   return 0;
 }
 
+// QR of M^T on one workgroup (f <= 64): M = R2 R1, or M = R2 when R1 is null
+// (both column-major f x f FP64).  Q_hat -> Qout (FP64, column-major),
+// R_hat -> Dout (type T, row-major ldd); floored pivots counted in st.
+template <typename T>
+int small_qr(eodabe_ctx* ctx, hipStream_t st, const double* R1, const double* R2, int f, double* Qout, T* Dout,
+             int64_t ldd, State* state) {
+  if (f <= 0) return 0;
+  if (f <= 16)
+    hipLaunchKernelGGL((k_small_qr<T, 16>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1);
+  else if (f <= 32)
+    hipLaunchKernelGGL((k_small_qr<T, 32>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1);
+  else if (f <= 64)
+    hipLaunchKernelGGL((k_small_qr<T, 64>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1);
+  else
+    return EODABE_EINVAL;
+  LAUNCHCHK();
+  return 0;
+}
+
 // Alg. 2 after Alg. 1: power iteration, C = Q^T A, QR(C^T), QR(R^T).
 // Writes U_hat (column-major mm x r, ld ldu) to Uout, V_hat^T (r x nn,
 // row-major ldv) to Vout and D_hat (r x r row-major, ldd) to Dout.
 template <typename T>
 int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, int64_t r,
               T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout, int64_t ldd) {
+  if (r <= 0) return 0;
   Ops<T> ops{ctx, st};
   T* q = (T*)w.q;
   T* cb = (T*)w.cbuf;
@@ -702,10 +755,28 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   }
   // a9: C = Q^T A (r x nn, row-major ld ldk)
   const int pid = prof_begin(ctx, st);
+  prof_attach(ctx, ops, pid);
   TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
+  prof_attach(ctx, ops, -1);
   prof_end(ctx, st, pid, EODABE_PROF_PROJECT, 0,
            (double)g.elem * ((double)g.mm * g.nn + (double)g.mm * r + (double)r * g.nn));
   TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb));
+  if (r <= 64) {
+    // a10: C^T = V R by CholeskyQR2, R = R2 R1 (rb2, rb1), V = (C^T R1^{-1}) R2^{-1};
+    // a11: R^T = Q_hat R_hat on one workgroup (Q_hat -> rb4, D_hat = R_hat -> Dout);
+    // V and U_hat = Q Q_hat in one launch.
+    CholArgs c1 = chol_args(w, w.rb1, w.deadbig, 1, 1, 1);
+    c1.Rinv = w.rb3;
+    TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c1));
+    CholArgs c2 = chol_args(w, w.rb2, w.deadbig, 0, 0, 1);
+    c2.Rinv = w.rb5;
+    TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c2, nullptr, 0, w.rb3));
+    TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st));
+    const ApplyJob jv{cb, g.ldk, Vout, ldv, w.rb5, g.nn, 0, (int)r, (int)r, nullptr, nullptr};
+    const ApplyJob ju{q, g.ldy, Uout, ldu, w.rb4, g.mm, 0, (int)r, (int)r, nullptr, nullptr};
+    TRY(ops.apply(jv, &ju, (int)r));
+    return 0;
+  }
   // a10: C^T = V R  (C^T is nn x r with element (j,a) at a*ldk + j = cbuf);
   //      V^T rows go straight to Vout, R^T (row-major R) to rb4 as a
   //      column-major r x r matrix.
@@ -952,23 +1023,34 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
       // U' -> ybig (column-major n x r), V'^T -> cbuf (r x m), D' -> rb_tmp
       T* ut = (T*)w.ybig;            // U' column-major (ld = ldy)
       TRY(run_close<T>(ctx, st, g, w, Ae, rank, ut, g.ldy, (T*)w.cbuf, g.ldk, (T*)w.tbig, rank));
-      // D'^T (r x r): tbig holds D' row-major (ld r) = D'^T column-major.
-      Ops<double> opd{ctx, st};
-      (void)opd;
-      const int64_t cnt = rank * rank;
-      hipLaunchKernelGGL((k_copy2d<T, double>), dim3((unsigned)cdiv(cnt, 32), 1), dim3(32, 8), 0, st,
-                         (const T*)w.tbig, cnt, w.rb4, cnt, (int64_t)1, cnt, 0);
-      LAUNCHCHK();
-      TRY(cholqr2<double>(ctx, st, g, w, w.rb4, rank, rank, (int)rank, w.rb3, 0, (double*)w.tbig));
-      // U_out = V' Q'' : V' column-major m x r is cbuf (element (i,a) at a*ldk + i)
       Ops<T> ops{ctx, st};
-      TRY(ops.update_d((T*)Ut, m, (const T*)w.cbuf, g.ldk, m, rank, (int)rank, w.rb4, rank));
-      // Vt_out = U'^T : U' column-major n x r (ld ldy) -> row a = column a
-      TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));
-      dim3 grid((unsigned)cdiv(rank, 32), (unsigned)cdiv(rank, 32));
-      hipLaunchKernelGGL((k_copy2d<double, T>), grid, dim3(32, 8), 0, st, w.rb3, rank, (T*)core, r_cap,
-                         rank, rank, 1);
-      LAUNCHCHK();
+      if (rank <= 64) {
+        // QR(D'^T) = Q'' R'' on one workgroup: D' column-major (FP64) -> rb2;
+        // U_out = V' Q'' (one MFMA pass), core = R'', Vt_out = U'^T.
+        dim3 gt((unsigned)cdiv(rank, 32), (unsigned)cdiv(rank, 32));
+        hipLaunchKernelGGL((k_copy2d<T, double>), gt, dim3(32, 8), 0, st, (const T*)w.tbig, rank, w.rb2,
+                           rank, rank, rank, 1);
+        LAUNCHCHK();
+        TRY(small_qr<T>(ctx, st, nullptr, w.rb2, (int)rank, w.rb4, (T*)core, r_cap, w.st));
+        const ApplyJob ju{w.cbuf, g.ldk, Ut, m, w.rb4, m, 0, (int)rank, (int)rank, nullptr, nullptr};
+        TRY(ops.apply(ju, nullptr, (int)rank));
+        TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));
+      } else {
+        // D'^T (r x r): tbig holds D' row-major (ld r) = D'^T column-major.
+        const int64_t cnt = rank * rank;
+        hipLaunchKernelGGL((k_copy2d<T, double>), dim3((unsigned)cdiv(cnt, 32), 1), dim3(32, 8), 0, st,
+                           (const T*)w.tbig, cnt, w.rb4, cnt, (int64_t)1, cnt, 0);
+        LAUNCHCHK();
+        TRY(cholqr2<double>(ctx, st, g, w, w.rb4, rank, rank, (int)rank, w.rb3, 0, (double*)w.tbig));
+        // U_out = V' Q'' : V' column-major m x r is cbuf (element (i,a) at a*ldk + i)
+        TRY(ops.update_d((T*)Ut, m, (const T*)w.cbuf, g.ldk, m, rank, (int)rank, w.rb4, rank));
+        // Vt_out = U'^T : U' column-major n x r (ld ldy) -> row a = column a
+        TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));
+        dim3 grid((unsigned)cdiv(rank, 32), (unsigned)cdiv(rank, 32));
+        hipLaunchKernelGGL((k_copy2d<double, T>), grid, dim3(32, 8), 0, st, w.rb3, rank, (T*)core, r_cap,
+                           rank, rank, 1);
+        LAUNCHCHK();
+      }
     }
     HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -660,35 +660,184 @@ __global__ __launch_bounds__(256) void k_update_rows(
   }
 }
 
-// Broadcast of a double from a wave-uniform lane (v_readlane on both halves).
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-__device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
 // ---------------------------------------------------------------------------
-// Cholesky of a symmetric positive semi-definite f x f matrix (f <= F <= 64,
-// FP64) on one wavefront, with the rules of the blocked CholeskyQR used here:
-//   * dead columns (flag set) are skipped: R(k,k) = 1, row and column zero;
-//   * a pivot G(k,k) - sum R(i,k)^2 <= FLOOR_C u64 G(k,k) is floored to that
-//     value when first_pass (the column stays alive but its row is zeroed so
-//     it does not feed later columns), and marks the column dead otherwise.
-// Lane j holds column j of G in registers (fully unrolled over F); pivots
-// and row entries are broadcast with v_readlane.  G: element (i,j) at
-// j*f + i; R is written the same way (lower part zero).
-// If R1 != nullptr this is the second pass of a basis block and the stop test
-// of Alg. 1 follows: d_c = |T(c,c)| = R(c,c) R1(c,c) (0 for dead columns);
-// the first c with d_c <= eps keeps columns 0..c-1 and stops the loop;
-// otherwise all f are kept and the loop ends after the last column of Omega.
-// Writes acc[block], wlog[block+1] = wlog[block] + acc, st->rank, the
-// examined d_c to diag_log[col0 + c] and stop_block.
+// Small FP64 matrices (f <= F <= 64, F in {16, 32, 64}) are kept in LDS
+// row-major with leading dimension F + 1 (the odd stride spreads a column
+// over the banks).
 // ---------------------------------------------------------------------------
-// Arguments of the Cholesky that closes a Gram pass (see chol_wave).
+template <int F>
+struct SmallCfg {
+  static constexpr int LD = F + 1;
+  static constexpr int SIZE = F * (F + 1);        // doubles per matrix
+  static constexpr int NR = F / 4;                // elimination: rows held per wave
+  static constexpr int NCL = (2 * F + 63) / 64;   // elimination: columns of [G | I] per lane
+};
+
+// C = op(A) op(B) for F x F FP64 matrices in LDS on the four waves of the
+// workgroup (v_mfma_f64_16x16x4, one 16 x 16 tile per wave at a time);
+// element (i, j) of the product is handed to out(i, j, v).
+template <int F, bool TA, bool TB, typename Out>
+__device__ __forceinline__ void lds_gemm(const double* A, const double* B, Out out) {
+  typedef Mfma<double> MF;
+  constexpr int TT = F / 16, LD = F + 1;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  for (int tile = wv; tile < TT * TT; tile += 4) {
+    const int ti = tile / TT, tj = tile - ti * TT;
+    const int ar = 16 * ti + r, bc = 16 * tj + r;
+    typename MF::acc_t acc = MF::zero();
+#pragma unroll 4
+    for (int k0 = 0; k0 < F; k0 += 4) {
+      const int kk = k0 + g;
+      const double a = TA ? A[kk * LD + ar] : A[ar * LD + kk];
+      const double b = TB ? B[bc * LD + kk] : B[kk * LD + bc];
+      acc = MF::op(a, b, acc);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out(16 * ti + MF::row(g, e), bc, acc[e]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky with inverse, on the four waves of a workgroup, of a symmetric
+// positive semi-definite f x f matrix G (FP64, f <= F): one elimination
+// sweep over the augmented rows [G | I].  With G = L U (L unit lower,
+// U = diag(alpha) R) the sweep turns I into L^{-1} = diag(alpha) R^{-T}, so
+// row k of the right half divided by alpha_k is column k of R^{-1}.
+//   Step k: pivot p = S(k,k) of the current Schur complement S;
+//     dead column (flag in dmask_in): R(k,k) = 1, row k and column k of R
+//       zero, no elimination;
+//     p <= FLOOR_C u64 G(k,k) or not finite: floored to that value on a
+//       first pass (R(k,k) = sqrt(floor), rest of row k zero, no
+//       elimination) and marked dead otherwise (R(k,k) = 1);
+//     else R(k,k) = sqrt(p), R(k,c) = S(k,c)/R(k,k) for live c > k, and
+//       every later row i subtracts S(k,i)/p times row k (dead columns of
+//       the left half excluded).
+// Layout: 64 lanes x 4 waves; lane c holds column c of [G | I] (two columns
+// per lane when F = 64), wave w rows 4(g+s)+w in slot s during group g of
+// four steps, so the pivot row of step 4g+u is slot 0 of wave u; the slots
+// move down by one after each group.  Row k goes through LDS (rowbuf), one
+// barrier per step.
+// Gs: G on entry (row-major, ld F+1), R on exit (zero below the diagonal
+// and in rows >= f); Ri: R^{-1} on exit (zero in columns >= f); rowbuf:
+// 4 x 2F doubles; dgs: F doubles.  Returns the dead mask after the sweep
+// and the number of floored pivots (uniform over the workgroup).
+// ---------------------------------------------------------------------------
+template <int F>
+__device__ void chol_inv(double* Gs, double* Ri, double* rowbuf, double* dgs, int f,
+                         uint64_t dmask_in, int first_pass, uint64_t* dmask_out, int* nfloor) {
+  typedef SmallCfg<F> C;
+  constexpr int LD = C::LD, NR = C::NR, NCL = C::NCL, W2 = 2 * F;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < f; i += 256) dgs[i] = Gs[i * LD + i];
+  double M[NR][NCL];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = 4 * s + w;
+#pragma unroll
+    for (int q = 0; q < NCL; ++q) {
+      const int c = lane + 64 * q;
+      double v = 0.0;
+      if (i < f && c < W2) {
+        if (c < F) v = c < f ? Gs[i * LD + c] : 0.0;
+        else v = (c - F == i) ? 1.0 : 0.0;
+      }
+      M[s][q] = v;
+    }
+  }
+  __syncthreads();                       // G consumed: Gs now receives R
+  uint64_t dout = dmask_in;
+  int nfl = 0;
+  for (int g = 0; 4 * g < f; ++g) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * g + u;
+      if (k >= f) break;
+      double* rb = rowbuf + u * W2;
+      if (w == u) {
+#pragma unroll
+        for (int q = 0; q < NCL; ++q) {
+          const int c = lane + 64 * q;
+          if (c < W2) rb[c] = M[0][q];
+        }
+      }
+      __syncthreads();
+      const double piv = rb[k];
+      const bool dk = (dmask_in >> k) & 1ull;
+      const double flo = FLOOR_C * U64 * dgs[k];
+      int fl = 0;
+      double alpha;
+      if (dk) {
+        fl = 2;
+        alpha = 1.0;
+      } else if (!(piv > flo) || !(piv < INFINITY)) {
+        fl = first_pass ? 1 : 2;
+        alpha = first_pass ? sqrt(flo > 1e-300 ? flo : 1e-300) : 1.0;
+      } else {
+        alpha = sqrt(piv);
+      }
+      if (fl == 2) dout |= 1ull << k;
+      nfl += (fl == 1);
+      if (w == u) {                      // row k of R, column k of R^{-1}
+        const double ia = 1.0 / alpha;
+#pragma unroll
+        for (int q = 0; q < NCL; ++q) {
+          const int c = lane + 64 * q;
+          if (c < F) {
+            double v = 0.0;
+            if (c == k) v = alpha;
+            else if (c > k && fl == 0 && !((dmask_in >> c) & 1ull)) v = M[0][q] * ia;
+            Gs[k * LD + c] = v;
+          } else if (c < W2) {
+            const int cc = c - F;
+            Ri[cc * LD + k] = cc <= k ? M[0][q] * ia : 0.0;
+          }
+        }
+      }
+      if (fl == 0) {
+        const double ip = 1.0 / piv;
+        double t[NCL];
+#pragma unroll
+        for (int q = 0; q < NCL; ++q) {
+          const int c = lane + 64 * q;
+          double v = c < W2 ? rb[c] : 0.0;
+          if (c < F && ((dmask_in >> c) & 1ull)) v = 0.0;
+          t[q] = v * ip;
+        }
+#pragma unroll
+        for (int s = 0; s < NR; ++s) {
+          if (s == 0 && w <= u) continue;  // rows <= k are finished
+          const int i = 4 * (g + s) + w;
+          if (i >= f) continue;
+          const double mlt = ((dmask_in >> i) & 1ull) ? 0.0 : rb[i];
+#pragma unroll
+          for (int q = 0; q < NCL; ++q) M[s][q] = fma(-mlt, t[q], M[s][q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s + 1 < NR; ++s)
+#pragma unroll
+      for (int q = 0; q < NCL; ++q) M[s][q] = M[s + 1][q];
+#pragma unroll
+    for (int q = 0; q < NCL; ++q) M[NR - 1][q] = 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < (F - f) * F; idx += 256) {   // padding rows / columns
+    const int a = f + idx / F, b = idx - (idx / F) * F;
+    Gs[a * LD + b] = 0.0;
+    Ri[b * LD + a] = 0.0;
+  }
+  __syncthreads();
+  *dmask_out = dout;
+  *nfloor = nfl;
+}
+
+// Arguments of the Cholesky that closes a Gram pass (k_gram_rows, and the
+// global-memory path for wide blocks).
 struct CholArgs {
-  double* R;               // R out: f x f, element (i,j) at j*f + i (lower part zero)
+  double* R;               // R out: f x f, element (i,j) at j*f + i (lower part zero); may be null
+  double* Rinv;            // R^{-1} out, same layout; may be null
   int32_t* dead;           // per-column dead flags (in/out)
   int first_pass;          // floor (1) or kill (0) non-positive pivots
   int fresh;               // ignore incoming dead flags (a new factorization)
@@ -699,172 +848,68 @@ struct CholArgs {
   int64_t* wlog;
   int32_t* acc;
   double* diag_log;
-  double* Rprod;           // non-null: also write R * R1 (R1 = the solve matrix)
-  int prod_transpose;      // product element (i,j) at i*f + j instead of j*f + i
-  void* Dout;              // non-null: product written in the data type, row-major, ld ldd
-  int64_t ldd;
   const double* norm_parts;  // non-null: finish ||A||_F and eps = tol ||A||_F first
   int64_t n_norm;
 };
 
-// Cholesky + fused epilogues on one wavefront (lane j = column j, j < f),
-// left-looking and in place in LDS: W (row-major, leading dimension F) holds
-// G on entry (upper triangle read) and R on exit; step k computes row k:
-//   s_j = G(k,j) - sum_{i<k} R(i,k) R(i,j),  j >= k.
-// The pivot s_k is broadcast with v_readlane; LDS operations of one wave
-// execute in order, so no barrier is needed between steps.  Pivot rules:
-//   * dead columns (flag set) are skipped: R(k,k) = 1, row and column zero;
-//   * a pivot s_k <= FLOOR_C u64 G(k,k) is floored to that value on a first
-//     pass (the column stays alive but its row is zeroed so it does not feed
-//     later columns), and marks the column dead otherwise.
-// Epilogues: the product R R1 (R1 in LDS, column-major, leading dimension
-// F+1), and for a basis block the stop test of Alg. 1: d_c = |T(c,c)| =
-// R(c,c) R1(c,c) (0 for dead columns); the first c with d_c <= eps keeps
-// columns 0..c-1 and stops the loop, otherwise all f are kept and the loop
-// ends after the last column of Omega.
-template <int F, typename T>
-__device__ __forceinline__ void chol_wave(double* W, int f, const CholArgs& ca, int block_id,
-                                          const double* R1l) {
-  const int j = threadIdx.x & 63;
-  const bool mine = j < f;
-  State* st = ca.st;
-  if (ca.norm_parts) {                    // ||A||_F from the sketch partials (fixed order)
-    double a = 0.0;
-    for (int64_t i = j; i < ca.n_norm; i += 64) a += ca.norm_parts[i];
-    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
-    if (j == 0) {
-      st->normsq = a;
-      const bool bad = !(a < INFINITY);
-      st->nonfinite = bad ? 1 : 0;
-      st->eps = bad ? 0.0 : st->tol * sqrt(a);
-    }
-  }
-  int deadj = mine ? (ca.fresh ? 0 : ca.dead[j]) : 1;
-  const double dgj = mine ? W[j * F + j] : 0.0;        // original G(j,j)
-  double diagj = 1.0;
-  int nfloor = 0;
-  for (int k = 0; k < f; ++k) {
-    double sj = 0.0;
-    if (mine && j >= k) {
-      sj = W[k * F + j];
-#pragma unroll 4
-      for (int i = 0; i < k; ++i) sj -= W[i * F + k] * W[i * F + j];
-    }
-    const double piv = readlane_d(sj, k);
-    const double dgk = readlane_d(dgj, k);
-    const int deadk = readlane_i(deadj, k);
-    int fl = 0;
-    double rkk;
-    if (deadk) {
-      fl = 2;
-      rkk = 1.0;
-    } else {
-      const double flo = FLOOR_C * U64 * dgk;
-      if (!(piv > flo) || !(piv < INFINITY)) {
-        fl = ca.first_pass ? 1 : 2;
-        rkk = ca.first_pass ? sqrt(flo > 1e-300 ? flo : 1e-300) : 1.0;
-      } else {
-        rkk = sqrt(piv);
-      }
-    }
-    nfloor += (fl == 1);
-    if (mine && j >= k) {
-      double v;
-      if (j == k) {
-        v = rkk;
-        diagj = rkk;
-        if (fl == 2) deadj = 1;
-      } else {
-        v = (fl != 0 || deadj) ? 0.0 : sj / rkk;
-      }
-      W[k * F + j] = v;
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  if (mine) {
-    for (int i = 0; i < f; ++i) ca.R[(int64_t)j * f + i] = (i <= j) ? W[i * F + j] : 0.0;
-    ca.dead[j] = deadj;
-  }
-  if (ca.count_floors && j == 0 && nfloor) atomicAdd(&st->floored, nfloor);
-  if (ca.Rprod && R1l && mine) {
-    // (R R1)(i,j) = sum_{k=i..j} R(i,k) R1(k,j)
-    for (int i = 0; i < f; ++i) {
-      double v = 0.0;
-      if (i <= j)
-        for (int k = i; k <= j; ++k) v += W[i * F + k] * R1l[j * (F + 1) + k];
-      if (ca.prod_transpose) ca.Rprod[(int64_t)i * f + j] = v;
-      else ca.Rprod[(int64_t)j * f + i] = v;
-      if (ca.Dout) reinterpret_cast<T*>(ca.Dout)[(int64_t)i * ca.ldd + j] = (T)v;
-    }
-  }
-  if (!ca.R1) return;
-  // stop test (Alg. 1): first column whose |T(c,c)| <= eps
-  const double eps = st->eps;
-  double d = 0.0;
-  bool hit = false;
-  if (mine) {
-    d = deadj ? 0.0 : diagj * ca.R1[(int64_t)j * f + j];
-    hit = (d <= eps) || st->nonfinite;
-  }
-  const unsigned long long mask = __ballot(hit);
-  const int keep = mask ? (int)__ffsll((long long)mask) - 1 : f;
-  if (mine && j <= keep) ca.diag_log[ca.col0 + j] = d;
-  if (j == 0) {
-    const bool stop = (mask != 0ull) || (ca.col0 + f >= ca.n);
-    ca.acc[block_id] = keep;
-    const int64_t wn = ca.wlog[block_id] + keep;
-    ca.wlog[block_id + 1] = wn;
-    st->rank = wn;
-    if (stop) st->stop_block = block_id;
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Gram matrix G = X^T X (FP64 accumulation) of a column-major rows x f block
-// X (f <= F <= 64), with an optional front end applied to each row first:
-//   MODE 0: X as stored;
-//   MODE 1: X := sum of nsrc partial blocks src + s*src_stride (written to X);
-//   MODE 2: X := X R^{-1} (forward substitution in FP64, R upper f x f,
-//           element (i,j) at j*f + i; written to X in the data type).
-// Each workgroup takes panels of RPW rows (grid-stride), stages the panel
-// (as stored, in the data type) in LDS column by column, and accumulates
-// on f64 MFMA with its 4 waves splitting the panel rows.  The waves are
-// folded in fixed order through LDS, the workgroup partial goes to
-// parts[blockIdx.x] (element (i,j) at j*f + i), and the last workgroup to
-// arrive (device-scope counter) sums the partials in fixed order and runs
-// the Cholesky of G (plus the stop test for a basis block) on its wave 0.
+// Gram matrix G = Z^T Z (FP64) of a rows x f block, then chol_inv of G:
+//   MODE 0: Z = X as stored (column-major, type T);
+//   MODE 1: Z = X W with W f x f FP64 (element (i,j) at j*f + i), formed
+//           panel by panel in FP64 on MFMA, rounded to T and written back
+//           over X; G is the Gram of the rounded Z, so the next Cholesky
+//           factor corrects the block actually stored (the second pass of
+//           CholeskyQR2 must see the Z it orthogonalises).
+// Each workgroup stages panels of RPW rows of X in LDS (grid-stride),
+// accumulates on f64 MFMA with its 4 waves splitting the panel rows, folds
+// the waves in fixed order and writes its partial to parts[blockIdx.x]
+// (element (i,j) at j*f + i).  The last workgroup to arrive (device-scope
+// counter) sums the partials in fixed order and runs chol_inv plus the
+// epilogues in ca: R, R^{-1}, dead flags, floors, the ||A||_F finish and
+// the stop test of Alg. 1:
+//   d_c = |T(c,c)| = R(c,c) R1(c,c) (0 for dead columns); the first c with
+//   d_c <= eps keeps columns 0..c-1 and stops the loop, otherwise all f are
+//   kept and the loop ends after the last column of Omega.
 // ---------------------------------------------------------------------------
 template <typename T, int F, int MODE>
 struct GramCfg {
-  // MODE 0: panel in the data type; MODE 2: panel in FP64 (the solved rows)
-  typedef typename std::conditional<MODE == 2, double, T>::type P;
-  static constexpr int RPW = (MODE == 2) ? (F <= 32 ? 256 : 128) : (F * (int)sizeof(T) <= 128 ? 256 : 128);
-  static constexpr int LDP = RPW + 16 / (int)sizeof(P);   // padded column stride (bank spread)
+  typedef SmallCfg<F> S;
+  static constexpr int RPW = MODE == 0 ? (F * (int)sizeof(T) <= 128 ? 256 : 128)
+                                       : (F <= 32 ? 256 : (sizeof(T) == 4 ? 128 : 64));
+  static constexpr int LDX = RPW + 16 / (int)sizeof(T);   // X panel column stride (T elements)
+  static constexpr int LDZ = RPW + 2;                     // Z panel column stride (doubles)
+  static constexpr int PBASE = MODE == 1 ? S::SIZE : 0;   // W first (MODE 1), then the phases
+  static constexpr int XD = (F * LDX * (int)sizeof(T) + 7) / 8;
+  static constexpr int ZD = MODE == 1 ? F * LDZ : 0;
+  static constexpr int FOLD = (F / 16) * (F / 16) * 256;
+  static constexpr int LOOPD = XD + ZD > FOLD ? XD + ZD : FOLD;
+  static constexpr int CHAIND = 2 * S::SIZE + 8 * F + F;
+  static constexpr int TOTAL = PBASE + (LOOPD > CHAIND ? LOOPD : CHAIND);
 };
 
 template <typename T, int F, int MODE>
 __global__ __launch_bounds__(256) void k_gram_rows(
-    T* __restrict__ X, int64_t ld, int64_t rows, int f, const double* __restrict__ Rm,
+    T* __restrict__ X, int64_t ld, int64_t rows, int f, const double* __restrict__ Wg,
     double* __restrict__ parts, uint32_t* __restrict__ counter, const int32_t* __restrict__ stop_block,
     int block_id, CholArgs ca) {
   typedef Mfma<double> MF;
   typedef GramCfg<T, F, MODE> Cfg;
-  typedef typename Cfg::P P;
-  constexpr int TT = F / 16;
-  constexpr int RPW = Cfg::RPW;
-  constexpr int LDP = Cfg::LDP;
+  typedef SmallCfg<F> S;
+  constexpr int TT = F / 16, RPW = Cfg::RPW, LDX = Cfg::LDX, LDZ = Cfg::LDZ, LD = S::LD;
+  static_assert(Cfg::TOTAL * 8 <= 160 * 1024, "LDS budget");
   if (stop_block && *stop_block < block_id) return;
-  __shared__ P pan[F * LDP];                 // column-major panel: pan[c*LDP + row]
-  __shared__ double Rs[MODE == 2 ? F * (F + 1) : 1];   // R1(k,c) at c*(F+1) + k
-  __shared__ double rinv[MODE == 2 ? F : 1];
+  __shared__ __align__(16) double lds[Cfg::TOTAL];
+  double* Wl = lds;                                   // MODE 1: W, row-major ld F+1
+  double* ph = lds + Cfg::PBASE;
+  T* pan = reinterpret_cast<T*>(ph);                  // X panel: pan[c*LDX + row]
+  double* pz = ph + Cfg::XD;                          // MODE 1: Z panel: pz[c*LDZ + row]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
-  if constexpr (MODE == 2) {
-    for (int idx = tid; idx < f * f; idx += 256) {
-      const int c = idx / f, kk = idx - c * f;
-      Rs[c * (F + 1) + kk] = Rm[idx];
+  if constexpr (MODE == 1) {
+    for (int idx = tid; idx < F * F; idx += 256) {
+      const int i = idx / F, jj = idx - i * F;
+      Wl[i * LD + jj] = (i < f && jj < f) ? Wg[(int64_t)jj * f + i] : 0.0;
     }
-    for (int c = tid; c < f; c += 256) rinv[c] = 1.0 / Rm[(int64_t)c * f + c];
   }
   typename MF::acc_t acc[TT][TT];
 #pragma unroll
@@ -872,51 +917,63 @@ __global__ __launch_bounds__(256) void k_gram_rows(
 #pragma unroll
     for (int u = 0; u < TT; ++u) acc[t][u] = MF::zero();
   const int64_t npan = (rows + RPW - 1) / RPW;
+  constexpr int NIT = F * RPW / 256;
+  static_assert(NIT % 8 == 0, "staging batches");
   for (int64_t pnl = blockIdx.x; pnl < npan; pnl += gridDim.x) {
     const int64_t rb = pnl * RPW;
-    __syncthreads();                          // previous panel consumed (and Rs ready)
-    if (tid < RPW) {
-      const int rl = tid;
-      const int64_t row = rb + rl;
-      const bool ok = row < rows;
-      // stage the row (loads batched 8 at a time)
-      for (int c0 = 0; c0 < F; c0 += 8) {
-        T xv[8];
+    __syncthreads();                          // previous panel consumed (and W ready)
+    for (int it0 = 0; it0 < NIT; it0 += 8) {  // stage X (zero outside rows x f), 8 loads in flight
+      T xv[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          xv[q] = (c0 + q < f && ok) ? X[(int64_t)(c0 + q) * ld + row] : (T)0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) pan[(c0 + q) * LDP + rl] = (P)xv[q];
+      for (int q = 0; q < 8; ++q) {
+        const int idx = tid + 256 * (it0 + q);
+        const int c = idx / RPW, rl = idx - c * RPW;
+        const int64_t row = rb + rl;
+        xv[q] = (c < f && row < rows) ? X[(int64_t)c * ld + row] : (T)0;
       }
-      if constexpr (MODE == 2) {
-        // z_c = (x_c - sum_{k<c} z_k R(k,c)) / R(c,c) in FP64, rounded to T
-        for (int c = 0; c < f; ++c) {
-          double v = pan[c * LDP + rl];
-#pragma unroll 4
-          for (int k = 0; k < c; ++k) v -= pan[k * LDP + rl] * Rs[c * (F + 1) + k];
-          v *= rinv[c];
-          pan[c * LDP + rl] = v;
-        }
-        for (int c = 0; c < f; ++c) {
-          const T zt = (T)pan[c * LDP + rl];
-          if (ok) X[(int64_t)c * ld + row] = zt;
-          pan[c * LDP + rl] = ok ? (double)zt : 0.0;
-        }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = tid + 256 * (it0 + q);
+        const int c = idx / RPW, rl = idx - c * RPW;
+        pan[c * LDX + rl] = xv[q];
       }
     }
     __syncthreads();
-    // MFMA over this panel: wave wv takes rows [wv*RPW/4, (wv+1)*RPW/4)
+    if constexpr (MODE == 1) {                // Z panel = X panel W (FP64 MFMA), rounded to T
+      for (int rt = wv; rt < RPW / 16; rt += 4) {
+        typename MF::acc_t z[TT];
+#pragma unroll
+        for (int u = 0; u < TT; ++u) z[u] = MF::zero();
+#pragma unroll 2
+        for (int k0 = 0; k0 < F; k0 += 4) {
+          const double a = (double)pan[(k0 + g) * LDX + 16 * rt + r];
+#pragma unroll
+          for (int u = 0; u < TT; ++u) z[u] = MF::op(a, Wl[(k0 + g) * LD + 16 * u + r], z[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < TT; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            pz[(16 * u + r) * LDZ + 16 * rt + MF::row(g, e)] = (double)(T)z[u][e];
+      }
+      __syncthreads();
+      for (int idx = tid; idx < f * RPW; idx += 256) {   // write Z back over X
+        const int c = idx / RPW, rl = idx - c * RPW;
+        const int64_t row = rb + rl;
+        if (row < rows) X[(int64_t)c * ld + row] = (T)pz[c * LDZ + rl];
+      }
+    }
+    // Gram over this panel: wave wv takes rows [wv*RPW/4, (wv+1)*RPW/4)
     constexpr int PW = RPW / 4;
 #pragma unroll
     for (int k0 = 0; k0 < PW; k0 += 16) {
       const int kr = wv * PW + k0 + 4 * g;
       V4<double> a[TT];
 #pragma unroll
-      for (int t = 0; t < TT; ++t) {
-        const P* q = &pan[(16 * t + r) * LDP + kr];
+      for (int t = 0; t < TT; ++t)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[t].v[e] = (double)q[e];
-      }
+        for (int e = 0; e < 4; ++e)
+          a[t].v[e] = MODE == 1 ? pz[(16 * t + r) * LDZ + kr + e] : (double)pan[(16 * t + r) * LDX + kr + e];
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -925,10 +982,9 @@ __global__ __launch_bounds__(256) void k_gram_rows(
           for (int u = t; u < TT; ++u) acc[t][u] = MF::op(a[t].v[v], a[u].v[v], acc[t][u]);
     }
   }
-  // fold the 4 waves (fixed order) through LDS (reuse the panel storage)
+  // fold the 4 waves (fixed order) through LDS
   __syncthreads();
-  double* red = reinterpret_cast<double*>(pan);   // needs TT*TT*256 doubles <= sizeof(pan)
-  static_assert(sizeof(P) * F * LDP >= sizeof(double) * TT * TT * 256, "fold buffer");
+  double* red = ph;
   for (int w = 0; w < 4; ++w) {
     if (wv == w) {
 #pragma unroll
@@ -950,7 +1006,7 @@ __global__ __launch_bounds__(256) void k_gram_rows(
     const int l = idx & 63, e = (idx >> 6) & 3, tu = idx >> 8;
     const int t = tu / TT, u = tu - t * TT;
     if (u < t) continue;
-    const int i = 16 * t + 4 * e + (l >> 4), jj = 16 * u + (l & 15);
+    const int i = 16 * t + MF::row(l >> 4, e), jj = 16 * u + (l & 15);
     if (i < f && jj < f) {
       const double v = red[idx];
       Pw[(int64_t)jj * f + i] = v;
@@ -965,30 +1021,211 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  // fixed-order sum of the partials (loads issued in groups of 8) into LDS
-  // (row-major, leading dimension F), then the Cholesky and stop test
   const int ff = f * f;
-  double* Gl = reinterpret_cast<double*>(pan);
-  static_assert(sizeof(P) * F * LDP >= sizeof(double) * F * F, "Cholesky buffer");
-  const unsigned nb = gridDim.x;
-  for (int idx = tid; idx < ff; idx += 256) {
-    double a = 0.0;
-    unsigned b = 0;
-    for (; b + 8 <= nb; b += 8) {
-      double v[8];
+  double* Gs = ph;                   // G, then R
+  double* Ri = Gs + S::SIZE;         // R^{-1}
+  double* rowbuf = Ri + S::SIZE;     // 4 x 2F
+  double* dgs = rowbuf + 8 * F;
+  {
+    // upper triangle, all partials of an element loaded before summing them
+    // in order b = 0, 1, ...
+    constexpr int EPT = (F * F + 255) / 256;
+    const unsigned nb = gridDim.x;
+    double sum[EPT];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = parts[(int64_t)(b + q) * ff + idx];
+    for (int e = 0; e < EPT; ++e) sum[e] = 0.0;
+    for (unsigned b = 0; b < nb; b += 4) {
+      double v[EPT][4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a += v[q];
+      for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 256 * e;
+        const int c = idx / (f > 0 ? f : 1), rr = idx - c * f;
+        const bool ok = idx < ff && rr <= c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          v[e][q] = (ok && b + q < nb) ? parts[(int64_t)(b + q) * ff + idx] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < EPT; ++e)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sum[e] += v[e][q];
     }
-    for (; b < nb; ++b) a += parts[(int64_t)b * ff + idx];
-    const int c = idx / f, rr = idx - c * f;          // element (rr, c); G is symmetric
-    Gl[rr * F + c] = a;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = tid + 256 * e;
+      const int c = idx / (f > 0 ? f : 1), rr = idx - c * f;
+      if (idx < ff && rr <= c) {
+        Gs[rr * LD + c] = sum[e];
+        Gs[c * LD + rr] = sum[e];
+      }
+    }
   }
   if (tid == 0) *counter = 0u;
+  State* st = ca.st;
+  if (ca.norm_parts && wv == 0) {    // ||A||_F from the sketch partials (fixed order)
+    double a = 0.0;
+    for (int64_t i = lane; i < ca.n_norm; i += 64) a += ca.norm_parts[i];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if (lane == 0) {
+      st->normsq = a;
+      const bool bad = !(a < INFINITY);
+      st->nonfinite = bad ? 1 : 0;
+      st->eps = bad ? 0.0 : st->tol * sqrt(a);
+    }
+  }
+  int dl = 0;
+  if (lane < f && !ca.fresh) dl = ca.dead[lane];
+  const uint64_t dmask_in = __ballot(dl != 0);
   __syncthreads();
-  if (wv != 0) return;
-  chol_wave<F, T>(Gl, f, ca, block_id, MODE == 2 ? Rs : nullptr);
+  uint64_t dmask;
+  int nfl;
+  chol_inv<F>(Gs, Ri, rowbuf, dgs, f, dmask_in, ca.first_pass, &dmask, &nfl);
+  for (int idx = tid; idx < ff; idx += 256) {
+    const int c = idx / f, rr = idx - c * f;          // element (rr, c) at c*f + rr
+    if (ca.R) ca.R[idx] = Gs[rr * LD + c];
+    if (ca.Rinv) ca.Rinv[idx] = Ri[rr * LD + c];
+  }
+  if (tid < f) ca.dead[tid] = (int32_t)((dmask >> tid) & 1ull);
+  if (ca.count_floors && tid == 0 && nfl) atomicAdd(&st->floored, nfl);
+  if (!ca.R1 || wv != 0) return;
+  // stop test (Alg. 1) on wave 0: first column whose |T(c,c)| <= eps
+  const int j = lane;
+  const bool mine = j < f;
+  const double eps = st->eps;
+  double d = 0.0;
+  bool hit = false;
+  if (mine) {
+    d = ((dmask >> j) & 1ull) ? 0.0 : Gs[j * LD + j] * ca.R1[(int64_t)j * f + j];
+    hit = (d <= eps) || st->nonfinite;
+  }
+  const unsigned long long mask = __ballot(hit);
+  const int keep = mask ? (int)__ffsll((long long)mask) - 1 : f;
+  if (mine && j <= keep) ca.diag_log[ca.col0 + j] = d;
+  if (j == 0) {
+    const bool stop = (mask != 0ull) || (ca.col0 + f >= ca.n);
+    ca.acc[block_id] = keep;
+    const int64_t wn = ca.wlog[block_id] + keep;
+    ca.wlog[block_id + 1] = wn;
+    st->rank = wn;
+    if (stop) st->stop_block = block_id;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Z = X W (FP64 MFMA, rounded to T) for one or two jobs (blockIdx.y):
+// X column-major rows x f (ldx), W f x f FP64 (element (i,j) at j*f + i,
+// any shape), Z column-major (ldz), columns zoff .. zoff+ncols-1 written.
+// With zoff_dev / ncols_dev the offset and count are read on the device
+// (the basis append: zoff = wlog[block], ncols = acc[block]).  Each wave
+// computes 16 complete rows, so Z may alias X when zoff = 0 and ldz = ldx.
+// ---------------------------------------------------------------------------
+struct ApplyJob {
+  const void* X;
+  int64_t ldx;
+  void* Z;
+  int64_t ldz;
+  const double* W;
+  int64_t rows, zoff;
+  int f, ncols;
+  const int64_t* zoff_dev;
+  const int32_t* ncols_dev;
+};
+
+template <typename T, int F>
+__global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
+                                               const int32_t* __restrict__ stop_block, int block_id) {
+  typedef Mfma<double> MF;
+  constexpr int TT = F / 16, LD = F + 1, KS = F / 4;
+  if (stop_block && *stop_block < block_id) return;
+  const ApplyJob jb = blockIdx.y == 0 ? j0 : j1;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  if (row0 >= jb.rows) return;
+  __shared__ double Wl[F * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
+  const int f = jb.f;
+  for (int idx = tid; idx < F * F; idx += 256) {
+    const int i = idx / F, jj = idx - i * F;
+    Wl[i * LD + jj] = (i < f && jj < f) ? jb.W[(int64_t)jj * f + i] : 0.0;
+  }
+  const int ncols = jb.ncols_dev ? jb.ncols_dev[block_id] : jb.ncols;
+  const int64_t zoff = jb.zoff_dev ? jb.zoff_dev[block_id] : jb.zoff;
+  const T* X = reinterpret_cast<const T*>(jb.X);
+  T* Z = reinterpret_cast<T*>(jb.Z);
+  const int64_t rbase = row0 + 16 * wv;
+  const int64_t arow = rbase + r;
+  const bool aok = arow < jb.rows;
+  double a[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const int k = 4 * kk + g;
+    a[kk] = (aok && k < f) ? (double)X[(int64_t)k * jb.ldx + arow] : 0.0;
+  }
+  __syncthreads();
+  typename MF::acc_t z[TT];
+#pragma unroll
+  for (int u = 0; u < TT; ++u) z[u] = MF::zero();
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+    for (int u = 0; u < TT; ++u) z[u] = MF::op(a[kk], Wl[(4 * kk + g) * LD + 16 * u + r], z[u]);
+#pragma unroll
+  for (int u = 0; u < TT; ++u) {
+    const int col = 16 * u + r;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = rbase + MF::row(g, e);
+      if (row < jb.rows) Z[(zoff + col) * jb.ldz + row] = (T)z[u][e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Closing QR of Alg. 2 on one workgroup: M = R2 R1 (the two Cholesky factors
+// of the CholeskyQR2 of C^T, f x f, element (i,j) at j*f + i; M = R2 when R1
+// is null), then M^T = Qh Rh by CholeskyQR2 in FP64 (first pass floored,
+// the second kills what stays non-positive).  Qh -> Qout (element (i,j) at
+// j*f + i), Rh = Rh2 Rh1 -> Dout (type T, row-major, ldd).
+// ---------------------------------------------------------------------------
+template <typename T, int F>
+__global__ __launch_bounds__(256) void k_small_qr(const double* __restrict__ R1g,
+                                                  const double* __restrict__ R2g, int f,
+                                                  double* __restrict__ Qout, T* __restrict__ Dout,
+                                                  int64_t ldd, State* st, int count_floors) {
+  typedef SmallCfg<F> S;
+  constexpr int LD = S::LD;
+  __shared__ double B0[S::SIZE], B1[S::SIZE], B2[S::SIZE], B3[S::SIZE];
+  __shared__ double rowbuf[8 * F], dgs[F];
+  const int tid = threadIdx.x;
+  double* Mt = R1g ? B1 : B0;
+  for (int idx = tid; idx < F * F; idx += 256) {
+    const int i = idx / F, jj = idx - i * F;
+    const bool ok = i < f && jj < f;
+    Mt[i * LD + jj] = ok ? R2g[(int64_t)jj * f + i] : 0.0;
+    if (R1g) B2[i * LD + jj] = ok ? R1g[(int64_t)jj * f + i] : 0.0;
+  }
+  __syncthreads();
+  if (R1g) {
+    lds_gemm<F, false, false>(B1, B2, [&](int i, int jj, double v) { B0[i * LD + jj] = v; });  // M
+    __syncthreads();
+  }
+  lds_gemm<F, false, true>(B0, B0, [&](int i, int jj, double v) { B1[i * LD + jj] = v; });   // M M^T
+  __syncthreads();
+  uint64_t dm1, dm2;
+  int nf1, nf2;
+  chol_inv<F>(B1, B2, rowbuf, dgs, f, 0ull, 1, &dm1, &nf1);                 // Rh1 (B1), Rh1^{-1} (B2)
+  lds_gemm<F, true, false>(B0, B2, [&](int i, int jj, double v) { B3[i * LD + jj] = v; });   // Z1 = M^T Rh1^{-1}
+  __syncthreads();
+  lds_gemm<F, true, false>(B3, B3, [&](int i, int jj, double v) { B0[i * LD + jj] = v; });   // Z1^T Z1
+  __syncthreads();
+  chol_inv<F>(B0, B2, rowbuf, dgs, f, dm1, 0, &dm2, &nf2);                  // Rh2 (B0), Rh2^{-1} (B2)
+  lds_gemm<F, false, false>(B3, B2, [&](int i, int jj, double v) {          // Qh = Z1 Rh2^{-1}
+    if (i < f && jj < f) Qout[(int64_t)jj * f + i] = v;
+  });
+  lds_gemm<F, false, false>(B0, B1, [&](int i, int jj, double v) {          // Rh = Rh2 Rh1
+    if (i < f && jj < f) Dout[(int64_t)i * ldd + jj] = (T)v;
+  });
+  if (count_floors && tid == 0 && nf1 + nf2) atomicAdd(&st->floored, nf1 + nf2);
 }
 
 // Same algorithm with G in global memory (large f); G is overwritten.
@@ -1055,51 +1292,11 @@ __global__ __launch_bounds__(256) void k_cholesky_global(
 }
 
 // ---------------------------------------------------------------------------
-// Z = X R^{-1} row by row (forward substitution in FP64):
-//   z_c = (x_c - sum_{k<c} z_k R(k,c)) / R(c,c).
-// X element (i, c) at c*ldx + i; Z likewise (ldz); may alias X.
-// R (f x f, element (i,j) at j*f + i) staged in LDS when small.
-// Only columns c < ncols_out(_dev) are written, at Z + (zoff(_dev) + c)*ldz:
-// for the basis append, zoff = wlog[block_id] and ncols_out = acc[block_id].
+// Z = X R^{-1} row by row (forward substitution in FP64) for blocks wider
+// than 64 columns:  z_c = (x_c - sum_{k<c} z_k R(k,c)) / R(c,c).
+// X element (i, c) at c*ldx + i; Z likewise (ldz), out of place; R (f x f,
+// element (i,j) at j*f + i) read through the cache.  Columns c < ncols_out.
 // ---------------------------------------------------------------------------
-template <typename Tin, typename Tout, int FMAX>
-__global__ __launch_bounds__(64) void k_trsm_rows(
-    const Tin* __restrict__ X, int64_t ldx, Tout* __restrict__ Zo, int64_t ldz, int64_t m,
-    int f, const double* __restrict__ R, int64_t zoff, int ncols_out,
-    const int64_t* __restrict__ wlog, const int32_t* __restrict__ acc_dev,
-    const int32_t* __restrict__ stop_block, int block_id) {
-  if (stop_block && *stop_block < block_id) return;
-  if (wlog) zoff = wlog[block_id];
-  if (acc_dev) ncols_out = acc_dev[block_id];
-  __shared__ double Rs[FMAX * FMAX];
-  __shared__ double rinv[FMAX];
-  __shared__ double zs[FMAX * 65];               // zs[c*65 + thread]
-  for (int idx = threadIdx.x; idx < f * f; idx += blockDim.x) Rs[idx] = R[idx];
-  for (int c = threadIdx.x; c < f; c += blockDim.x) rinv[c] = 1.0 / R[(int64_t)c * f + c];
-  const int t = threadIdx.x;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + t;
-  const bool ok = i < m;
-  for (int c0 = 0; c0 < f; c0 += 8) {            // row loads, 8 in flight
-    Tin xv[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) xv[q] = (c0 + q < f && ok) ? X[(int64_t)(c0 + q) * ldx + i] : (Tin)0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (c0 + q < FMAX) zs[(c0 + q) * 65 + t] = (double)xv[q];
-  }
-  __syncthreads();
-  // z_c = (x_c - sum_{k<c} z_k R(k,c)) / R(c,c)
-  for (int c = 0; c < f; ++c) {
-    double v = zs[c * 65 + t];
-#pragma unroll 4
-    for (int k = 0; k < c; ++k) v -= zs[k * 65 + t] * Rs[c * f + k];
-    zs[c * 65 + t] = v * rinv[c];
-  }
-  if (!ok) return;
-  for (int c = 0; c < ncols_out; ++c) Zo[(zoff + c) * ldz + i] = (Tout)zs[c * 65 + t];
-}
-
-// Large-f variant: R read from global memory (L2), z kept in global scratch.
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void k_trsm_rows_big(
     const Tin* __restrict__ X, int64_t ldx, Tout* __restrict__ Zo, int64_t ldz, int64_t m,

@@ -204,6 +204,22 @@ def test_factor_wide_matrix():
     check_factor(A, torch.float64, 1e-9, b=8, seed=4)
 
 
+def test_factor_wide_high_rank():
+    # m < n with rank above 64: the closing QR of D'^T takes the wide path
+    A = W.lowrank_haar(5, m=100, n=260, r=80, noise_std=0.0)
+    check_factor(A, torch.float64, 1e-9, b=32, seed=5)
+
+
+@pytest.mark.parametrize("b", [24, 48])
+def test_factor_multi_block_wide_blocks(b):
+    # several blocks of 17..64 columns (Cholesky kernels of width 32 and 64),
+    # each later block projected against the basis before and after its
+    # first Cholesky pass
+    A = W.lowrank_haar(11, m=600, n=300, r=100, noise_std=1e-11)
+    f, ref = check_factor(A, torch.float64, 1e-8, b=b, seed=11)
+    assert f.blocks >= 3
+
+
 def test_factor_full_rank_ragged():
     A = np.random.default_rng(0).standard_normal((333, 70))
     f, ref = check_factor(A, torch.float64, 1e-13, b=16, seed=2)

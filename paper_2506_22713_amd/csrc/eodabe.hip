@@ -30,7 +30,7 @@ struct eodabe_ctx {
   bool host_only;
   // live timing (eodabe_profile)
   bool prof_on = false;
-  struct Mark { hipEvent_t a, b; int kind; int block; double bytes; };
+  struct Mark { hipEvent_t a, b; int kind; int block; double bytes, bytes_per_r; };
   std::vector<hipEvent_t> ev_pool;
   std::vector<Mark> marks;
   double prof_ms[EODABE_PROF_KINDS] = {0, 0};
@@ -108,18 +108,22 @@ hipEvent_t prof_event(eodabe_ctx* ctx) {
 }
 int prof_begin(eodabe_ctx* ctx, hipStream_t st) {
   if (!ctx->prof_on) return -1;
-  eodabe_ctx::Mark mk{prof_event(ctx), prof_event(ctx), 0, 0, 0.0};
+  eodabe_ctx::Mark mk{prof_event(ctx), prof_event(ctx), 0, 0, 0.0, 0.0};
   if (!mk.a || !mk.b) return -1;
   (void)st;
   ctx->marks.push_back(mk);
   return (int)ctx->marks.size() - 1;
 }
-void prof_end(eodabe_ctx* ctx, hipStream_t st, int id, int kind, int block, double bytes) {
+// Marks of closing steps enqueued ahead of the stop flag carry SPEC_BLOCK.
+constexpr int SPEC_BLOCK = -2;
+void prof_end(eodabe_ctx* ctx, hipStream_t st, int id, int kind, int block, double bytes,
+              double bytes_per_r = 0.0) {
   if (id < 0) return;
   auto& mk = ctx->marks[id];
   mk.kind = kind;
   mk.block = block;
   mk.bytes = bytes;
+  mk.bytes_per_r = bytes_per_r;
   (void)st;
 }
 // Attach (or detach, id < 0) the events of mark id to the next timed launch.
@@ -128,16 +132,19 @@ void prof_attach(eodabe_ctx* ctx, O& ops, int id) {
   ops.pe0 = id >= 0 ? ctx->marks[id].a : nullptr;
   ops.pe1 = id >= 0 ? ctx->marks[id].b : nullptr;
 }
-// After the stream has been synchronised: fold the marks of blocks that ran
-// (block <= last_block) into the totals and recycle the events.
-void prof_collect(eodabe_ctx* ctx, int last_block) {
+// After the stream has been synchronised: fold the marks of launches that
+// did their work (blocks <= last_block; speculative closing steps only when
+// spec_ran) into the totals and recycle the events.  rank sizes the
+// rank-dependent bytes.
+void prof_collect(eodabe_ctx* ctx, int last_block, bool spec_ran, int64_t rank) {
   for (auto& mk : ctx->marks) {
-    if (mk.block <= last_block) {
+    const bool ran = mk.block == SPEC_BLOCK ? spec_ran : (mk.block >= 0 && mk.block <= last_block);
+    if (ran) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, mk.a, mk.b) == hipSuccess) {
         ctx->prof_ms[mk.kind] += ms;
         ctx->prof_n[mk.kind] += 1;
-        ctx->prof_bytes[mk.kind] += mk.bytes;
+        ctx->prof_bytes[mk.kind] += mk.bytes + mk.bytes_per_r * (double)rank;
       }
     }
     ctx->ev_pool.push_back(mk.a);
@@ -341,8 +348,10 @@ struct Ops {
     return 0;
   }
 
+  // M_dev: row count read on the device (M is then its host-side bound).
   int gemm_nn(const T* X, int64_t ldx, const T* Z, int64_t ldz, int64_t M, int64_t N, int64_t K,
-              int splits, T* out, int64_t ldo, int64_t part_stride) {
+              int splits, T* out, int64_t ldo, int64_t part_stride, Gate gate = Gate{},
+              const int64_t* M_dev = nullptr) {
     if (M <= 0 || N <= 0) return 0;
     const int64_t kchunk = split_chunk(K, splits);
     splits = eff_splits(K, splits);
@@ -352,7 +361,7 @@ struct Ops {
     dim3 grid((unsigned)cdiv(N, 256), splits, (unsigned)cdiv(M, 16 * rt));
 #define NN_CASE(RR)                                                                                   \
   hipExtLaunchKernelGGL((k_gemm_nn<T, RR>), grid, dim3(256), 0, st, pe0, pe1, 0, X, ldx, Z, ldz, M, N, \
-                        K, kchunk, out, ldo, part_stride)
+                        K, kchunk, out, ldo, part_stride, gate, M_dev)
     if (rt == 1) NN_CASE(1);
     else if (rt == 2) NN_CASE(2);
     else if (rt == 3) NN_CASE(3);
@@ -364,22 +373,22 @@ struct Ops {
 
   template <typename U>
   int reduce(const U* parts, int nparts, int64_t stride, int64_t count, U* out,
-             const int32_t* stopb = nullptr, int blk = 0) {
+             const int32_t* stopb = nullptr, int blk = 0, Gate gate = Gate{}) {
     if (count <= 0) return 0;
     unsigned nb = (unsigned)std::min<int64_t>(cdiv(count, 256), 4096);
     hipLaunchKernelGGL((k_reduce_parts<U>), dim3(nb), dim3(256), 0, st, parts, nparts, stride, count,
-                       out, stopb, blk);
+                       out, stopb, blk, gate);
     LAUNCHCHK();
     return 0;
   }
 
   template <typename U>
   int reduce_wide(const U* parts, int nparts, int64_t stride, int64_t count, U* out,
-                  const int32_t* stopb = nullptr, int blk = 0) {
+                  const int32_t* stopb = nullptr, int blk = 0, Gate gate = Gate{}) {
     if (count <= 0) return 0;
-    if (nparts <= 4) return reduce(parts, nparts, stride, count, out, stopb, blk);
+    if (nparts <= 4) return reduce(parts, nparts, stride, count, out, stopb, blk, gate);
     hipLaunchKernelGGL((k_reduce_parts_wide<U>), dim3((unsigned)cdiv(count, 64)), dim3(64, 16), 0, st,
-                       parts, nparts, stride, count, out, stopb, blk);
+                       parts, nparts, stride, count, out, stopb, blk, gate);
     LAUNCHCHK();
     return 0;
   }
@@ -396,18 +405,18 @@ struct Ops {
 
   // Z = X W for blocks of f <= 64 columns (one job, or two in one launch).
   int apply(const ApplyJob& j0, const ApplyJob* j1, int f, const int32_t* stopb = nullptr,
-            int blk = 0) {
+            int blk = 0, Gate gate = Gate{}) {
     if (f <= 0) return 0;
     const int64_t rows = std::max<int64_t>(j0.rows, j1 ? j1->rows : 0);
     if (rows <= 0) return 0;
     dim3 grid((unsigned)cdiv(rows, 64), j1 ? 2 : 1);
     const ApplyJob jb = j1 ? *j1 : j0;
     if (f <= 16)
-      hipLaunchKernelGGL((k_apply<T, 16>), grid, dim3(256), 0, st, j0, jb, stopb, blk);
+      hipLaunchKernelGGL((k_apply<T, 16>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else if (f <= 32)
-      hipLaunchKernelGGL((k_apply<T, 32>), grid, dim3(256), 0, st, j0, jb, stopb, blk);
+      hipLaunchKernelGGL((k_apply<T, 32>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else
-      hipLaunchKernelGGL((k_apply<T, 64>), grid, dim3(256), 0, st, j0, jb, stopb, blk);
+      hipLaunchKernelGGL((k_apply<T, 64>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     LAUNCHCHK();
     return 0;
   }
@@ -522,7 +531,7 @@ int cholqr2(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, T* X, in
     CholArgs c2 = chol_args(w, w.rb2, w.deadbig, 0, 0, 1);
     c2.Rinv = w.rb5;
     TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, c2, nullptr, 0, w.rb3));
-    const ApplyJob a{X, ld, Zout, ldz, w.rb5, rows, 0, f, f, nullptr, nullptr};
+    const ApplyJob a{X, ld, Zout, ldz, w.rb5, rows, 0, f, f, nullptr, nullptr, nullptr};
     TRY(ops.apply(a, nullptr, f));
     return 0;
   }
@@ -569,9 +578,14 @@ int copy2d(eodabe_ctx* ctx, hipStream_t st, const T* src, int64_t lds, T* dst, i
 
 // Alg. 1 on the (already oriented) mm x nn matrix Ae.  On return the basis
 // is in w.q (column-major, ld g.ldy) and *rank holds its width.
-template <typename T>
+// after_chunk(jend) is called once the blocks [.., jend) are enqueued and
+// before the host reads the stop flag; it returns 1 if it enqueued the
+// (gated) closing steps, 0 if not, < 0 on error.  *spec_ran tells whether
+// such closing steps ran to completion for the chunk that ended the loop.
+template <typename T, typename Hook>
 int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, double tol,
-              int64_t* rank, int* blocks, double* norm_a) {
+              int64_t* rank, int* blocks, double* norm_a, Hook&& after_chunk, bool* spec_ran) {
+  *spec_ran = false;
   Ops<T> ops{ctx, st};
   const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
   const int nwlog = (int)(g.nblk + 2);
@@ -660,7 +674,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
         TRY(gram_chol<T>(ctx, st, w, y, g.ldy, g.mm, f, w.gpart, ca, stopb, blk,
                          (fuse && pass == 1) ? w.r1inv : nullptr));
         if (pass == 0 && small && !fuse) {
-          const ApplyJob a{y, g.ldy, y, g.ldy, w.r1inv, g.mm, 0, f, f, nullptr, nullptr};
+          const ApplyJob a{y, g.ldy, y, g.ldy, w.r1inv, g.mm, 0, f, f, nullptr, nullptr, nullptr};
           TRY(ops.apply(a, nullptr, f, stopb, blk));
         }
         if (pass == 0 && !small) {
@@ -670,7 +684,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       }
       // a6: append P = Z R2^{-1} (accepted columns) into Q at column wlog[j]
       if (small) {
-        const ApplyJob a{y, g.ldy, q, g.ldy, w.r2inv, g.mm, 0, f, 0, w.wlog, w.accv};
+        const ApplyJob a{y, g.ldy, q, g.ldy, w.r2inv, g.mm, 0, f, 0, w.wlog, w.accv, nullptr};
         TRY(ops.apply(a, nullptr, f, stopb, blk));
       } else {
         // large blocks: solve into scratch, then copy the accepted columns
@@ -683,14 +697,21 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
         TRY(copy2d<T>(ctx, st, (T*)w.tbig, g.ldy, q + wj * g.ldy, g.ldy, f, g.ldy, 0));
       }
     }
+    const int spec = after_chunk(j);
+    if (spec < 0) return spec;
     // host check of the stop flag (one small D2H copy per chunk)
     HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (ctx->host_state->nonfinite) return EODABE_ENONFINITE;
-    if (ctx->host_state->stop_block != 0x7fffffff || j >= g.nblk) finished = true;
+    const State& hs = *ctx->host_state;
+    if (hs.stop_block != 0x7fffffff || j >= g.nblk) finished = true;
+    // the gated closing steps ran iff the loop stopped with a finite norm
+    // and 0 < rank <= r_cap (the gate of those kernels)
+    const bool ran = spec == 1 && hs.stop_block != 0x7fffffff && !hs.nonfinite && hs.rank > 0 &&
+                     hs.rank <= g.r_cap;
     if (ctx->prof_on)
-      prof_collect(ctx, ctx->host_state->stop_block != 0x7fffffff ? ctx->host_state->stop_block
-                                                                   : (int)g.nblk);
+      prof_collect(ctx, hs.stop_block != 0x7fffffff ? hs.stop_block : (int)g.nblk, ran, hs.rank);
+    if (hs.nonfinite) return EODABE_ENONFINITE;
+    if (finished) *spec_ran = ran;
     if (ctx->o.blocks_per_sync <= 0) per_sync = std::min(per_sync * 2, 4);
   }
   int64_t r = 0;
@@ -712,17 +733,80 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
 // R_hat -> Dout (type T, row-major ldd); floored pivots counted in st.
 template <typename T>
 int small_qr(eodabe_ctx* ctx, hipStream_t st, const double* R1, const double* R2, int f, double* Qout, T* Dout,
-             int64_t ldd, State* state) {
+             int64_t ldd, State* state, Gate gate = Gate{}, const int64_t* f_dev = nullptr) {
   if (f <= 0) return 0;
   if (f <= 16)
-    hipLaunchKernelGGL((k_small_qr<T, 16>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1);
+    hipLaunchKernelGGL((k_small_qr<T, 16>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1,
+                       gate, f_dev);
   else if (f <= 32)
-    hipLaunchKernelGGL((k_small_qr<T, 32>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1);
+    hipLaunchKernelGGL((k_small_qr<T, 32>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1,
+                       gate, f_dev);
   else if (f <= 64)
-    hipLaunchKernelGGL((k_small_qr<T, 64>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1);
+    hipLaunchKernelGGL((k_small_qr<T, 64>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1,
+                       gate, f_dev);
   else
     return EODABE_EINVAL;
   LAUNCHCHK();
+  return 0;
+}
+
+// K-splits of the r x nn products over mm rows: about 1024 waves, bounded
+// by the partial buffer (planned for r_cap) and by 256 rows per split.
+int core_splits(const Geo& g, int64_t r) {
+  const int64_t tiles = cdiv(g.nn, 256) * cdiv(r, 16 * std::min<int64_t>(4, cdiv(r, 16)));
+  int64_t sc = std::max<int64_t>(1, cdiv(256, tiles));
+  sc = std::min<int64_t>(sc, std::max<int64_t>(1, g.mm / 256));
+  sc = std::min<int64_t>(sc, std::max<int64_t>(1, ((int64_t)g.s_core * std::max<int64_t>(g.r_cap, 1)) / r));
+  return (int)std::min<int64_t>(sc, 1024);
+}
+
+// a9-a11 of Alg. 2 for a rank of at most 64: C = Q^T A; C^T = V R by
+// CholeskyQR2 (R = R2 R1 in rb2, rb1; V = (C^T R1^{-1}) R2^{-1}); R^T =
+// Q_hat R_hat on one workgroup (Q_hat -> rb4, D_hat = R_hat -> Dout); V and
+// U_hat = Q Q_hat in one launch.  r bounds the rank (template widths and
+// partial layouts); with r_dev the exact rank is read on the device and
+// gate holds every kernel until the basis loop has stopped (closing steps
+// enqueued before the host has seen the stop flag).  prof_block tags the
+// timed projection (SPEC_BLOCK for gated launches).
+template <typename T>
+int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, int64_t r,
+                Gate gate, const int64_t* r_dev, T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout,
+                int64_t ldd, int prof_block) {
+  if (r <= 0 || r > 64) return EODABE_EINVAL;
+  Ops<T> ops{ctx, st};
+  T* q = (T*)w.q;
+  T* cb = (T*)w.cbuf;
+  const int64_t cstride = r * g.ldk;
+  const int s_core = core_splits(g, r);
+  // a9: C = Q^T A (r x nn, row-major ld ldk)
+  const int pid = prof_begin(ctx, st);
+  prof_attach(ctx, ops, pid);
+  TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride, gate,
+                  r_dev));
+  prof_attach(ctx, ops, -1);
+  // algorithmic bytes: A once, Q (mm x r) and C (r x nn) once
+  if (r_dev)
+    prof_end(ctx, st, pid, EODABE_PROF_PROJECT, prof_block, (double)g.elem * g.mm * g.nn,
+             (double)g.elem * (g.mm + g.nn));
+  else
+    prof_end(ctx, st, pid, EODABE_PROF_PROJECT, prof_block,
+             (double)g.elem * ((double)g.mm * g.nn + (double)g.mm * r + (double)r * g.nn));
+  TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb, nullptr, 0,
+                      gate));
+  CholArgs c1 = chol_args(w, w.rb1, w.deadbig, 1, 1, 1);
+  c1.Rinv = w.rb3;
+  c1.gate = gate;
+  c1.f_dev = r_dev;
+  TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c1));
+  CholArgs c2 = chol_args(w, w.rb2, w.deadbig, 0, 0, 1);
+  c2.Rinv = w.rb5;
+  c2.gate = gate;
+  c2.f_dev = r_dev;
+  TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c2, nullptr, 0, w.rb3));
+  TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st, gate, r_dev));
+  const ApplyJob jv{cb, g.ldk, Vout, ldv, w.rb5, g.nn, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
+  const ApplyJob ju{q, g.ldy, Uout, ldu, w.rb4, g.mm, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
+  TRY(ops.apply(jv, &ju, (int)r, nullptr, 0, gate));
   return 0;
 }
 
@@ -737,13 +821,7 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   T* q = (T*)w.q;
   T* cb = (T*)w.cbuf;
   const int64_t cstride = r * g.ldk;
-  // K-splits of the r x nn products over mm rows: about 1024 waves, bounded
-  // by the partial buffer (planned for r_cap) and by 256 rows per split.
-  const int64_t tiles = cdiv(g.nn, 256) * cdiv(r, 16 * std::min<int64_t>(4, cdiv(r, 16)));
-  int64_t sc = std::max<int64_t>(1, cdiv(256, tiles));
-  sc = std::min<int64_t>(sc, std::max<int64_t>(1, g.mm / 256));
-  sc = std::min<int64_t>(sc, std::max<int64_t>(1, ((int64_t)g.s_core * std::max<int64_t>(g.r_cap, 1)) / r));
-  const int s_core = (int)std::min<int64_t>(sc, 1024);
+  const int s_core = core_splits(g, r);
   for (int it = 0; it < ctx->o.power_iters; ++it) {
     // Y~^T = Q^T A (r x nn), QR(Y~) -> Q~ (stored as Q~^T = cbuf rows)
     TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
@@ -753,6 +831,8 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
     TRY(ops.template gemm_nt<T>(Ae, g.lda_eff, cb, g.ldk, g.mm, r, g.nn, 1, q, g.ldy, g.ldy * r));
     TRY(cholqr2<T>(ctx, st, g, w, q, g.ldy, g.mm, (int)r, w.rb4, 0, (T*)w.tbig));
   }
+  if (r <= 64)
+    return close_small<T>(ctx, st, g, w, Ae, r, Gate{}, nullptr, Uout, ldu, Vout, ldv, Dout, ldd, 0);
   // a9: C = Q^T A (r x nn, row-major ld ldk)
   const int pid = prof_begin(ctx, st);
   prof_attach(ctx, ops, pid);
@@ -761,22 +841,6 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   prof_end(ctx, st, pid, EODABE_PROF_PROJECT, 0,
            (double)g.elem * ((double)g.mm * g.nn + (double)g.mm * r + (double)r * g.nn));
   TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb));
-  if (r <= 64) {
-    // a10: C^T = V R by CholeskyQR2, R = R2 R1 (rb2, rb1), V = (C^T R1^{-1}) R2^{-1};
-    // a11: R^T = Q_hat R_hat on one workgroup (Q_hat -> rb4, D_hat = R_hat -> Dout);
-    // V and U_hat = Q Q_hat in one launch.
-    CholArgs c1 = chol_args(w, w.rb1, w.deadbig, 1, 1, 1);
-    c1.Rinv = w.rb3;
-    TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c1));
-    CholArgs c2 = chol_args(w, w.rb2, w.deadbig, 0, 0, 1);
-    c2.Rinv = w.rb5;
-    TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c2, nullptr, 0, w.rb3));
-    TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st));
-    const ApplyJob jv{cb, g.ldk, Vout, ldv, w.rb5, g.nn, 0, (int)r, (int)r, nullptr, nullptr};
-    const ApplyJob ju{q, g.ldy, Uout, ldu, w.rb4, g.mm, 0, (int)r, (int)r, nullptr, nullptr};
-    TRY(ops.apply(jv, &ju, (int)r));
-    return 0;
-  }
   // a10: C^T = V R  (C^T is nn x r with element (j,a) at a*ldk + j = cbuf);
   //      V^T rows go straight to Vout, R^T (row-major R) to rb4 as a
   //      column-major r x r matrix.
@@ -995,7 +1059,20 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
       TRY(copy2d<T>(ctx, st, (const T*)A, lda, (T*)w.apack, g.lda_eff, g.mm, g.nn, g.transposed ? 1 : 0));
       Ae = (const T*)w.apack;
     }
-    TRY(run_basis<T>(ctx, st, g, w, Ae, tol, &rank, &blocks, &norm_a));
+    // With a small enough basis the closing steps are enqueued right behind
+    // each chunk of blocks, gated on the device-side stop flag, so a
+    // factorization that stops in its first chunk needs one host sync.
+    const bool can_spec = !g.transposed && !basis_only && ctx->o.power_iters == 0;
+    auto after_chunk = [&](int64_t jend) -> int {
+      if (!can_spec) return 0;
+      const int64_t rb = std::min<int64_t>(g.nn, jend * (int64_t)g.b);
+      if (rb <= 0 || rb > 64) return 0;
+      TRY(close_small<T>(ctx, st, g, w, Ae, rb, Gate{w.st, g.r_cap}, &w.st->rank, (T*)Ut, m, (T*)Vt,
+                         n, (T*)core, g.r_cap, SPEC_BLOCK));
+      return 1;
+    };
+    bool spec_ran = false;
+    TRY(run_basis<T>(ctx, st, g, w, Ae, tol, &rank, &blocks, &norm_a, after_chunk, &spec_ran));
     info->rank = rank;
     info->blocks = blocks;
     info->norm_a = norm_a;
@@ -1016,8 +1093,12 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
       HIPCHK(hipStreamSynchronize(st));
       return 0;
     }
+    if (spec_ran) {                  // closing steps done; the state was read after them
+      if (ctx->host_state->floored) info->status_flags |= 4;
+      return 0;
+    }
     if (!g.transposed) {
-      TRY(run_close<T>(ctx, st, g, w, Ae, rank, (T*)Ut, m, (T*)Vt, n, (T*)core, r_cap));
+      TRY(run_close<T>(ctx, st, g, w, Ae, rank, (T*)Ut, m, (T*)Vt, n, (T*)core, g.r_cap));
     } else {
       // factor of A^T = U' D' V'^T (U' nn... here mm = n rows): A = V' D'^T U'^T.
       // U' -> ybig (column-major n x r), V'^T -> cbuf (r x m), D' -> rb_tmp
@@ -1031,8 +1112,8 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
         hipLaunchKernelGGL((k_copy2d<T, double>), gt, dim3(32, 8), 0, st, (const T*)w.tbig, rank, w.rb2,
                            rank, rank, rank, 1);
         LAUNCHCHK();
-        TRY(small_qr<T>(ctx, st, nullptr, w.rb2, (int)rank, w.rb4, (T*)core, r_cap, w.st));
-        const ApplyJob ju{w.cbuf, g.ldk, Ut, m, w.rb4, m, 0, (int)rank, (int)rank, nullptr, nullptr};
+        TRY(small_qr<T>(ctx, st, nullptr, w.rb2, (int)rank, w.rb4, (T*)core, g.r_cap, w.st));
+        const ApplyJob ju{w.cbuf, g.ldk, Ut, m, w.rb4, m, 0, (int)rank, (int)rank, nullptr, nullptr, nullptr};
         TRY(ops.apply(ju, nullptr, (int)rank));
         TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));
       } else {
@@ -1047,14 +1128,14 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
         // Vt_out = U'^T : U' column-major n x r (ld ldy) -> row a = column a
         TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));
         dim3 grid((unsigned)cdiv(rank, 32), (unsigned)cdiv(rank, 32));
-        hipLaunchKernelGGL((k_copy2d<double, T>), grid, dim3(32, 8), 0, st, w.rb3, rank, (T*)core, r_cap,
+        hipLaunchKernelGGL((k_copy2d<double, T>), grid, dim3(32, 8), 0, st, w.rb3, rank, (T*)core, g.r_cap,
                            rank, rank, 1);
         LAUNCHCHK();
       }
     }
     HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (ctx->prof_on) prof_collect(ctx, 0x7fffffff);
+    if (ctx->prof_on) prof_collect(ctx, 0x7fffffff, false, rank);
     if (ctx->host_state->floored) info->status_flags |= 4;
     return 0;
   };

@@ -25,6 +25,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int WAVE = 64;
 constexpr double U64 = 1.1102230246251565e-16;   // 2^-53
 constexpr double FLOOR_C = 64.0;                 // pivot floor: FLOOR_C * u64 * G(k,k)
+constexpr double PIV_MIN = 1e-290;               // smaller pivots count as non-positive (1/p overflows)
 
 // Control block shared by the kernels of one factorization (device memory).
 struct State {
@@ -38,6 +39,20 @@ struct State {
   int64_t rank;          // basis width after the latest decided block
   uint32_t counter[8];   // arrival counters (reset by the last arriving workgroup)
 };
+
+// Gate of closing-step kernels enqueued before the host has seen the stop
+// flag of the basis loop: they run only once the loop has stopped, ||A||_F
+// is finite and the rank r satisfies 0 < r <= r_cap; otherwise every such
+// kernel returns at once (a later, host-checked launch takes over).
+struct Gate {
+  const State* st;       // null: always open
+  int64_t r_cap;
+};
+__device__ __forceinline__ bool gate_shut(const Gate& g) {
+  if (!g.st) return false;
+  return g.st->stop_block == 0x7fffffff || g.st->nonfinite != 0 || g.st->rank <= 0 ||
+         g.st->rank > g.r_cap;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11) and Box-Muller.
@@ -473,8 +488,10 @@ template <typename T, int RT>
 __global__ __launch_bounds__(256) void k_gemm_nn(
     const T* __restrict__ X, int64_t ldx, const T* __restrict__ Z, int64_t ldz,
     int64_t M, int64_t N, int64_t K, int64_t kchunk, T* __restrict__ out, int64_t ldo,
-    int64_t part_stride) {
+    int64_t part_stride, Gate gate, const int64_t* __restrict__ M_dev) {
   typedef Mfma<T> MF;
+  if (gate_shut(gate)) return;
+  if (M_dev) M = *M_dev;                // row count known on the device only
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int64_t j0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
@@ -547,8 +564,9 @@ __global__ __launch_bounds__(256) void k_gemm_nn(
 template <typename T>
 __global__ void k_reduce_parts(const T* __restrict__ parts, int nparts, int64_t stride,
                                int64_t count, T* __restrict__ out,
-                               const int32_t* __restrict__ stop_block, int block_id) {
+                               const int32_t* __restrict__ stop_block, int block_id, Gate gate) {
   if (stop_block && *stop_block < block_id) return;
+  if (gate_shut(gate)) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
     T acc = parts[i];
@@ -565,8 +583,9 @@ __global__ __launch_bounds__(1024) void k_reduce_parts_wide(const T* __restrict_
                                                            int64_t stride, int64_t count,
                                                            T* __restrict__ out,
                                                            const int32_t* __restrict__ stop_block,
-                                                           int block_id) {
+                                                           int block_id, Gate gate) {
   if (stop_block && *stop_block < block_id) return;
+  if (gate_shut(gate)) return;
   __shared__ T red[16][64];
   const int64_t i = blockIdx.x * (int64_t)64 + threadIdx.x;
   T acc = 0;
@@ -707,28 +726,69 @@ __device__ __forceinline__ void lds_gemm(const double* A, const double* B, Out o
 //   Step k: pivot p = S(k,k) of the current Schur complement S;
 //     dead column (flag in dmask_in): R(k,k) = 1, row k and column k of R
 //       zero, no elimination;
-//     p <= FLOOR_C u64 G(k,k) or not finite: floored to that value on a
-//       first pass (R(k,k) = sqrt(floor), rest of row k zero, no
-//       elimination) and marked dead otherwise (R(k,k) = 1);
+//     p <= FLOOR_C u64 G(k,k), p <= PIV_MIN or not finite: floored to
+//       FLOOR_C u64 G(k,k) on a first pass (R(k,k) = sqrt(floor), rest of
+//       row k zero, no elimination) and marked dead otherwise (R(k,k) = 1);
 //     else R(k,k) = sqrt(p), R(k,c) = S(k,c)/R(k,k) for live c > k, and
 //       every later row i subtracts S(k,i)/p times row k (dead columns of
 //       the left half excluded).
 // Layout: 64 lanes x 4 waves; lane c holds column c of [G | I] (two columns
 // per lane when F = 64), wave w rows 4(g+s)+w in slot s during group g of
 // four steps, so the pivot row of step 4g+u is slot 0 of wave u; the slots
-// move down by one after each group.  Row k goes through LDS (rowbuf), one
-// barrier per step.
+// move down by one after each group.  Row k and its pivot scalars (alpha,
+// 1/alpha, 1/p, status) go through LDS (rowbuf[k mod 4]) with one barrier
+// per step; the wave holding row k+1 updates and publishes it first, so
+// the square root of the next pivot overlaps the rest of the update.
 // Gs: G on entry (row-major, ld F+1), R on exit (zero below the diagonal
 // and in rows >= f); Ri: R^{-1} on exit (zero in columns >= f); rowbuf:
-// 4 x 2F doubles; dgs: F doubles.  Returns the dead mask after the sweep
-// and the number of floored pivots (uniform over the workgroup).
+// 4 x (2F+4) doubles; dgs: F doubles.  Returns the dead mask after the
+// sweep and the number of floored pivots (uniform over the workgroup).
 // ---------------------------------------------------------------------------
+template <int F>
+__device__ __forceinline__ void publish_row(double* rb, const double (&row)[(2 * F + 63) / 64], int k,
+                                            double dgk, bool dead_k, int first_pass) {
+  constexpr int NCL = (2 * F + 63) / 64, W2 = 2 * F;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < NCL; ++q) {
+    const int c = lane + 64 * q;
+    if (c < W2) rb[c] = row[q];
+  }
+  if (lane == k) {                       // lane k holds S(k,k) (k < F <= 64)
+    const double piv = row[0];
+    const double flo = FLOOR_C * U64 * dgk;
+    double fl = 0.0, alpha, ia, ip = 0.0;
+    if (dead_k) {
+      fl = 2.0;
+      alpha = 1.0;
+      ia = 1.0;
+    } else if (!(piv > flo) || !(piv > PIV_MIN) || !(piv < INFINITY)) {
+      fl = first_pass ? 1.0 : 2.0;
+      alpha = first_pass ? sqrt(flo > 1e-300 ? flo : 1e-300) : 1.0;
+      ia = 1.0 / alpha;
+    } else {
+      // 1/sqrt(p): hardware estimate and two Newton steps (about 1 ulp)
+      double y = __builtin_amdgcn_rsq(piv);
+      y = y * fma(-0.5 * piv, y * y, 1.5);
+      y = y * fma(-0.5 * piv, y * y, 1.5);
+      ia = y;
+      alpha = piv * y;
+      ip = y * y;
+    }
+    rb[W2 + 0] = alpha;
+    rb[W2 + 1] = ia;
+    rb[W2 + 2] = ip;
+    rb[W2 + 3] = fl;
+  }
+}
+
 template <int F>
 __device__ void chol_inv(double* Gs, double* Ri, double* rowbuf, double* dgs, int f,
                          uint64_t dmask_in, int first_pass, uint64_t* dmask_out, int* nfloor) {
   typedef SmallCfg<F> C;
-  constexpr int LD = C::LD, NR = C::NR, NCL = C::NCL, W2 = 2 * F;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int LD = C::LD, NR = C::NR, NCL = C::NCL, W2 = 2 * F, RBS = 2 * F + 4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index (scalar)
   for (int i = tid; i < f; i += 256) dgs[i] = Gs[i * LD + i];
   double M[NR][NCL];
 #pragma unroll
@@ -745,7 +805,8 @@ __device__ void chol_inv(double* Gs, double* Ri, double* rowbuf, double* dgs, in
       M[s][q] = v;
     }
   }
-  __syncthreads();                       // G consumed: Gs now receives R
+  __syncthreads();                       // G consumed: Gs now receives R; dgs ready
+  if (w == 0 && f > 0) publish_row<F>(rowbuf, M[0], 0, dgs[0], dmask_in & 1ull, first_pass);
   uint64_t dout = dmask_in;
   int nfl = 0;
   for (int g = 0; 4 * g < f; ++g) {
@@ -753,66 +814,69 @@ __device__ void chol_inv(double* Gs, double* Ri, double* rowbuf, double* dgs, in
     for (int u = 0; u < 4; ++u) {
       const int k = 4 * g + u;
       if (k >= f) break;
-      double* rb = rowbuf + u * W2;
-      if (w == u) {
+      const double* rb = rowbuf + u * RBS;
+      __syncthreads();                   // row k and its pivot scalars published
+      // every LDS operand of the step is requested before any is used
+      const double alpha = rb[W2 + 0], ia = rb[W2 + 1], ip = rb[W2 + 2];
+      const int fl = (int)rb[W2 + 3];
+      double rowc[NCL], mv[NR];
 #pragma unroll
-        for (int q = 0; q < NCL; ++q) {
-          const int c = lane + 64 * q;
-          if (c < W2) rb[c] = M[0][q];
-        }
+      for (int q = 0; q < NCL; ++q) {
+        const int c = lane + 64 * q;
+        rowc[q] = rb[c < W2 ? c : 0];
       }
-      __syncthreads();
-      const double piv = rb[k];
-      const bool dk = (dmask_in >> k) & 1ull;
-      const double flo = FLOOR_C * U64 * dgs[k];
-      int fl = 0;
-      double alpha;
-      if (dk) {
-        fl = 2;
-        alpha = 1.0;
-      } else if (!(piv > flo) || !(piv < INFINITY)) {
-        fl = first_pass ? 1 : 2;
-        alpha = first_pass ? sqrt(flo > 1e-300 ? flo : 1e-300) : 1.0;
-      } else {
-        alpha = sqrt(piv);
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        const int i = 4 * (g + s) + w;
+        mv[s] = rb[i < f ? i : 0];
       }
       if (fl == 2) dout |= 1ull << k;
       nfl += (fl == 1);
       if (w == u) {                      // row k of R, column k of R^{-1}
-        const double ia = 1.0 / alpha;
 #pragma unroll
         for (int q = 0; q < NCL; ++q) {
           const int c = lane + 64 * q;
           if (c < F) {
             double v = 0.0;
             if (c == k) v = alpha;
-            else if (c > k && fl == 0 && !((dmask_in >> c) & 1ull)) v = M[0][q] * ia;
+            else if (c > k && fl == 0 && !((dmask_in >> c) & 1ull)) v = rowc[q] * ia;
             Gs[k * LD + c] = v;
           } else if (c < W2) {
             const int cc = c - F;
-            Ri[cc * LD + k] = cc <= k ? M[0][q] * ia : 0.0;
+            Ri[cc * LD + k] = cc <= k ? rowc[q] * ia : 0.0;
           }
         }
       }
+      // row k+1: wave (u+1) mod 4, slot 0 (slot 1 of wave 0 when u = 3)
+      const int wn = (u + 1) & 3, sn = (u == 3) ? 1 : 0;
+      const bool has_next = k + 1 < f;
+      double* rbn = rowbuf + ((u + 1) & 3) * RBS;
       if (fl == 0) {
-        const double ip = 1.0 / piv;
         double t[NCL];
 #pragma unroll
         for (int q = 0; q < NCL; ++q) {
           const int c = lane + 64 * q;
-          double v = c < W2 ? rb[c] : 0.0;
-          if (c < F && ((dmask_in >> c) & 1ull)) v = 0.0;
-          t[q] = v * ip;
+          const bool live = c < W2 && (c >= F || !((dmask_in >> c) & 1ull));
+          t[q] = live ? rowc[q] * ip : 0.0;
         }
+        if (w == wn && has_next) {       // lookahead: row k+1 first, then publish it
+          const double mlt = ((dmask_in >> (k + 1)) & 1ull) ? 0.0 : mv[sn];
+#pragma unroll
+          for (int q = 0; q < NCL; ++q) M[sn][q] = fma(-mlt, t[q], M[sn][q]);
+          publish_row<F>(rbn, M[sn], k + 1, dgs[k + 1], (dmask_in >> (k + 1)) & 1ull, first_pass);
+        }
+        // rows i > k below the pivot, branch-free (multiplier 0 elsewhere)
 #pragma unroll
         for (int s = 0; s < NR; ++s) {
-          if (s == 0 && w <= u) continue;  // rows <= k are finished
           const int i = 4 * (g + s) + w;
-          if (i >= f) continue;
-          const double mlt = ((dmask_in >> i) & 1ull) ? 0.0 : rb[i];
+          const bool doit = (s > 0 || w > u) && i < f && !((dmask_in >> i) & 1ull) &&
+                            !(w == wn && s == sn);
+          const double mlt = doit ? mv[s] : 0.0;
 #pragma unroll
           for (int q = 0; q < NCL; ++q) M[s][q] = fma(-mlt, t[q], M[s][q]);
         }
+      } else if (w == wn && has_next) {  // no elimination: row k+1 is already current
+        publish_row<F>(rbn, M[sn], k + 1, dgs[k + 1], (dmask_in >> (k + 1)) & 1ull, first_pass);
       }
     }
 #pragma unroll
@@ -850,6 +914,8 @@ struct CholArgs {
   double* diag_log;
   const double* norm_parts;  // non-null: finish ||A||_F and eps = tol ||A||_F first
   int64_t n_norm;
+  Gate gate;               // closing steps enqueued ahead of the stop flag
+  const int64_t* f_dev;    // non-null: block width read on the device (<= the template width)
 };
 
 // ---------------------------------------------------------------------------
@@ -883,7 +949,7 @@ struct GramCfg {
   static constexpr int ZD = MODE == 1 ? F * LDZ : 0;
   static constexpr int FOLD = (F / 16) * (F / 16) * 256;
   static constexpr int LOOPD = XD + ZD > FOLD ? XD + ZD : FOLD;
-  static constexpr int CHAIND = 2 * S::SIZE + 8 * F + F;
+  static constexpr int CHAIND = 2 * S::SIZE + 4 * (2 * F + 4) + F;
   static constexpr int TOTAL = PBASE + (LOOPD > CHAIND ? LOOPD : CHAIND);
 };
 
@@ -898,6 +964,9 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   constexpr int TT = F / 16, RPW = Cfg::RPW, LDX = Cfg::LDX, LDZ = Cfg::LDZ, LD = S::LD;
   static_assert(Cfg::TOTAL * 8 <= 160 * 1024, "LDS budget");
   if (stop_block && *stop_block < block_id) return;
+  if (gate_shut(ca.gate)) return;
+  if (ca.f_dev) f = (int)*ca.f_dev;
+  if (f > F) return;                    // cannot happen: the launch width bounds the rank
   __shared__ __align__(16) double lds[Cfg::TOTAL];
   double* Wl = lds;                                   // MODE 1: W, row-major ld F+1
   double* ph = lds + Cfg::PBASE;
@@ -918,22 +987,22 @@ __global__ __launch_bounds__(256) void k_gram_rows(
     for (int u = 0; u < TT; ++u) acc[t][u] = MF::zero();
   const int64_t npan = (rows + RPW - 1) / RPW;
   constexpr int NIT = F * RPW / 256;
-  static_assert(NIT % 8 == 0, "staging batches");
+  static_assert(NIT <= 32, "staging registers");
   for (int64_t pnl = blockIdx.x; pnl < npan; pnl += gridDim.x) {
     const int64_t rb = pnl * RPW;
     __syncthreads();                          // previous panel consumed (and W ready)
-    for (int it0 = 0; it0 < NIT; it0 += 8) {  // stage X (zero outside rows x f), 8 loads in flight
-      T xv[8];
+    {                                         // stage X (zero outside rows x f), all loads in flight
+      T xv[NIT];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int idx = tid + 256 * (it0 + q);
+      for (int q = 0; q < NIT; ++q) {
+        const int idx = tid + 256 * q;
         const int c = idx / RPW, rl = idx - c * RPW;
         const int64_t row = rb + rl;
         xv[q] = (c < f && row < rows) ? X[(int64_t)c * ld + row] : (T)0;
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int idx = tid + 256 * (it0 + q);
+      for (int q = 0; q < NIT; ++q) {
+        const int idx = tid + 256 * q;
         const int c = idx / RPW, rl = idx - c * RPW;
         pan[c * LDX + rl] = xv[q];
       }
@@ -941,15 +1010,16 @@ __global__ __launch_bounds__(256) void k_gram_rows(
     __syncthreads();
     if constexpr (MODE == 1) {                // Z panel = X panel W (FP64 MFMA), rounded to T
       for (int rt = wv; rt < RPW / 16; rt += 4) {
+        double a[F / 4];
+#pragma unroll
+        for (int kk = 0; kk < F / 4; ++kk) a[kk] = (double)pan[(4 * kk + g) * LDX + 16 * rt + r];
         typename MF::acc_t z[TT];
 #pragma unroll
         for (int u = 0; u < TT; ++u) z[u] = MF::zero();
-#pragma unroll 2
-        for (int k0 = 0; k0 < F; k0 += 4) {
-          const double a = (double)pan[(k0 + g) * LDX + 16 * rt + r];
 #pragma unroll
-          for (int u = 0; u < TT; ++u) z[u] = MF::op(a, Wl[(k0 + g) * LD + 16 * u + r], z[u]);
-        }
+        for (int kk = 0; kk < F / 4; ++kk)
+#pragma unroll
+          for (int u = 0; u < TT; ++u) z[u] = MF::op(a[kk], Wl[(4 * kk + g) * LD + 16 * u + r], z[u]);
 #pragma unroll
         for (int u = 0; u < TT; ++u)
 #pragma unroll
@@ -957,10 +1027,21 @@ __global__ __launch_bounds__(256) void k_gram_rows(
             pz[(16 * u + r) * LDZ + 16 * rt + MF::row(g, e)] = (double)(T)z[u][e];
       }
       __syncthreads();
-      for (int idx = tid; idx < f * RPW; idx += 256) {   // write Z back over X
-        const int c = idx / RPW, rl = idx - c * RPW;
-        const int64_t row = rb + rl;
-        if (row < rows) X[(int64_t)c * ld + row] = (T)pz[c * LDZ + rl];
+      {                                       // write Z back over X (LDS reads batched)
+        double zv[NIT];
+#pragma unroll
+        for (int q = 0; q < NIT; ++q) {
+          const int idx = tid + 256 * q;
+          const int c = idx / RPW, rl = idx - c * RPW;
+          zv[q] = pz[c * LDZ + rl];
+        }
+#pragma unroll
+        for (int q = 0; q < NIT; ++q) {
+          const int idx = tid + 256 * q;
+          const int c = idx / RPW, rl = idx - c * RPW;
+          const int64_t row = rb + rl;
+          if (c < f && row < rows) X[(int64_t)c * ld + row] = (T)zv[q];
+        }
       }
     }
     // Gram over this panel: wave wv takes rows [wv*RPW/4, (wv+1)*RPW/4)
@@ -1024,8 +1105,8 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   const int ff = f * f;
   double* Gs = ph;                   // G, then R
   double* Ri = Gs + S::SIZE;         // R^{-1}
-  double* rowbuf = Ri + S::SIZE;     // 4 x 2F
-  double* dgs = rowbuf + 8 * F;
+  double* rowbuf = Ri + S::SIZE;     // 4 x (2F + 4)
+  double* dgs = rowbuf + 4 * (2 * F + 4);
   {
     // upper triangle, all partials of an element loaded before summing them
     // in order b = 0, 1, ...
@@ -1034,21 +1115,22 @@ __global__ __launch_bounds__(256) void k_gram_rows(
     double sum[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) sum[e] = 0.0;
-    for (unsigned b = 0; b < nb; b += 4) {
-      double v[EPT][4];
+    constexpr int PB = EPT <= 4 ? 16 : 4;        // partials per batch (loads in flight)
+    for (unsigned b = 0; b < nb; b += PB) {
+      double v[EPT][PB];
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int idx = tid + 256 * e;
         const int c = idx / (f > 0 ? f : 1), rr = idx - c * f;
         const bool ok = idx < ff && rr <= c;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < PB; ++q)
           v[e][q] = (ok && b + q < nb) ? parts[(int64_t)(b + q) * ff + idx] : 0.0;
       }
 #pragma unroll
       for (int e = 0; e < EPT; ++e)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sum[e] += v[e][q];
+        for (int q = 0; q < PB; ++q) sum[e] += v[e][q];
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -1129,25 +1211,29 @@ struct ApplyJob {
   int f, ncols;
   const int64_t* zoff_dev;
   const int32_t* ncols_dev;
+  const int64_t* f_dev;          // if set: f = ncols = *f_dev (closing steps)
 };
 
 template <typename T, int F>
 __global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
-                                               const int32_t* __restrict__ stop_block, int block_id) {
+                                               const int32_t* __restrict__ stop_block, int block_id,
+                                               Gate gate) {
   typedef Mfma<double> MF;
   constexpr int TT = F / 16, LD = F + 1, KS = F / 4;
   if (stop_block && *stop_block < block_id) return;
+  if (gate_shut(gate)) return;
   const ApplyJob jb = blockIdx.y == 0 ? j0 : j1;
   const int64_t row0 = (int64_t)blockIdx.x * 64;
   if (row0 >= jb.rows) return;
   __shared__ double Wl[F * LD];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
-  const int f = jb.f;
+  const int f = jb.f_dev ? (int)*jb.f_dev : jb.f;
+  if (f > F) return;                    // cannot happen: the launch width bounds the rank
   for (int idx = tid; idx < F * F; idx += 256) {
     const int i = idx / F, jj = idx - i * F;
     Wl[i * LD + jj] = (i < f && jj < f) ? jb.W[(int64_t)jj * f + i] : 0.0;
   }
-  const int ncols = jb.ncols_dev ? jb.ncols_dev[block_id] : jb.ncols;
+  const int ncols = jb.f_dev ? f : (jb.ncols_dev ? jb.ncols_dev[block_id] : jb.ncols);
   const int64_t zoff = jb.zoff_dev ? jb.zoff_dev[block_id] : jb.zoff;
   const T* X = reinterpret_cast<const T*>(jb.X);
   T* Z = reinterpret_cast<T*>(jb.Z);
@@ -1191,11 +1277,15 @@ template <typename T, int F>
 __global__ __launch_bounds__(256) void k_small_qr(const double* __restrict__ R1g,
                                                   const double* __restrict__ R2g, int f,
                                                   double* __restrict__ Qout, T* __restrict__ Dout,
-                                                  int64_t ldd, State* st, int count_floors) {
+                                                  int64_t ldd, State* st, int count_floors, Gate gate,
+                                                  const int64_t* __restrict__ f_dev) {
   typedef SmallCfg<F> S;
   constexpr int LD = S::LD;
+  if (gate_shut(gate)) return;
+  if (f_dev) f = (int)*f_dev;
+  if (f > F) return;                    // cannot happen: the launch width bounds the rank
   __shared__ double B0[S::SIZE], B1[S::SIZE], B2[S::SIZE], B3[S::SIZE];
-  __shared__ double rowbuf[8 * F], dgs[F];
+  __shared__ double rowbuf[4 * (2 * F + 4)], dgs[F];
   const int tid = threadIdx.x;
   double* Mt = R1g ? B1 : B0;
   for (int idx = tid; idx < F * F; idx += 256) {

@@ -719,81 +719,46 @@ __device__ __forceinline__ void lds_gemm(const double* A, const double* B, Out o
 
 // ---------------------------------------------------------------------------
 // Cholesky with inverse, on the four waves of a workgroup, of a symmetric
-// positive semi-definite f x f matrix G (FP64, f <= F): one elimination
-// sweep over the augmented rows [G | I].  With G = L U (L unit lower,
-// U = diag(alpha) R) the sweep turns I into L^{-1} = diag(alpha) R^{-T}, so
-// row k of the right half divided by alpha_k is column k of R^{-1}.
-//   Step k: pivot p = S(k,k) of the current Schur complement S;
-//     dead column (flag in dmask_in): R(k,k) = 1, row k and column k of R
-//       zero, no elimination;
-//     p <= FLOOR_C u64 G(k,k), p <= PIV_MIN or not finite: floored to
-//       FLOOR_C u64 G(k,k) on a first pass (R(k,k) = sqrt(floor), rest of
-//       row k zero, no elimination) and marked dead otherwise (R(k,k) = 1);
-//     else R(k,k) = sqrt(p), R(k,c) = S(k,c)/R(k,k) for live c > k, and
-//       every later row i subtracts S(k,i)/p times row k (dead columns of
-//       the left half excluded).
-// Layout: 64 lanes x 4 waves; lane c holds column c of [G | I] (two columns
-// per lane when F = 64), wave w rows 4(g+s)+w in slot s during group g of
-// four steps, so the pivot row of step 4g+u is slot 0 of wave u; the slots
-// move down by one after each group.  Row k and its pivot scalars (alpha,
-// 1/alpha, 1/p, status) go through LDS (rowbuf[k mod 4]) with one barrier
-// per step; the wave holding row k+1 updates and publishes it first, so
-// the square root of the next pivot overlaps the rest of the update.
+// positive semi-definite f x f matrix G (FP64, f <= F): elimination over
+// the augmented rows [G | I].  With G = L U (L unit lower, U = diag(alpha)
+// R) the elimination turns I into L^{-1} = diag(alpha) R^{-T}, so row k of
+// the right half divided by alpha_k is column k of R^{-1}.  Pivot rules:
+//   dead column (flag in dmask_in): R(k,k) = 1, row k and column k of R
+//     zero, no elimination;
+//   p <= FLOOR_C u64 G(k,k), p <= PIV_MIN or not finite: floored to
+//     FLOOR_C u64 G(k,k) on a first pass (R(k,k) = sqrt(floor), rest of row
+//     k zero, no elimination) and marked dead otherwise (R(k,k) = 1);
+//   else R(k,k) = sqrt(p), R(k,c) = S(k,c)/R(k,k) for live c > k and every
+//     later row i subtracts S(k,i)/p times row k (dead columns excluded),
+// with p = S(k,k) of the current Schur complement S.
+// Blocked by panels of 8 pivots (the same arithmetic, reordered): the 8
+// panel rows are published in LDS; every thread factors the 8 x 8 diagonal
+// block in registers (pivot rules above) and applies the panel's unit lower
+// factor to the columns it owns, which gives the panel rows of R (S part)
+// and of R^{-T} (right half); the rows below take the rank-8 update
+// S(i,:) -= sum_j R(k_j,i) X(j,:).  Two barriers per panel.
+// Layout: lane c owns column c of [G | I] (two columns per lane when
+// F = 64); wave w holds rows 8(p + s/2) + 4(s%2) + w in slot s during panel
+// p (slots move down by two after each panel).
 // Gs: G on entry (row-major, ld F+1), R on exit (zero below the diagonal
-// and in rows >= f); Ri: R^{-1} on exit (zero in columns >= f); rowbuf:
-// 4 x (2F+4) doubles; dgs: F doubles.  Returns the dead mask after the
-// sweep and the number of floored pivots (uniform over the workgroup).
+// and in rows >= f); Ri: R^{-1} on exit (zero in columns >= f); work:
+// 24F doubles; dgs: F doubles.  Returns the dead mask afterwards and the
+// number of floored pivots (uniform over the workgroup).
 // ---------------------------------------------------------------------------
 template <int F>
-__device__ __forceinline__ void publish_row(double* rb, const double (&row)[(2 * F + 63) / 64], int k,
-                                            double dgk, bool dead_k, int first_pass) {
-  constexpr int NCL = (2 * F + 63) / 64, W2 = 2 * F;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int q = 0; q < NCL; ++q) {
-    const int c = lane + 64 * q;
-    if (c < W2) rb[c] = row[q];
-  }
-  if (lane == k) {                       // lane k holds S(k,k) (k < F <= 64)
-    const double piv = row[0];
-    const double flo = FLOOR_C * U64 * dgk;
-    double fl = 0.0, alpha, ia, ip = 0.0;
-    if (dead_k) {
-      fl = 2.0;
-      alpha = 1.0;
-      ia = 1.0;
-    } else if (!(piv > flo) || !(piv > PIV_MIN) || !(piv < INFINITY)) {
-      fl = first_pass ? 1.0 : 2.0;
-      alpha = first_pass ? sqrt(flo > 1e-300 ? flo : 1e-300) : 1.0;
-      ia = 1.0 / alpha;
-    } else {
-      // 1/sqrt(p): hardware estimate and two Newton steps (about 1 ulp)
-      double y = __builtin_amdgcn_rsq(piv);
-      y = y * fma(-0.5 * piv, y * y, 1.5);
-      y = y * fma(-0.5 * piv, y * y, 1.5);
-      ia = y;
-      alpha = piv * y;
-      ip = y * y;
-    }
-    rb[W2 + 0] = alpha;
-    rb[W2 + 1] = ia;
-    rb[W2 + 2] = ip;
-    rb[W2 + 3] = fl;
-  }
-}
-
-template <int F>
-__device__ void chol_inv(double* Gs, double* Ri, double* rowbuf, double* dgs, int f,
+__device__ void chol_inv(double* Gs, double* Ri, double* work, double* dgs, int f,
                          uint64_t dmask_in, int first_pass, uint64_t* dmask_out, int* nfloor) {
   typedef SmallCfg<F> C;
-  constexpr int LD = C::LD, NR = C::NR, NCL = C::NCL, W2 = 2 * F, RBS = 2 * F + 4;
+  constexpr int LD = C::LD, NR = C::NR, NCL = C::NCL, W2 = 2 * F;
+  double* P = work;                      // panel rows: P[j*W2 + c], j < 8
+  double* XT = work + 8 * W2;            // multipliers: XT[j*F + i] = R(kp+j, i)
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index (scalar)
   for (int i = tid; i < f; i += 256) dgs[i] = Gs[i * LD + i];
   double M[NR][NCL];
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
-    const int i = 4 * s + w;
+    const int i = 8 * (s / 2) + 4 * (s % 2) + w;
 #pragma unroll
     for (int q = 0; q < NCL; ++q) {
       const int c = lane + 64 * q;
@@ -806,85 +771,169 @@ __device__ void chol_inv(double* Gs, double* Ri, double* rowbuf, double* dgs, in
     }
   }
   __syncthreads();                       // G consumed: Gs now receives R; dgs ready
-  if (w == 0 && f > 0) publish_row<F>(rowbuf, M[0], 0, dgs[0], dmask_in & 1ull, first_pass);
   uint64_t dout = dmask_in;
   int nfl = 0;
-  for (int g = 0; 4 * g < f; ++g) {
+  for (int kp = 0; kp < f; kp += 8) {
+    // (a) publish the panel rows kp + w and kp + 4 + w
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = 4 * g + u;
-      if (k >= f) break;
-      const double* rb = rowbuf + u * RBS;
-      __syncthreads();                   // row k and its pivot scalars published
-      // every LDS operand of the step is requested before any is used
-      const double alpha = rb[W2 + 0], ia = rb[W2 + 1], ip = rb[W2 + 2];
-      const int fl = (int)rb[W2 + 3];
-      double rowc[NCL], mv[NR];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int q = 0; q < NCL; ++q) {
         const int c = lane + 64 * q;
-        rowc[q] = rb[c < W2 ? c : 0];
+        if (c < W2) P[(4 * h + w) * W2 + c] = M[h][q];
       }
+    __syncthreads();
+    // (b) 8 x 8 diagonal block in registers: R_loc (upper triangle of d).
+    // Fast path when no panel pivot is dead or padding and every pivot
+    // passes the floor test; otherwise the block is reloaded and factored
+    // with the full pivot rules.
+    double d[8][8];
 #pragma unroll
-      for (int s = 0; s < NR; ++s) {
-        const int i = 4 * (g + s) + w;
-        mv[s] = rb[i < f ? i : 0];
-      }
-      if (fl == 2) dout |= 1ull << k;
-      nfl += (fl == 1);
-      if (w == u) {                      // row k of R, column k of R^{-1}
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int q = 0; q < NCL; ++q) {
-          const int c = lane + 64 * q;
-          if (c < F) {
-            double v = 0.0;
-            if (c == k) v = alpha;
-            else if (c > k && fl == 0 && !((dmask_in >> c) & 1ull)) v = rowc[q] * ia;
-            Gs[k * LD + c] = v;
-          } else if (c < W2) {
-            const int cc = c - F;
-            Ri[cc * LD + k] = cc <= k ? rowc[q] * ia : 0.0;
-          }
-        }
-      }
-      // row k+1: wave (u+1) mod 4, slot 0 (slot 1 of wave 0 when u = 3)
-      const int wn = (u + 1) & 3, sn = (u == 3) ? 1 : 0;
-      const bool has_next = k + 1 < f;
-      double* rbn = rowbuf + ((u + 1) & 3) * RBS;
-      if (fl == 0) {
-        double t[NCL];
+      for (int j = i; j < 8; ++j) d[i][j] = P[i * W2 + kp + j];
+    double yv[NCL][8];
 #pragma unroll
-        for (int q = 0; q < NCL; ++q) {
-          const int c = lane + 64 * q;
-          const bool live = c < W2 && (c >= F || !((dmask_in >> c) & 1ull));
-          t[q] = live ? rowc[q] * ip : 0.0;
-        }
-        if (w == wn && has_next) {       // lookahead: row k+1 first, then publish it
-          const double mlt = ((dmask_in >> (k + 1)) & 1ull) ? 0.0 : mv[sn];
+    for (int q = 0; q < NCL; ++q) {
+      const int c = lane + 64 * q;
 #pragma unroll
-          for (int q = 0; q < NCL; ++q) M[sn][q] = fma(-mlt, t[q], M[sn][q]);
-          publish_row<F>(rbn, M[sn], k + 1, dgs[k + 1], (dmask_in >> (k + 1)) & 1ull, first_pass);
-        }
-        // rows i > k below the pivot, branch-free (multiplier 0 elsewhere)
+      for (int j = 0; j < 8; ++j) yv[q][j] = P[j * W2 + (c < W2 ? c : 0)];
+    }
+    double dgk[8];
 #pragma unroll
-        for (int s = 0; s < NR; ++s) {
-          const int i = 4 * (g + s) + w;
-          const bool doit = (s > 0 || w > u) && i < f && !((dmask_in >> i) & 1ull) &&
-                            !(w == wn && s == sn);
-          const double mlt = doit ? mv[s] : 0.0;
+    for (int j = 0; j < 8; ++j) dgk[j] = dgs[kp + j];
+    double alpha[8], ia[8];
+    bool okj[8];
+    bool fast = kp + 8 <= f && ((dmask_in >> kp) & 0xffull) == 0;
+    if (fast) {
 #pragma unroll
-          for (int q = 0; q < NCL; ++q) M[s][q] = fma(-mlt, t[q], M[s][q]);
-        }
-      } else if (w == wn && has_next) {  // no elimination: row k+1 is already current
-        publish_row<F>(rbn, M[sn], k + 1, dgs[k + 1], (dmask_in >> (k + 1)) & 1ull, first_pass);
+      for (int j = 0; j < 8; ++j) {
+        const double piv = d[j][j];
+        const bool ok = piv > FLOOR_C * U64 * dgk[j] && piv > PIV_MIN && piv < INFINITY;
+        fast = fast && ok;
+        // 1/sqrt(p): hardware estimate and two Newton steps (about 1 ulp)
+        double y = __builtin_amdgcn_rsq(piv);
+        y = y * fma(-0.5 * piv, y * y, 1.5);
+        y = y * fma(-0.5 * piv, y * y, 1.5);
+        alpha[j] = piv * y;
+        ia[j] = y;
+        okj[j] = true;
+#pragma unroll
+        for (int i = j + 1; i < 8; ++i) d[j][i] *= y;
+#pragma unroll
+        for (int i = j + 1; i < 8; ++i)
+#pragma unroll
+          for (int i2 = i; i2 < 8; ++i2) d[i][i2] = fma(-d[j][i], d[j][i2], d[i][i2]);
       }
     }
+    if (!fast) {
 #pragma unroll
-    for (int s = 0; s + 1 < NR; ++s)
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
-      for (int q = 0; q < NCL; ++q) M[s][q] = M[s + 1][q];
+        for (int j = i; j < 8; ++j) d[i][j] = P[i * W2 + kp + j];
 #pragma unroll
-    for (int q = 0; q < NCL; ++q) M[NR - 1][q] = 0.0;
+      for (int j = 0; j < 8; ++j) {
+        const int k = kp + j;
+        const bool valid = k < f;
+        const double piv = d[j][j];
+        const double flo = FLOOR_C * U64 * dgk[j];
+        int fl;
+        double a, y;
+        if (!valid) {
+          fl = 3;
+          a = 1.0;
+          y = 1.0;
+        } else if ((dmask_in >> k) & 1ull) {
+          fl = 2;
+          a = 1.0;
+          y = 1.0;
+        } else if (!(piv > flo) || !(piv > PIV_MIN) || !(piv < INFINITY)) {
+          fl = first_pass ? 1 : 2;
+          a = first_pass ? sqrt(flo > 1e-300 ? flo : 1e-300) : 1.0;
+          y = 1.0 / a;
+        } else {
+          fl = 0;
+          y = __builtin_amdgcn_rsq(piv);
+          y = y * fma(-0.5 * piv, y * y, 1.5);
+          y = y * fma(-0.5 * piv, y * y, 1.5);
+          a = piv * y;
+        }
+        if (fl == 2) dout |= 1ull << k;
+        nfl += (fl == 1);
+        alpha[j] = a;
+        ia[j] = y;
+        okj[j] = (fl == 0);
+#pragma unroll
+        for (int i = j + 1; i < 8; ++i) {
+          const bool live = okj[j] && kp + i < f && !((dmask_in >> (kp + i)) & 1ull);
+          d[j][i] = live ? d[j][i] * y : 0.0;        // R_loc(j, i)
+        }
+#pragma unroll
+        for (int i = j + 1; i < 8; ++i)
+#pragma unroll
+          for (int i2 = i; i2 < 8; ++i2) d[i][i2] = fma(-d[j][i], d[j][i2], d[i][i2]);
+      }
+    }
+    // own columns: z_j = (v_j - sum_{i<j} R_loc(i,j) z_i) / alpha_j, i.e. the
+    // panel rows after the panel's elimination, scaled; X = z with the S part
+    // masked (R(k_j, c) = 0 for a dead column c or a pivot that did not
+    // eliminate)
+    double X[NCL][8];
+#pragma unroll
+    for (int q = 0; q < NCL; ++q) {
+      const int c = lane + 64 * q;
+      const bool sdead = c < F && ((dmask_in >> (c < F ? c : 0)) & 1ull);
+      double z[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        double acc = yv[q][j];
+#pragma unroll
+        for (int i = 0; i < j; ++i) acc = fma(-d[i][j], z[i], acc);
+        z[j] = acc * ia[j];
+        X[q][j] = (c < F && (!okj[j] || sdead)) ? 0.0 : z[j];
+      }
+    }
+    // panel rows of R, columns of R^{-1}, multipliers: rows 2w and 2w+1 by wave w
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = kp + j;
+      if ((j >> 1) != w || k >= f) continue;
+#pragma unroll
+      for (int q = 0; q < NCL; ++q) {
+        const int c = lane + 64 * q;
+        if (c >= W2) continue;
+        if (c < F) {
+          Gs[k * LD + c] = (c == k) ? alpha[j] : (c > k ? X[q][j] : 0.0);
+          XT[j * F + c] = X[q][j];
+        } else {
+          const int cc = c - F;
+          Ri[cc * LD + k] = cc <= k ? X[q][j] : 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    // (c) rank-8 update of the rows below the panel
+#pragma unroll
+    for (int s = 2; s < NR; ++s) {
+      const int i = kp + 8 * (s / 2) + 4 * (s % 2) + w;
+      if (i >= f) continue;
+      double mj[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) mj[j] = XT[j * F + i];
+#pragma unroll
+      for (int q = 0; q < NCL; ++q)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) M[s][q] = fma(-mj[j], X[q][j], M[s][q]);
+    }
+#pragma unroll
+    for (int s = 0; s + 2 < NR; ++s)
+#pragma unroll
+      for (int q = 0; q < NCL; ++q) M[s][q] = M[s + 2][q];
+#pragma unroll
+    for (int q = 0; q < NCL; ++q) {
+      M[NR - 2][q] = 0.0;
+      M[NR - 1][q] = 0.0;
+    }
   }
   __syncthreads();
   for (int idx = tid; idx < (F - f) * F; idx += 256) {   // padding rows / columns
@@ -949,7 +998,7 @@ struct GramCfg {
   static constexpr int ZD = MODE == 1 ? F * LDZ : 0;
   static constexpr int FOLD = (F / 16) * (F / 16) * 256;
   static constexpr int LOOPD = XD + ZD > FOLD ? XD + ZD : FOLD;
-  static constexpr int CHAIND = 2 * S::SIZE + 4 * (2 * F + 4) + F;
+  static constexpr int CHAIND = 2 * S::SIZE + 24 * F + F;
   static constexpr int TOTAL = PBASE + (LOOPD > CHAIND ? LOOPD : CHAIND);
 };
 
@@ -1105,8 +1154,8 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   const int ff = f * f;
   double* Gs = ph;                   // G, then R
   double* Ri = Gs + S::SIZE;         // R^{-1}
-  double* rowbuf = Ri + S::SIZE;     // 4 x (2F + 4)
-  double* dgs = rowbuf + 4 * (2 * F + 4);
+  double* rowbuf = Ri + S::SIZE;     // elimination work area, 24F
+  double* dgs = rowbuf + 24 * F;
   {
     // upper triangle, all partials of an element loaded before summing them
     // in order b = 0, 1, ...
@@ -1285,7 +1334,7 @@ __global__ __launch_bounds__(256) void k_small_qr(const double* __restrict__ R1g
   if (f_dev) f = (int)*f_dev;
   if (f > F) return;                    // cannot happen: the launch width bounds the rank
   __shared__ double B0[S::SIZE], B1[S::SIZE], B2[S::SIZE], B3[S::SIZE];
-  __shared__ double rowbuf[4 * (2 * F + 4)], dgs[F];
+  __shared__ double rowbuf[24 * F], dgs[F];
   const int tid = threadIdx.x;
   double* Mt = R1g ? B1 : B0;
   for (int idx = tid; idx < F * F; idx += 256) {

@@ -128,9 +128,10 @@ int eodabe_last_hip_error(const eodabe_ctx* ctx);
 #define EODABE_PROF_KINDS   2
 
 /* Turn HIP-event timing of the dominant kernels on (enable != 0) or off,
- * and reset the accumulated totals.  Events are recorded on the context's
- * stream immediately before and after each timed launch; launches of
- * speculative blocks that returned early are not counted. */
+ * and reset the accumulated totals.  The events are attached to the timed
+ * kernel's own dispatch (start and end of its execution on the context's
+ * stream); launches of speculative blocks or gated closing steps that
+ * returned early are not counted. */
 int eodabe_profile(eodabe_ctx* ctx, int enable);
 
 /* Accumulated timing of one kernel kind since the last eodabe_profile():

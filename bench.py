@@ -48,6 +48,33 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<workload>.txt), or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_2506_22713_amd/csrc/eodabe_kernels.hpp", "paper_2506_22713_amd/csrc/eodabe.hip"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    fields, kernels = {}, {}
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        if line.startswith("kernel "):
+            name = line.split()[1]
+            kernels[name] = float(line.rsplit("bytes", 1)[1])
+        else:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return kernels.get(kernel)
+
+
 def cpu_baseline(A64: np.ndarray, tol: float, block: int, budget_s: float):
     """Time the oracle (as it stands) on whole factorizations of the same
     matrix, repeating until about budget_s seconds of CPU work."""
@@ -141,14 +168,17 @@ def main():
     log(f"rank {f.rank} blocks {f.blocks} relerr {rel:.4e} ms/step {ms_per_step:.3f} (wall {ms_wall:.3f})")
 
     # dominant kernel: largest accumulated time
-    names = {E.PROF_SKETCH: "sketch Y = A*Omega_j (k_gemm_nt)", E.PROF_PROJECT: "projection C = Q^T A (k_gemm_nn)"}
+    names = {E.PROF_SKETCH: "sketch Y = A*Omega_j (k_sketch)", E.PROF_PROJECT: "projection C = Q^T A (k_gemm_nn)"}
+    kernel_id = {E.PROF_SKETCH: "k_sketch", E.PROF_PROJECT: "k_gemm_nn"}
     kind = max(prof, key=lambda k: prof[k][0])
     tot_ms, launches, by = prof[kind]
     avg_ms = tot_ms / max(launches, 1)
     per_launch_bytes = by / max(launches, 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = measured_traffic(args.workload, kernel_id[kind])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None,
+                    frac=round(achieved / PEAK_HBM_GBS, 4),
+                    traffic=None if traffic is None else int(traffic),
                     kernel=names[kind], avg_us=round(avg_ms * 1e3, 2), launches=int(launches),
                     bytes_per_launch=int(per_launch_bytes))
     others = {names[k]: dict(avg_us=round(prof[k][0] / max(prof[k][1], 1) * 1e3, 2),

@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--workload", default="image4096")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sketch", default="native", choices=["native", "f16", "bf16"],
+                    help="precision of the sketches after the second block (FP32 data only)")
+    ap.add_argument("--block", type=int, default=0, help="block width b (0: the workload's default)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of A (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -120,10 +123,13 @@ def main():
 
     log("generating", args.workload)
     A_np, tol, block, dt, extra = make_workload(args.workload)
+    if args.block:
+        block = args.block
+    sketch_code = {"native": E.SKETCH_NATIVE, "f16": E.SKETCH_F16, "bf16": E.SKETCH_BF16}[args.sketch]
     tdt = torch.float32 if dt == "f32" else torch.float64
     m, n = A_np.shape
     A = torch.from_numpy(np.ascontiguousarray(A_np)).to(device="cuda", dtype=tdt)
-    ctx = E.Context(block=block, seed=0, dtype=tdt)
+    ctx = E.Context(block=block, seed=0, dtype=tdt, sketch=sketch_code)
     rc = min(m, n)
     ws = ctx.workspace(m, n, rc)
     out = E.alloc_outputs(A, rc)
@@ -209,6 +215,7 @@ def main():
         "dtype": dt,
         "data": "synthetic",
         "config": dict(workload=args.workload, m=m, n=n, tol=tol, block=block, power_iters=0,
+                       sketch=args.sketch,
                        rank=int(f.rank), blocks=int(f.blocks), relerr=rel,
                        ranks_constant=len(set(ranks)) == 1, ms_wall_per_step=round(ms_wall, 4),
                        kernels=others, **extra, **orc),

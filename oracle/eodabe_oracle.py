@@ -135,6 +135,42 @@ def qr_posdiag(Y: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
 
 
 # ---------------------------------------------------------------------------
+# Low-precision sketch operands (the FP16 / BF16 sketch form).  Not part of
+# the paper: this emulates a run whose sketches from the third block on
+# multiply FP16 or BF16 copies of A and Omega (exact products, wide
+# accumulation), so that its rank and error can be compared with the GPU.
+# ---------------------------------------------------------------------------
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round FP32 values to bfloat16 (nearest, ties to even); returned as
+    FP64 holding the bfloat16 values.  bfloat16 keeps the FP32 exponent and
+    the top 7 fraction bits."""
+    u = np.ascontiguousarray(np.asarray(x, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_f16(x: np.ndarray) -> np.ndarray:
+    """Round FP32 values to IEEE binary16 (nearest, ties to even)."""
+    return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float64)
+
+
+def lp_scale(A: np.ndarray, mode: str) -> float:
+    """Power of two applied to A before the FP16 rounding: with
+    max|A| = f 2^e, f in [0.5, 1), the scale 2^(14-e) puts the largest entry
+    in [2^13, 2^14) (FP16 holds up to 65504).  BF16 has FP32's range: 1."""
+    mx = float(np.max(np.abs(A))) if A.size else 0.0
+    if mode != "f16" or not (mx > 0.0) or not math.isfinite(mx):
+        return 1.0
+    _, e = math.frexp(np.float32(mx))
+    return math.ldexp(1.0, 14 - e)
+
+
+def lp_round(x: np.ndarray, mode: str) -> np.ndarray:
+    return round_f16(x) if mode == "f16" else round_bf16(x)
+
+
+# ---------------------------------------------------------------------------
 # Alg. 1, BasisExt (section 3.1).
 # ---------------------------------------------------------------------------
 def basis_ext(A: np.ndarray, eps: float, k: int, seed: int,
@@ -151,10 +187,17 @@ def basis_ext(A: np.ndarray, eps: float, k: int, seed: int,
     ``sketch_dtype=np.float32`` is an emulation of a run whose matrix data
     (A, Omega, Y, Q) is held in FP32 while the small QR stays in FP64; it
     is used only to classify instances as precision-stable.
+    ``sketch_dtype="f16"`` / ``"bf16"``: the low-precision sketch form, in
+    which blocks 3, 4, ... use Y_j = (round(s A) round(Omega_j)) / s with s
+    from lp_scale (the products of the rounded operands are exact in FP64).
     """
     m, n = A.shape
+    lp = sketch_dtype if isinstance(sketch_dtype, str) else None
     lo = sketch_dtype == np.float32
     Aw = A.astype(np.float32) if lo else A
+    if lp:
+        sc = lp_scale(A, lp)
+        A_lp = lp_round((A * sc).astype(np.float32), lp)
     Q = np.zeros((m, 0), dtype=Aw.dtype)
     diag_log: list[float] = []
     blocks = 0
@@ -164,7 +207,10 @@ def basis_ext(A: np.ndarray, eps: float, k: int, seed: int,
         Om = omega_columns(seed, n, c, f)
         if lo:
             Om = Om.astype(np.float32)
-        Y = Aw @ Om
+        if lp and blocks >= 2:
+            Y = (A_lp @ lp_round(Om, lp)) / sc
+        else:
+            Y = Aw @ Om
         for _ in range(2):
             Y = Y - Q @ (Q.T @ Y)
         P, T = qr_posdiag(Y.astype(np.float64))
@@ -305,9 +351,11 @@ def siam_bound_sq(A: np.ndarray, r: int, Omega_r: np.ndarray, q: int = 0) -> flo
     return float(alpha ** (4 * q) * lead + np.sum(S0 ** 2))
 
 
-def precision_stable(A: np.ndarray, tol: float, k: int = 32, seed: int = 0) -> tuple[bool, int, int]:
-    """Classify an instance as precision-stable for FP32 data: the FP64 run
-    and the FP32-data emulation of Alg. 1 return the same rank."""
+def precision_stable(A: np.ndarray, tol: float, k: int = 32, seed: int = 0,
+                     lowp=np.float32) -> tuple[bool, int, int]:
+    """Classify an instance as precision-stable: the FP64 run of Alg. 1 and
+    the emulation with lower-precision data (FP32 data by default, or the
+    "f16" / "bf16" sketch form) return the same rank."""
     m, n = A.shape
     At = np.asarray(A, dtype=np.float64)
     if m < n:
@@ -315,5 +363,5 @@ def precision_stable(A: np.ndarray, tol: float, k: int = 32, seed: int = 0) -> t
     nrm = float(np.sqrt(np.sum(At * At)))
     eps = tol * nrm
     r64 = basis_ext(At, eps, k, seed)["rank"] if nrm > 0 else 0
-    r32 = basis_ext(At, eps, k, seed, np.float32)["rank"] if nrm > 0 else 0
+    r32 = basis_ext(At, eps, k, seed, lowp)["rank"] if nrm > 0 else 0
     return r64 == r32, r64, r32

@@ -169,6 +169,8 @@ struct Geo {
   int s_gram;           // K-splits of block Grams
   int s_core;           // K-splits of the r-column products (C = Q^T A etc.)
   size_t elem;
+  int lp;               // low-precision sketch: 0 none, 1 FP16, 2 BF16
+  int64_t ld_lp;        // leading dimension of the low-precision copy of A (multiple of 8)
 };
 
 struct WS {
@@ -177,7 +179,9 @@ struct WS {
   int32_t* accv;
   int32_t* dead;        // nblk x BN_MAX
   double* diag_log;     // nn
-  double* normparts;    // per sketch workgroup
+  double* normparts;    // per sketch workgroup: sum of squares
+  float* maxparts;      // per sketch workgroup: max |A|
+  uint16_t* alp;        // low-precision copy of A (mm x ld_lp), if g.lp
   void* omega;          // bn x ldk
   void* ypart;          // s_sketch x ldy x bn
   void* y;              // ldy x bn
@@ -219,6 +223,8 @@ WS carve(void* base, const Geo& g) {
   w.dead = c.take<int32_t>((g.nblk + 1) * BN_MAX);
   w.diag_log = c.take<double>(g.nn + BN_MAX);
   w.normparts = c.take<double>((int64_t)g.s_sketch * cdiv(g.mm, 128) + 64);
+  w.maxparts = c.take<float>((int64_t)g.s_sketch * cdiv(g.mm, 128) + 64);
+  w.alp = g.lp ? c.take<uint16_t>(g.mm * g.ld_lp) : nullptr;
   w.omega = c.take<char>((int64_t)g.bn * g.ldk * e);
   w.ypart = c.take<char>((int64_t)g.s_sketch * g.ldy * g.bn * e);
   w.y = c.take<char>(g.ldy * g.bn * e);
@@ -266,6 +272,8 @@ bool plan(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t lda, const void* 
   const bool aligned = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
   g.packed = g.transposed || !aligned;
   g.lda_eff = g.packed ? rup(std::max<int64_t>(g.nn, 1), 4) : lda;
+  g.lp = (dt == EODABE_F32) ? ctx->o.sketch_dtype : 0;
+  g.ld_lp = rup(std::max<int64_t>(g.nn, 1), 8);
   g.b = ctx->o.block;
   g.bn = (int)rup(g.b, 16);
   g.nblk = cdiv(g.nn, g.b);
@@ -325,17 +333,32 @@ struct Ops {
   }
 
   // Y partials = A Omega^T (bn <= 128 columns), see k_sketch
+  // lp_write (1 FP16, 2 BF16; FP32 data only): also store the low-precision
+  // copy of A (scaled by lp_st->lp_scale) to lp_out (row-major, ld_lp).
   int sketch(const T* A, int64_t lda, const T* Om, int64_t ldk, int64_t M, int bn, int64_t K,
              int splits, T* out, int64_t ldo, int64_t part_stride, double* sumsq,
-             const int32_t* stopb, int blk) {
+             const int32_t* stopb, int blk, float* maxabs = nullptr, int lp_write = 0,
+             uint16_t* lp_out = nullptr, int64_t ld_lp = 0, const State* lp_st = nullptr) {
     if (M <= 0 || bn <= 0) return 0;
     const int64_t kchunk = split_chunk(K, splits);
     splits = eff_splits(K, splits);
-#define SK_CASE(CC)                                                                                   \
+#define SK_LAUNCH(CC, LW)                                                                             \
   do {                                                                                                \
     dim3 grid((unsigned)cdiv(M, 128), splits, 1);                                                     \
-    hipExtLaunchKernelGGL((k_sketch<T, 2, CC>), grid, dim3(256), 0, st, pe0, pe1, 0, A, lda, Om, ldk, M, \
-                          bn, K, kchunk, out, ldo, part_stride, sumsq, stopb, blk);                   \
+    hipExtLaunchKernelGGL((k_sketch<T, 2, CC, LW>), grid, dim3(256), 0, st, pe0, pe1, 0, A, lda, Om,  \
+                          ldk, M, bn, K, kchunk, out, ldo, part_stride, sumsq, maxabs, lp_out, ld_lp, \
+                          lp_st, stopb, blk);                                                         \
+  } while (0)
+#define SK_CASE(CC)                                                                                   \
+  do {                                                                                                \
+    if constexpr (sizeof(T) == 4) {                                                                   \
+      if (lp_write == 1) SK_LAUNCH(CC, 1);                                                            \
+      else if (lp_write == 2) SK_LAUNCH(CC, 2);                                                       \
+      else SK_LAUNCH(CC, 0);                                                                          \
+    } else {                                                                                          \
+      if (lp_write) return EODABE_EINVAL;                                                             \
+      SK_LAUNCH(CC, 0);                                                                               \
+    }                                                                                                 \
   } while (0)
     if (bn <= 16) SK_CASE(1);
     else if (bn <= 32) SK_CASE(2);
@@ -344,6 +367,37 @@ struct Ops {
     else if (bn <= 96) SK_CASE(6);
     else SK_CASE(8);
 #undef SK_CASE
+#undef SK_LAUNCH
+    LAUNCHCHK();
+    return 0;
+  }
+
+  // Low-precision sketch partials from the FP16 (lp 1) or BF16 (lp 2) copy of A.
+  int sketch_lp(int lp, const uint16_t* Alp, int64_t ld_lp, const float* Om, int64_t ldk, int64_t M,
+                int bn, int64_t K, int splits, float* out, int64_t ldo, int64_t part_stride,
+                const State* lp_st, const int32_t* stopb, int blk) {
+    if (M <= 0 || bn <= 0) return 0;
+    const int64_t kchunk = split_chunk(K, splits);
+    splits = eff_splits(K, splits);
+#define SL_LAUNCH(LP, CC)                                                                             \
+  do {                                                                                                \
+    dim3 grid((unsigned)cdiv(M, 128), splits, 1);                                                     \
+    hipExtLaunchKernelGGL((k_sketch_lp<LP, CC>), grid, dim3(256), 0, st, pe0, pe1, 0, Alp, ld_lp, Om, \
+                          ldk, M, bn, K, kchunk, out, ldo, part_stride, lp_st, stopb, blk);           \
+  } while (0)
+#define SL_CASE(CC)                          \
+  do {                                       \
+    if (lp == 1) SL_LAUNCH(1, CC);           \
+    else SL_LAUNCH(2, CC);                   \
+  } while (0)
+    if (bn <= 16) SL_CASE(1);
+    else if (bn <= 32) SL_CASE(2);
+    else if (bn <= 48) SL_CASE(3);
+    else if (bn <= 64) SL_CASE(4);
+    else if (bn <= 96) SL_CASE(6);
+    else SL_CASE(8);
+#undef SL_CASE
+#undef SL_LAUNCH
     LAUNCHCHK();
     return 0;
   }
@@ -492,7 +546,8 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
   Ops<T> ops{ctx, st};
   if (ca.fresh) hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, ca.dead, (int64_t)f);
   if (ca.norm_parts)
-    hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, ca.norm_parts, ca.n_norm, w.st);
+    hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, ca.norm_parts, ca.max_parts, ca.n_norm,
+                       w.st);
   TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, 1, parts, f, (int64_t)f * f, nullptr,
                                    nullptr, stopb, blk));
   hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.dead, w.dg,
@@ -590,7 +645,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
   const int nwlog = (int)(g.nblk + 2);
   hipLaunchKernelGGL(k_init_state, dim3(64), dim3(256), 0, st, w.st, tol, w.wlog, nwlog, w.dead,
-                     (int64_t)(g.nblk + 1) * BN_MAX, w.accv, (int)(g.nblk + 1));
+                     (int64_t)(g.nblk + 1) * BN_MAX, w.accv, (int)(g.nblk + 1), g.lp);
   LAUNCHCHK();
   T* omega = (T*)w.omega;
   T* y = (T*)w.y;
@@ -622,13 +677,26 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       }
       // a2: sketch Y = A Omega_j (K-split partials; block 0 also ||A||_F)
       const int64_t ystride = g.ldy * g.bn;
+      // low-precision form: block 1 also writes the FP16/BF16 copy of A
+      // (scale from block 0's max |A|), later blocks sketch that copy
       const int pid = prof_begin(ctx, st);
       prof_attach(ctx, ops, pid);
-      TRY(ops.sketch(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch, (T*)w.ypart, g.ldy,
-                     ystride, j == 0 ? w.normparts : nullptr, stopb, blk));
+      double abytes = (double)g.elem * g.mm * g.nn;
+      if (g.lp && j >= 2) {
+        if constexpr (sizeof(T) == 4)
+          TRY(ops.sketch_lp(g.lp, w.alp, g.ld_lp, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch,
+                            (T*)w.ypart, g.ldy, ystride, w.st, stopb, blk));
+        abytes = 2.0 * g.mm * g.nn;
+      } else {
+        TRY(ops.sketch(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch, (T*)w.ypart, g.ldy,
+                       ystride, j == 0 ? w.normparts : nullptr, stopb, blk,
+                       j == 0 ? w.maxparts : nullptr, (g.lp && j == 1) ? g.lp : 0, w.alp, g.ld_lp,
+                       w.st));
+        if (g.lp && j == 1) abytes += 2.0 * g.mm * g.nn;
+      }
       prof_attach(ctx, ops, -1);
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
-               (double)g.elem * ((double)g.mm * g.nn + (double)g.nn * f + (double)g.mm * f));
+               abytes + (double)g.elem * ((double)g.nn * f + (double)g.mm * f));
       const int nsp = eff_splits(g.nn, g.s_sketch);
       if (j > 0) TRY(ops.reduce((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       // a3 + a4: two rounds of [project against the basis so far (width
@@ -655,6 +723,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           if (small) ca.Rinv = w.r1inv;
           if (j == 0) {
             ca.norm_parts = w.normparts;
+            ca.max_parts = w.maxparts;
             ca.n_norm = sketch_wgs * (int64_t)nsp;
           }
         } else {
@@ -878,13 +947,27 @@ SketchPlan sketch_plan(int64_t m, int64_t n, int64_t ncols) {
   p.s = std::max<int64_t>(1, std::min<int64_t>(s, 64));
   return p;
 }
+struct SketchLp {
+  State* st;
+  double* normp;
+  float* maxp;
+  uint16_t* alp;
+  int64_t ld_lp;
+};
 template <typename T>
-size_t sketch_carve(void* base, int64_t m, const SketchPlan& p, T** om, T** yp, T** ap, T** yr) {
+size_t sketch_carve(void* base, int64_t m, int64_t n, const SketchPlan& p, T** om, T** yp, T** ap,
+                    T** yr, SketchLp* lp) {
   Carver c(base);
   *om = c.take<T>(p.bn * p.ldk);
   *yp = c.take<T>(p.s * p.ldyp * p.bn);
   *ap = c.take<T>(m * p.ldk);
   *yr = c.take<T>(p.ldyp * p.bn);
+  const int64_t nparts = p.s * std::max<int64_t>(cdiv(m, 128), 1) + 64;
+  lp->ld_lp = rup(std::max<int64_t>(n, 1), 8);
+  lp->st = c.take<State>(1);
+  lp->normp = c.take<double>(nparts);
+  lp->maxp = c.take<float>(nparts);
+  lp->alp = c.take<uint16_t>(m * lp->ld_lp);
   return c.off + 256;
 }
 }  // namespace
@@ -910,7 +993,11 @@ static int validate_opts(const eodabe_opts* opts) {
   if (opts->block < 1 || opts->block > BN_MAX) return EODABE_EINVAL;
   if (opts->power_iters < 0 || opts->power_iters > 16) return EODABE_EINVAL;
   if (opts->a_dtype != EODABE_F32 && opts->a_dtype != EODABE_F64) return EODABE_EINVAL;
-  if (opts->sketch_dtype != EODABE_SKETCH_NATIVE) return EODABE_EINVAL;
+  if (opts->sketch_dtype != EODABE_SKETCH_NATIVE && opts->sketch_dtype != EODABE_SKETCH_F16 &&
+      opts->sketch_dtype != EODABE_SKETCH_BF16)
+    return EODABE_EINVAL;
+  // the low-precision sketch rounds FP32 data; FP64 data keeps the native sketch
+  if (opts->sketch_dtype != EODABE_SKETCH_NATIVE && opts->a_dtype != EODABE_F32) return EODABE_EINVAL;
   if (opts->blocks_per_sync < 0) return EODABE_EINVAL;
   return EODABE_OK;
 }
@@ -1198,12 +1285,13 @@ int eodabe_omega(eodabe_ctx* ctx, int dtype, int64_t n, int64_t col0, int64_t nc
 size_t eodabe_sketch_workspace_size(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t ncols) {
   if (!ctx || m < 0 || n < 0 || ncols < 0 || ncols > BN_MAX) return 0;
   SketchPlan p = sketch_plan(m, n, ncols);
+  SketchLp lp;
   if (ctx->o.a_dtype == EODABE_F64) {
     double *a, *b, *c, *d;
-    return sketch_carve<double>(nullptr, m, p, &a, &b, &c, &d);
+    return sketch_carve<double>(nullptr, m, n, p, &a, &b, &c, &d, &lp);
   }
   float *a, *b, *c, *d;
-  return sketch_carve<float>(nullptr, m, p, &a, &b, &c, &d);
+  return sketch_carve<float>(nullptr, m, n, p, &a, &b, &c, &d, &lp);
 }
 
 int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, int64_t col0,
@@ -1222,7 +1310,8 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
   auto body = [&](auto tag) -> int {
     typedef decltype(tag) T;
     T *om, *yp, *ap, *yr;
-    sketch_carve<T>(ws, m, p, &om, &yp, &ap, &yr);
+    SketchLp lp;
+    sketch_carve<T>(ws, m, n, p, &om, &yp, &ap, &yr, &lp);
     const T* Ae = (const T*)A;
     int64_t la = lda;
     if (!(((uintptr_t)A % 16 == 0) && (lda % 4 == 0))) {
@@ -1238,7 +1327,24 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
     LAUNCHCHK();
     Ops<T> ops{ctx, st};
     const int64_t ystr = ldyp * bn;
-    TRY(ops.sketch(Ae, la, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, nullptr, nullptr, 0));
+    const int lpm = ctx->o.a_dtype == EODABE_F32 ? ctx->o.sketch_dtype : 0;
+    if (lpm) {
+      // low-precision form: max |A| -> scale, write the FP16/BF16 copy of A,
+      // then sketch the copy (the two FP32 passes' Y partials are discarded)
+      hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, lp.st, 1.0, (int64_t*)nullptr, 0,
+                         (int32_t*)nullptr, (int64_t)0, (int32_t*)nullptr, 0, lpm);
+      TRY(ops.sketch(Ae, la, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, lp.normp, nullptr, 0,
+                     lp.maxp));
+      const int64_t nparts = (int64_t)eff_splits(n, (int)p.s) * std::max<int64_t>(cdiv(m, 128), 1);
+      hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, lp.normp, lp.maxp, nparts, lp.st);
+      TRY(ops.sketch(Ae, la, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, nullptr, nullptr, 0,
+                     nullptr, lpm, lp.alp, lp.ld_lp, lp.st));
+      if constexpr (sizeof(T) == 4)
+        TRY(ops.sketch_lp(lpm, lp.alp, lp.ld_lp, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, lp.st,
+                          nullptr, 0));
+    } else {
+      TRY(ops.sketch(Ae, la, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, nullptr, nullptr, 0));
+    }
     TRY(ops.reduce((const T*)yp, eff_splits(n, (int)p.s), ystr, ystr, yr));
     TRY(copy2d<T>(ctx, st, yr, ldyp, (T*)Y, ldy, ncols, m, 0));
     HIPCHK(hipStreamSynchronize(st));

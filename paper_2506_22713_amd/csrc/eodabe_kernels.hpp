@@ -38,7 +38,35 @@ struct State {
   int32_t pad;
   int64_t rank;          // basis width after the latest decided block
   uint32_t counter[8];   // arrival counters (reset by the last arriving workgroup)
+  double lp_scale;       // power of two applied to A before rounding it to FP16 (1 for BF16)
+  int32_t lp_mode;       // 0: none, 1: FP16, 2: BF16 (low-precision sketch form)
+  int32_t pad2;
 };
+
+// Low-precision copies of A for the sketch: IEEE binary16 or bfloat16,
+// both rounded to nearest even from FP32 and stored as 16-bit patterns.
+__device__ __forceinline__ uint16_t to_f16_bits(float x) {
+  const _Float16 h = (_Float16)x;
+  return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ uint16_t to_bf16_bits(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+template <int LPT>
+__device__ __forceinline__ uint16_t to_lp_bits(float x) {
+  if constexpr (LPT == 1) return to_f16_bits(x);
+  else return to_bf16_bits(x);
+}
+// Scale for the FP16 copy: 2^(14 - e) with max|A| = f 2^e, f in [0.5, 1),
+// so the largest entry lands in [2^13, 2^14).  BF16 needs none.
+__device__ __forceinline__ double lp_scale_of(float maxabs, int lp_mode) {
+  if (lp_mode != 1 || !(maxabs > 0.0f) || !(maxabs < INFINITY)) return 1.0;
+  int e = 0;
+  (void)frexpf(maxabs, &e);
+  return ldexp(1.0, 14 - e);
+}
 
 // Gate of closing-step kernels enqueued before the host has seen the stop
 // flag of the basis loop: they run only once the loop has stopped, ||A||_F
@@ -334,11 +362,13 @@ struct SketchCfg {
   static constexpr int LDO = KS + 16 / (int)sizeof(T);
 };
 
-template <typename T, int RT, int CT>
+template <typename T, int RT, int CT, int LPW>
 __global__ __launch_bounds__(256) void k_sketch(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ Om, int64_t ldk, int64_t M, int N,
     int64_t K, int64_t kchunk, T* __restrict__ out, int64_t ldo, int64_t part_stride,
-    double* __restrict__ sumsq, const int32_t* __restrict__ stop_block, int block_id) {
+    double* __restrict__ sumsq, float* __restrict__ maxabs, uint16_t* __restrict__ lp_out,
+    int64_t ld_lp, const State* __restrict__ lp_st, const int32_t* __restrict__ stop_block,
+    int block_id) {
   typedef Mfma<T> MF;
   typedef SketchCfg<T, RT, CT> Cfg;
   constexpr int KS = Cfg::KS, LDO = Cfg::LDO, NC = 16 * CT;
@@ -352,6 +382,9 @@ __global__ __launch_bounds__(256) void k_sketch(
   const int64_t kb = (int64_t)s * kchunk, ke = min(K, kb + kchunk);
   const bool do_ss = sumsq != nullptr;
   double ss = 0.0;
+  float mx = 0.0f;
+  float lps = 1.0f;                       // scale of the low-precision copy (LPW != 0)
+  if constexpr (LPW != 0) lps = (float)lp_st->lp_scale;
   const T* ap[RT];
   bool aval[RT];
 #pragma unroll
@@ -408,7 +441,30 @@ __global__ __launch_bounds__(256) void k_sketch(
         for (int t = 0; t < RT; ++t)
           if (aval[t])
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ss += (double)a[t].v[v] * (double)a[t].v[v];
+            for (int v = 0; v < 4; ++v) {
+              ss += (double)a[t].v[v] * (double)a[t].v[v];
+              mx = fmaxf(mx, fabsf((float)a[t].v[v]));
+            }
+      }
+      if constexpr (LPW != 0) {            // low-precision copy of this chunk of A
+        const int64_t k = sb + kl + 4 * g;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          if (!aval[t]) continue;
+          uint16_t* dst = lp_out + (m0 + 16 * t + r) * ld_lp + k;
+          if (k + 3 < se) {
+            uint2 pk;
+            pk.x = (uint32_t)to_lp_bits<LPW>((float)a[t].v[0] * lps) |
+                   ((uint32_t)to_lp_bits<LPW>((float)a[t].v[1] * lps) << 16);
+            pk.y = (uint32_t)to_lp_bits<LPW>((float)a[t].v[2] * lps) |
+                   ((uint32_t)to_lp_bits<LPW>((float)a[t].v[3] * lps) << 16);
+            *reinterpret_cast<uint2*>(dst) = pk;
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (k + v < se) dst[v] = to_lp_bits<LPW>((float)a[t].v[v] * lps);
+          }
+        }
       }
     };
     // 4-deep register pipeline over the full 16-K chunks of this slab
@@ -466,11 +522,176 @@ __global__ __launch_bounds__(256) void k_sketch(
     }
   }
   if (do_ss) {
-    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
-    if (lane == 0) ss_red[wv] = ss;
+    __shared__ float mx_red[4];
+    for (int off = 32; off > 0; off >>= 1) {
+      ss += __shfl_xor(ss, off);
+      mx = fmaxf(mx, __shfl_xor(mx, off));
+    }
+    if (lane == 0) {
+      ss_red[wv] = ss;
+      mx_red[wv] = mx;
+    }
     __syncthreads();
-    if (tid == 0)
-      sumsq[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ss_red[0] + ss_red[1] + ss_red[2] + ss_red[3];
+    if (tid == 0) {
+      const int64_t p = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+      sumsq[p] = ss_red[0] + ss_red[1] + ss_red[2] + ss_red[3];
+      if (maxabs) maxabs[p] = fmaxf(fmaxf(mx_red[0], mx_red[1]), fmaxf(mx_red[2], mx_red[3]));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Low-precision sketch partials: out_s (M x N, N <= 16*CT) = (A_lp Omega_lp)
+// / scale over K-split s, with A_lp the FP16 (LPT 1) or BF16 (LPT 2) copy of
+// A (row-major, ld_lp, 16-bit patterns) and Omega_lp = Omega^T rounded the
+// same way while it is staged in LDS; v_mfma_f32_16x16x16 f16 / bf16 with
+// FP32 accumulation.  Workgroup = 4 waves x 32 rows; each lane loads 8
+// consecutive K values of a row (16 bytes) per 32-wide K chunk and feeds
+// them to two MFMAs (K offsets 8g..8g+3 and 8g+4..8g+7 of lane group g;
+// Omega uses the same offsets, so the K sum is complete).  Partials as in
+// k_sketch (column-major, out + s*part_stride + col*ldo + row).
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+template <int LPT>
+__device__ __forceinline__ f32x4 mfma_lp(uint2 a, uint2 b, f32x4 c) {
+  if constexpr (LPT == 1)
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(f16x4, a), __builtin_bit_cast(f16x4, b),
+                                                c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                     __builtin_bit_cast(s16x4, b), c, 0, 0, 0);
+}
+
+template <int CT>
+struct SketchLpCfg {
+  static constexpr int KS = CT <= 4 ? 512 : 256;   // K per LDS slab
+  static constexpr int LDO = KS + 8;               // padded row of the staged Omega (16-bit)
+};
+
+template <int LPT, int CT>
+__global__ __launch_bounds__(256) void k_sketch_lp(
+    const uint16_t* __restrict__ A, int64_t ld_lp, const float* __restrict__ Om, int64_t ldk,
+    int64_t M, int N, int64_t K, int64_t kchunk, float* __restrict__ out, int64_t ldo,
+    int64_t part_stride, const State* __restrict__ lp_st, const int32_t* __restrict__ stop_block,
+    int block_id) {
+  constexpr int RT = 2, KS = SketchLpCfg<CT>::KS, LDO = SketchLpCfg<CT>::LDO, NC = 16 * CT;
+  if (stop_block && *stop_block < block_id) return;
+  __shared__ __align__(16) uint16_t oms[NC * LDO];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * (64 * RT) + wv * (16 * RT);
+  const int s = blockIdx.y;
+  const int64_t kb = (int64_t)s * kchunk, ke = min(K, kb + kchunk);
+  const float inv_scale = (float)(1.0 / lp_st->lp_scale);
+  const uint16_t* ap[RT];
+  bool aval[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int64_t row = m0 + 16 * t + r;
+    aval[t] = row < M;
+    ap[t] = A + (aval[t] ? row : (M - 1)) * ld_lp + 8 * g;
+  }
+  f32x4 acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bool active = (m0 < M);
+  for (int64_t sb = kb; sb < ke; sb += KS) {
+    const int64_t se = min(ke, sb + KS);
+    const int slen = (int)(se - sb);
+    __syncthreads();
+    // stage Omega^T[0:NC, sb:se] rounded to the low precision (zero beyond se and N)
+    for (int idx = tid; idx < NC * (KS / 4); idx += 256) {
+      const int c = idx / (KS / 4), k4 = (idx - c * (KS / 4)) * 4;
+      float v[4];
+      if (c >= N) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = 0.f;
+      } else if (k4 + 3 < slen) {
+        const f32x4 x = *reinterpret_cast<const f32x4*>(Om + (int64_t)c * ldk + sb + k4);
+        v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (k4 + e < slen) ? Om[(int64_t)c * ldk + sb + k4 + e] : 0.f;
+      }
+      uint2 pk;
+      pk.x = (uint32_t)to_lp_bits<LPT>(v[0]) | ((uint32_t)to_lp_bits<LPT>(v[1]) << 16);
+      pk.y = (uint32_t)to_lp_bits<LPT>(v[2]) | ((uint32_t)to_lp_bits<LPT>(v[3]) << 16);
+      *reinterpret_cast<uint2*>(&oms[c * LDO + k4]) = pk;
+    }
+    __syncthreads();
+    if (!active) continue;
+    const int nfull = slen / 32;
+    auto compute = [&](const uint4 (&a)[RT], int kl) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint2 b[CT];
+#pragma unroll
+        for (int u = 0; u < CT; ++u)
+          b[u] = *reinterpret_cast<const uint2*>(&oms[(16 * u + r) * LDO + kl + 8 * g + 4 * h]);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const uint2 av = h == 0 ? uint2{a[t].x, a[t].y} : uint2{a[t].z, a[t].w};
+#pragma unroll
+          for (int u = 0; u < CT; ++u) acc[t][u] = mfma_lp<LPT>(av, b[u], acc[t][u]);
+        }
+      }
+    };
+    // 4-deep register pipeline over the full 32-K chunks of this slab
+    uint4 a[4][RT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nfull)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) a[q][t] = *reinterpret_cast<const uint4*>(ap[t] + sb + 32 * q);
+    for (int c = 0; c < nfull; c += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (c + q < nfull) {
+          compute(a[q], 32 * (c + q));
+          if (c + q + 4 < nfull)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+              a[q][t] = *reinterpret_cast<const uint4*>(ap[t] + sb + 32 * (c + q + 4));
+        }
+      }
+    }
+    if (nfull * 32 < slen) {                  // ragged tail: element loads, zero beyond se
+      uint4 at[RT];
+      const int64_t k = sb + 32 * nfull + 8 * g;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        uint16_t v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (k + e < se) ? ap[t][k - 8 * g + e] : (uint16_t)0;
+        at[t].x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+        at[t].y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+        at[t].z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+        at[t].w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+      }
+      compute(at, 32 * nfull);
+    }
+  }
+  if (!active) return;
+  float* o = out + (int64_t)s * part_stride;
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+      const int64_t col = 16 * u + r;
+      if (col >= N) continue;
+      const int64_t row = m0 + 16 * t + 4 * g;
+      float* p = o + col * ldo + row;
+      if (row + 3 < M && ((ldo & 3) == 0) && ((part_stride & 3) == 0)) {
+        *reinterpret_cast<f32x4*>(p) = acc[t][u] * inv_scale;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (row + e < M) p[e] = acc[t][u][e] * inv_scale;
+      }
+    }
   }
 }
 
@@ -962,6 +1183,7 @@ struct CholArgs {
   int32_t* acc;
   double* diag_log;
   const double* norm_parts;  // non-null: finish ||A||_F and eps = tol ||A||_F first
+  const float* max_parts;    // with norm_parts: per-workgroup max |A| -> st->lp_scale
   int64_t n_norm;
   Gate gate;               // closing steps enqueued ahead of the stop flag
   const int64_t* f_dev;    // non-null: block width read on the device (<= the template width)
@@ -1195,13 +1417,21 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   State* st = ca.st;
   if (ca.norm_parts && wv == 0) {    // ||A||_F from the sketch partials (fixed order)
     double a = 0.0;
-    for (int64_t i = lane; i < ca.n_norm; i += 64) a += ca.norm_parts[i];
-    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    float mx = 0.0f;
+    for (int64_t i = lane; i < ca.n_norm; i += 64) {
+      a += ca.norm_parts[i];
+      if (ca.max_parts) mx = fmaxf(mx, ca.max_parts[i]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off);
+      mx = fmaxf(mx, __shfl_xor(mx, off));
+    }
     if (lane == 0) {
       st->normsq = a;
       const bool bad = !(a < INFINITY);
       st->nonfinite = bad ? 1 : 0;
       st->eps = bad ? 0.0 : st->tol * sqrt(a);
+      st->lp_scale = lp_scale_of(mx, st->lp_mode);
     }
   }
   int dl = 0;
@@ -1475,15 +1705,26 @@ __global__ void k_decide(const double* __restrict__ R1, const double* __restrict
   if (stop) st->stop_block = block_id;
 }
 
-// ||A||_F from per-workgroup partial sums (fixed order), eps = tol ||A||_F.
-__global__ void k_finish_norm(const double* __restrict__ parts, int64_t nparts, State* st) {
+// ||A||_F from per-workgroup partial sums (fixed order), eps = tol ||A||_F,
+// and the scale of the low-precision copy from the per-workgroup max |A|.
+__global__ void k_finish_norm(const double* __restrict__ parts, const float* __restrict__ maxp,
+                              int64_t nparts, State* st) {
   __shared__ double red[256];
+  __shared__ float redm[256];
   double a = 0.0;
-  for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) a += parts[i];
+  float mx = 0.0f;
+  for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+    a += parts[i];
+    if (maxp) mx = fmaxf(mx, maxp[i]);
+  }
   red[threadIdx.x] = a;
+  redm[threadIdx.x] = mx;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    if ((int)threadIdx.x < off) {
+      red[threadIdx.x] += red[threadIdx.x + off];
+      redm[threadIdx.x] = fmaxf(redm[threadIdx.x], redm[threadIdx.x + off]);
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -1492,15 +1733,17 @@ __global__ void k_finish_norm(const double* __restrict__ parts, int64_t nparts, 
     const bool bad = !(s < INFINITY);   // NaN or Inf
     st->nonfinite = bad ? 1 : 0;
     st->eps = bad ? 0.0 : st->tol * sqrt(s);
+    st->lp_scale = lp_scale_of(redm[0], st->lp_mode);
   }
 }
 
 __global__ void k_init_state(State* st, double tol, int64_t* wlog, int nwlog, int32_t* dead,
-                             int64_t ndead, int32_t* acc, int nacc) {
+                             int64_t ndead, int32_t* acc, int nacc, int lp_mode) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->eps = 0.0; st->normsq = 0.0; st->tol = tol;
     st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->pad = 0; st->rank = 0;
     for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
+    st->lp_scale = 1.0; st->lp_mode = lp_mode; st->pad2 = 0;
   }
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = t; i < nwlog; i += nt) wlog[i] = 0;

@@ -294,3 +294,71 @@ def test_hyperspectral_small_fp32():
 def test_mat2_fp64():
     A = W.mat2(1, 600, 240)
     check_factor(A, torch.float64, 1e-12, b=32, seed=1)
+
+
+# ------------------------------------------------- low-precision sketch form
+@pytest.mark.parametrize("mode", ["f16", "bf16"])
+def test_sketch_lp_kernel(mode):
+    say("sketch lp kernel", mode)
+    rng = np.random.default_rng(7)
+    A = (rng.standard_normal((1000, 700)) * 40.0).astype(np.float32).astype(np.float64)
+    code = E.SKETCH_F16 if mode == "f16" else E.SKETCH_BF16
+    c = E.Context(seed=21, sketch=code)
+    Y = E.sketch(c, dev(A, torch.float32), 5, 40).cpu().numpy().astype(np.float64)
+    s = O.lp_scale(A, mode)
+    Alp = O.lp_round((A * s).astype(np.float32), mode)
+    Om = O.lp_round(O.omega_columns(21, 700, 5, 40).astype(np.float32), mode)
+    ref = (Alp @ Om) / s
+    bound = 2 * 700 * U32 * (np.abs(Alp) @ np.abs(Om)) / s
+    assert np.all(np.abs(Y - ref) <= bound + 1e-30)
+
+
+# Error bars of the low-precision form, as absolute differences of RelErr
+# from the FP64 oracle: FP16 (2^-11 relative rounding of A) within 1e-3;
+# BF16 (2^-8, about 1.6e-3 RMS relative rounding of A) within 2e-3.
+LP_ERR = {"f16": 1e-3, "bf16": 2e-3}
+
+
+def _check_lp_factor(A, tol, b, seed, mode, err_tol=None):
+    code = E.SKETCH_F16 if mode == "f16" else E.SKETCH_BF16
+    f = E.factor(dev(A, torch.float32), tol, block=b, seed=seed, sketch=code)
+    torch.cuda.synchronize()
+    ref = O.eod_abe(A, tol, k=b, q=0, seed=seed)
+    stable, r64, rlp = O.precision_stable(A, tol, b, seed, mode)
+    assert f.blocks >= 3                       # the low-precision blocks did run
+    if stable:
+        assert f.rank == r64, (f.rank, r64, rlp)
+    else:
+        assert f.rank in (r64, rlp), (f.rank, r64, rlp)
+    e_gpu, U, D, Vt = gpu_relerr(A, f)
+    e_ref = O.rel_err(A, ref.U, ref.D, ref.V)
+    if err_tol is None:
+        assert abs(e_gpu - e_ref) <= LP_ERR[mode], (e_gpu, e_ref)
+    else:
+        assert e_gpu <= err_tol, (e_gpu, e_ref)
+    r = f.rank
+    assert np.linalg.norm(U.T @ U - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
+    assert np.linalg.norm(Vt @ Vt.T - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
+    return f, ref
+
+
+def test_factor_f16_sketch_image():
+    say("factor f16 sketch image 1024")
+    A = W.image(0, 1024, 0.05).astype(np.float64)
+    _check_lp_factor(A, 1e-3, 8, 0, "f16")
+
+
+@pytest.mark.parametrize("mode", ["f16", "bf16"])
+def test_factor_lp_sketch_hyperspectral(mode):
+    say("factor lp sketch hyperspectral 16384", mode)
+    A = W.hyperspectral(0, pixels=16384).astype(np.float64)
+    _check_lp_factor(A, 1e-2, 4, 0, mode)
+
+
+def test_factor_f16_sketch_exact_rank():
+    say("factor f16 sketch exact rank")
+    # exact rank 40 with sigma_40 = sigma_1 / 10: the rank is exact, and the
+    # subspace tilt by ||A - A_f16|| / sigma_40 keeps RelErr under tol
+    A = W.lowrank_haar(4, m=400, n=300, r=40, noise_std=0.0, decades=1.0).astype(np.float32).astype(np.float64)
+    f, ref = _check_lp_factor(A, 1e-2, 8, 4, "f16", err_tol=1e-2)
+    assert f.rank == 40

@@ -305,3 +305,43 @@ def test_planted_mistake_is_caught(monkeypatch, mutant):
     except Exception:
         return                                      # a crash also counts as caught
     assert not _pins_hold(A, res)
+
+
+# ------------------------------------------------- low-precision sketch form
+def test_bf16_rounding_pins():
+    # bfloat16 keeps 7 fraction bits: 1 + 2^-8 is a tie between 1 and
+    # 1 + 2^-7 and goes to the even neighbour 1; 1 + 3*2^-8 goes up to the
+    # even neighbour 1 + 2^-6; pi -> 0x4049 = 3.140625
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, np.pi, -3.0], dtype=np.float32)
+    got = O.round_bf16(x)
+    assert got.tolist() == [1.0, 1.0, 1.0 + 2.0 ** -6, 3.140625, -3.0]
+    bits = np.array([3.140625], dtype=np.float32).view(np.uint32)[0] >> 16
+    assert bits == 0x4049
+
+
+def test_f16_scale_rule():
+    # max|A| = 255.047 = 0.996 * 2^8 -> scale 2^(14-8) = 64, max*scale in [2^13, 2^14)
+    A = np.array([[255.047, -3.0], [1e-3, 0.0]])
+    s = O.lp_scale(A, "f16")
+    assert s == 64.0 and 2 ** 13 <= 255.047 * s < 2 ** 14
+    assert O.lp_scale(A, "bf16") == 1.0
+    assert O.lp_scale(np.zeros((2, 2)), "f16") == 1.0
+
+
+def test_lp_form_first_two_blocks_exact_and_rank_recovery():
+    # blocks 1 and 2 sketch A itself; with an exact-rank input (E = 0) whose
+    # rank fits in two blocks, the f16 form returns the FP64 run exactly
+    A = W.lowrank_haar(3, m=300, n=200, r=12, noise_std=0.0)
+    nrm = np.linalg.norm(A)
+    ref = O.basis_ext(A, 1e-6 * nrm, 8, 3)
+    lp = O.basis_ext(A, 1e-6 * nrm, 8, 3, "f16")
+    assert ref["rank"] == lp["rank"] == 12
+    assert np.array_equal(ref["diagT"], lp["diagT"])
+    # ranks beyond two blocks: FP16 rounding (2^-11 relative per entry)
+    # keeps the captured subspace well inside tol = 1e-2, so the exact rank
+    # is recovered; BF16 (2^-8) tilts it by about ||A - A_bf16|| / sigma_r,
+    # which can push the test over a few columns but never past the block
+    A = W.lowrank_haar(4, m=400, n=300, r=40, noise_std=0.0, decades=1.0)
+    assert O.basis_ext(A, 1e-2 * np.linalg.norm(A), 8, 4, "f16")["rank"] == 40
+    r = O.basis_ext(A, 1e-2 * np.linalg.norm(A), 8, 4, "bf16")["rank"]
+    assert 40 <= r <= 48, r

@@ -170,6 +170,42 @@ int eodabe_basis(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t l
                  double tol, void* ws, size_t ws_bytes, void* Q, int64_t r_cap,
                  double* diagT, int64_t diag_cap, eodabe_info* info);
 
+/* ---- many small matrices (tiles) in one launch -------------------------
+ * Each tile A_t (m[t] x n[t] FP32, row-major, lda[t] >= n[t], device
+ * pointer A[t]; 1 <= m[t], n[t] <= 1024) is factored exactly as
+ * eodabe_factor would with q = 0, the context's seed and a block width per
+ * tile-size bucket (opts.block clamped to 64, or the width chosen by
+ * eodabe_tune_batched).  The tiles run in one persistent launch (one
+ * workgroup per tile at a time, largest tiles first), replayed from a
+ * hipGraph when the same workspace, pool, tile count, tol and seed come
+ * back.  Outputs go to the device pool out_pool (FP32, pool_len elements)
+ * at element offset out_offsets[t]: Ut (r_caps[t] x m[t] row-major), then core
+ * (r_caps[t] x r_caps[t]), then Vt (r_caps[t] x n[t]), laid out as for
+ * eodabe_factor; r_caps[t] <= min(m[t], n[t]), 0 = min(m[t], n[t]); each
+ * tile's r_cap * (m + r_cap + n) elements must lie inside the pool (tiles
+ * must not overlap each other or the inputs: not checked).
+ * Host outputs: ranks[t], status[t] (0 ok, 2 non-finite, 3 rank > r_cap)
+ * and, when non-NULL, blocks_used[t] (the block width used).  A tile whose
+ * rank exceeds 64 is finished by the single-matrix path within the same
+ * call.  All arrays except A's targets and out_pool are host arrays.
+ * Errors: EINVAL (sizes, tol, dtype not F32, NULL arrays), EWORKSPACE,
+ * EHIP; the call returns after the batch has completed. */
+size_t eodabe_batched_workspace_size(eodabe_ctx* ctx, int ntiles);
+int eodabe_factor_batched(eodabe_ctx* ctx, int ntiles, const void* const* A, const int64_t* m,
+                          const int64_t* n, const int64_t* lda, double tol, void* ws, size_t ws_bytes,
+                          void* out_pool, int64_t pool_len, const int64_t* out_offsets,
+                          const int64_t* r_caps, int64_t* ranks, int32_t* status, int32_t* blocks_used);
+
+/* Autotuner of the batched launch: for each tile-size bucket present
+ * (max side <= 128, 256, 512, 1024) it times eodabe_factor_batched on the
+ * given tiles with block widths 16, 32 and 64 and keeps the fastest in the
+ * context (chosen[4] receives the widths, 0 for absent buckets).  Same
+ * arguments and errors as eodabe_factor_batched. */
+int eodabe_tune_batched(eodabe_ctx* ctx, int ntiles, const void* const* A, const int64_t* m,
+                        const int64_t* n, const int64_t* lda, double tol, void* ws, size_t ws_bytes,
+                        void* out_pool, int64_t pool_len, const int64_t* out_offsets, const int64_t* r_caps,
+                        int32_t* chosen);
+
 #ifdef __cplusplus
 }
 #endif

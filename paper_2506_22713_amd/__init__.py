@@ -40,6 +40,7 @@ EXPORTED = [
     "eodabe_default_opts", "eodabe_create", "eodabe_create_host", "eodabe_destroy", "eodabe_workspace_size",
     "eodabe_factor", "eodabe_strerror", "eodabe_last_hip_error", "eodabe_philox",
     "eodabe_omega", "eodabe_sketch_workspace_size", "eodabe_sketch", "eodabe_basis",
+    "eodabe_batched_workspace_size", "eodabe_factor_batched", "eodabe_tune_batched",
     "eodabe_profile", "eodabe_profile_read",
 ]
 PROF_SKETCH, PROF_PROJECT = 0, 1
@@ -88,6 +89,13 @@ _lib.eodabe_sketch_workspace_size.argtypes = [_vp, _i64, _i64, _i64]
 _lib.eodabe_sketch_workspace_size.restype = _sz
 _lib.eodabe_sketch.argtypes = [_vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _sz]
 _lib.eodabe_sketch.restype = ctypes.c_int
+_lib.eodabe_batched_workspace_size.argtypes = [_vp, ctypes.c_int]
+_lib.eodabe_batched_workspace_size.restype = _sz
+_batched_args = [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _sz, _vp, ctypes.c_int64, _vp, _vp]
+_lib.eodabe_factor_batched.argtypes = _batched_args + [_vp, _vp, _vp]
+_lib.eodabe_factor_batched.restype = ctypes.c_int
+_lib.eodabe_tune_batched.argtypes = _batched_args + [_vp]
+_lib.eodabe_tune_batched.restype = ctypes.c_int
 _lib.eodabe_profile.argtypes = [_vp, ctypes.c_int]
 _lib.eodabe_profile.restype = ctypes.c_int
 _lib.eodabe_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -274,3 +282,67 @@ def sketch(ctx: Context, A: torch.Tensor, col0: int, ncols: int) -> torch.Tensor
     ctx._check(_lib.eodabe_sketch(ctx.h, A.data_ptr(), m, n, lda, col0, ncols, Yt.data_ptr(),
                                   max(m, 1), ws.data_ptr(), ws.numel()), "eodabe_sketch")
     return Yt[:ncols, :m].T
+
+
+# ---------------------------------------------------------------- batched tiles
+TILE_STATUS = {0: "ok", 1: "rank above the in-kernel cap (finished by the single-matrix path)",
+               2: "non-finite", 3: "rank above r_cap"}
+
+
+class Batch:
+    """Argument arrays, output pool and workspace of eodabe_factor_batched
+    for a fixed list of FP32 tiles (kept alive between calls)."""
+
+    def __init__(self, ctx: Context, tiles, r_caps=None):
+        import numpy as np
+        self.ctx, self.tiles = ctx, list(tiles)
+        nt = len(self.tiles)
+        for T in self.tiles:
+            _check_matrix(T, torch.float32)
+        self.m = np.array([T.shape[0] for T in self.tiles], dtype=np.int64)
+        self.n = np.array([T.shape[1] for T in self.tiles], dtype=np.int64)
+        self.lda = np.array([T.stride(0) if T.shape[0] > 1 else max(T.shape[1], 1) for T in self.tiles],
+                            dtype=np.int64)
+        self.ptrs = (ctypes.c_void_p * max(nt, 1))(*[T.data_ptr() for T in self.tiles])
+        rc = np.minimum(self.m, self.n) if r_caps is None else np.asarray(r_caps, dtype=np.int64)
+        self.r_caps = rc.astype(np.int64)
+        sizes = self.r_caps * self.m + self.r_caps * self.r_caps + self.r_caps * self.n
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64) if nt else np.zeros(0, np.int64)
+        dev = self.tiles[0].device if nt else torch.device("cuda")
+        self.pool = torch.empty(int(sizes.sum()) if nt else 1, dtype=torch.float32, device=dev)
+        nb = int(_lib.eodabe_batched_workspace_size(ctx.h, nt))
+        self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        self.ranks = np.zeros(nt, dtype=np.int64)
+        self.status = np.zeros(nt, dtype=np.int32)
+        self.blocks = np.zeros(nt, dtype=np.int32)
+
+    def _args(self, tol):
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        return [self.ctx.h, len(self.tiles), ctypes.cast(self.ptrs, ctypes.c_void_p), p(self.m), p(self.n),
+                p(self.lda), float(tol), self.ws.data_ptr(), self.ws.numel(), self.pool.data_ptr(),
+                self.pool.numel(), p(self.offsets), p(self.r_caps)]
+
+    def run(self, tol: float):
+        """eodabe_factor_batched; ranks, status and block widths land in
+        self.ranks, self.status, self.blocks."""
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        st = _lib.eodabe_factor_batched(*self._args(tol), p(self.ranks), p(self.status), p(self.blocks))
+        self.ctx._check(st, "eodabe_factor_batched")
+        return self
+
+    def tune(self, tol: float):
+        """eodabe_tune_batched: block width per tile-size bucket (kept in ctx)."""
+        import numpy as np
+        chosen = np.zeros(4, dtype=np.int32)
+        st = _lib.eodabe_tune_batched(*self._args(tol), chosen.ctypes.data_as(ctypes.c_void_p))
+        self.ctx._check(st, "eodabe_tune_batched")
+        return chosen
+
+    def result(self, t: int):
+        """(U (m x r), D (r x r), Vt (r x n), rank, status) of tile t."""
+        m, n, rc, off = int(self.m[t]), int(self.n[t]), int(self.r_caps[t]), int(self.offsets[t])
+        r = int(self.ranks[t])
+        Ut = self.pool[off: off + rc * m].view(rc, m)
+        core = self.pool[off + rc * m: off + rc * m + rc * rc].view(rc, rc)
+        Vt = self.pool[off + rc * m + rc * rc: off + rc * m + rc * rc + rc * n].view(rc, n)
+        return Ut[:r].T, core[:r, :r], Vt[:r], r, int(self.status[t])

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -15,6 +16,7 @@
 
 #include "../../include/eodabe.h"
 #include "eodabe_kernels.hpp"
+#include "eodabe_tiles.hpp"
 
 using namespace eodabe;
 
@@ -36,6 +38,17 @@ struct eodabe_ctx {
   double prof_ms[EODABE_PROF_KINDS] = {0, 0};
   int64_t prof_n[EODABE_PROF_KINDS] = {0, 0};
   double prof_bytes[EODABE_PROF_KINDS] = {0, 0};
+  // batched tiles: pinned staging of descriptors and results, a private
+  // stream for the captured launch, the graph and its key, tuned widths
+  void* tile_host = nullptr;
+  size_t tile_host_bytes = 0;
+  hipStream_t tile_stream = nullptr;
+  hipEvent_t tile_ev = nullptr;
+  hipGraph_t tile_graph = nullptr;
+  hipGraphExec_t tile_exec = nullptr;
+  struct { const void* ws; const void* pool; int ntiles, grid; double tol; uint64_t seed; } tile_key{};
+  int tile_b[4] = {0, 0, 0, 0};   // block width per tile-size bucket (0: opts.block)
+  int tile_graphs = 1;            // capture the launch in a hipGraph
 };
 
 namespace {
@@ -972,10 +985,236 @@ size_t sketch_carve(void* base, int64_t m, int64_t n, const SketchPlan& p, T** o
 }
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Batched tiles
+// ---------------------------------------------------------------------------
+namespace {
+int tile_bucket(int64_t side) { return side <= 128 ? 0 : (side <= 256 ? 1 : (side <= 512 ? 2 : 3)); }
+int tile_slots(const eodabe_ctx* ctx) { return ctx->host_only ? 256 : std::max(ctx->cu_count, 1); }
+
+struct BatchWS {
+  TileDesc* descs;
+  TileResult* res;
+  uint32_t* queue;
+  char* slots;
+  void* fws;            // workspace of the regular path (tiles above the in-kernel rank cap)
+  size_t fws_bytes;
+  size_t total;
+};
+BatchWS batch_carve(void* base, eodabe_ctx* ctx, int ntiles) {
+  Carver c(base);
+  BatchWS b{};
+  b.descs = c.take<TileDesc>(std::max(ntiles, 1));
+  b.res = c.take<TileResult>(std::max(ntiles, 1));
+  b.queue = c.take<uint32_t>(64);
+  b.slots = c.take<char>((int64_t)tile_slots(ctx) * TileSlot::BYTES);
+  eodabe_opts o = ctx->o;
+  o.a_dtype = EODABE_F32;
+  eodabe_ctx tmp{};
+  tmp.o = o;
+  tmp.host_only = true;
+  b.fws_bytes = eodabe_workspace_size(&tmp, TILE_MAX, TILE_MAX, TILE_MAX);
+  b.fws = c.take<char>((int64_t)b.fws_bytes);
+  b.total = c.off + 256;
+  return b;
+}
+
+int tile_block(const eodabe_ctx* ctx, int64_t h, int64_t w) {
+  const int t = ctx->tile_b[tile_bucket(std::max(h, w))];
+  const int b = t > 0 ? t : ctx->o.block;
+  return std::max(1, std::min(b, TILE_BMAX));
+}
+
+// Enqueue the batch on the private stream (descriptor copy, queue reset,
+// persistent kernel, result copy), captured once into a hipGraph per key and
+// replayed afterwards; the host copies read the pinned staging buffer when
+// they execute, so new descriptors need no new capture.
+int batch_launch(eodabe_ctx* ctx, const BatchWS& b, int ntiles, int grid, float* pool, double tol,
+                 void* ws) {
+  hipStream_t st = ctx->tile_stream;
+  TileDesc* hd = (TileDesc*)ctx->tile_host;
+  TileResult* hr = (TileResult*)((char*)ctx->tile_host + (size_t)ntiles * sizeof(TileDesc));
+  const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
+  auto enqueue = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(b.descs, hd, (size_t)ntiles * sizeof(TileDesc), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_zero<uint32_t>, dim3(1), dim3(64), 0, st, b.queue, (int64_t)64);
+    hipLaunchKernelGGL(k_tiles, dim3(grid), dim3(256), 0, st, b.descs, ntiles, b.queue, b.slots, pool,
+                       b.res, tol, k0, k1);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(hr, b.res, (size_t)ntiles * sizeof(TileResult), hipMemcpyDeviceToHost, st));
+    return 0;
+  };
+  if (!ctx->tile_graphs) {
+    TRY(enqueue());
+    return 0;
+  }
+  const bool same = ctx->tile_exec && ctx->tile_key.ws == ws && ctx->tile_key.pool == pool &&
+                    ctx->tile_key.ntiles == ntiles && ctx->tile_key.grid == grid &&
+                    ctx->tile_key.tol == tol && ctx->tile_key.seed == ctx->o.seed;
+  if (!same) {
+    if (ctx->tile_exec) (void)hipGraphExecDestroy(ctx->tile_exec);
+    if (ctx->tile_graph) (void)hipGraphDestroy(ctx->tile_graph);
+    ctx->tile_exec = nullptr;
+    ctx->tile_graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int e = enqueue();
+    hipGraph_t gph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(st, &gph);
+    TRY(e);
+    HIPCHK(ce);
+    ctx->tile_graph = gph;
+    HIPCHK(hipGraphInstantiate(&ctx->tile_exec, gph, nullptr, nullptr, 0));
+    ctx->tile_key.ws = ws;
+    ctx->tile_key.pool = pool;
+    ctx->tile_key.ntiles = ntiles;
+    ctx->tile_key.grid = grid;
+    ctx->tile_key.tol = tol;
+    ctx->tile_key.seed = ctx->o.seed;
+  }
+  HIPCHK(hipGraphLaunch(ctx->tile_exec, st));
+  return 0;
+}
+}  // namespace
+
 // ==========================================================================
 // C ABI
 // ==========================================================================
 extern "C" {
+
+size_t eodabe_batched_workspace_size(eodabe_ctx* ctx, int ntiles) {
+  if (!ctx || ntiles < 0) return 0;
+  return batch_carve(nullptr, ctx, ntiles).total;
+}
+
+int eodabe_factor_batched(eodabe_ctx* ctx, int ntiles, const void* const* A, const int64_t* m,
+                          const int64_t* n, const int64_t* lda, double tol, void* ws, size_t ws_bytes,
+                          void* out_pool, int64_t pool_len, const int64_t* out_offsets,
+                          const int64_t* r_caps, int64_t* ranks, int32_t* status, int32_t* blocks_used) {
+  TRY(check_ctx(ctx));
+  if (ntiles < 0 || (ntiles > 0 && (!A || !m || !n || !lda || !out_offsets || !r_caps || !ranks || !status)))
+    return EODABE_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return EODABE_EINVAL;
+  if (ctx->o.a_dtype != EODABE_F32) return EODABE_EINVAL;
+  for (int t = 0; t < ntiles; ++t) {
+    if (m[t] < 1 || n[t] < 1 || m[t] > TILE_MAX || n[t] > TILE_MAX || lda[t] < n[t] || !A[t]) return EODABE_EINVAL;
+    if (r_caps[t] < 0 || r_caps[t] > std::min(m[t], n[t]) || out_offsets[t] < 0) return EODABE_EINVAL;
+    const int64_t rc = r_caps[t] ? r_caps[t] : std::min(m[t], n[t]);
+    if (out_offsets[t] > pool_len || rc * (m[t] + rc + n[t]) > pool_len - out_offsets[t]) return EODABE_EINVAL;
+  }
+  if (ntiles == 0) return EODABE_OK;
+  const BatchWS b = batch_carve(ws, ctx, ntiles);
+  if (!ws || ws_bytes < b.total || !out_pool) return EODABE_EWORKSPACE;
+  TRY(check_dev(ctx));
+  if (!ctx->tile_stream) {
+    HIPCHK(hipStreamCreateWithFlags(&ctx->tile_stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->tile_ev, hipEventDisableTiming));
+  }
+  const size_t hbytes = (size_t)ntiles * (sizeof(TileDesc) + sizeof(TileResult));
+  if (ctx->tile_host_bytes < hbytes) {
+    if (ctx->tile_host) HIPCHK(hipHostFree(ctx->tile_host));
+    ctx->tile_host = nullptr;
+    ctx->tile_host_bytes = 0;
+    HIPCHK(hipHostMalloc(&ctx->tile_host, hbytes, hipHostMallocDefault));
+    ctx->tile_host_bytes = hbytes;
+    if (ctx->tile_exec) (void)hipGraphExecDestroy(ctx->tile_exec);   // staging moved
+    ctx->tile_exec = nullptr;
+  }
+  // largest tiles first (longest-processing-time order over the workgroups)
+  std::vector<int> order(ntiles);
+  for (int t = 0; t < ntiles; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return m[a] * n[a] > m[c] * n[c]; });
+  TileDesc* hd = (TileDesc*)ctx->tile_host;
+  for (int i = 0; i < ntiles; ++i) {
+    const int t = order[i];
+    TileDesc d{};
+    d.A = (const float*)A[t];
+    d.h = m[t];
+    d.w = n[t];
+    d.lda = lda[t];
+    d.out_off = out_offsets[t];
+    d.r_cap = r_caps[t] ? r_caps[t] : std::min(m[t], n[t]);
+    d.b = tile_block(ctx, m[t], n[t]);
+    d.index = t;
+    hd[i] = d;
+  }
+  // inputs are produced on the caller's stream
+  HIPCHK(hipEventRecord(ctx->tile_ev, ctx->stream));
+  HIPCHK(hipStreamWaitEvent(ctx->tile_stream, ctx->tile_ev, 0));
+  const int grid = std::min(ntiles, tile_slots(ctx));
+  TRY(batch_launch(ctx, b, ntiles, grid, (float*)out_pool, tol, ws));
+  HIPCHK(hipStreamSynchronize(ctx->tile_stream));
+  const TileResult* hr = (const TileResult*)((char*)ctx->tile_host + (size_t)ntiles * sizeof(TileDesc));
+  int first_err = EODABE_OK;
+  for (int t = 0; t < ntiles; ++t) {
+    ranks[t] = hr[t].rank;
+    status[t] = hr[t].status;
+    if (blocks_used) blocks_used[t] = tile_block(ctx, m[t], n[t]);
+  }
+  // tiles whose rank went above the in-kernel cap: the regular path
+  for (int t = 0; t < ntiles; ++t) {
+    if (status[t] != TS_RANK) continue;
+    eodabe_opts o = ctx->o;
+    o.block = tile_block(ctx, m[t], n[t]);
+    eodabe_ctx* sub = nullptr;
+    o.stream = ctx->stream;
+    TRY(eodabe_create(&sub, &o));
+    const int64_t rc = r_caps[t] ? r_caps[t] : std::min(m[t], n[t]);
+    float* Ut = (float*)out_pool + out_offsets[t];
+    float* core = Ut + rc * m[t];
+    float* Vt = core + rc * rc;
+    eodabe_info info{};
+    const int e = eodabe_factor(sub, A[t], m[t], n[t], lda[t], tol, b.fws, b.fws_bytes, Ut, core, Vt, rc,
+                                &info);
+    eodabe_destroy(sub);
+    ranks[t] = info.rank;
+    status[t] = e == EODABE_ECAPACITY ? TS_CAPACITY : (e == EODABE_ENONFINITE ? TS_NONFINITE : (e < 0 ? -1 : TS_OK));
+    if (e < 0 && e != EODABE_ECAPACITY && e != EODABE_ENONFINITE && first_err == EODABE_OK) first_err = e;
+  }
+  return first_err;
+}
+
+// Pick the block width per tile-size bucket (sides <= 128, 256, 512, 1024)
+// among {16, 32, 64} by timing the whole batch, one bucket at a time; the
+// choice is kept in the context for later eodabe_factor_batched calls.
+int eodabe_tune_batched(eodabe_ctx* ctx, int ntiles, const void* const* A, const int64_t* m,
+                        const int64_t* n, const int64_t* lda, double tol, void* ws, size_t ws_bytes,
+                        void* out_pool, int64_t pool_len, const int64_t* out_offsets, const int64_t* r_caps,
+                        int32_t* chosen) {
+  TRY(check_ctx(ctx));
+  TRY(check_dev(ctx));
+  if (ntiles <= 0) return EODABE_EINVAL;
+  std::vector<int64_t> rk(ntiles);
+  std::vector<int32_t> stt(ntiles);
+  const int cand[3] = {16, 32, 64};
+  for (int k = 0; k < 4; ++k) {
+    bool present = false;
+    for (int t = 0; t < ntiles; ++t) present = present || tile_bucket(std::max(m[t], n[t])) == k;
+    if (!present) continue;
+    double best = 1e300;
+    int bestb = ctx->tile_b[k];
+    for (int c : cand) {
+      ctx->tile_b[k] = c;
+      double tot = 0.0;
+      for (int rep = 0; rep < 2; ++rep) {
+        const auto t0 = std::chrono::steady_clock::now();
+        TRY(eodabe_factor_batched(ctx, ntiles, A, m, n, lda, tol, ws, ws_bytes, out_pool, pool_len, out_offsets,
+                                  r_caps, rk.data(), stt.data(), nullptr));
+        const auto t1 = std::chrono::steady_clock::now();
+        if (rep) tot += std::chrono::duration<double>(t1 - t0).count();
+      }
+      if (tot < best) {
+        best = tot;
+        bestb = c;
+      }
+    }
+    ctx->tile_b[k] = bestb;
+  }
+  if (chosen)
+    for (int k = 0; k < 4; ++k) chosen[k] = ctx->tile_b[k];
+  return EODABE_OK;
+}
+
 
 void eodabe_default_opts(eodabe_opts* o) {
   if (!o) return;
@@ -1078,6 +1317,11 @@ void eodabe_destroy(eodabe_ctx* ctx) {
   }
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+  if (ctx->tile_exec) (void)hipGraphExecDestroy(ctx->tile_exec);
+  if (ctx->tile_graph) (void)hipGraphDestroy(ctx->tile_graph);
+  if (ctx->tile_ev) (void)hipEventDestroy(ctx->tile_ev);
+  if (ctx->tile_stream) (void)hipStreamDestroy(ctx->tile_stream);
+  if (ctx->tile_host) (void)hipHostFree(ctx->tile_host);
   delete ctx;
 }
 

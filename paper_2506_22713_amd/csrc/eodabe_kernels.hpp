@@ -111,6 +111,14 @@ __device__ __forceinline__ void box_muller(uint32_t x, uint32_t y, float& z0, fl
   z1 = (float)(rad * s);
 }
 
+// Rows 4q .. 4q+3 of column c of Omega: Philox counter (q, c, 0, 0); words
+// (x0,x1) -> rows 4q, 4q+1 and (x2,x3) -> rows 4q+2, 4q+3.
+__device__ __forceinline__ void omega4(uint32_t k0, uint32_t k1, int64_t q, int64_t c, float (&z)[4]) {
+  U4 r = philox4x32_10(U4{(uint32_t)q, (uint32_t)c, 0u, 0u}, k0, k1);
+  box_muller(r.x, r.y, z[0], z[1]);
+  box_muller(r.z, r.w, z[2], z[3]);
+}
+
 __global__ void k_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                          int64_t count, uint32_t* __restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -131,11 +139,7 @@ __global__ void k_omega(uint32_t k0, uint32_t k1, int64_t n, int64_t col0, int n
   const int j = blockIdx.y;
   if (4 * q >= ldo || j >= ncols) return;
   float z[4] = {0.f, 0.f, 0.f, 0.f};
-  if (4 * q < n) {
-    U4 r = philox4x32_10(U4{(uint32_t)q, (uint32_t)(col0 + j), 0u, 0u}, k0, k1);
-    box_muller(r.x, r.y, z[0], z[1]);
-    box_muller(r.z, r.w, z[2], z[3]);
-  }
+  if (4 * q < n) omega4(k0, k1, q, col0 + j, z);
   T* o = out + (int64_t)j * ldo + 4 * q;
 #pragma unroll
   for (int e = 0; e < 4; ++e)

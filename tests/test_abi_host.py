@@ -91,3 +91,39 @@ def test_factor_argument_errors_without_device(E):
     need = c.workspace_size(4, 4)
     big = ctypes.create_string_buffer(need)
     assert f(c.h, ws, 4, 4, 4, 1e-3, big, need, ws, ws, ws, 0, ctypes.byref(info)) == E.EODABE_ENODEVICE
+
+
+def test_batched_argument_errors_without_device(E):
+    """Host checks of eodabe_factor_batched: sizes, tol, dtype, output pool
+    extent and workspace, all before any device use."""
+    import numpy as np
+    import torch
+    c = E.Context(host_only=True)
+    f = E._lib.eodabe_factor_batched
+    buf = ctypes.create_string_buffer(64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+
+    def call(m, n, lda, rc, off, pool_len, tol=1e-3, ctx=None, ws_bytes=64):
+        nt = len(m)
+        ptrs = (ctypes.c_void_p * nt)(*([ctypes.addressof(buf)] * nt))
+        a = [np.asarray(x, dtype=np.int64) for x in (m, n, lda, off, rc)]
+        ranks, status = np.zeros(nt, np.int64), np.zeros(nt, np.int32)
+        return f((ctx or c).h, nt, ctypes.cast(ptrs, ctypes.c_void_p), p(a[0]), p(a[1]), p(a[2]), tol, buf,
+                 ws_bytes, buf, pool_len, p(a[3]), p(a[4]), p(ranks), p(status), None)
+
+    ok = dict(m=[8], n=[6], lda=[6], rc=[0], off=[0], pool_len=6 * (8 + 6 + 6))
+    assert call(**ok) == E.EODABE_EWORKSPACE                     # everything valid but the workspace
+    assert call(**{**ok, "m": [0]}) == E.EODABE_EINVAL
+    assert call(**{**ok, "n": [1025]}) == E.EODABE_EINVAL        # tiles are at most 1024 x 1024
+    assert call(**{**ok, "lda": [5]}) == E.EODABE_EINVAL
+    assert call(**{**ok, "rc": [7]}) == E.EODABE_EINVAL          # r_cap > min(m, n)
+    assert call(**{**ok, "off": [-1]}) == E.EODABE_EINVAL
+    assert call(**{**ok, "pool_len": 6 * 20 - 1}) == E.EODABE_EINVAL   # outputs overrun the pool
+    assert call(**{**ok, "off": [1]}) == E.EODABE_EINVAL
+    assert call(**{**ok, "rc": [2], "off": [6 * 20 - 2 * 16]}) == E.EODABE_EWORKSPACE   # fits exactly
+    for tol in (0.0, float("nan")):
+        assert call(**ok, tol=tol) == E.EODABE_EINVAL
+    c64 = E.Context(host_only=True, dtype=torch.float64)
+    assert call(**ok, ctx=c64) == E.EODABE_EINVAL                # FP32 tiles only
+    wsz = E._lib.eodabe_batched_workspace_size
+    assert wsz(c.h, 1000) > wsz(c.h, 1) > 0 and wsz(None, 1) == 0 and wsz(c.h, -1) == 0

@@ -362,3 +362,59 @@ def test_factor_f16_sketch_exact_rank():
     A = W.lowrank_haar(4, m=400, n=300, r=40, noise_std=0.0, decades=1.0).astype(np.float32).astype(np.float64)
     f, ref = _check_lp_factor(A, 1e-2, 8, 4, "f16", err_tol=1e-2)
     assert f.rank == 40
+
+
+# ------------------------------------------------- batched tiles
+def _batch_tiles():
+    tiles = W.tiles(5, count=22, lo=64, hi=1024, rank_lo=5, rank_hi=80, noise_std=1e-4)
+    rng = np.random.default_rng(11)
+    wide = (W.lowrank_haar(6, m=90, n=700, r=17, noise_std=0.0) * 100).astype(np.float32)
+    tiles += [wide, np.zeros((64, 80), dtype=np.float32)]
+    tiles += [(rng.standard_normal((70, 66)) * 10).astype(np.float32)]     # full rank 66 > 64
+    return tiles
+
+
+def test_batched_tiles_against_oracle():
+    say("batched tiles")
+    tiles = _batch_tiles()
+    c = E.Context(seed=3, block=32)
+    bt = E.Batch(c, [dev(T.astype(np.float64), torch.float32) for T in tiles])
+    bt.run(1e-4)
+    torch.cuda.synchronize()
+    assert set(bt.status.tolist()) <= {0}, bt.status
+    for t, T in enumerate(tiles):
+        A = T.astype(np.float64)
+        U, D, Vt, r, st = bt.result(t)
+        b = int(bt.blocks[t])
+        ref = O.eod_abe(A, 1e-4, k=b, q=0, seed=3)
+        if not np.any(A):
+            assert r == 0
+            continue
+        stable, r64, _ = O.precision_stable(A, 1e-4, b, 3)
+        if stable:
+            assert r == ref.rank, (t, T.shape, r, ref.rank)
+        Un, Dn, Vn = (x.double().cpu().numpy() for x in (U, D, Vt))
+        e_gpu = np.linalg.norm(A - Un @ Dn @ Vn) / np.linalg.norm(A)
+        e_ref = O.rel_err(A, ref.U, ref.D, ref.V)
+        if r == ref.rank:
+            assert abs(e_gpu - e_ref) <= RELERR_TOL[torch.float32], (t, T.shape, e_gpu, e_ref)
+        assert np.linalg.norm(Un.T @ Un - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
+        assert np.linalg.norm(Vn @ Vn.T - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
+        assert np.all(np.tril(Dn, -1) == 0) and np.all(np.diag(Dn) >= 0)
+
+
+def test_batched_replay_deterministic_and_tuner():
+    say("batched replay + tuner")
+    tiles = W.tiles(8, count=12, lo=64, hi=512, rank_lo=5, rank_hi=40, noise_std=1e-4)
+    c = E.Context(seed=4, block=32)
+    bt = E.Batch(c, [dev(T.astype(np.float64), torch.float32) for T in tiles])
+    bt.run(1e-4)
+    first = bt.pool.clone()
+    r1 = bt.ranks.copy()
+    bt.run(1e-4)                       # graph replay
+    assert np.array_equal(bt.ranks, r1)
+    assert torch.equal(bt.pool, first)
+    chosen = bt.tune(1e-4)
+    assert set(int(x) for x in chosen) <= {0, 16, 32, 64}
+    bt.run(1e-4)
+    assert set(bt.blocks.tolist()) <= {16, 32, 64}

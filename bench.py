@@ -12,6 +12,10 @@ Workloads (``--workload``):
   image4096_n05  same image with noise std 0.5 as written (rank ~ 0.75 n).
   hsi262144      262144 x 200 FP32 hyperspectral-shaped matrix, tol 1e-2.
   lowrank512     512 x 512 FP64 exact rank 20 + 1e-12 noise, tol 1e-8.
+  tiles1024      1024 FP32 tiles, sides uniform in [64, 1024], exact-rank
+                 content 5..80 + N(0, 1e-4) noise, tol 1e-4: one step is one
+                 eodabe_factor_batched call over all tiles, compared with
+                 1024 sequential eodabe_factor calls on the same tiles.
 """
 from __future__ import annotations
 
@@ -57,7 +61,8 @@ def measured_traffic(workload: str, kernel: str):
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for f in ("paper_2506_22713_amd/csrc/eodabe_kernels.hpp", "paper_2506_22713_amd/csrc/eodabe.hip"):
+    for f in ("paper_2506_22713_amd/csrc/eodabe_kernels.hpp", "paper_2506_22713_amd/csrc/eodabe_tiles.hpp",
+              "paper_2506_22713_amd/csrc/eodabe.hip"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     fields, kernels = {}, {}
@@ -99,6 +104,140 @@ def cpu_baseline(A64: np.ndarray, tol: float, block: int, budget_s: float):
                        f"matrix (FP64 NumPy oracle), median {med * 1e3:.1f} ms"), res
 
 
+def cpu_baseline_tiles(tiles, tol, blocks, budget_s):
+    """Oracle (as it stands) on the tiles in order until about budget_s
+    seconds of CPU work: matrices/s over the tiles it finished."""
+    import oracle.eodabe_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    done, t0 = 0, time.perf_counter()
+    for T, b in zip(tiles, blocks):
+        O.eod_abe(T.astype(np.float64), tol, k=int(b), q=0, seed=0)
+        done += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=done / el, unit="matrices/s", cores=int(cores), kind="oracle",
+                sample=f"the first {done} of the {len(tiles)} tiles (LPT-independent order), "
+                       f"FP64 NumPy oracle, {el:.1f} s")
+
+
+def run_tiles(args):
+    """Batched persistent launch over 1024 uneven tiles against 1024
+    sequential single-matrix calls on the same tiles (same seed, tol and
+    block width per tile)."""
+    import torch
+    import paper_2506_22713_amd as E
+    import workloads as W
+    tol, seed = 1e-4, 0
+    log("generating 1024 tiles")
+    tiles = W.tiles(0, count=1024)
+    dev = [torch.from_numpy(np.ascontiguousarray(T)).cuda() for T in tiles]
+    ctx = E.Context(block=args.block or 32, seed=seed)
+    bt = E.Batch(ctx, dev)
+    torch.cuda.synchronize()
+    chosen = None
+    if not args.no_tune:
+        log("autotune")
+        chosen = [int(x) for x in bt.tune(tol)]
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        bt.run(tol)
+    log("timed", args.steps)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.run(tol)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    tot_ms, launches, by = ctx.profile_read(E.PROF_TILES)
+    ctx.profile(False)
+    ranks_b, status_b, blocks = bt.ranks.copy(), bt.status.copy(), bt.blocks.copy()
+
+    # sequential plain calls, one context per block width in use
+    log("sequential plain calls")
+    ctxs = {int(b): E.Context(block=int(b), seed=seed) for b in set(blocks.tolist())}
+    wss = {}
+    for b, c in ctxs.items():
+        need = max(c.workspace_size(A.shape[0], A.shape[1], min(A.shape)) for A in dev)
+        wss[b] = torch.empty(need, dtype=torch.uint8, device="cuda")
+    outs = [E.alloc_outputs(A, min(A.shape)) for A in dev]
+    seq = [None] * len(dev)
+    for t, A in enumerate(dev):                          # warm every path once
+        b = int(blocks[t])
+        seq[t] = E.factor(A, tol, ctx=ctxs[b], ws=wss[b], out=outs[t])
+    passes = 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        for t, A in enumerate(dev):
+            b = int(blocks[t])
+            seq[t] = E.factor(A, tol, ctx=ctxs[b], ws=wss[b], out=outs[t])
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3 / passes
+
+    # equal-error check (same tiles, seed, tol and block width)
+    log("errors")
+    agree, excess, e_b_all, e_s_all = 0, 0.0, [], []
+    for t, A in enumerate(dev):
+        A64 = A.double()
+        nA = torch.linalg.norm(A64)
+        U, D, Vt, r, st = bt.result(t)
+        eb = float(torch.linalg.norm(A64 - U.double() @ D.double() @ Vt.double()) / nA)
+        f = seq[t]
+        es = float(torch.linalg.norm(A64 - f.U.double() @ f.D.double() @ f.Vt.double()) / nA)
+        agree += int(r == f.rank)
+        excess = max(excess, eb - es)
+        e_b_all.append(eb)
+        e_s_all.append(es)
+
+    avg_ms = tot_ms / max(launches, 1)
+    per_launch = by / max(launches, 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = measured_traffic("tiles1024", "k_tiles")
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None if traffic is None else int(traffic),
+                    kernel="persistent tile kernel (k_tiles, with its descriptor/result copies)",
+                    avg_us=round(avg_ms * 1e3, 2), launches=int(launches), bytes_per_launch=int(per_launch))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline_tiles(tiles, tol, blocks, args.cpu_budget)
+    elems = int(sum(T.size for T in tiles))
+    hist = np.bincount(np.minimum(ranks_b // 16, 8), minlength=9).tolist()
+    line = {
+        "metric": METRIC,
+        "value": round(len(tiles) * 1e3 / ms_per_step, 1),
+        "unit": "matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": dict(workload="tiles1024", tiles=len(tiles), elements=elems, tol=tol, sides="U[64,1024]",
+                       content_rank="U[5,80]", noise_std=1e-4, block_default=args.block or 32,
+                       tuned_blocks=chosen, blocks_per_tile_mean=float(np.mean(bt.blocks)),
+                       rank_hist_by16=hist, status_counts=np.bincount(status_b.clip(0), minlength=4).tolist(),
+                       sequential=dict(ms_per_pass=round(ms_seq, 3),
+                                       matrices_per_s=round(len(tiles) * 1e3 / ms_seq, 1)),
+                       speedup_vs_sequential=round(ms_seq / ms_per_step, 2),
+                       rank_agree=agree, max_relerr_excess=excess,
+                       relerr_mean=float(np.mean(e_b_all)), relerr_seq_mean=float(np.mean(e_s_all))),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +249,7 @@ def main():
     ap.add_argument("--sketch", default="native", choices=["native", "f16", "bf16"],
                     help="precision of the sketches after the second block (FP32 data only)")
     ap.add_argument("--block", type=int, default=0, help="block width b (0: the workload's default)")
+    ap.add_argument("--no-tune", action="store_true", help="tiles1024: skip the block-width autotuner")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of A (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -117,6 +257,10 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "this build does not run across GPUs", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "tiles1024":
+        run_tiles(args)
+        return
 
     import torch
     import paper_2506_22713_amd as E

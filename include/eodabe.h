@@ -125,7 +125,9 @@ int eodabe_last_hip_error(const eodabe_ctx* ctx);
 /* ---- live kernel timing ------------------------------------------------ */
 #define EODABE_PROF_SKETCH  0   /* a2: Y = A Omega_j, one launch per executed block */
 #define EODABE_PROF_PROJECT 1   /* a9: C = Q^T A, one launch per factorization      */
-#define EODABE_PROF_KINDS   2
+#define EODABE_PROF_TILES   2   /* eodabe_factor_batched: one persistent launch per call
+                                   (timed with its descriptor and result copies)   */
+#define EODABE_PROF_KINDS   3
 
 /* Turn HIP-event timing of the dominant kernels on (enable != 0) or off,
  * and reset the accumulated totals.  The events are attached to the timed
@@ -136,7 +138,9 @@ int eodabe_profile(eodabe_ctx* ctx, int enable);
 
 /* Accumulated timing of one kernel kind since the last eodabe_profile():
  * total milliseconds, number of launches, and algorithmic bytes moved
- * (sketch: A + Omega_j + Y_j; projection: A + Q + C, in the data type). */
+ * (sketch: A + Omega_j + Y_j; projection: A + Q + C, in the data type;
+ * tiles: per tile 4 h w (J + 1) for the J sketch passes and C^T = A^T Q,
+ * plus 4 r (h + w + r) for U, core and V^T). */
 int eodabe_profile_read(const eodabe_ctx* ctx, int kind, double* total_ms, int64_t* launches,
                         double* bytes);
 

@@ -43,7 +43,7 @@ EXPORTED = [
     "eodabe_batched_workspace_size", "eodabe_factor_batched", "eodabe_tune_batched",
     "eodabe_profile", "eodabe_profile_read",
 ]
-PROF_SKETCH, PROF_PROJECT = 0, 1
+PROF_SKETCH, PROF_PROJECT, PROF_TILES = 0, 1, 2
 
 
 class Opts(ctypes.Structure):
@@ -309,7 +309,7 @@ class Batch:
         sizes = self.r_caps * self.m + self.r_caps * self.r_caps + self.r_caps * self.n
         self.offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64) if nt else np.zeros(0, np.int64)
         dev = self.tiles[0].device if nt else torch.device("cuda")
-        self.pool = torch.empty(int(sizes.sum()) if nt else 1, dtype=torch.float32, device=dev)
+        self.pool = torch.zeros(int(sizes.sum()) if nt else 1, dtype=torch.float32, device=dev)
         nb = int(_lib.eodabe_batched_workspace_size(ctx.h, nt))
         self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
         self.ranks = np.zeros(nt, dtype=np.int64)

@@ -35,9 +35,9 @@ struct eodabe_ctx {
   struct Mark { hipEvent_t a, b; int kind; int block; double bytes, bytes_per_r; };
   std::vector<hipEvent_t> ev_pool;
   std::vector<Mark> marks;
-  double prof_ms[EODABE_PROF_KINDS] = {0, 0};
-  int64_t prof_n[EODABE_PROF_KINDS] = {0, 0};
-  double prof_bytes[EODABE_PROF_KINDS] = {0, 0};
+  double prof_ms[EODABE_PROF_KINDS] = {};
+  int64_t prof_n[EODABE_PROF_KINDS] = {};
+  double prof_bytes[EODABE_PROF_KINDS] = {};
   // batched tiles: pinned staging of descriptors and results, a private
   // stream for the captured launch, the graph and its key, tuned widths
   void* tile_host = nullptr;
@@ -1013,7 +1013,11 @@ BatchWS batch_carve(void* base, eodabe_ctx* ctx, int ntiles) {
   eodabe_ctx tmp{};
   tmp.o = o;
   tmp.host_only = true;
-  b.fws_bytes = eodabe_workspace_size(&tmp, TILE_MAX, TILE_MAX, TILE_MAX);
+  b.fws_bytes = 0;                      // any tile block width (tile_block: 1 .. TILE_BMAX)
+  for (int bw = 1; bw <= TILE_BMAX; ++bw) {
+    tmp.o.block = bw;
+    b.fws_bytes = std::max(b.fws_bytes, eodabe_workspace_size(&tmp, TILE_MAX, TILE_MAX, TILE_MAX));
+  }
   b.fws = c.take<char>((int64_t)b.fws_bytes);
   b.total = c.off + 256;
   return b;
@@ -1142,23 +1146,42 @@ int eodabe_factor_batched(eodabe_ctx* ctx, int ntiles, const void* const* A, con
   HIPCHK(hipEventRecord(ctx->tile_ev, ctx->stream));
   HIPCHK(hipStreamWaitEvent(ctx->tile_stream, ctx->tile_ev, 0));
   const int grid = std::min(ntiles, tile_slots(ctx));
+  hipEvent_t pa = ctx->prof_on ? prof_event(ctx) : nullptr, pb = ctx->prof_on ? prof_event(ctx) : nullptr;
+  if (pa && pb) HIPCHK(hipEventRecord(pa, ctx->tile_stream));
   TRY(batch_launch(ctx, b, ntiles, grid, (float*)out_pool, tol, ws));
+  if (pa && pb) HIPCHK(hipEventRecord(pb, ctx->tile_stream));
   HIPCHK(hipStreamSynchronize(ctx->tile_stream));
   const TileResult* hr = (const TileResult*)((char*)ctx->tile_host + (size_t)ntiles * sizeof(TileDesc));
   int first_err = EODABE_OK;
+  double bytes = 0.0;
   for (int t = 0; t < ntiles; ++t) {
     ranks[t] = hr[t].rank;
     status[t] = hr[t].status;
     if (blocks_used) blocks_used[t] = tile_block(ctx, m[t], n[t]);
+    const double hw = 4.0 * (double)m[t] * (double)n[t], r = (double)hr[t].rank;
+    bytes += status[t] == TS_OK ? hw * (hr[t].blocks + 1) + 4.0 * r * (double)(m[t] + n[t] + hr[t].rank)
+                                : hw * hr[t].blocks;
   }
+  if (pa && pb) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pa, pb) == hipSuccess) {
+      ctx->prof_ms[EODABE_PROF_TILES] += ms;
+      ctx->prof_n[EODABE_PROF_TILES] += 1;
+      ctx->prof_bytes[EODABE_PROF_TILES] += bytes;
+    }
+  }
+  if (pa) ctx->ev_pool.push_back(pa);
+  if (pb) ctx->ev_pool.push_back(pb);
   // tiles whose rank went above the in-kernel cap: the regular path
+  eodabe_ctx* sub = nullptr;
   for (int t = 0; t < ntiles; ++t) {
     if (status[t] != TS_RANK) continue;
-    eodabe_opts o = ctx->o;
-    o.block = tile_block(ctx, m[t], n[t]);
-    eodabe_ctx* sub = nullptr;
-    o.stream = ctx->stream;
-    TRY(eodabe_create(&sub, &o));
+    if (!sub) {
+      eodabe_opts o = ctx->o;
+      o.stream = ctx->stream;
+      TRY(eodabe_create(&sub, &o));
+    }
+    sub->o.block = tile_block(ctx, m[t], n[t]);
     const int64_t rc = r_caps[t] ? r_caps[t] : std::min(m[t], n[t]);
     float* Ut = (float*)out_pool + out_offsets[t];
     float* core = Ut + rc * m[t];
@@ -1166,11 +1189,11 @@ int eodabe_factor_batched(eodabe_ctx* ctx, int ntiles, const void* const* A, con
     eodabe_info info{};
     const int e = eodabe_factor(sub, A[t], m[t], n[t], lda[t], tol, b.fws, b.fws_bytes, Ut, core, Vt, rc,
                                 &info);
-    eodabe_destroy(sub);
     ranks[t] = info.rank;
     status[t] = e == EODABE_ECAPACITY ? TS_CAPACITY : (e == EODABE_ENONFINITE ? TS_NONFINITE : (e < 0 ? -1 : TS_OK));
     if (e < 0 && e != EODABE_ECAPACITY && e != EODABE_ENONFINITE && first_err == EODABE_OK) first_err = e;
   }
+  if (sub) eodabe_destroy(sub);
   return first_err;
 }
 

@@ -968,18 +968,23 @@ __device__ __forceinline__ void lds_gemm(const double* A, const double* B, Out o
 // Gs: G on entry (row-major, ld F+1), R on exit (zero below the diagonal
 // and in rows >= f); Ri: R^{-1} on exit (zero in columns >= f); work:
 // 24F doubles; dgs: F doubles.  Returns the dead mask afterwards and the
-// number of floored pivots (uniform over the workgroup).
+// number of floored pivots (uniform over the workgroup).  dg_in (optional):
+// the diagonal the floor rule refers to (G's own diagonal when null; the
+// trailing block of a blocked factorization passes the original one).
+// nolive_out (optional): bits of the pivots that did not eliminate (dead or
+// floored).
 // ---------------------------------------------------------------------------
 template <int F>
 __device__ void chol_inv(double* Gs, double* Ri, double* work, double* dgs, int f,
-                         uint64_t dmask_in, int first_pass, uint64_t* dmask_out, int* nfloor) {
+                         uint64_t dmask_in, int first_pass, uint64_t* dmask_out, int* nfloor,
+                         const double* dg_in = nullptr, uint64_t* nolive_out = nullptr) {
   typedef SmallCfg<F> C;
   constexpr int LD = C::LD, NR = C::NR, NCL = C::NCL, W2 = 2 * F;
   double* P = work;                      // panel rows: P[j*W2 + c], j < 8
   double* XT = work + 8 * W2;            // multipliers: XT[j*F + i] = R(kp+j, i)
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index (scalar)
-  for (int i = tid; i < f; i += 256) dgs[i] = Gs[i * LD + i];
+  for (int i = tid; i < f; i += 256) dgs[i] = dg_in ? dg_in[i] : Gs[i * LD + i];
   double M[NR][NCL];
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
@@ -996,7 +1001,7 @@ __device__ void chol_inv(double* Gs, double* Ri, double* work, double* dgs, int 
     }
   }
   __syncthreads();                       // G consumed: Gs now receives R; dgs ready
-  uint64_t dout = dmask_in;
+  uint64_t dout = dmask_in, nlive = 0;
   int nfl = 0;
   for (int kp = 0; kp < f; kp += 8) {
     // (a) publish the panel rows kp + w and kp + 4 + w
@@ -1084,6 +1089,7 @@ __device__ void chol_inv(double* Gs, double* Ri, double* work, double* dgs, int 
           a = piv * y;
         }
         if (fl == 2) dout |= 1ull << k;
+        if (fl == 1 || fl == 2) nlive |= 1ull << k;
         nfl += (fl == 1);
         alpha[j] = a;
         ia[j] = y;
@@ -1169,6 +1175,127 @@ __device__ void chol_inv(double* Gs, double* Ri, double* work, double* dgs, int 
   __syncthreads();
   *dmask_out = dout;
   *nfloor = nfl;
+  if (nolive_out) *nolive_out = nlive;
+}
+
+// ---------------------------------------------------------------------------
+// C = op(A) op(B) for FP64 matrices in global or LDS memory (M, N, K <=
+// 128): element (i,k) of op(A) at TA ? A[k*lda + i] : A[i*lda + k], (k,j)
+// of op(B) at TB ? B[j*ldb + k] : B[k*ldb + j]; element (i, j) of the
+// product is handed to out(i, j, v) for i < M, j < N.  The four waves take
+// the 16 x 16 tiles in turn; a tile loads its K strip 64 at a time before
+// the MFMAs, so a chunk costs one memory round trip.
+// ---------------------------------------------------------------------------
+template <bool TA, bool TB, typename Out>
+__device__ __forceinline__ void gmm64(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
+                                      Out out) {
+  typedef Mfma<double> MF;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int TM = (M + 15) / 16, TN = (N + 15) / 16;
+  for (int tile = wv; tile < TM * TN; tile += 4) {
+    const int ti = tile / TN, tj = tile - ti * TN;
+    const int ar = 16 * ti + r, bc = 16 * tj + r;
+    MF::acc_t acc = MF::zero();
+    for (int k0 = 0; k0 < K; k0 += 64) {
+      double a[16], b[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int kk = k0 + 4 * q + g;
+        const bool ok = kk < K;
+        a[q] = (ok && ar < M) ? (TA ? A[(int64_t)kk * lda + ar] : A[(int64_t)ar * lda + kk]) : 0.0;
+        b[q] = (ok && bc < N) ? (TB ? B[(int64_t)bc * ldb + kk] : B[(int64_t)kk * ldb + bc]) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc = MF::op(a[q], b[q], acc);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * ti + MF::row(g, e);
+      if (i < M && bc < N) out(i, bc, acc[e]);
+    }
+  }
+}
+
+// LDS (doubles) used by chol_inv128.
+constexpr int CHOL128_LDS = 3 * SmallCfg<64>::SIZE + 24 * 64 + 2 * 64;
+
+// ---------------------------------------------------------------------------
+// Cholesky with inverse of a symmetric positive semi-definite f x f matrix,
+// 64 < f <= 128, blocked 2 x 2 over 64 on the four waves of a workgroup.
+// It yields the R of the unblocked elimination with the pivot rules of
+// chol_inv (up to rounding order):
+//   R11 = chol(G11);
+//   R12 = R11^{-T} G12 with the rows of pivots that did not eliminate and
+//         the dead columns set to zero (those rows of R12 never enter the
+//         elimination);
+//   R22 = chol(G22 - R12^T R12), its floor rule referred to G22's diagonal;
+//   R^{-1} = [R11^{-1}, -R11^{-1} R12 R22^{-1}; 0, R22^{-1}].
+// G (read only), R, Rinv: global FP64, row-major, leading dimension ldg.
+// lds: CHOL128_LDS doubles.  dm_in / dm_out: dead masks of columns 0-63 and
+// 64-127.  Returns the number of floored pivots (uniform).
+// ---------------------------------------------------------------------------
+__device__ int chol_inv128(const double* G, int ldg, int f, double* R, double* Rinv, double* lds,
+                           uint64_t dm_in0, uint64_t dm_in1, int first_pass, uint64_t* dm_out0,
+                           uint64_t* dm_out1) {
+  typedef SmallCfg<64> S;
+  constexpr int LD = S::LD;
+  double* Gs = lds;                        // block being factored -> its R
+  double* Ri = Gs + S::SIZE;               // its inverse
+  double* T = Ri + S::SIZE;                // R12 (64 x n2), then P = R11^{-1} R12
+  double* work = T + S::SIZE;
+  double* dgs = work + 24 * 64;
+  double* dg2 = dgs + 64;                  // diagonal of G22
+  const int tid = threadIdx.x, n2 = f - 64;
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    Gs[i * LD + j] = G[(int64_t)i * ldg + j];
+  }
+  for (int j = tid; j < n2; j += 256) dg2[j] = G[(int64_t)(64 + j) * ldg + 64 + j];
+  __syncthreads();
+  uint64_t nl1 = 0, nl2 = 0;
+  int nf1 = 0, nf2 = 0;
+  chol_inv<64>(Gs, Ri, work, dgs, 64, dm_in0, first_pass, dm_out0, &nf1, nullptr, &nl1);
+  // R11, R11^{-1}; zero lower-left blocks
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    R[(int64_t)i * ldg + j] = Gs[i * LD + j];
+    Rinv[(int64_t)i * ldg + j] = Ri[i * LD + j];
+  }
+  for (int idx = tid; idx < n2 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    R[(int64_t)(64 + i) * ldg + j] = 0.0;
+    Rinv[(int64_t)(64 + i) * ldg + j] = 0.0;
+  }
+  // R12 = R11^{-T} G12, masked
+  gmm64<true, false>(Ri, LD, G + 64, ldg, 64, n2, 64, [&](int i, int j, double v) {
+    const bool z = ((nl1 >> i) & 1ull) || ((dm_in1 >> j) & 1ull);
+    T[i * LD + j] = z ? 0.0 : v;
+  });
+  __syncthreads();
+  // S = G22 - R12^T R12 (into Gs; R11 is stored), R12 out
+  gmm64<true, false>(T, LD, T, LD, n2, n2, 64, [&](int i, int j, double v) {
+    Gs[i * LD + j] = G[(int64_t)(64 + i) * ldg + 64 + j] - v;
+  });
+  for (int idx = tid; idx < 64 * n2; idx += 256) {
+    const int i = idx / n2, j = idx - i * n2;
+    R[(int64_t)i * ldg + 64 + j] = T[i * LD + j];
+  }
+  __syncthreads();
+  chol_inv<64>(Gs, Ri, work, dgs, n2, dm_in1, first_pass, dm_out1, &nf2, dg2, &nl2);
+  for (int idx = tid; idx < n2 * n2; idx += 256) {
+    const int i = idx / n2, j = idx - i * n2;
+    R[(int64_t)(64 + i) * ldg + 64 + j] = Gs[i * LD + j];
+    Rinv[(int64_t)(64 + i) * ldg + 64 + j] = Ri[i * LD + j];
+  }
+  __syncthreads();
+  // R^{-1}_12 = -(R11^{-1} R12) R22^{-1}
+  gmm64<false, false>(Rinv, ldg, T, LD, 64, n2, 64, [&](int i, int j, double v) { Gs[i * LD + j] = v; });
+  __syncthreads();
+  gmm64<false, false>(Gs, LD, Ri, LD, 64, n2, n2, [&](int i, int j, double v) {
+    Rinv[(int64_t)i * ldg + 64 + j] = -v;
+  });
+  __syncthreads();
+  return nf1 + nf2;
 }
 
 // Arguments of the Cholesky that closes a Gram pass (k_gram_rows, and the

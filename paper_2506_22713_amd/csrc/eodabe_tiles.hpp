@@ -4,14 +4,15 @@
 // tiles from a device work queue until it is empty.  Tiles up to
 // TILE_MAX x TILE_MAX; ranks up to TILE_RMAX are finished in the kernel
 // (a tile whose rank goes above reports status TS_RANK and is left to the
-// caller).
+// caller).  Ranks up to 64 close on LDS-resident FP64 matrices; wider ranks
+// use the 2 x 2-blocked Cholesky with inverse on L2-resident ones.
 #pragma once
 #include "eodabe_kernels.hpp"
 
 namespace eodabe {
 
 constexpr int TILE_MAX = 1024;                 // largest tile side
-constexpr int TILE_RMAX = 64;                  // rank finished inside the kernel
+constexpr int TILE_RMAX = 128;                 // rank finished inside the kernel
 constexpr int TILE_BMAX = 64;                  // largest block width
 constexpr int TILE_QW = TILE_RMAX + TILE_BMAX; // basis columns held (rank + one block)
 
@@ -36,17 +37,20 @@ struct TileResult {
 // Scratch of one workgroup (floats unless marked).
 struct TileSlot {
   static constexpr int64_t LD = TILE_MAX;                // leading dimension of tall buffers
-  static constexpr int64_t AT = 0;                       // transposed / repacked tile, LD x LD
-  static constexpr int64_t OM = AT + LD * LD;            // Omega^T rows, TILE_BMAX x LD
+  static constexpr int64_t OM = 0;                       // Omega^T rows, TILE_BMAX x LD
   static constexpr int64_t Y = OM + TILE_BMAX * LD;      // block, LD x TILE_BMAX
   static constexpr int64_t Q = Y + LD * TILE_BMAX;       // basis, LD x TILE_QW
   static constexpr int64_t CT = Q + LD * TILE_QW;        // C^T, LD x TILE_RMAX
-  static constexpr int64_t VP = CT + LD * TILE_RMAX;     // V' of a transposed tile, LD x TILE_RMAX
+  static constexpr int64_t VP = CT + LD * TILE_RMAX;     // V' of a wide tile, LD x TILE_RMAX
   static constexpr int64_t FLOATS = VP + LD * TILE_RMAX;
-  // FP64 small matrices after the floats (TILE_RMAX^2 each)
-  static constexpr int64_t SM = TILE_RMAX * TILE_RMAX;
+  // FP64 matrices after the floats: ranks <= 64 (64 x 64, column-major)
+  static constexpr int64_t SM = 64 * 64;
   static constexpr int64_t R1 = 0, R2 = SM, QH = 2 * SM, DH = 3 * SM, QH2 = 4 * SM, DH2 = 5 * SM;
-  static constexpr int64_t DOUBLES = 6 * SM;
+  // ranks 65..128 (128 x 128, row-major, leading dimension LB)
+  static constexpr int LB = 128;
+  static constexpr int64_t B2 = (int64_t)LB * LB;
+  static constexpr int64_t BIG = 6 * SM;                 // 16 buffers of B2
+  static constexpr int64_t DOUBLES = BIG + 16 * B2;
   static constexpr int64_t BYTES = FLOATS * 4 + DOUBLES * 8;
 };
 
@@ -54,9 +58,12 @@ struct TileSlot {
 // diagonal, then 72 scalars that live across phases (||A||^2, R1 diagonal).
 constexpr int TILE_SQR = 4 * SmallCfg<64>::SIZE + 24 * 64 + 64;
 constexpr int TILE_LDS = TILE_SQR + 72;
-// basis-phase carve: Gram/R, R^{-1}, Cholesky work, diagonal, fold buffer
+// basis-phase carve: Gram/R, R^{-1}, Cholesky work, diagonal; W = Q^T Y
+// (TILE_QW x TILE_BMAX) from 0; the reductions' fold buffer after both.
 constexpr int TL_GS = 0, TL_RI = SmallCfg<64>::SIZE, TL_WORK = 2 * SmallCfg<64>::SIZE,
-              TL_DGS = TL_WORK + 24 * 64, TL_FOLD = TL_DGS + 64, TL_FOLD_N = 8 * 256;
+              TL_DGS = TL_WORK + 24 * 64, TL_W = 0, TL_FOLD = TILE_QW * TILE_BMAX, TL_FOLD_N = 16 * 256;
+static_assert(TL_DGS + 64 <= TL_FOLD, "Cholesky carve below the fold buffer");
+static_assert(CHOL128_LDS <= TILE_SQR && 128 * 129 <= TILE_SQR, "wide-rank closing inside the arena");
 static_assert(TL_FOLD + TL_FOLD_N <= TILE_SQR, "basis carve inside the arena");
 
 // ---------------------------------------------------------------------------
@@ -76,16 +83,31 @@ __device__ void tile_omega(float* Om, int64_t ldk, int64_t n, int64_t col0, int 
 }
 
 // ---------------------------------------------------------------------------
-// Y (m x 16CT, column-major ldy) = A (m x n row-major) Omega^T (16CT rows,
-// ldk).  Wave w takes 64-row panels w, w+4, ...; each element of A is read
-// once.  ss (LDS, may be null): sum of squares of A (fixed order).
+// Y (m x nb, column-major ldy) = A B^T: A m x n row-major (lda), B given by
+// its rows (row c at B + c*ldb, n entries, 16-byte aligned; rows >= nb read
+// as zero), nb <= 64.  Wave w takes 64-row panels w, w+4, ...; each element
+// of A is read once.  AL: rows of A 16-byte aligned (vector loads), else
+// scalar loads.  ss (LDS, may be null): sum of squares of A.
 // ---------------------------------------------------------------------------
-template <int CT>
-__device__ void tile_sketch(const float* A, int64_t lda, int64_t m, int64_t n, const float* Om,
-                            int64_t ldk, float* Yb, int64_t ldy, double* ss, double* red) {
+template <bool AL>
+__device__ __forceinline__ V4<float> tile_lda4(const float* p) {
+  if constexpr (AL) {
+    return ld4(p);
+  } else {
+    V4<float> v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v.v[e] = p[e];
+    return v;
+  }
+}
+template <bool AL>
+__device__ __forceinline__ void tile_rowprod(const float* A, int64_t lda, int64_t m, int64_t n, const float* B,
+                                             int64_t ldb, int nb, float* Yb, int64_t ldy, double* ss,
+                                             double* red) {
   typedef Mfma<float> MF;
-  constexpr int RT = 4;
+  constexpr int RT = 4, CT = 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  const int CTr = (nb + 15) / 16;
   double sq = 0.0;
   for (int64_t p0 = (int64_t)wv * 64; p0 < m; p0 += 256) {
     const float* ap[RT];
@@ -102,19 +124,21 @@ __device__ void tile_sketch(const float* A, int64_t lda, int64_t m, int64_t n, c
 #pragma unroll
       for (int u = 0; u < CT; ++u) acc[t][u] = MF::zero();
     auto compute = [&](const V4<float>(&a)[RT], int64_t k) {
-      V4<float> b[CT];
+      V4<float> bv[CT];
       const bool full = k + 16 <= n;
 #pragma unroll
       for (int u = 0; u < CT; ++u) {
-        const float* ob = Om + (int64_t)(16 * u + r) * ldk + k;
-        b[u] = full ? ld4(ob + 4 * g) : ld4_masked(ob + 4 * g, k + 4 * g, n);
+        const float* ob = B + (int64_t)(16 * u + r) * ldb + k + 4 * g;
+        if (u < CTr && 16 * u + r < nb) bv[u] = full ? ld4(ob) : ld4_masked(ob, k + 4 * g, n);
+        else bv[u] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
-          for (int u = 0; u < CT; ++u) acc[t][u] = MF::op(a[t].v[v], b[u].v[v], acc[t][u]);
+          for (int u = 0; u < CT; ++u)
+            if (u < CTr) acc[t][u] = MF::op(a[t].v[v], bv[u].v[v], acc[t][u]);
       if (ss) {
 #pragma unroll
         for (int t = 0; t < RT; ++t)
@@ -129,7 +153,7 @@ __device__ void tile_sketch(const float* A, int64_t lda, int64_t m, int64_t n, c
     for (int q = 0; q < 4; ++q)
       if (q < nfull)
 #pragma unroll
-        for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + 16 * q);
+        for (int t = 0; t < RT; ++t) a[q][t] = tile_lda4<AL>(ap[t] + 16 * q);
     for (int64_t c = 0; c < nfull; c += 4) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -137,7 +161,7 @@ __device__ void tile_sketch(const float* A, int64_t lda, int64_t m, int64_t n, c
           compute(a[q], 16 * (c + q));
           if (c + q + 4 < nfull)
 #pragma unroll
-            for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + 16 * (c + q + 4));
+            for (int t = 0; t < RT; ++t) a[q][t] = tile_lda4<AL>(ap[t] + 16 * (c + q + 4));
         }
       }
     }
@@ -153,10 +177,13 @@ __device__ void tile_sketch(const float* A, int64_t lda, int64_t m, int64_t n, c
 #pragma unroll
       for (int u = 0; u < CT; ++u) {
         const int64_t row = p0 + 16 * t + 4 * g;
-        float* py = Yb + (int64_t)(16 * u + r) * ldy + row;
+        const int col = 16 * u + r;
+        if (u < CTr && col < nb) {
+          float* py = Yb + (int64_t)col * ldy + row;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (row + e < m) py[e] = acc[t][u][e];
+          for (int e = 0; e < 4; ++e)
+            if (row + e < m) py[e] = acc[t][u][e];
+        }
       }
   }
   if (ss) {
@@ -169,77 +196,166 @@ __device__ void tile_sketch(const float* A, int64_t lda, int64_t m, int64_t n, c
 }
 
 // ---------------------------------------------------------------------------
-// out (LDS, row-major, leading dimension ldo) = X^T Y in FP64, X m x wx and
-// Y m x wy column-major (ldx, ldy; columns beyond wx / wy read as zero).
-// Waves split the rows (16-row steps, interleaved); partial tiles are folded
-// in wave order through red (>= 8 * 256 doubles, disjoint from out).  One 16-column tile of Y
-// per pass keeps at most 8 accumulators.
+// Ct (n x r, column-major ldc) = A^T Q: A m x n row-major (lda), Q m x r
+// column-major (ldq multiple of 4, 16-byte aligned columns), r <= 64.
+// Wave w takes 64-column chunks of A (w, w+4, ...), so A is read once;
+// element (j, i) of the product at i*ldc + j.  ss (LDS, may be null): sum
+// of squares of A.
 // ---------------------------------------------------------------------------
-__device__ void tile_xty(const float* X, int64_t ldx, int wx, const float* Yb, int64_t ldy, int wy,
-                         int64_t m, double* out, int ldo, double* red) {
-  typedef Mfma<double> MF;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-  const int TX = (wx + 15) / 16, TY = (wy + 15) / 16;
-  for (int u = 0; u < TY; ++u) {
-    MF::acc_t acc[8];
+__device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_t m, int64_t n, const float* Q,
+                                             int64_t ldq, int r, float* Ct, int64_t ldc, double* ss,
+                                             double* red) {
+  typedef Mfma<float> MF;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, rr = lane & 15, g = lane >> 4;
+  const int TR = (r + 15) / 16;
+  double sq = 0.0;
+  for (int64_t c0 = 64 * (int64_t)wv; c0 < n; c0 += 256) {
+    MF::acc_t acc[4][4];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = MF::zero();
-    const int ycol = 16 * u + r;
-    for (int64_t k0 = 16 * (int64_t)wv; k0 < m; k0 += 64) {
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
+    for (int64_t k0 = 0; k0 < m; k0 += 16) {
       const int64_t kr = k0 + 4 * g;
-      double bv[4];
+      const bool full = kr + 4 <= m;
+      V4<float> qv[4];
+      float av[4][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) bv[e] = (ycol < wy && kr + e < m) ? (double)Yb[(int64_t)ycol * ldy + kr + e] : 0.0;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        if (t >= TX) break;
-        const int xcol = 16 * t + r;
-        double av[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) av[e] = (xcol < wx && kr + e < m) ? (double)X[(int64_t)xcol * ldx + kr + e] : 0.0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[t] = MF::op(av[v], bv[v], acc[t]);
+      for (int t = 0; t < 4; ++t) {
+        const int qc = 16 * t + rr;
+        const float* qp = Q + (int64_t)qc * ldq + kr;
+        if (t < TR && qc < r) qv[t] = full ? ld4(qp) : ld4_masked(qp, kr, m);
+        else qv[t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t ac = c0 + 16 * u + rr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) av[u][e] = (ac < n && kr + e < m) ? A[(kr + e) * lda + ac] : 0.f;
+      }
+      if (ss) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) sq += (double)av[u][e] * (double)av[u][e];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < TR)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(qv[t].v[v], av[u][v], acc[t][u]);
     }
-    // fold the waves in order
-    for (int w = 0; w < 4; ++w) {
-      if (wv == w) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          if (t >= TX) break;
+    for (int t = 0; t < 4; ++t) {
+      if (t < TR) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            double* q = &red[(t * 4 + e) * 64 + lane];
-            *q = (w == 0) ? acc[t][e] : *q + acc[t][e];
+        for (int u = 0; u < 4; ++u) {
+          const int64_t j = c0 + 16 * u + rr;
+          if (j < n) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int i = 16 * t + 4 * g + e;
+              if (i < r) Ct[(int64_t)i * ldc + j] = acc[t][u][e];
+            }
           }
         }
       }
-      __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < TX * 256; idx += 256) {
-      const int l = idx & 63, e = (idx >> 6) & 3, t = idx >> 8;
-      const int i = 16 * t + MF::row(l >> 4, e), j = 16 * u + (l & 15);
-      if (i < wx && j < wy) out[i * ldo + j] = red[idx];
+  }
+  if (ss) {
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+    if (lane == 0) red[wv] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) *ss = red[0] + red[1] + red[2] + red[3];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// out (LDS or global, row-major, leading dimension ldo) = X^T Y in FP64: X
+// m x wx and Y m x wy column-major (ldx, ldy multiples of 4, 16-byte aligned
+// columns; columns beyond wx / wy read as zero), wx, wy <= 64.  Waves split
+// the rows (16-row steps, interleaved) and accumulate every 16 x 16 tile of
+// the product at once; the partial tiles are folded in wave order through
+// red (16 * 256 doubles, disjoint from out).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tile_xty(const float* X, int64_t ldx, int wx, const float* Yb, int64_t ldy,
+                                         int wy, int64_t m, double* out, int ldo, double* red) {
+  typedef Mfma<double> MF;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  const int TX = (wx + 15) / 16, TY = (wy + 15) / 16;
+  MF::acc_t acc[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
+  for (int64_t k0 = 16 * (int64_t)wv; k0 < m; k0 += 64) {
+    const int64_t kr = k0 + 4 * g;
+    const bool full = kr + 4 <= m;
+    V4<float> xa[4], yb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 16 * t + r;
+      const float* xp = X + (int64_t)c * ldx + kr;
+      if (t < TX && c < wx) xa[t] = full ? ld4(xp) : ld4_masked(xp, kr, m);
+      else xa[t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
+      const float* yp = Yb + (int64_t)c * ldy + kr;
+      if (t < TY && c < wy) yb[t] = full ? ld4(yp) : ld4_masked(yp, kr, m);
+      else yb[t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < TX)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (u < TY) acc[t][u] = MF::op((double)xa[t].v[v], (double)yb[u].v[v], acc[t][u]);
+  }
+  // fold the waves in order
+  for (int w = 0; w < 4; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < TX)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (u < TY)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                double* q = &red[((t * TY + u) * 4 + e) * 64 + lane];
+                *q = (w == 0) ? acc[t][u][e] : *q + acc[t][u][e];
+              }
     }
     __syncthreads();
   }
+  for (int idx = threadIdx.x; idx < TX * TY * 256; idx += 256) {
+    const int l = idx & 63, e = (idx >> 6) & 3, tu = idx >> 8;
+    const int t = tu / TY, u = tu - t * TY;
+    const int i = 16 * t + MF::row(l >> 4, e), j = 16 * u + (l & 15);
+    if (i < wx && j < wy) out[i * ldo + j] = red[idx];
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Z (column-major, ldz, columns zoff .. zoff+ncols-1) = X (m x f, ldx) W
-// (f x f FP64 in LDS, element (i,j) at i*ldw + j) on f64 MFMA; each wave
-// computes 16 whole rows at a time, so Z may alias X.
+// (f x ncols FP64, LDS or global, element (i,j) at i*ldw + j), f <= 4 KSM,
+// on f64 MFMA; each wave computes 16 whole rows at a time, so Z may alias X.
 // ---------------------------------------------------------------------------
-__device__ void tile_apply(const float* X, int64_t ldx, int64_t m, int f, const double* W, int ldw,
-                           float* Z, int64_t ldz, int64_t zoff, int ncols) {
+template <int KSM = 16>
+__device__ __forceinline__ void tile_apply(const float* X, int64_t ldx, int64_t m, int f, const double* W,
+                                           int ldw, float* Z, int64_t ldz, int64_t zoff, int ncols) {
   typedef Mfma<double> MF;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
   const int TT = (ncols + 15) / 16, KS = (f + 3) / 4;
   for (int64_t row0 = 16 * (int64_t)wv; row0 < m; row0 += 64) {
     const int64_t arow = row0 + r;
-    double a[16];
+    double a[KSM];
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
+    for (int kk = 0; kk < KSM; ++kk) {
       const int k = 4 * kk + g;
       a[kk] = (kk < KS && k < f && arow < m) ? (double)X[(int64_t)k * ldx + arow] : 0.0;
     }
@@ -247,11 +363,12 @@ __device__ void tile_apply(const float* X, int64_t ldx, int64_t m, int f, const 
       MF::acc_t z = MF::zero();
       const int col = 16 * u + r;
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        if (kk >= KS) break;
-        const int k = 4 * kk + g;
-        const double b = (k < f && col < ncols) ? W[k * ldw + col] : 0.0;
-        z = MF::op(a[kk], b, z);
+      for (int kk = 0; kk < KSM; ++kk) {
+        if (kk < KS) {
+          const int k = 4 * kk + g;
+          const double b = (k < f && col < ncols) ? W[k * ldw + col] : 0.0;
+          z = MF::op(a[kk], b, z);
+        }
       }
       if (col < ncols) {
 #pragma unroll
@@ -267,10 +384,10 @@ __device__ void tile_apply(const float* X, int64_t ldx, int64_t m, int f, const 
 
 // ---------------------------------------------------------------------------
 // Y (m x f) -= Q (m x w) W (w x f, FP64 in LDS, element (i,j) at i*ldw + j),
-// in FP32 on MFMA (the projection step of block Gram-Schmidt).
+// in FP32 on MFMA (the projection step of block Gram-Schmidt), f <= 64.
 // ---------------------------------------------------------------------------
-__device__ void tile_update(float* Yb, int64_t ldy, const float* Q, int64_t ldq, int64_t m, int w,
-                            int f, const double* W, int ldw) {
+__device__ __forceinline__ void tile_update(float* Yb, int64_t ldy, const float* Q, int64_t ldq, int64_t m,
+                                            int w, int f, const double* W, int ldw) {
   typedef Mfma<float> MF;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
   const int TT = (f + 15) / 16;
@@ -284,78 +401,21 @@ __device__ void tile_update(float* Yb, int64_t ldy, const float* Q, int64_t ldq,
       const float a = (k < w && arow < m) ? Q[(int64_t)k * ldq + arow] : 0.f;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (u >= TT) break;
-        const int col = 16 * u + r;
-        const float b = (k < w && col < f) ? (float)W[k * ldw + col] : 0.f;
-        z[u] = MF::op(a, b, z[u]);
+        if (u < TT) {
+          const int col = 16 * u + r;
+          const float b = (k < w && col < f) ? (float)W[k * ldw + col] : 0.f;
+          z[u] = MF::op(a, b, z[u]);
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (u >= TT) break;
       const int col = 16 * u + r;
-      if (col >= f) continue;
-      const int64_t row = row0 + 4 * g;
+      if (u < TT && col < f) {
+        const int64_t row = row0 + 4 * g;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (row + e < m) Yb[(int64_t)col * ldy + row + e] -= z[u][e];
-    }
-  }
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// C^T (n x r, column-major ldc) = A^T Q: A m x n row-major, Q m x r
-// column-major.  Wave w takes 64-column chunks of A (w, w+4, ...), so A is
-// read once; C^T element (j, i) at i*ldc + j.
-// ---------------------------------------------------------------------------
-__device__ void tile_ct(const float* A, int64_t lda, int64_t m, int64_t n, const float* Q, int64_t ldq,
-                        int r, float* Ct, int64_t ldc) {
-  typedef Mfma<float> MF;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, rr = lane & 15, g = lane >> 4;
-  const int TR = (r + 15) / 16;
-  for (int64_t c0 = 64 * (int64_t)wv; c0 < n; c0 += 256) {
-    MF::acc_t acc[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
-    for (int64_t k0 = 0; k0 < m; k0 += 16) {
-      const int64_t kr = k0 + 4 * g;
-      float qv[4][4], av[4][4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int qc = 16 * t + rr;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) qv[t][e] = (t < TR && qc < r && kr + e < m) ? Q[(int64_t)qc * ldq + kr + e] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t ac = c0 + 16 * u + rr;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) av[u][e] = (ac < n && kr + e < m) ? A[(kr + e) * lda + ac] : 0.f;
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if (t >= TR) break;
-#pragma unroll
-          for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(qv[t][v], av[u][v], acc[t][u]);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t >= TR) break;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t j = c0 + 16 * u + rr;
-        if (j >= n) continue;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int i = 16 * t + 4 * g + e;
-          if (i < r) Ct[(int64_t)i * ldc + j] = acc[t][u][e];
-        }
+        for (int e = 0; e < 4; ++e)
+          if (row + e < m) Yb[(int64_t)col * ldy + row + e] -= z[u][e];
       }
     }
   }
@@ -449,38 +509,91 @@ __device__ void tile_store_small(const double* in, int ld, int f, double* Mg) {
 }
 
 // ---------------------------------------------------------------------------
-// One tile: orientation, Alg. 1 with BCGS2 + CholeskyQR2 blocks and the
-// device rank test, then Alg. 2 (q = 0): C^T = A^T Q, CholeskyQR2 of C^T,
-// QR of (R2 R1)^T, U = Q Qh; a transposed tile re-triangularises its core.
+// Ranks 65..128: FP64 matrices row-major with leading dimension LB in the
+// slot (L2-resident); the LDS arena stages the right-hand factors.
+// ---------------------------------------------------------------------------
+// G = X^T X (f x f, 64 < f <= 128) of X (rows x f, column-major ldx): the
+// blocks G11, G12 and G22 (chol_inv128 does not read G21).
+__device__ __attribute__((noinline)) void tile_gram_big(const float* X, int64_t ldx, int f, int64_t rows,
+                                                        double* G, double* red) {
+  constexpr int LB = TileSlot::LB;
+  const int f2 = f - 64;
+  tile_xty(X, ldx, 64, X, ldx, 64, rows, G, LB, red);
+  tile_xty(X, ldx, 64, X + 64 * ldx, ldx, f2, rows, G + 64, LB, red);
+  tile_xty(X + 64 * ldx, ldx, f2, X + 64 * ldx, ldx, f2, rows, G + 64 * LB + 64, LB, red);
+}
+
+// Z (columns 0..ncols-1, ldz) = X (m x f, ldx) W with W (f x ncols, f <= 128)
+// row-major in global memory (ld LB), staged through the arena (ld 129).
+__device__ __attribute__((noinline)) void tile_apply_big(const float* X, int64_t ldx, int64_t m, int f,
+                                                         const double* Wg, double* lds, float* Z, int64_t ldz,
+                                                         int ncols) {
+  for (int idx = threadIdx.x; idx < f * ncols; idx += 256) {
+    const int i = idx / ncols, j = idx - i * ncols;
+    lds[i * 129 + j] = Wg[(int64_t)i * TileSlot::LB + j];
+  }
+  __syncthreads();
+  tile_apply<32>(X, ldx, m, f, lds, 129, Z, ldz, 0, ncols);
+}
+
+// QR of M^T (M = R2 R1, or R2 when R1 is null; f x f, 64 < f <= 128) by
+// CholeskyQR2 in FP64: Qh and Rh out; scr: 7 buffers of B2.  All row-major
+// with leading dimension LB.
+__device__ __attribute__((noinline)) void tile_small_qr_big(double* lds, const double* R1g, const double* R2g,
+                                                            int f, double* Qh, double* Rh, double* scr) {
+  constexpr int LB = TileSlot::LB;
+  constexpr int64_t B2 = TileSlot::B2;
+  double* M = scr;
+  double* G = scr + B2;
+  double* H1 = scr + 2 * B2;
+  double* H1i = scr + 3 * B2;
+  double* Z1 = scr + 4 * B2;
+  double* H2 = scr + 5 * B2;
+  double* H2i = scr + 6 * B2;
+  const double* Mp = R2g;
+  if (R1g) {
+    gmm64<false, false>(R2g, LB, R1g, LB, f, f, f, [&](int i, int j, double v) { M[i * LB + j] = v; });
+    __syncthreads();
+    Mp = M;
+  }
+  gmm64<false, true>(Mp, LB, Mp, LB, f, f, f, [&](int i, int j, double v) { G[i * LB + j] = v; });
+  __syncthreads();
+  uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+  chol_inv128(G, LB, f, H1, H1i, lds, 0ull, 0ull, 1, &a0, &a1);
+  gmm64<true, false>(Mp, LB, H1i, LB, f, f, f, [&](int i, int j, double v) { Z1[i * LB + j] = v; });
+  __syncthreads();
+  gmm64<true, false>(Z1, LB, Z1, LB, f, f, f, [&](int i, int j, double v) { G[i * LB + j] = v; });
+  __syncthreads();
+  chol_inv128(G, LB, f, H2, H2i, lds, a0, a1, 0, &b0, &b1);
+  gmm64<false, false>(Z1, LB, H2i, LB, f, f, f, [&](int i, int j, double v) { Qh[i * LB + j] = v; });
+  gmm64<false, false>(H2, LB, H1, LB, f, f, f, [&](int i, int j, double v) { Rh[i * LB + j] = v; });
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// One tile: Alg. 1 with BCGS2 + CholeskyQR2 blocks and the device rank
+// test, then Alg. 2 (q = 0): C^T = A^T Q, CholeskyQR2 of C^T, QR of
+// (R2 R1)^T, U = Q Qh.  A wide tile (h < w) is factored as A^T without
+// moving it: its sketch A^T Omega and its C^T = A Q are the two products
+// of a tall tile with the roles of the routines exchanged; the core is
+// then re-triangularised.
 // ---------------------------------------------------------------------------
 __device__ void tile_factor(const TileDesc& td, float* slot, double* sdbl, double* lds, float* out_pool,
                             TileResult* res, double tol, uint32_t k0, uint32_t k1) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int64_t LD = TileSlot::LD;
   const bool tr = td.h < td.w;
-  const int64_t m = tr ? td.w : td.h, n = tr ? td.h : td.w;
+  const int64_t m = tr ? td.w : td.h, n = tr ? td.h : td.w;     // oriented: m >= n
+  const bool al = ((uintptr_t)td.A % 16 == 0) && (td.lda % 4 == 0);
   // LDS carve for the basis phase
-  double* Gs = lds + TL_GS;                          // Gram -> R, or W = Q^T Y (ld 64)
+  double* Gs = lds + TL_GS;                          // Gram -> R (ld chol_width(f) + 1)
   double* Ri = lds + TL_RI;                          // R^{-1}
   double* work = lds + TL_WORK;                      // Cholesky work area (24 x 64)
   double* dgs = lds + TL_DGS;                        // Cholesky diagonal
+  double* Wp = lds + TL_W;                           // W = Q^T Y (TILE_QW x TILE_BMAX)
   double* fold = lds + TL_FOLD;                      // wave fold buffer of the reductions
   double* scal = lds + TILE_SQR;                     // [0] ||A||^2, [1..64] R1 diagonal
   __shared__ int s_keep, s_stop;
-  // orient / repack: Ae row-major m x n with leading dimension lde
-  const float* Ae = td.A;
-  int64_t lde = td.lda;
-  const bool aligned = ((uintptr_t)td.A % 16 == 0) && (td.lda % 4 == 0);
-  if (tr || !aligned) {
-    float* At = slot + TileSlot::AT;
-    for (int64_t idx = tid; idx < m * n; idx += 256) {
-      const int64_t i = idx / n, j = idx - i * n;
-      At[i * LD + j] = tr ? td.A[j * td.lda + i] : td.A[i * td.lda + j];
-    }
-    __syncthreads();
-    Ae = At;
-    lde = LD;
-  }
   float* Om = slot + TileSlot::OM;
   float* Yb = slot + TileSlot::Y;
   float* Q = slot + TileSlot::Q;
@@ -493,19 +606,14 @@ __device__ void tile_factor(const TileDesc& td, float* slot, double* sdbl, doubl
   for (int64_t col0 = 0; col0 < n; col0 += b) {
     const int f = (int)((n - col0) < b ? (n - col0) : b);
     const int fpad = ((f + 15) / 16) * 16;
-    if (wcols + f > TILE_QW) {                       // basis would not fit
-      status = TS_RANK;
-      break;
-    }
     ++blocks;
     tile_omega(Om, ldk, n, col0, f, fpad, k0, k1);
     __syncthreads();
     double* ss = (col0 == 0) ? &scal[0] : nullptr;
-    const int ct = fpad / 16;
-    if (ct == 1) tile_sketch<1>(Ae, lde, m, n, Om, ldk, Yb, LD, ss, fold);
-    else if (ct == 2) tile_sketch<2>(Ae, lde, m, n, Om, ldk, Yb, LD, ss, fold);
-    else if (ct == 3) tile_sketch<3>(Ae, lde, m, n, Om, ldk, Yb, LD, ss, fold);
-    else tile_sketch<4>(Ae, lde, m, n, Om, ldk, Yb, LD, ss, fold);
+    // Y = A_o Omega_j (A_o the oriented tile, m x n)
+    if (tr) tile_colprod(td.A, td.lda, n, m, Om, ldk, f, Yb, LD, ss, fold);
+    else if (al) tile_rowprod<true>(td.A, td.lda, m, n, Om, ldk, f, Yb, LD, ss, fold);
+    else tile_rowprod<false>(td.A, td.lda, m, n, Om, ldk, f, Yb, LD, ss, fold);
     if (col0 == 0) {
       const double a = scal[0];
       if (!(a < INFINITY)) {
@@ -520,9 +628,12 @@ __device__ void tile_factor(const TileDesc& td, float* slot, double* sdbl, doubl
     int nf = 0;
     for (int pass = 0; pass < 2; ++pass) {
       if (wcols > 0) {
-        // W = Q^T Y (wcols x f) into the Gs/Ri region, then Y -= Q W
-        tile_xty(Q, LD, (int)wcols, Yb, LD, f, m, Gs, TILE_BMAX, fold);
-        tile_update(Yb, LD, Q, LD, m, (int)wcols, f, Gs, TILE_BMAX);
+        // W = Q^T Y (wcols x f), then Y -= Q W
+        for (int64_t q0 = 0; q0 < wcols; q0 += 64) {
+          const int wq = (int)((wcols - q0) < 64 ? (wcols - q0) : 64);
+          tile_xty(Q + q0 * LD, LD, wq, Yb, LD, f, m, Wp + q0 * TILE_BMAX, TILE_BMAX, fold);
+        }
+        tile_update(Yb, LD, Q, LD, m, (int)wcols, f, Wp, TILE_BMAX);
       }
       tile_xty(Yb, LD, f, Yb, LD, f, m, Gs, LDG, fold);
       tile_chol(Gs, Ri, work, dgs, f, pass == 0 ? 0ull : dm1, pass == 0, pass == 0 ? &dm1 : &dm2, &nf);
@@ -551,59 +662,106 @@ __device__ void tile_factor(const TileDesc& td, float* slot, double* sdbl, doubl
     if (keep > 0) tile_apply(Yb, LD, m, f, Ri, LDG, Q, LD, wcols, keep);      // append Z R2^{-1}
     wcols += keep;
     if (stop) break;
+    if (wcols > TILE_RMAX) {                        // the rank will exceed the in-kernel cap
+      status = TS_RANK;
+      break;
+    }
   }
   const int64_t r = wcols;
   if (status == TS_OK && r > TILE_RMAX) status = TS_RANK;
   if (status == TS_OK && r > td.r_cap) status = TS_CAPACITY;
   if (status == TS_OK && r > 0) {
-    // a9: C^T = A^T Q (n x r)
-    float* Ct = slot + TileSlot::CT;
-    tile_ct(Ae, lde, m, n, Q, LD, (int)r, Ct, LD);
-    // a10: C^T = V R by CholeskyQR2 (V over C^T in place), R1, R2 kept
     const int ri = (int)r;
-    const int LDG = chol_width(ri) + 1;
-    uint64_t dm1 = 0, dm2 = 0;
-    int nf = 0;
-    tile_xty(Ct, LD, ri, Ct, LD, ri, n, Gs, LDG, fold);
-    tile_chol(Gs, Ri, work, dgs, ri, 0ull, 1, &dm1, &nf);
-    tile_store_small(Gs, LDG, ri, sdbl + TileSlot::R1);
-    tile_apply(Ct, LD, n, ri, Ri, LDG, Ct, LD, 0, ri);
-    tile_xty(Ct, LD, ri, Ct, LD, ri, n, Gs, LDG, fold);
-    tile_chol(Gs, Ri, work, dgs, ri, dm1, 0, &dm2, &nf);
-    tile_store_small(Gs, LDG, ri, sdbl + TileSlot::R2);
-    // V = C^T R2^{-1}: the output V (non-transposed) or V' (transposed)
-    float* Vdst = tr ? slot + TileSlot::VP : out_pool + td.out_off + td.r_cap * td.h + td.r_cap * td.r_cap;
-    const int64_t ldv = tr ? LD : td.w;
-    tile_apply(Ct, LD, n, ri, Ri, LDG, Vdst, ldv, 0, ri);
-    // a11: (R2 R1)^T = Qh Rh on the arena
-    int nfq = 0;
-    tile_small_qr_any(lds, sdbl + TileSlot::R1, sdbl + TileSlot::R2, ri, sdbl + TileSlot::QH,
-                      sdbl + TileSlot::DH, &nfq);
-    // U_hat = Q Qh (m x r)
-    const int LDW = chol_width(ri) + 1;
-    tile_load_small(sdbl + TileSlot::QH, ri, Gs, LDW);
+    // a9: C^T = A_o^T Q (n x r), 64 columns of Q at a time
+    float* Ct = slot + TileSlot::CT;
+    for (int c0 = 0; c0 < ri; c0 += 64) {
+      const int rc = (ri - c0) < 64 ? ri - c0 : 64;
+      if (!tr) tile_colprod(td.A, td.lda, m, n, Q + c0 * LD, LD, rc, Ct + c0 * LD, LD, nullptr, fold);
+      else if (al) tile_rowprod<true>(td.A, td.lda, n, m, Q + c0 * LD, LD, rc, Ct + c0 * LD, LD, nullptr, fold);
+      else tile_rowprod<false>(td.A, td.lda, n, m, Q + c0 * LD, LD, rc, Ct + c0 * LD, LD, nullptr, fold);
+    }
     float* Ut = out_pool + td.out_off;
     float* core = Ut + td.r_cap * td.h;
     float* Vt = core + td.r_cap * td.r_cap;
-    if (!tr) {
-      tile_apply(Q, LD, m, ri, Gs, LDW, Ut, td.h, 0, ri);                     // U (h x r)
-      for (int idx = tid; idx < ri * ri; idx += 256) {                         // core = Rh
-        const int i = idx / ri, j = idx - i * ri;
-        core[(int64_t)i * td.r_cap + j] = (float)sdbl[TileSlot::DH + (int64_t)j * ri + i];
+    // V = C^T R2^{-1}: the output V (tall tile) or V' (wide tile)
+    float* Vdst = tr ? slot + TileSlot::VP : Vt;
+    const int64_t ldv = tr ? LD : td.w;
+    if (ri <= 64) {
+      // a10: C^T = V R by CholeskyQR2 (V over C^T in place), R1, R2 kept
+      const int LDG = chol_width(ri) + 1;
+      uint64_t dm1 = 0, dm2 = 0;
+      int nf = 0;
+      tile_xty(Ct, LD, ri, Ct, LD, ri, n, Gs, LDG, fold);
+      tile_chol(Gs, Ri, work, dgs, ri, 0ull, 1, &dm1, &nf);
+      tile_store_small(Gs, LDG, ri, sdbl + TileSlot::R1);
+      tile_apply(Ct, LD, n, ri, Ri, LDG, Ct, LD, 0, ri);
+      tile_xty(Ct, LD, ri, Ct, LD, ri, n, Gs, LDG, fold);
+      tile_chol(Gs, Ri, work, dgs, ri, dm1, 0, &dm2, &nf);
+      tile_store_small(Gs, LDG, ri, sdbl + TileSlot::R2);
+      tile_apply(Ct, LD, n, ri, Ri, LDG, Vdst, ldv, 0, ri);
+      // a11: (R2 R1)^T = Qh Rh on the arena
+      int nfq = 0;
+      tile_small_qr_any(lds, sdbl + TileSlot::R1, sdbl + TileSlot::R2, ri, sdbl + TileSlot::QH,
+                        sdbl + TileSlot::DH, &nfq);
+      // U_hat = Q Qh (m x r)
+      const int LDW = chol_width(ri) + 1;
+      tile_load_small(sdbl + TileSlot::QH, ri, Gs, LDW);
+      if (!tr) {
+        tile_apply(Q, LD, m, ri, Gs, LDW, Ut, td.h, 0, ri);                   // U (h x r)
+        for (int idx = tid; idx < ri * ri; idx += 256) {                       // core = Rh
+          const int i = idx / ri, j = idx - i * ri;
+          core[(int64_t)i * td.r_cap + j] = (float)sdbl[TileSlot::DH + (int64_t)j * ri + i];
+        }
+      } else {
+        // A^T = U' D' V'^T with U' = Q Qh (w x r) and V' (h x r): A = V' D'^T U'^T,
+        // QR(D'^T) = Q'' R'': U = V' Q'', core = R'', V = U'.
+        tile_apply(Q, LD, m, ri, Gs, LDW, Vt, td.w, 0, ri);                   // V = U' (w x r)
+        int nfq2 = 0;
+        // M = D' (element (i,j) at j*r + i) -> QR(M^T) = QR(D'^T)
+        tile_small_qr_any(lds, nullptr, sdbl + TileSlot::DH, ri, sdbl + TileSlot::QH2, sdbl + TileSlot::DH2,
+                          &nfq2);
+        tile_load_small(sdbl + TileSlot::QH2, ri, Gs, LDW);
+        tile_apply(slot + TileSlot::VP, LD, n, ri, Gs, LDW, Ut, td.h, 0, ri);  // U = V' Q'' (h x r)
+        for (int idx = tid; idx < ri * ri; idx += 256) {
+          const int i = idx / ri, j = idx - i * ri;
+          core[(int64_t)i * td.r_cap + j] = (float)sdbl[TileSlot::DH2 + (int64_t)j * ri + i];
+        }
       }
     } else {
-      // A^T = U' D' V'^T with U' = Q Qh (w x r) and V' (h x r): A = V' D'^T U'^T,
-      // QR(D'^T) = Q'' R'': U = V' Q'', core = R'', V = U'.
-      tile_apply(Q, LD, m, ri, Gs, LDW, Vt, td.w, 0, ri);                     // V = U' (w x r)
-      int nfq2 = 0;
-      // M = D' (element (i,j) at j*r + i) -> QR(M^T) = QR(D'^T)
-      tile_small_qr_any(lds, nullptr, sdbl + TileSlot::DH, ri, sdbl + TileSlot::QH2, sdbl + TileSlot::DH2,
-                        &nfq2);
-      tile_load_small(sdbl + TileSlot::QH2, ri, Gs, LDW);
-      tile_apply(slot + TileSlot::VP, LD, n, ri, Gs, LDW, Ut, td.h, 0, ri);  // U = V' Q'' (h x r)
+      // the same steps with the blocked 128-wide Cholesky and L2-resident matrices
+      constexpr int LB = TileSlot::LB;
+      constexpr int64_t B2 = TileSlot::B2;
+      double* dd = sdbl + TileSlot::BIG;
+      double* Gg = dd;
+      double* R1g = dd + B2;
+      double* R1i = dd + 2 * B2;
+      double* R2g = dd + 3 * B2;
+      double* R2i = dd + 4 * B2;
+      double* Qh = dd + 5 * B2;
+      double* Rh = dd + 6 * B2;
+      double* Qh2 = dd + 7 * B2;
+      double* Rh2 = dd + 8 * B2;
+      double* scr = dd + 9 * B2;                    // 7 buffers
+      uint64_t d10 = 0, d11 = 0, d20 = 0, d21 = 0;
+      tile_gram_big(Ct, LD, ri, n, Gg, fold);
+      chol_inv128(Gg, LB, ri, R1g, R1i, lds, 0ull, 0ull, 1, &d10, &d11);
+      tile_apply_big(Ct, LD, n, ri, R1i, lds, Ct, LD, ri);
+      tile_gram_big(Ct, LD, ri, n, Gg, fold);
+      chol_inv128(Gg, LB, ri, R2g, R2i, lds, d10, d11, 0, &d20, &d21);
+      tile_apply_big(Ct, LD, n, ri, R2i, lds, Vdst, ldv, ri);
+      tile_small_qr_big(lds, R1g, R2g, ri, Qh, Rh, scr);
+      const double* Rc = Rh;
+      if (!tr) {
+        tile_apply_big(Q, LD, m, ri, Qh, lds, Ut, td.h, ri);                   // U (h x r)
+      } else {
+        tile_apply_big(Q, LD, m, ri, Qh, lds, Vt, td.w, ri);                   // V = U' (w x r)
+        tile_small_qr_big(lds, nullptr, Rh, ri, Qh2, Rh2, scr);                // QR(D'^T)
+        tile_apply_big(slot + TileSlot::VP, LD, n, ri, Qh2, lds, Ut, td.h, ri); // U = V' Q''
+        Rc = Rh2;
+      }
       for (int idx = tid; idx < ri * ri; idx += 256) {
         const int i = idx / ri, j = idx - i * ri;
-        core[(int64_t)i * td.r_cap + j] = (float)sdbl[TileSlot::DH2 + (int64_t)j * ri + i];
+        core[(int64_t)i * td.r_cap + j] = (float)Rc[(int64_t)i * LB + j];
       }
     }
     __syncthreads();

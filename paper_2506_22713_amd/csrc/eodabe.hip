@@ -221,6 +221,7 @@ struct WS {
   int32_t* deadbig;     // r_cap
   double* dg;           // r_cap
   void* tbig;           // ldy x r_cap scratch for large-f triangular solves
+  double* sq128;        // 7 x 128 x 128: closing QR scratch for ranks 65..128
   size_t total;
 };
 
@@ -266,6 +267,7 @@ WS carve(void* base, const Geo& g) {
   w.deadbig = c.take<int32_t>(rc + 64);
   w.dg = c.take<double>(std::max<int64_t>(rc, g.bn) + 64);
   w.tbig = c.take<char>(std::max(g.ldy, g.ldk) * rc * std::max<size_t>(e, 8));
+  w.sq128 = rb > 64 ? c.take<double>(7 * 128 * 128) : nullptr;
   w.total = c.off + 256;
   return w;
 }
@@ -470,7 +472,7 @@ struct Ops {
     return 0;
   }
 
-  // Z = X W for blocks of f <= 64 columns (one job, or two in one launch).
+  // Z = X W for blocks of f <= 128 columns (one job, or two in one launch).
   int apply(const ApplyJob& j0, const ApplyJob* j1, int f, const int32_t* stopb = nullptr,
             int blk = 0, Gate gate = Gate{}) {
     if (f <= 0) return 0;
@@ -482,8 +484,12 @@ struct Ops {
       hipLaunchKernelGGL((k_apply<T, 16>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else if (f <= 32)
       hipLaunchKernelGGL((k_apply<T, 32>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
-    else
+    else if (f <= 64)
       hipLaunchKernelGGL((k_apply<T, 64>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
+    else if (f <= 128)
+      hipLaunchKernelGGL((k_apply<T, 128>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
+    else
+      return EODABE_EINVAL;
     LAUNCHCHK();
     return 0;
   }
@@ -526,8 +532,10 @@ CholArgs chol_args(const WS& w, double* R, int32_t* dead, int first, int fresh, 
 // FP64, element (i,j) at j*f + i, Z rounded to T and written over X), then
 // the Cholesky with the floor/kill rules and the epilogues in ca (R,
 // R^{-1}, stop test, ||A||_F finish).  f <= 64: one launch (k_gram_rows; its last workgroup runs the
-// Cholesky with inverse).  Wider blocks: generic GEMM, global Cholesky,
-// separate stop test (no W, no inverse).
+// Cholesky with inverse).  64 < f <= 128 with ca.Rinv: generic GEMM, then the
+// blocked Cholesky with inverse on one workgroup (k_chol128), separate stop
+// test.  Wider blocks: generic GEMM, global Cholesky, separate stop test (no
+// W, no inverse).
 template <typename T>
 int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, int64_t rows, int f,
               double* parts, const CholArgs& ca, const int32_t* stopb = nullptr, int blk = 0,
@@ -555,16 +563,21 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
     LAUNCHCHK();
     return 0;
   }
-  if (W || ca.Rinv) return EODABE_EINVAL;   // fused forms only for f <= 64
+  if (W || ca.gate.st || ca.f_dev) return EODABE_EINVAL;   // fused / gated forms only for f <= 64
+  if (ca.Rinv && f > 128) return EODABE_EINVAL;
   Ops<T> ops{ctx, st};
-  if (ca.fresh) hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, ca.dead, (int64_t)f);
+  if (ca.fresh && !ca.Rinv) hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, ca.dead, (int64_t)f);
   if (ca.norm_parts)
     hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, ca.norm_parts, ca.max_parts, ca.n_norm,
                        w.st);
   TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, 1, parts, f, (int64_t)f * f, nullptr,
                                    nullptr, stopb, blk));
-  hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.dead, w.dg,
-                     ca.first_pass, w.st, ca.count_floors);
+  if (ca.Rinv)
+    hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, ca.dead, ca.first_pass,
+                       ca.fresh, w.st, ca.count_floors, stopb, blk);
+  else
+    hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.dead, w.dg,
+                       ca.first_pass, w.st, ca.count_floors);
   if (ca.R1)
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, ca.R1, ca.R, ca.dead, f, ca.col0, ca.n, w.st,
                        ca.wlog, ca.acc, ca.diag_log, blk);
@@ -589,16 +602,24 @@ int cholqr2(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, T* X, in
     Zout = X;
     ldz = ld;
   }
-  if (f <= 64) {
-    // [Gram, chol_inv] -> R1 (rb1), R1^{-1} (rb3); [X := X R1^{-1}, Gram,
-    // chol_inv] -> R2 (rb2), R2^{-1} (rb5); Z = X R2^{-1}.  Rout and Dout are
-    // not written on this path (the closing steps take R1, R2 from rb1, rb2).
+  if (f <= 128) {
+    // [Gram, Cholesky with inverse] -> R1 (rb1), R1^{-1} (rb3); [X := X R1^{-1},
+    // Gram, Cholesky with inverse] -> R2 (rb2), R2^{-1} (rb5); Z = X R2^{-1}.
+    // Up to 64 columns the normalisation is fused into the second Gram
+    // kernel.  Rout and Dout are not written on this path (the closing
+    // steps take R1, R2 from rb1, rb2).
     CholArgs c1 = chol_args(w, w.rb1, w.deadbig, 1, 1, 1);
     c1.Rinv = w.rb3;
     TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, c1));
     CholArgs c2 = chol_args(w, w.rb2, w.deadbig, 0, 0, 1);
     c2.Rinv = w.rb5;
-    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, c2, nullptr, 0, w.rb3));
+    if (f <= 64) {
+      TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, c2, nullptr, 0, w.rb3));
+    } else {
+      const ApplyJob a1{X, ld, X, ld, w.rb3, rows, 0, f, f, nullptr, nullptr, nullptr};
+      TRY(ops.apply(a1, nullptr, f));
+      TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, c2));
+    }
     const ApplyJob a{X, ld, Zout, ldz, w.rb5, rows, 0, f, f, nullptr, nullptr, nullptr};
     TRY(ops.apply(a, nullptr, f));
     return 0;
@@ -719,7 +740,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       // stop test (a5); the second solve is the append below.
       int32_t* deadj = w.dead + j * BN_MAX;
       const int64_t wmax = std::min<int64_t>(j * g.b, g.nn);
-      const bool small = f <= 64;
+      const bool small = f <= 64;     // fused Gram + Cholesky-with-inverse kernels
+      const bool mid = f <= 128;      // explicit R^{-1} (blocked Cholesky above 64 columns) + apply
       if (j == 0) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       for (int pass = 0; pass < 2; ++pass) {
         if (j > 0) {
@@ -733,14 +755,14 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
         }
         CholArgs ca = chol_args(w, pass == 0 ? w.r1 : w.r2, deadj, pass == 0, 0, 0);
         if (pass == 0) {
-          if (small) ca.Rinv = w.r1inv;
+          if (mid) ca.Rinv = w.r1inv;
           if (j == 0) {
             ca.norm_parts = w.normparts;
             ca.max_parts = w.maxparts;
             ca.n_norm = sketch_wgs * (int64_t)nsp;
           }
         } else {
-          if (small) ca.Rinv = w.r2inv;
+          if (mid) ca.Rinv = w.r2inv;
           ca.R1 = w.r1;
           ca.col0 = col0;
           ca.n = g.nn;
@@ -755,17 +777,17 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
         const bool fuse = small && j == 0;
         TRY(gram_chol<T>(ctx, st, w, y, g.ldy, g.mm, f, w.gpart, ca, stopb, blk,
                          (fuse && pass == 1) ? w.r1inv : nullptr));
-        if (pass == 0 && small && !fuse) {
+        if (pass == 0 && mid && !fuse) {
           const ApplyJob a{y, g.ldy, y, g.ldy, w.r1inv, g.mm, 0, f, f, nullptr, nullptr, nullptr};
           TRY(ops.apply(a, nullptr, f, stopb, blk));
         }
-        if (pass == 0 && !small) {
+        if (pass == 0 && !mid) {
           TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r1, f));
           TRY(copy2d<T>(ctx, st, (T*)w.tbig, g.ldy, y, g.ldy, f, g.ldy, 0));
         }
       }
       // a6: append P = Z R2^{-1} (accepted columns) into Q at column wlog[j]
-      if (small) {
+      if (mid) {
         const ApplyJob a{y, g.ldy, q, g.ldy, w.r2inv, g.mm, 0, f, 0, w.wlog, w.accv, nullptr};
         TRY(ops.apply(a, nullptr, f, stopb, blk));
       } else {
@@ -810,12 +832,15 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   return 0;
 }
 
-// QR of M^T on one workgroup (f <= 64): M = R2 R1, or M = R2 when R1 is null
+// QR of M^T on one workgroup (f <= 128): M = R2 R1, or M = R2 when R1 is null
 // (both column-major f x f FP64).  Q_hat -> Qout (FP64, column-major),
 // R_hat -> Dout (type T, row-major ldd); floored pivots counted in st.
+// Above 64 the matrices stay in global memory (scr: 7 x 128 x 128 doubles;
+// no gated form).
 template <typename T>
 int small_qr(eodabe_ctx* ctx, hipStream_t st, const double* R1, const double* R2, int f, double* Qout, T* Dout,
-             int64_t ldd, State* state, Gate gate = Gate{}, const int64_t* f_dev = nullptr) {
+             int64_t ldd, State* state, Gate gate = Gate{}, const int64_t* f_dev = nullptr,
+             double* scr = nullptr) {
   if (f <= 0) return 0;
   if (f <= 16)
     hipLaunchKernelGGL((k_small_qr<T, 16>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1,
@@ -826,6 +851,9 @@ int small_qr(eodabe_ctx* ctx, hipStream_t st, const double* R1, const double* R2
   else if (f <= 64)
     hipLaunchKernelGGL((k_small_qr<T, 64>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1,
                        gate, f_dev);
+  else if (f <= 128 && scr && !gate.st && !f_dev)
+    hipLaunchKernelGGL((k_small_qr128<T>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1,
+                       scr);
   else
     return EODABE_EINVAL;
   LAUNCHCHK();
@@ -842,19 +870,19 @@ int core_splits(const Geo& g, int64_t r) {
   return (int)std::min<int64_t>(sc, 1024);
 }
 
-// a9-a11 of Alg. 2 for a rank of at most 64: C = Q^T A; C^T = V R by
+// a9-a11 of Alg. 2 for a rank of at most 128: C = Q^T A; C^T = V R by
 // CholeskyQR2 (R = R2 R1 in rb2, rb1; V = (C^T R1^{-1}) R2^{-1}); R^T =
 // Q_hat R_hat on one workgroup (Q_hat -> rb4, D_hat = R_hat -> Dout); V and
 // U_hat = Q Q_hat in one launch.  r bounds the rank (template widths and
-// partial layouts); with r_dev the exact rank is read on the device and
-// gate holds every kernel until the basis loop has stopped (closing steps
-// enqueued before the host has seen the stop flag).  prof_block tags the
-// timed projection (SPEC_BLOCK for gated launches).
+// partial layouts); with r_dev (ranks <= 64 only) the exact rank is read on
+// the device and gate holds every kernel until the basis loop has stopped
+// (closing steps enqueued before the host has seen the stop flag).
+// prof_block tags the timed projection (SPEC_BLOCK for gated launches).
 template <typename T>
 int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, int64_t r,
                 Gate gate, const int64_t* r_dev, T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout,
                 int64_t ldd, int prof_block) {
-  if (r <= 0 || r > 64) return EODABE_EINVAL;
+  if (r <= 0 || r > 128 || (r > 64 && (gate.st || r_dev))) return EODABE_EINVAL;
   Ops<T> ops{ctx, st};
   T* q = (T*)w.q;
   T* cb = (T*)w.cbuf;
@@ -884,8 +912,14 @@ int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, cons
   c2.Rinv = w.rb5;
   c2.gate = gate;
   c2.f_dev = r_dev;
-  TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c2, nullptr, 0, w.rb3));
-  TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st, gate, r_dev));
+  if (r <= 64) {
+    TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c2, nullptr, 0, w.rb3));
+  } else {
+    const ApplyJob a1{cb, g.ldk, cb, g.ldk, w.rb3, g.nn, 0, (int)r, (int)r, nullptr, nullptr, nullptr};
+    TRY(ops.apply(a1, nullptr, (int)r));
+    TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c2));
+  }
+  TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st, gate, r_dev, w.sq128));
   const ApplyJob jv{cb, g.ldk, Vout, ldv, w.rb5, g.nn, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
   const ApplyJob ju{q, g.ldy, Uout, ldu, w.rb4, g.mm, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
   TRY(ops.apply(jv, &ju, (int)r, nullptr, 0, gate));
@@ -913,7 +947,7 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
     TRY(ops.template gemm_nt<T>(Ae, g.lda_eff, cb, g.ldk, g.mm, r, g.nn, 1, q, g.ldy, g.ldy * r));
     TRY(cholqr2<T>(ctx, st, g, w, q, g.ldy, g.mm, (int)r, w.rb4, 0, (T*)w.tbig));
   }
-  if (r <= 64)
+  if (r <= 128)
     return close_small<T>(ctx, st, g, w, Ae, r, Gate{}, nullptr, Uout, ldu, Vout, ldv, Dout, ldd, 0);
   // a9: C = Q^T A (r x nn, row-major ld ldk)
   const int pid = prof_begin(ctx, st);
@@ -1459,14 +1493,15 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
       T* ut = (T*)w.ybig;            // U' column-major (ld = ldy)
       TRY(run_close<T>(ctx, st, g, w, Ae, rank, ut, g.ldy, (T*)w.cbuf, g.ldk, (T*)w.tbig, rank));
       Ops<T> ops{ctx, st};
-      if (rank <= 64) {
+      if (rank <= 128) {
         // QR(D'^T) = Q'' R'' on one workgroup: D' column-major (FP64) -> rb2;
         // U_out = V' Q'' (one MFMA pass), core = R'', Vt_out = U'^T.
         dim3 gt((unsigned)cdiv(rank, 32), (unsigned)cdiv(rank, 32));
         hipLaunchKernelGGL((k_copy2d<T, double>), gt, dim3(32, 8), 0, st, (const T*)w.tbig, rank, w.rb2,
                            rank, rank, rank, 1);
         LAUNCHCHK();
-        TRY(small_qr<T>(ctx, st, nullptr, w.rb2, (int)rank, w.rb4, (T*)core, g.r_cap, w.st));
+        TRY(small_qr<T>(ctx, st, nullptr, w.rb2, (int)rank, w.rb4, (T*)core, g.r_cap, w.st, Gate{}, nullptr,
+                        w.sq128));
         const ApplyJob ju{w.cbuf, g.ldk, Ut, m, w.rb4, m, 0, (int)rank, (int)rank, nullptr, nullptr, nullptr};
         TRY(ops.apply(ju, nullptr, (int)rank));
         TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));

@@ -1230,13 +1230,17 @@ constexpr int CHOL128_LDS = 3 * SmallCfg<64>::SIZE + 24 * 64 + 2 * 64;
 //         elimination);
 //   R22 = chol(G22 - R12^T R12), its floor rule referred to G22's diagonal;
 //   R^{-1} = [R11^{-1}, -R11^{-1} R12 R22^{-1}; 0, R22^{-1}].
-// G (read only), R, Rinv: global FP64, row-major, leading dimension ldg.
-// lds: CHOL128_LDS doubles.  dm_in / dm_out: dead masks of columns 0-63 and
-// 64-127.  Returns the number of floored pivots (uniform).
+// G (read only, symmetric), R, Rinv: global FP64, leading dimension ldg;
+// R and Rinv row-major (element (i,j) at i*ldg + j), or column-major (at
+// j*ldg + i) with CM.  lds: CHOL128_LDS doubles.  dm_in / dm_out: dead
+// masks of columns 0-63 and 64-127.  Returns the number of floored pivots
+// (uniform).
 // ---------------------------------------------------------------------------
+template <bool CM = false>
 __device__ int chol_inv128(const double* G, int ldg, int f, double* R, double* Rinv, double* lds,
                            uint64_t dm_in0, uint64_t dm_in1, int first_pass, uint64_t* dm_out0,
                            uint64_t* dm_out1) {
+  auto at = [&](int i, int j) -> int64_t { return CM ? (int64_t)j * ldg + i : (int64_t)i * ldg + j; };
   typedef SmallCfg<64> S;
   constexpr int LD = S::LD;
   double* Gs = lds;                        // block being factored -> its R
@@ -1258,13 +1262,13 @@ __device__ int chol_inv128(const double* G, int ldg, int f, double* R, double* R
   // R11, R11^{-1}; zero lower-left blocks
   for (int idx = tid; idx < 64 * 64; idx += 256) {
     const int i = idx >> 6, j = idx & 63;
-    R[(int64_t)i * ldg + j] = Gs[i * LD + j];
-    Rinv[(int64_t)i * ldg + j] = Ri[i * LD + j];
+    R[at(i, j)] = Gs[i * LD + j];
+    Rinv[at(i, j)] = Ri[i * LD + j];
   }
   for (int idx = tid; idx < n2 * 64; idx += 256) {
     const int i = idx >> 6, j = idx & 63;
-    R[(int64_t)(64 + i) * ldg + j] = 0.0;
-    Rinv[(int64_t)(64 + i) * ldg + j] = 0.0;
+    R[at(64 + i, j)] = 0.0;
+    Rinv[at(64 + i, j)] = 0.0;
   }
   // R12 = R11^{-T} G12, masked
   gmm64<true, false>(Ri, LD, G + 64, ldg, 64, n2, 64, [&](int i, int j, double v) {
@@ -1278,24 +1282,107 @@ __device__ int chol_inv128(const double* G, int ldg, int f, double* R, double* R
   });
   for (int idx = tid; idx < 64 * n2; idx += 256) {
     const int i = idx / n2, j = idx - i * n2;
-    R[(int64_t)i * ldg + 64 + j] = T[i * LD + j];
+    R[at(i, 64 + j)] = T[i * LD + j];
   }
   __syncthreads();
   chol_inv<64>(Gs, Ri, work, dgs, n2, dm_in1, first_pass, dm_out1, &nf2, dg2, &nl2);
   for (int idx = tid; idx < n2 * n2; idx += 256) {
     const int i = idx / n2, j = idx - i * n2;
-    R[(int64_t)(64 + i) * ldg + 64 + j] = Gs[i * LD + j];
-    Rinv[(int64_t)(64 + i) * ldg + 64 + j] = Ri[i * LD + j];
+    R[at(64 + i, 64 + j)] = Gs[i * LD + j];
+    Rinv[at(64 + i, 64 + j)] = Ri[i * LD + j];
   }
   __syncthreads();
   // R^{-1}_12 = -(R11^{-1} R12) R22^{-1}
-  gmm64<false, false>(Rinv, ldg, T, LD, 64, n2, 64, [&](int i, int j, double v) { Gs[i * LD + j] = v; });
+  gmm64<CM, false>(Rinv, ldg, T, LD, 64, n2, 64, [&](int i, int j, double v) { Gs[i * LD + j] = v; });
   __syncthreads();
-  gmm64<false, false>(Gs, LD, Ri, LD, 64, n2, n2, [&](int i, int j, double v) {
-    Rinv[(int64_t)i * ldg + 64 + j] = -v;
-  });
+  gmm64<false, false>(Gs, LD, Ri, LD, 64, n2, n2, [&](int i, int j, double v) { Rinv[at(i, 64 + j)] = -v; });
   __syncthreads();
   return nf1 + nf2;
+}
+
+// ---------------------------------------------------------------------------
+// QR of M^T (M = R2 R1, or M = R2 when R1 is null; f x f, 64 < f <= 128) by
+// CholeskyQR2 in FP64 on one workgroup, with the matrices in global memory:
+// G = M M^T = Rh1^T Rh1, Z1 = M^T Rh1^{-1}, Z1^T Z1 = Rh2^T Rh2, Qh =
+// Z1 Rh2^{-1}, Rh = Rh2 Rh1 (first Cholesky floored, the second kills what
+// stays non-positive).  R1, R2: element (i,j) at j*ldi + i (CMI) or
+// i*ldi + j.  Qh and Rh go out through put_q(i, j, v) and put_r(i, j, v).
+// scr: 7 buffers of 128 x 128 doubles.  lds: CHOL128_LDS doubles.  Returns
+// the number of floored pivots.
+// ---------------------------------------------------------------------------
+template <bool CMI, typename PutQ, typename PutR>
+__device__ int small_qr_mid(double* lds, const double* R1g, const double* R2g, int f, int ldi, double* scr,
+                            PutQ put_q, PutR put_r) {
+  constexpr int LB = 128;
+  constexpr int64_t B2 = (int64_t)LB * LB;
+  double* M = scr;
+  double* G = scr + B2;
+  double* H1 = scr + 2 * B2;
+  double* H1i = scr + 3 * B2;
+  double* Z1 = scr + 4 * B2;
+  double* H2 = scr + 5 * B2;
+  double* H2i = scr + 6 * B2;
+  if (R1g) {
+    gmm64<CMI, CMI>(R2g, ldi, R1g, ldi, f, f, f, [&](int i, int j, double v) { M[i * LB + j] = v; });
+  } else {
+    for (int idx = threadIdx.x; idx < f * f; idx += 256) {
+      const int i = idx / f, j = idx - i * f;
+      M[i * LB + j] = CMI ? R2g[(int64_t)j * ldi + i] : R2g[(int64_t)i * ldi + j];
+    }
+  }
+  __syncthreads();
+  gmm64<false, true>(M, LB, M, LB, f, f, f, [&](int i, int j, double v) { G[i * LB + j] = v; });
+  __syncthreads();
+  uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+  int nf = chol_inv128(G, LB, f, H1, H1i, lds, 0ull, 0ull, 1, &a0, &a1);
+  gmm64<true, false>(M, LB, H1i, LB, f, f, f, [&](int i, int j, double v) { Z1[i * LB + j] = v; });
+  __syncthreads();
+  gmm64<true, false>(Z1, LB, Z1, LB, f, f, f, [&](int i, int j, double v) { G[i * LB + j] = v; });
+  __syncthreads();
+  nf += chol_inv128(G, LB, f, H2, H2i, lds, a0, a1, 0, &b0, &b1);
+  gmm64<false, false>(Z1, LB, H2i, LB, f, f, f, put_q);
+  gmm64<false, false>(H2, LB, H1, LB, f, f, f, put_r);
+  __syncthreads();
+  return nf;
+}
+
+// Cholesky with inverse (chol_inv128) of an f x f Gram matrix, 64 < f <=
+// 128, on one workgroup: G, R, R^{-1} column-major f x f (element (i,j) at
+// j*f + i); dead: per-column flags, read unless fresh, written back; the
+// floored pivots are added to st->floored when count_floors.
+__global__ __launch_bounds__(256) void k_chol128(const double* __restrict__ G, int f, double* __restrict__ R,
+                                                 double* __restrict__ Rinv, int32_t* __restrict__ dead,
+                                                 int first_pass, int fresh, State* st, int count_floors,
+                                                 const int32_t* __restrict__ stop_block, int block_id) {
+  __shared__ double lds[CHOL128_LDS];
+  if (stop_block && *stop_block < block_id) return;
+  uint64_t d0 = 0, d1 = 0;
+  if (!fresh)
+    for (int c = 0; c < f; ++c)
+      if (dead[c]) {
+        if (c < 64) d0 |= 1ull << c;
+        else d1 |= 1ull << (c - 64);
+      }
+  __syncthreads();
+  uint64_t o0 = 0, o1 = 0;
+  const int nf = chol_inv128<true>(G, f, f, R, Rinv, lds, d0, d1, first_pass, &o0, &o1);
+  for (int c = threadIdx.x; c < f; c += 256) dead[c] = (int32_t)(((c < 64) ? (o0 >> c) : (o1 >> (c - 64))) & 1ull);
+  if (count_floors && threadIdx.x == 0 && nf && st) atomicAdd(&st->floored, nf);
+}
+
+// Closing QR (as k_small_qr) for 64 < f <= 128: R1, R2 column-major f x f
+// (R1 may be null), Qh -> Qout (column-major), Rh -> Dout (type T,
+// row-major ldd); scr: 7 x 128 x 128 doubles.
+template <typename T>
+__global__ __launch_bounds__(256) void k_small_qr128(const double* __restrict__ R1g,
+                                                     const double* __restrict__ R2g, int f,
+                                                     double* __restrict__ Qout, T* __restrict__ Dout,
+                                                     int64_t ldd, State* st, int count_floors, double* scr) {
+  __shared__ double lds[CHOL128_LDS];
+  const int nf = small_qr_mid<true>(lds, R1g, R2g, f, f, scr,
+                                    [&](int i, int j, double v) { Qout[(int64_t)j * f + i] = v; },
+                                    [&](int i, int j, double v) { Dout[(int64_t)i * ldd + j] = (T)v; });
+  if (count_floors && threadIdx.x == 0 && nf && st) atomicAdd(&st->floored, nf);
 }
 
 // Arguments of the Cholesky that closes a Gram pass (k_gram_rows, and the

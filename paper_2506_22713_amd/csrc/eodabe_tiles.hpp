@@ -536,38 +536,14 @@ __device__ __attribute__((noinline)) void tile_apply_big(const float* X, int64_t
   tile_apply<32>(X, ldx, m, f, lds, 129, Z, ldz, 0, ncols);
 }
 
-// QR of M^T (M = R2 R1, or R2 when R1 is null; f x f, 64 < f <= 128) by
-// CholeskyQR2 in FP64: Qh and Rh out; scr: 7 buffers of B2.  All row-major
-// with leading dimension LB.
+// QR of M^T (M = R2 R1, or R2 when R1 is null; f x f, 64 < f <= 128):
+// small_qr_mid on row-major matrices (leading dimension LB); Qh and Rh out
+// row-major; scr: 7 buffers of B2.
 __device__ __attribute__((noinline)) void tile_small_qr_big(double* lds, const double* R1g, const double* R2g,
                                                             int f, double* Qh, double* Rh, double* scr) {
   constexpr int LB = TileSlot::LB;
-  constexpr int64_t B2 = TileSlot::B2;
-  double* M = scr;
-  double* G = scr + B2;
-  double* H1 = scr + 2 * B2;
-  double* H1i = scr + 3 * B2;
-  double* Z1 = scr + 4 * B2;
-  double* H2 = scr + 5 * B2;
-  double* H2i = scr + 6 * B2;
-  const double* Mp = R2g;
-  if (R1g) {
-    gmm64<false, false>(R2g, LB, R1g, LB, f, f, f, [&](int i, int j, double v) { M[i * LB + j] = v; });
-    __syncthreads();
-    Mp = M;
-  }
-  gmm64<false, true>(Mp, LB, Mp, LB, f, f, f, [&](int i, int j, double v) { G[i * LB + j] = v; });
-  __syncthreads();
-  uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-  chol_inv128(G, LB, f, H1, H1i, lds, 0ull, 0ull, 1, &a0, &a1);
-  gmm64<true, false>(Mp, LB, H1i, LB, f, f, f, [&](int i, int j, double v) { Z1[i * LB + j] = v; });
-  __syncthreads();
-  gmm64<true, false>(Z1, LB, Z1, LB, f, f, f, [&](int i, int j, double v) { G[i * LB + j] = v; });
-  __syncthreads();
-  chol_inv128(G, LB, f, H2, H2i, lds, a0, a1, 0, &b0, &b1);
-  gmm64<false, false>(Z1, LB, H2i, LB, f, f, f, [&](int i, int j, double v) { Qh[i * LB + j] = v; });
-  gmm64<false, false>(H2, LB, H1, LB, f, f, f, [&](int i, int j, double v) { Rh[i * LB + j] = v; });
-  __syncthreads();
+  small_qr_mid<false>(lds, R1g, R2g, f, LB, scr, [&](int i, int j, double v) { Qh[i * LB + j] = v; },
+                      [&](int i, int j, double v) { Rh[i * LB + j] = v; });
 }
 
 // ---------------------------------------------------------------------------

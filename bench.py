@@ -62,6 +62,7 @@ def measured_traffic(workload: str, kernel: str):
         return None
     h = hashlib.sha256()
     for f in ("paper_2506_22713_amd/csrc/eodabe_kernels.hpp", "paper_2506_22713_amd/csrc/eodabe_tiles.hpp",
+              "paper_2506_22713_amd/csrc/eodabe_mlp.hpp",
               "paper_2506_22713_amd/csrc/eodabe.hip"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())

@@ -42,6 +42,8 @@ EXPORTED = [
     "eodabe_omega", "eodabe_sketch_workspace_size", "eodabe_sketch", "eodabe_basis",
     "eodabe_batched_workspace_size", "eodabe_factor_batched", "eodabe_tune_batched",
     "eodabe_profile", "eodabe_profile_read",
+    "eodabe_mlp_param_count", "eodabe_mlp_workspace_size", "eodabe_mlp_forward", "eodabe_mlp_grad",
+    "eodabe_mlp_adam", "eodabe_mlp_features", "eodabe_set_predictor", "eodabe_last_prediction",
 ]
 PROF_SKETCH, PROF_PROJECT, PROF_TILES = 0, 1, 2
 
@@ -96,6 +98,23 @@ _lib.eodabe_factor_batched.argtypes = _batched_args + [_vp, _vp, _vp]
 _lib.eodabe_factor_batched.restype = ctypes.c_int
 _lib.eodabe_tune_batched.argtypes = _batched_args + [_vp]
 _lib.eodabe_tune_batched.restype = ctypes.c_int
+_lib.eodabe_mlp_param_count.argtypes = []
+_lib.eodabe_mlp_param_count.restype = ctypes.c_int64
+_lib.eodabe_mlp_workspace_size.argtypes = [ctypes.c_int]
+_lib.eodabe_mlp_workspace_size.restype = _sz
+_lib.eodabe_mlp_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _sz]
+_lib.eodabe_mlp_forward.restype = ctypes.c_int
+_lib.eodabe_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _sz, ctypes.POINTER(ctypes.c_double)]
+_lib.eodabe_mlp_grad.restype = ctypes.c_int
+_lib.eodabe_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_int]
+_lib.eodabe_mlp_adam.restype = ctypes.c_int
+_lib.eodabe_mlp_features.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _vp]
+_lib.eodabe_mlp_features.restype = ctypes.c_int
+_lib.eodabe_set_predictor.argtypes = [_vp, _vp, ctypes.c_double]
+_lib.eodabe_set_predictor.restype = ctypes.c_int
+_lib.eodabe_last_prediction.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+_lib.eodabe_last_prediction.restype = ctypes.c_int
 _lib.eodabe_profile.argtypes = [_vp, ctypes.c_int]
 _lib.eodabe_profile.restype = ctypes.c_int
 _lib.eodabe_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -142,6 +161,25 @@ class Context:
         if st != EODABE_OK:
             raise EodAbeError(st, "eodabe_create_host" if host_only else "eodabe_create")
         self.h = h
+
+    def set_predictor(self, params: torch.Tensor | None, margin: float = 0.1):
+        """eodabe_set_predictor: attach (or detach with None) the learned warm
+        start; the tensor is kept alive by the context.  Size workspaces
+        afterwards (they depend on it)."""
+        if params is not None:
+            if params.dtype != torch.float32 or not params.is_cuda or not params.is_contiguous() \
+                    or params.numel() != _lib.eodabe_mlp_param_count():
+                raise EodAbeError(EODABE_EINVAL, "set_predictor: contiguous FP32 device parameters expected")
+        self._check(_lib.eodabe_set_predictor(self.h, params.data_ptr() if params is not None else None,
+                                              float(margin)), "eodabe_set_predictor")
+        self._pred = params
+
+    def last_prediction(self):
+        """eodabe_last_prediction -> (d0, log(1+rank) head, 0.9-quantile head, used)."""
+        d0, y0, y1, used = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        self._check(_lib.eodabe_last_prediction(self.h, ctypes.byref(d0), ctypes.byref(y0), ctypes.byref(y1),
+                                                ctypes.byref(used)), "eodabe_last_prediction")
+        return int(d0.value), float(y0.value), float(y1.value), int(used.value)
 
     def close(self):
         if getattr(self, "h", None):

@@ -17,6 +17,7 @@
 #include "../../include/eodabe.h"
 #include "eodabe_kernels.hpp"
 #include "eodabe_tiles.hpp"
+#include "eodabe_mlp.hpp"
 
 using namespace eodabe;
 
@@ -49,6 +50,10 @@ struct eodabe_ctx {
   struct { const void* ws; const void* pool; int ntiles, grid; double tol; uint64_t seed; } tile_key{};
   int tile_b[4] = {0, 0, 0, 0};   // block width per tile-size bucket (0: opts.block)
   int tile_graphs = 1;            // capture the launch in a hipGraph
+  // learned warm start (eodabe_set_predictor): device parameters of the MLP
+  const float* pred_params = nullptr;
+  double pred_margin = 0.1;
+  struct { int64_t d0 = 0; double y0 = 0, y1 = 0; int used = 0; } pred_last;
 };
 
 namespace {
@@ -184,7 +189,11 @@ struct Geo {
   size_t elem;
   int lp;               // low-precision sketch: 0 none, 1 FP16, 2 BF16
   int64_t ld_lp;        // leading dimension of the low-precision copy of A (multiple of 8)
+  bool wide;            // learned warm start: buffers of the wide sketch
 };
+
+// Widest sketch of the learned warm start in one pass over A (columns).
+constexpr int WIDE_COLS = 128;
 
 struct WS {
   State* st;
@@ -222,6 +231,11 @@ struct WS {
   double* dg;           // r_cap
   void* tbig;           // ldy x r_cap scratch for large-f triangular solves
   double* sq128;        // 7 x 128 x 128: closing QR scratch for ranks 65..128
+  // learned warm start (g.wide): wide Omega, sketch partials and sketch, prediction
+  void* omega_w;        // WIDE_COLS x ldk
+  void* ypart_w;        // s_sketch x ldy x WIDE_COLS
+  void* y_w;            // ldy x WIDE_COLS
+  MlpPred* pred;
   size_t total;
 };
 
@@ -268,6 +282,12 @@ WS carve(void* base, const Geo& g) {
   w.dg = c.take<double>(std::max<int64_t>(rc, g.bn) + 64);
   w.tbig = c.take<char>(std::max(g.ldy, g.ldk) * rc * std::max<size_t>(e, 8));
   w.sq128 = rb > 64 ? c.take<double>(7 * 128 * 128) : nullptr;
+  if (g.wide) {
+    w.omega_w = c.take<char>((int64_t)WIDE_COLS * g.ldk * e);
+    w.ypart_w = c.take<char>((int64_t)g.s_sketch * g.ldy * WIDE_COLS * e);
+    w.y_w = c.take<char>(g.ldy * WIDE_COLS * e);
+    w.pred = c.take<MlpPred>(1);
+  }
   w.total = c.off + 256;
   return w;
 }
@@ -289,6 +309,7 @@ bool plan(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t lda, const void* 
   g.lda_eff = g.packed ? rup(std::max<int64_t>(g.nn, 1), 4) : lda;
   g.lp = (dt == EODABE_F32) ? ctx->o.sketch_dtype : 0;
   g.ld_lp = rup(std::max<int64_t>(g.nn, 1), 8);
+  g.wide = ctx->pred_params != nullptr && g.lp == 0 && g.nn > 64 && ctx->o.block <= 64;
   g.b = ctx->o.block;
   g.bn = (int)rup(g.b, 16);
   g.nblk = cdiv(g.nn, g.b);
@@ -693,14 +714,55 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   int64_t j = 0;
   bool finished = (g.nn == 0);
   int64_t sketch_wgs = cdiv(g.mm, 128);
+  // Learned warm start: the blocks covering Omega's first 64 columns run as
+  // a probe; if they do not stop, the predictor reads their stopping-test
+  // values (device) and returns a width d0; the blocks up to column d0 then
+  // take their sketches from one wide pass over A (WIDE_COLS columns at a
+  // time) and are orthogonalised as usual; past d0 the plain loop resumes.
+  const bool learned = g.wide && ctx->pred_params != nullptr;
+  ctx->pred_last = {};
+  bool probed = !learned;
+  int64_t pred_end = 0;                 // warm-start end column (exclusive)
+  int64_t pre_j0 = 0, pre_j1 = 0;       // blocks whose sketch sits in y_w
   while (!finished) {
-    const int64_t jend = std::min<int64_t>(g.nblk, j + per_sync);
+    int64_t jend = std::min<int64_t>(g.nblk, j + per_sync);
+    if (!probed) {
+      jend = std::min<int64_t>(g.nblk, cdiv(64, g.b));
+    } else if (learned && j * g.b < pred_end) {
+      // one wide sketch for the next blocks up to the predicted width
+      const int64_t kw = std::min<int64_t>({(int64_t)(WIDE_COLS / g.b), cdiv(pred_end - j * g.b, g.b), g.nblk - j});
+      const int64_t col0 = j * g.b;
+      const int fw = (int)std::min<int64_t>(kw * g.b, g.nn - col0);
+      const int bnw = (int)rup(fw, 16);
+      T* omw = (T*)w.omega_w;
+      dim3 grid((unsigned)cdiv(cdiv(g.ldk, 4), 256), bnw);
+      hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, fw, g.ldk, omw, stopb, (int)j);
+      if (fw < bnw)
+        hipLaunchKernelGGL(k_zero<T>, dim3(64), dim3(256), 0, st, omw + (int64_t)fw * g.ldk,
+                           (int64_t)(bnw - fw) * g.ldk);
+      LAUNCHCHK();
+      const int64_t ystride = g.ldy * bnw;
+      const int pid = prof_begin(ctx, st);
+      prof_attach(ctx, ops, pid);
+      TRY(ops.sketch(Ae, g.lda_eff, omw, g.ldk, g.mm, bnw, g.nn, g.s_sketch, (T*)w.ypart_w, g.ldy, ystride,
+                     nullptr, stopb, (int)j));
+      prof_attach(ctx, ops, -1);
+      prof_end(ctx, st, pid, EODABE_PROF_SKETCH, (int)j,
+               (double)g.elem * ((double)g.mm * g.nn + (double)g.nn * fw + (double)g.mm * fw));
+      TRY(ops.reduce((const T*)w.ypart_w, eff_splits(g.nn, g.s_sketch), ystride, ystride, (T*)w.y_w, stopb,
+                     (int)j));
+      pre_j0 = j;
+      pre_j1 = j + kw;
+      jend = pre_j1;
+    }
     for (; j < jend; ++j) {
       const int blk = (int)j;
       const int64_t col0 = j * g.b;
       const int f = (int)std::min<int64_t>(g.b, g.nn - col0);
+      const bool pre = j >= pre_j0 && j < pre_j1;
+      T* y = pre ? (T*)w.y_w + (j - pre_j0) * (int64_t)g.b * g.ldy : (T*)w.y;
       // a1: Omega_j (bn rows; rows f..bn-1 zero)
-      {
+      if (!pre) {
         dim3 grid((unsigned)cdiv(cdiv(g.ldk, 4), 256), g.bn);
         hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.ldk, omega,
                            stopb, blk);
@@ -711,8 +773,10 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       }
       // a2: sketch Y = A Omega_j (K-split partials; block 0 also ||A||_F)
       const int64_t ystride = g.ldy * g.bn;
+      const int nsp = eff_splits(g.nn, g.s_sketch);
       // low-precision form: block 1 also writes the FP16/BF16 copy of A
       // (scale from block 0's max |A|), later blocks sketch that copy
+      if (!pre) {
       const int pid = prof_begin(ctx, st);
       prof_attach(ctx, ops, pid);
       double abytes = (double)g.elem * g.mm * g.nn;
@@ -731,8 +795,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       prof_attach(ctx, ops, -1);
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
                abytes + (double)g.elem * ((double)g.nn * f + (double)g.mm * f));
-      const int nsp = eff_splits(g.nn, g.s_sketch);
       if (j > 0) TRY(ops.reduce((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+      }
       // a3 + a4: two rounds of [project against the basis so far (width
       // wlog[j] <= j*b), FP64-Gram Cholesky, triangular solve]: block
       // Gram-Schmidt with re-orthogonalisation interleaved with CholeskyQR2
@@ -816,6 +880,24 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       prof_collect(ctx, hs.stop_block != 0x7fffffff ? hs.stop_block : (int)g.nblk, ran, hs.rank);
     if (hs.nonfinite) return EODABE_ENONFINITE;
     if (finished) *spec_ran = ran;
+    if (!probed) {
+      probed = true;
+      if (!finished) {
+        // predictor on the device from the probe's stopping-test values
+        hipLaunchKernelGGL(k_mlp_infer1, dim3(1), dim3(256), 0, st, ctx->pred_params, w.diag_log, g.mm, g.nn, tol,
+                           g.b, ctx->pred_margin, w.pred);
+        LAUNCHCHK();
+        MlpPred hp{};
+        HIPCHK(hipMemcpyAsync(&hp, w.pred, sizeof(MlpPred), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ctx->pred_last.d0 = hp.d0;
+        ctx->pred_last.y0 = hp.y0;
+        ctx->pred_last.y1 = hp.y1;
+        ctx->pred_last.used = 1;
+        pred_end = std::min<int64_t>(hp.d0, g.nn);
+      }
+      continue;
+    }
     if (ctx->o.blocks_per_sync <= 0) per_sync = std::min(per_sync * 2, 4);
   }
   int64_t r = 0;
@@ -824,6 +906,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
     nb = (int)std::min<int64_t>(ctx->host_state->stop_block, g.nblk - 1) + 1;
     r = ctx->host_state->rank;           // set by the stop test of the last block
     *norm_a = std::sqrt(ctx->host_state->normsq);
+    // the warm start did not contain the stop: the plain loop went on past d0
+    if (ctx->pred_last.used && r >= pred_end && pred_end < g.nn) ctx->pred_last.used = 2;
   } else {
     *norm_a = 0.0;
   }
@@ -1272,6 +1356,165 @@ int eodabe_tune_batched(eodabe_ctx* ctx, int ntiles, const void* const* A, const
   return EODABE_OK;
 }
 
+
+// ---- learned predictor: training and inference kernels --------------------
+}  // extern "C"
+namespace {
+struct MlpWS {
+  float *z1, *h1, *z2, *h2, *z3, *h3, *y, *dy, *g1, *g2;
+  double* loss;
+  size_t total;
+};
+MlpWS mlp_carve(void* base, int B) {
+  Carver c(base);
+  MlpWS w{};
+  const int64_t bh = (int64_t)std::max(B, 1) * MLP_H;
+  w.z1 = c.take<float>(bh);
+  w.h1 = c.take<float>(bh);
+  w.z2 = c.take<float>(bh);
+  w.h2 = c.take<float>(bh);
+  w.z3 = c.take<float>(bh);
+  w.h3 = c.take<float>(bh);
+  w.y = c.take<float>(2 * (int64_t)std::max(B, 1));
+  w.dy = c.take<float>(2 * (int64_t)std::max(B, 1));
+  w.g1 = c.take<float>(bh);
+  w.g2 = c.take<float>(bh);
+  w.loss = c.take<double>(1);
+  w.total = c.off + 256;
+  return w;
+}
+template <bool TA, bool TB>
+int mlp_gemm(eodabe_ctx* ctx, hipStream_t st, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
+             int M, int N, int K, const float* bias) {
+  dim3 grid((unsigned)cdiv(N, 64), (unsigned)cdiv(M, 64));
+  hipLaunchKernelGGL((k_mlp_gemm<TA, TB>), grid, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, bias);
+  LAUNCHCHK();
+  return 0;
+}
+int mlp_act(eodabe_ctx* ctx, hipStream_t st, const float* Z, float* H, int64_t cnt) {
+  hipLaunchKernelGGL(k_gelu_fwd, dim3((unsigned)std::min<int64_t>(cdiv(cnt, 256), 2048)), dim3(256), 0, st, Z, H,
+                     cnt);
+  LAUNCHCHK();
+  return 0;
+}
+int mlp_act_grad(eodabe_ctx* ctx, hipStream_t st, float* G, const float* Z, int64_t cnt) {
+  hipLaunchKernelGGL(k_gelu_bwd, dim3((unsigned)std::min<int64_t>(cdiv(cnt, 256), 2048)), dim3(256), 0, st, G, Z, G,
+                     cnt);
+  LAUNCHCHK();
+  return 0;
+}
+int mlp_forward_impl(eodabe_ctx* ctx, hipStream_t st, const float* P, const float* X, int B, const MlpWS& w) {
+  TRY((mlp_gemm<false, true>(ctx, st, X, MLP_IN, P + MLP_W1, MLP_IN, w.z1, MLP_H, B, MLP_H, MLP_IN, P + MLP_B1)));
+  TRY(mlp_act(ctx, st, w.z1, w.h1, (int64_t)B * MLP_H));
+  TRY((mlp_gemm<false, true>(ctx, st, w.h1, MLP_H, P + MLP_W2, MLP_H, w.z2, MLP_H, B, MLP_H, MLP_H, P + MLP_B2)));
+  TRY(mlp_act(ctx, st, w.z2, w.h2, (int64_t)B * MLP_H));
+  TRY((mlp_gemm<false, true>(ctx, st, w.h2, MLP_H, P + MLP_W3, MLP_H, w.z3, MLP_H, B, MLP_H, MLP_H, P + MLP_B3)));
+  TRY(mlp_act(ctx, st, w.z3, w.h3, (int64_t)B * MLP_H));
+  TRY((mlp_gemm<false, true>(ctx, st, w.h3, MLP_H, P + MLP_W4, MLP_H, w.y, MLP_OUT, B, MLP_OUT, MLP_H,
+                             P + MLP_B4)));
+  return 0;
+}
+// dW = dZ^T H_prev, db = column sums of dZ, dH_prev = dZ W (then times GELU'(Z_prev))
+int mlp_layer_grad(eodabe_ctx* ctx, hipStream_t st, const float* dZ, int nout, const float* Hprev, int nin, int B,
+                   const float* W, float* dW, float* db, float* dHprev) {
+  TRY((mlp_gemm<true, false>(ctx, st, dZ, nout, Hprev, nin, dW, nin, nout, nin, B, nullptr)));
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)cdiv(nout, 256)), dim3(256), 0, st, dZ, B, nout, db);
+  LAUNCHCHK();
+  if (dHprev) TRY((mlp_gemm<false, false>(ctx, st, dZ, nout, W, nin, dHprev, nin, B, nin, nout, nullptr)));
+  return 0;
+}
+int mlp_backward_impl(eodabe_ctx* ctx, hipStream_t st, const float* P, const float* X, const float* T, int B,
+                      float* G, const MlpWS& w) {
+  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, st, w.y, T, B, w.dy, w.loss);
+  LAUNCHCHK();
+  const int64_t bh = (int64_t)B * MLP_H;
+  TRY(mlp_layer_grad(ctx, st, w.dy, MLP_OUT, w.h3, MLP_H, B, P + MLP_W4, G + MLP_W4, G + MLP_B4, w.g1));
+  TRY(mlp_act_grad(ctx, st, w.g1, w.z3, bh));
+  TRY(mlp_layer_grad(ctx, st, w.g1, MLP_H, w.h2, MLP_H, B, P + MLP_W3, G + MLP_W3, G + MLP_B3, w.g2));
+  TRY(mlp_act_grad(ctx, st, w.g2, w.z2, bh));
+  TRY(mlp_layer_grad(ctx, st, w.g2, MLP_H, w.h1, MLP_H, B, P + MLP_W2, G + MLP_W2, G + MLP_B2, w.g1));
+  TRY(mlp_act_grad(ctx, st, w.g1, w.z1, bh));
+  TRY(mlp_layer_grad(ctx, st, w.g1, MLP_H, X, MLP_IN, B, P + MLP_W1, G + MLP_W1, G + MLP_B1, nullptr));
+  return 0;
+}
+}  // namespace
+extern "C" {
+
+int64_t eodabe_mlp_param_count(void) { return MLP_NPARAM; }
+
+size_t eodabe_mlp_workspace_size(int batch) { return batch < 1 ? 0 : mlp_carve(nullptr, batch).total; }
+
+int eodabe_mlp_forward(eodabe_ctx* ctx, const float* params, const float* X, int batch, float* Y, void* ws,
+                       size_t ws_bytes) {
+  TRY(check_ctx(ctx));
+  if (batch < 1 || !params || !X || !Y) return EODABE_EINVAL;
+  const MlpWS w = mlp_carve(ws, batch);
+  if (!ws || ws_bytes < w.total) return EODABE_EWORKSPACE;
+  TRY(check_dev(ctx));
+  hipStream_t st = ctx->stream;
+  TRY(mlp_forward_impl(ctx, st, params, X, batch, w));
+  HIPCHK(hipMemcpyAsync(Y, w.y, sizeof(float) * 2 * (size_t)batch, hipMemcpyDeviceToDevice, st));
+  return 0;
+}
+
+int eodabe_mlp_grad(eodabe_ctx* ctx, const float* params, const float* X, const float* T, int batch, float* grads,
+                    void* ws, size_t ws_bytes, double* loss) {
+  TRY(check_ctx(ctx));
+  if (batch < 1 || !params || !X || !T || !grads) return EODABE_EINVAL;
+  const MlpWS w = mlp_carve(ws, batch);
+  if (!ws || ws_bytes < w.total) return EODABE_EWORKSPACE;
+  TRY(check_dev(ctx));
+  hipStream_t st = ctx->stream;
+  TRY(mlp_forward_impl(ctx, st, params, X, batch, w));
+  TRY(mlp_backward_impl(ctx, st, params, X, T, batch, grads, w));
+  if (loss) {
+    HIPCHK(hipMemcpyAsync(loss, w.loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return 0;
+}
+
+int eodabe_mlp_adam(eodabe_ctx* ctx, float* params, const float* grads, float* m, float* v, float lr, int step) {
+  TRY(check_ctx(ctx));
+  if (!params || !grads || !m || !v || step < 1 || !(lr > 0.0f)) return EODABE_EINVAL;
+  TRY(check_dev(ctx));
+  const double b1 = 0.9, b2 = 0.999;
+  AdamCoef a;
+  a.lr = lr;
+  a.b1 = (float)b1;
+  a.omb1 = (float)(1.0 - b1);
+  a.b2 = (float)b2;
+  a.omb2 = (float)(1.0 - b2);
+  a.c1 = (float)(1.0 - std::pow(b1, (double)step));
+  a.c2 = (float)(1.0 - std::pow(b2, (double)step));
+  a.eps = 1e-8f;
+  hipLaunchKernelGGL(k_adam, dim3(256), dim3(256), 0, ctx->stream, params, grads, m, v, (int64_t)MLP_NPARAM, a);
+  LAUNCHCHK();
+  return 0;
+}
+
+int eodabe_mlp_features(const double* diag, int64_t m, int64_t n, double tol, float* out) {
+  if (!diag || !out || m < 1 || n < 1 || !(tol > 0.0)) return EODABE_EINVAL;
+  for (int c = 0; c < MLP_IN; ++c) out[c] = mlp_feature(diag, c, m, n, tol);
+  return 0;
+}
+
+int eodabe_set_predictor(eodabe_ctx* ctx, const float* params, double margin) {
+  TRY(check_ctx(ctx));
+  if (!(margin >= 0.0) || margin > 10.0) return EODABE_EINVAL;
+  ctx->pred_params = params;
+  ctx->pred_margin = margin;
+  return 0;
+}
+
+int eodabe_last_prediction(const eodabe_ctx* ctx, int64_t* d0, double* log_rank, double* log_rank_q, int* used) {
+  TRY(check_ctx(ctx));
+  if (d0) *d0 = ctx->pred_last.d0;
+  if (log_rank) *log_rank = ctx->pred_last.y0;
+  if (log_rank_q) *log_rank_q = ctx->pred_last.y1;
+  if (used) *used = ctx->pred_last.used;
+  return 0;
+}
 
 void eodabe_default_opts(eodabe_opts* o) {
   if (!o) return;

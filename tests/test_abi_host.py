@@ -127,3 +127,38 @@ def test_batched_argument_errors_without_device(E):
     assert call(**ok, ctx=c64) == E.EODABE_EINVAL                # FP32 tiles only
     wsz = E._lib.eodabe_batched_workspace_size
     assert wsz(c.h, 1000) > wsz(c.h, 1) > 0 and wsz(None, 1) == 0 and wsz(c.h, -1) == 0
+
+
+def test_predictor_features_match_oracle(E):
+    """eodabe_mlp_features (host) against the oracle's feature map."""
+    import numpy as np
+    from oracle import predictor_oracle as PO
+    from paper_2506_22713_amd import predictor as PR
+    rng = np.random.default_rng(3)
+    cases = [10.0 ** (-0.1 * np.arange(64)), np.exp(-rng.random(64).cumsum()), 10.0 ** (-1.0 * np.arange(64)),
+             np.concatenate([np.ones(10), np.zeros(54)])]
+    for d, (m, n, tol) in zip(cases, [(4096, 4096, 1e-3), (777, 300, 1e-8), (65, 65, 0.5), (1000, 999, 1e-4)]):
+        got = PR.features(d, m, n, tol)
+        ref = PO.features(d, m, n, tol).astype(np.float32)
+        assert np.array_equal(got, ref), (got - ref)
+
+
+def test_predictor_checkpoint_roundtrip(tmp_path):
+    """Checkpoint format: JSON header + params, m, v; resume keeps the step."""
+    import numpy as np
+    import torch
+    from paper_2506_22713_amd import predictor as PR
+    pr = PR.Predictor(seed=5, device="cpu")
+    pr.m.uniform_(-1, 1)
+    pr.v.uniform_(0, 1)
+    pr.step = 17
+    path = str(tmp_path / "p.ckpt")
+    pr.save(path, meta={"note": "roundtrip"})
+    q = PR.Predictor.load(path, device="cpu")
+    assert q.step == 17 and q.meta["note"] == "roundtrip"
+    for a, b in ((pr.params, q.params), (pr.m, q.m), (pr.v, q.v)):
+        assert torch.equal(a, b)
+    with open(path, "rb") as fh:
+        head = fh.readline()
+    assert b'"format": "eodabe-mlp-1"' in head
+    assert PR.init_params(5).size == PR.NPARAM == 149506

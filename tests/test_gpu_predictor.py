@@ -1,0 +1,165 @@
+"""GPU parity of the learned warm start: the MLP kernels against the FP64
+oracle (forward, gradient, Adam), the in-loop inference against the
+oracle's features and network, and warm-started factorizations against the
+plain loop (same rank, same factors up to rounding, fewer sketch passes)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2506_22713_amd as E
+from paper_2506_22713_amd import predictor as PR
+from oracle import predictor_oracle as PO
+from oracle import eodabe_oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _rand_params(seed, scale=1.0):
+    p = PR.init_params(seed).astype(np.float64) * scale
+    rng = np.random.default_rng(seed + 1)
+    off = 0
+    for name, shp in PO.SHAPES:                 # non-zero biases too
+        cnt = int(np.prod(shp))
+        if name.startswith("b"):
+            p[off:off + cnt] = rng.standard_normal(cnt) * 0.1
+        off += cnt
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("B", [1, 37, 300])
+def test_mlp_forward_matches_oracle(B):
+    say("mlp forward", B)
+    ctx = E.Context()
+    p = _rand_params(11)
+    X = np.random.default_rng(B).uniform(-1, 1, size=(B, 67)).astype(np.float32)
+    pr = PR.Predictor(p)
+    Y = pr.forward(ctx, torch.from_numpy(X).cuda()).cpu().numpy()
+    Yr, _ = PO.forward(p.astype(np.float64), X.astype(np.float64))
+    assert np.allclose(Y, Yr, rtol=1e-5, atol=1e-5), np.abs(Y - Yr).max()
+
+
+@pytest.mark.parametrize("B", [5, 130])
+def test_mlp_gradient_matches_oracle(B):
+    say("mlp gradient", B)
+    ctx = E.Context()
+    p = _rand_params(21)
+    rng = np.random.default_rng(B + 100)
+    X = rng.uniform(-1, 1, size=(B, 67)).astype(np.float32)
+    y0, _ = PO.forward(p.astype(np.float64), X.astype(np.float64))
+    # targets away from the quantile head's kink
+    T = (y0[:, 1] + np.where(rng.random(B) < 0.5, 0.5, -0.5)).astype(np.float32)
+    pr = PR.Predictor(p)
+    loss = pr.grad(ctx, torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    g = pr.grads.cpu().numpy().astype(np.float64)
+    Lr, gr = PO.grad(p.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - Lr) <= 1e-5 * max(1.0, abs(Lr))
+    off = 0
+    for name, shp in PO.SHAPES:
+        cnt = int(np.prod(shp))
+        a, b = g[off:off + cnt], gr[off:off + cnt]
+        assert np.abs(a - b).max() <= 1e-4 * max(np.abs(b).max(), 1e-3), (name, np.abs(a - b).max())
+        off += cnt
+
+
+def test_mlp_adam_matches_oracle():
+    say("mlp adam")
+    ctx = E.Context()
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(PR.NPARAM).astype(np.float32)
+    g = rng.standard_normal(PR.NPARAM).astype(np.float32)
+    m = (rng.standard_normal(PR.NPARAM) * 0.1).astype(np.float32)
+    v = rng.random(PR.NPARAM).astype(np.float32) * 0.01
+    pr = PR.Predictor(p)
+    pr.grads.copy_(torch.from_numpy(g))
+    pr.m.copy_(torch.from_numpy(m))
+    pr.v.copy_(torch.from_numpy(v))
+    pr.step = 6
+    pr.adam(ctx, 1e-3)
+    pr_, m_, v_ = PO.adam_step(p.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                               v.astype(np.float64), 7, 1e-3)
+    assert np.allclose(pr.params.cpu().numpy(), pr_, rtol=1e-6, atol=1e-6)
+    assert np.allclose(pr.m.cpu().numpy(), m_, rtol=1e-6, atol=1e-7)
+    assert np.allclose(pr.v.cpu().numpy(), v_, rtol=1e-6, atol=1e-9)
+
+
+def test_training_reduces_loss():
+    say("mlp training")
+    ctx = E.Context()
+    rng = np.random.default_rng(9)
+    X = rng.uniform(-1, 0, size=(512, 67)).astype(np.float32)
+    T = (3.0 + 2.0 * X[:, :8].mean(1) - X[:, 64]).astype(np.float32)   # a smooth target
+    pr = PR.Predictor(seed=1)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    first = pr.grad(ctx, Xd, Td)
+    for _ in range(200):
+        last = pr.train_step(ctx, Xd, Td, 1e-3)
+    assert last < 0.1 * first, (first, last)
+
+
+def _probe_diag(A, tol, b, seed, dtype):
+    """Stopping-test values of the plain loop (eodabe_basis) for the first 64 columns."""
+    Q, d, info = E.basis(torch.from_numpy(np.ascontiguousarray(A)).to("cuda", dtype), tol, block=b, seed=seed,
+                         dtype=dtype)
+    return d, info
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_warm_start_inference_matches_oracle(dtype):
+    say("warm-start inference", dtype)
+    A = W.lowrank_haar(31, m=700, n=500, r=160, noise_std=1e-9)
+    tol, b = 1e-6 if dtype == torch.float64 else 1e-4, 32
+    d, info = _probe_diag(A, tol, b, 2, dtype)
+    p = _rand_params(33, scale=0.5)
+    pr = PR.Predictor(p)
+    ctx = E.Context(block=b, seed=2, dtype=dtype)
+    pr.attach(ctx, margin=0.2)
+    f = E.factor(torch.from_numpy(A).to("cuda", dtype), tol, ctx=ctx)
+    d0, y0, y1, used = ctx.last_prediction()
+    assert used in (1, 2)
+    x = PO.features(d[:64], 700, 500, tol)
+    yr, _ = PO.forward(p.astype(np.float64), x[None, :])
+    assert abs(y0 - yr[0, 0]) <= 1e-4 * max(1, abs(yr[0, 0])) and abs(y1 - yr[0, 1]) <= 1e-4 * max(1, abs(yr[0, 1]))
+    assert d0 == PO.predicted_width(y1, b, 0.2)
+
+
+@pytest.mark.parametrize("r,lift", [(100, 0.0), (180, 0.0), (300, 0.0), (150, 2.0), (150, -3.0)])
+def test_warm_start_same_rank_fewer_passes(r, lift):
+    """A predictor whose quantile head is a constant (zero weights, bias b4)
+    sets d0 directly: exact, too small (fallback) or too large; the rank and
+    factors are the plain loop's, and the sketch passes drop when d0 covers
+    the rank."""
+    say("warm start", r, lift)
+    A = W.lowrank_haar(40 + r, m=1200, n=700, r=r, noise_std=1e-10)
+    tol, b = 1e-7, 32
+    plain = E.factor(torch.from_numpy(A).cuda().double(), tol, ctx=E.Context(block=b, seed=4, dtype=torch.float64))
+    p = np.zeros(PR.NPARAM, dtype=np.float32)
+    target = max(plain.rank + lift * 32, 1)
+    p[-1] = math.log(1.0 + target)              # head 1 bias: rhat = target
+    p[-2] = math.log(1.0 + target)
+    pr = PR.Predictor(p)
+    ctx = E.Context(block=b, seed=4, dtype=torch.float64)
+    pr.attach(ctx, margin=0.0)
+    ctx.profile(True)
+    f = E.factor(torch.from_numpy(A).cuda().double(), tol, ctx=ctx)
+    ms, launches, _ = ctx.profile_read(E.PROF_SKETCH)
+    ctx.profile(False)
+    d0, y0, y1, used = ctx.last_prediction()
+    assert f.rank == plain.rank, (f.rank, plain.rank)
+    assert used == (2 if d0 <= plain.rank else 1), (d0, plain.rank, used)
+    A64 = A
+    e_plain = np.linalg.norm(A64 - plain.U.cpu().numpy() @ plain.D.cpu().numpy() @ plain.Vt.cpu().numpy())
+    e_warm = np.linalg.norm(A64 - f.U.cpu().numpy() @ f.D.cpu().numpy() @ f.Vt.cpu().numpy())
+    assert abs(e_warm - e_plain) <= 1e-10 * np.linalg.norm(A64)
+    js = plain.rank // b                         # block whose stopping test fires
+    if used == 1:
+        # probe (64 columns = 2 blocks), then wide passes of 128 columns up to
+        # the one holding block js, against js + 1 sketch passes of the plain loop
+        assert launches == 2 + (js - 2) // (128 // b) + 1, (launches, d0, js)
+        assert launches < js + 1

@@ -9,11 +9,12 @@ library.
 
 What it defines, written out plainly in NumPy FP64:
 
-* features(diag, m, n, tol): 67 inputs from the first 64 values
+* features(diag, m, n, eps): 67 inputs from the first 64 values
   d_c = |T(c,c)| of the stopping test of Alg. 1 (the diagonal of the R factor
   of A Omega[:, :64] computed by block Gram-Schmidt), normalised by d_0 on a
   log10 scale clamped at -16 and divided by 16, then log2 m / 16,
-  log2 n / 16 and log10 tol / 16.
+  log2 n / 16 and log10(eps / d_0) / 16 with eps = tol ||A||_F, the
+  threshold of the stopping test on the same scale (clamped like the d_c).
 * the network 67 -> 256 -> 256 -> 256 -> 2 with the erf form of GELU,
   GELU(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2, after each hidden layer;
   flat parameter layout W1 (256 x 67, row-major), b1, W2 (256 x 256), b2,
@@ -53,8 +54,9 @@ def unpack(p: np.ndarray) -> dict:
     return out
 
 
-def features(diag: np.ndarray, m: int, n: int, tol: float) -> np.ndarray:
-    """67 network inputs from the stopping-test values d_0..d_63."""
+def features(diag: np.ndarray, m: int, n: int, eps: float) -> np.ndarray:
+    """67 network inputs from the stopping-test values d_0..d_63 and the
+    threshold eps = tol ||A||_F."""
     d = np.asarray(diag, dtype=np.float64)[:64]
     x = np.empty(NIN)
     for c in range(64):
@@ -64,7 +66,10 @@ def features(diag: np.ndarray, m: int, n: int, tol: float) -> np.ndarray:
             x[c] = -1.0
     x[64] = math.log2(m) / 16.0
     x[65] = math.log2(n) / 16.0
-    x[66] = math.log10(tol) / 16.0
+    if d[0] > 0 and eps > 0:
+        x[66] = min(max(math.log10(eps / d[0]), -16.0), 16.0) / 16.0
+    else:
+        x[66] = -1.0
     return x
 
 

@@ -104,12 +104,12 @@ def test_adam_first_step_closed_form():
 
 def test_features_geometric():
     d = 10.0 ** (-0.25 * np.arange(64))           # log10(d_c / d_0) = -c/4
-    x = P.features(d * 7.0, 4096, 1024, 1e-3)
+    x = P.features(d * 7.0, 4096, 1024, 7e-3)     # eps / d_0 = 1e-3
     assert np.allclose(x[:64], np.maximum(-0.25 * np.arange(64), -16.0) / 16.0, atol=1e-14)
     assert x[64] == 12 / 16 and x[65] == 10 / 16 and abs(x[66] + 3 / 16) < 1e-15
     d2 = 10.0 ** (-1.0 * np.arange(64))           # clamped after 16 decades
-    x2 = P.features(d2, 512, 512, 1e-8)
-    assert x2[20] == -1.0 and abs(x2[10] + 10 / 16) < 1e-14
+    x2 = P.features(d2, 512, 512, 1e-30)
+    assert x2[20] == -1.0 and abs(x2[10] + 10 / 16) < 1e-14 and x2[66] == -1.0
     assert P.features(np.zeros(64), 8, 8, 0.5)[0] == -1.0
 
 

@@ -215,8 +215,9 @@ int eodabe_tune_batched(eodabe_ctx* ctx, int ntiles, const void* const* A, const
  * parameters, flat: W1 256x67 row-major, b1, W2 256x256, b2, W3, b3,
  * W4 2x256, b4) predicts log(1 + rank) (head 0) and its 0.9-quantile
  * (head 1) from the first 64 values d_c = |T(c,c)| of the stopping test of
- * Alg. 1 (log10(d_c / d_0) clamped at -16, over 16) and log2 m / 16,
- * log2 n / 16, log10 tol / 16.  The warm start sizes the basis loop from
+ * Alg. 1 (log10(d_c / d_0) clamped at -16, over 16), log2 m / 16,
+ * log2 n / 16 and log10(eps / d_0) / 16 (clamped to [-1, 1]), eps =
+ * tol ||A||_F the threshold of the test.  The warm start sizes the basis loop from
  * head 1: d0 = b ceil((rhat (1 + margin) + 1) / b), rhat = exp(y1) - 1.
  * The predictor is not part of the paper; the loop of Alg. 1 stays the
  * judge: blocks past d0 run as usual if the test has not fired, and the
@@ -244,8 +245,9 @@ int eodabe_mlp_adam(eodabe_ctx* ctx, float* params, const float* grads, float* m
                     int step);
 /* The 67 network inputs (host out) from the stopping-test values d_0..d_63
  * (host, as returned in the diag output of eodabe_basis) of an m x n matrix
- * (m >= n) at tolerance tol; the same function the device inference uses. */
-int eodabe_mlp_features(const double* diag, int64_t m, int64_t n, double tol, float* out67);
+ * (m >= n) with threshold eps = tol ||A||_F (eodabe_info.eps); the same
+ * function the device inference uses. */
+int eodabe_mlp_features(const double* diag, int64_t m, int64_t n, double eps, float* out67);
 /* Attach (params non-NULL) or detach (NULL) the predictor.  The parameters
  * must stay valid while the context factors matrices.  Workspace sizes
  * depend on it: size workspaces after attaching.  margin in [0, 10].

@@ -483,16 +483,6 @@ struct Ops {
     return 0;
   }
 
-  // Z = X R^{-1} (R f x f FP64, f > 64 in practice), out of place.
-  int trsm(const T* X, int64_t ldx, T* Zo, int64_t ldz, int64_t m, int f, const double* R,
-           int ncols_out) {
-    if (m <= 0 || f <= 0) return 0;
-    hipLaunchKernelGGL((k_trsm_rows_big<T, T>), dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, X, ldx,
-                       Zo, ldz, m, f, R, ncols_out);
-    LAUNCHCHK();
-    return 0;
-  }
-
   // Z = X W for blocks of f <= 128 columns (one job, or two in one launch).
   int apply(const ApplyJob& j0, const ApplyJob* j1, int f, const int32_t* stopb = nullptr,
             int blk = 0, Gate gate = Gate{}) {
@@ -553,10 +543,11 @@ CholArgs chol_args(const WS& w, double* R, int32_t* dead, int first, int fresh, 
 // FP64, element (i,j) at j*f + i, Z rounded to T and written over X), then
 // the Cholesky with the floor/kill rules and the epilogues in ca (R,
 // R^{-1}, stop test, ||A||_F finish).  f <= 64: one launch (k_gram_rows; its last workgroup runs the
-// Cholesky with inverse).  64 < f <= 128 with ca.Rinv: generic GEMM, then the
+// Cholesky with inverse).  64 < f <= 128: generic GEMM, then the 2 x 2-
 // blocked Cholesky with inverse on one workgroup (k_chol128), separate stop
-// test.  Wider blocks: generic GEMM, global Cholesky, separate stop test (no
-// W, no inverse).
+// test.  Wider: generic GEMM, panel-blocked Cholesky with inverse on one
+// workgroup (k_chol_big, the Gram overwritten).  Above 64 columns ca.Rinv is
+// required and there is no fused W.
 template <typename T>
 int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, int64_t rows, int f,
               double* parts, const CholArgs& ca, const int32_t* stopb = nullptr, int blk = 0,
@@ -584,21 +575,19 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
     LAUNCHCHK();
     return 0;
   }
-  if (W || ca.gate.st || ca.f_dev) return EODABE_EINVAL;   // fused / gated forms only for f <= 64
-  if (ca.Rinv && f > 128) return EODABE_EINVAL;
+  if (W || ca.gate.st || ca.f_dev || !ca.Rinv) return EODABE_EINVAL;   // fused / gated forms only for f <= 64
   Ops<T> ops{ctx, st};
-  if (ca.fresh && !ca.Rinv) hipLaunchKernelGGL(k_zero<int32_t>, dim3(1), dim3(256), 0, st, ca.dead, (int64_t)f);
   if (ca.norm_parts)
     hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, ca.norm_parts, ca.max_parts, ca.n_norm,
                        w.st);
   TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, 1, parts, f, (int64_t)f * f, nullptr,
                                    nullptr, stopb, blk));
-  if (ca.Rinv)
+  if (f <= 128)
     hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, ca.dead, ca.first_pass,
                        ca.fresh, w.st, ca.count_floors, stopb, blk);
   else
-    hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.dead, w.dg,
-                       ca.first_pass, w.st, ca.count_floors);
+    hipLaunchKernelGGL(k_chol_big, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, w.dg, ca.dead,
+                       ca.first_pass, ca.fresh, w.st, ca.count_floors);
   if (ca.R1)
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, ca.R1, ca.R, ca.dead, f, ca.col0, ca.n, w.st,
                        ca.wlog, ca.acc, ca.diag_log, blk);
@@ -645,11 +634,15 @@ int cholqr2(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, T* X, in
     TRY(ops.apply(a, nullptr, f));
     return 0;
   }
+  // wider: [Gram, blocked Cholesky with inverse] twice, X := X R^{-1} through
+  // scratch after each (explicit inverse, FP64 weights)
   double* Rs[2] = {w.rb1, w.rb2};
+  double* Ris[2] = {w.rb3, w.rb5};
   for (int pass = 0; pass < 2; ++pass) {
-    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig,
-                     chol_args(w, Rs[pass], w.deadbig, pass == 0, pass == 0, 1)));
-    TRY(ops.trsm(X, ld, tmp, ld, rows, f, Rs[pass], f));
+    CholArgs ca = chol_args(w, Rs[pass], w.deadbig, pass == 0, pass == 0, 1);
+    ca.Rinv = Ris[pass];
+    TRY(gram_chol<T>(ctx, st, w, X, ld, rows, f, w.gbig, ca));
+    TRY(ops.update_d(tmp, ld, X, ld, rows, f, f, Ris[pass], f));
     const int64_t cnt = ld * (int64_t)f;
     hipLaunchKernelGGL((k_copy2d<T, T>), dim3((unsigned)cdiv(cnt, 32), 1), dim3(32, 8), 0, st, tmp,
                        cnt, X, cnt, (int64_t)1, cnt, 0);
@@ -845,24 +838,14 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           const ApplyJob a{y, g.ldy, y, g.ldy, w.r1inv, g.mm, 0, f, f, nullptr, nullptr, nullptr};
           TRY(ops.apply(a, nullptr, f, stopb, blk));
         }
-        if (pass == 0 && !mid) {
-          TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r1, f));
-          TRY(copy2d<T>(ctx, st, (T*)w.tbig, g.ldy, y, g.ldy, f, g.ldy, 0));
-        }
+        if (pass == 0 && !mid) return EODABE_EINVAL;   // blocks are at most BN_MAX = 128 wide
       }
       // a6: append P = Z R2^{-1} (accepted columns) into Q at column wlog[j]
       if (mid) {
         const ApplyJob a{y, g.ldy, q, g.ldy, w.r2inv, g.mm, 0, f, 0, w.wlog, w.accv, nullptr};
         TRY(ops.apply(a, nullptr, f, stopb, blk));
       } else {
-        // large blocks: solve into scratch, then copy the accepted columns
-        TRY(ops.trsm(y, g.ldy, (T*)w.tbig, g.ldy, g.mm, f, w.r2, f));
-        // the copy below uses the host-known bound f; rows past acc are
-        // overwritten by later blocks (the basis is sized nn + bn).
-        HIPCHK(hipStreamSynchronize(st));
-        int64_t wj = 0;
-        HIPCHK(hipMemcpy(&wj, w.wlog + j, sizeof(int64_t), hipMemcpyDeviceToHost));
-        TRY(copy2d<T>(ctx, st, (T*)w.tbig, g.ldy, q + wj * g.ldy, g.ldy, f, g.ldy, 0));
+        return EODABE_EINVAL;          // blocks are at most BN_MAX = 128 wide
       }
     }
     const int spec = after_chunk(j);
@@ -884,8 +867,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       probed = true;
       if (!finished) {
         // predictor on the device from the probe's stopping-test values
-        hipLaunchKernelGGL(k_mlp_infer1, dim3(1), dim3(256), 0, st, ctx->pred_params, w.diag_log, g.mm, g.nn, tol,
-                           g.b, ctx->pred_margin, w.pred);
+        hipLaunchKernelGGL(k_mlp_infer1, dim3(1), dim3(256), 0, st, ctx->pred_params, w.diag_log, g.mm, g.nn,
+                           (const State*)w.st, g.b, ctx->pred_margin, w.pred);
         LAUNCHCHK();
         MlpPred hp{};
         HIPCHK(hipMemcpyAsync(&hp, w.pred, sizeof(MlpPred), hipMemcpyDeviceToHost, st));
@@ -1493,9 +1476,9 @@ int eodabe_mlp_adam(eodabe_ctx* ctx, float* params, const float* grads, float* m
   return 0;
 }
 
-int eodabe_mlp_features(const double* diag, int64_t m, int64_t n, double tol, float* out) {
-  if (!diag || !out || m < 1 || n < 1 || !(tol > 0.0)) return EODABE_EINVAL;
-  for (int c = 0; c < MLP_IN; ++c) out[c] = mlp_feature(diag, c, m, n, tol);
+int eodabe_mlp_features(const double* diag, int64_t m, int64_t n, double eps, float* out) {
+  if (!diag || !out || m < 1 || n < 1 || !(eps >= 0.0)) return EODABE_EINVAL;
+  for (int c = 0; c < MLP_IN; ++c) out[c] = mlp_feature(diag, c, m, n, eps);
   return 0;
 }
 

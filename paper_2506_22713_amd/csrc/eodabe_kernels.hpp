@@ -1385,6 +1385,121 @@ __global__ __launch_bounds__(256) void k_small_qr128(const double* __restrict__ 
   if (count_floors && threadIdx.x == 0 && nf && st) atomicAdd(&st->floored, nf);
 }
 
+// LDS (doubles) of chol_inv_blocked.
+constexpr int CHOLB_LDS = 4 * SmallCfg<64>::SIZE + 24 * 64 + 64;
+
+// ---------------------------------------------------------------------------
+// Cholesky with inverse of a symmetric positive semi-definite f x f matrix of
+// any width on one workgroup, right-looking over panels of 64 columns with
+// the pivot rules of chol_inv (the same R as the unblocked elimination up to
+// rounding order; see chol_inv128 for the blocked form of the rules):
+//   R_pp = chol(S_pp) with the floor rule referred to G's own diagonal;
+//   R_pq = R_pp^{-T} S_pq (q > p), rows of non-eliminating pivots and dead
+//          columns zero;
+//   S_qr -= R_pq^T R_pr (p < q <= r);
+// then R^{-1} by block back substitution: (R^{-1})_ic = -R_ii^{-1}
+// sum_{i < k <= c} R_ik (R^{-1})_kc.  G (overwritten by the Schur
+// complements), R, Rinv: global, column-major, leading dimension ld; dg:
+// f doubles (G's diagonal); dead: per-column flags, read unless fresh and
+// written back.  lds: CHOLB_LDS doubles.  Returns the floored pivots.
+// ---------------------------------------------------------------------------
+__device__ int chol_inv_blocked(double* G, int ld, int f, double* R, double* Rinv, double* dg,
+                                int32_t* dead, int first_pass, int fresh, double* lds) {
+  typedef SmallCfg<64> S;
+  constexpr int LD = S::LD;
+  double* Gs = lds;
+  double* Ri = Gs + S::SIZE;
+  double* Acc = Ri + S::SIZE;
+  double* Tm = Acc + S::SIZE;
+  double* work = Tm + S::SIZE;
+  double* dgs = work + 24 * 64;
+  const int tid = threadIdx.x, P = (f + 63) / 64;
+  auto at = [&](int i, int j) -> int64_t { return (int64_t)j * ld + i; };
+  for (int i = tid; i < f; i += 256) {
+    dg[i] = G[at(i, i)];
+    if (fresh) dead[i] = 0;
+  }
+  // blocks below the diagonal of R and R^{-1} are zero
+  for (int idx = tid; idx < f * f; idx += 256) {
+    const int j = idx / f, i = idx - j * f;
+    if (i / 64 > j / 64) {
+      R[at(i, j)] = 0.0;
+      Rinv[at(i, j)] = 0.0;
+    }
+  }
+  __syncthreads();
+  int nf = 0;
+  for (int p = 0; p < P; ++p) {
+    const int k0 = 64 * p, pw = (f - k0) < 64 ? f - k0 : 64;
+    uint64_t dm = 0, dmo = 0, nl = 0;
+    for (int c = 0; c < pw; ++c) dm |= (uint64_t)(dead[k0 + c] != 0) << c;
+    for (int idx = tid; idx < pw * pw; idx += 256) {
+      const int i = idx / pw, j = idx - i * pw;
+      Gs[i * LD + j] = G[at(k0 + i, k0 + j)];
+    }
+    __syncthreads();
+    int nfp = 0;
+    chol_inv<64>(Gs, Ri, work, dgs, pw, dm, first_pass, &dmo, &nfp, dg + k0, &nl);
+    nf += nfp;
+    for (int idx = tid; idx < pw * pw; idx += 256) {
+      const int i = idx / pw, j = idx - i * pw;
+      R[at(k0 + i, k0 + j)] = Gs[i * LD + j];
+      Rinv[at(k0 + i, k0 + j)] = Ri[i * LD + j];
+    }
+    for (int c = tid; c < pw; c += 256) dead[k0 + c] = (int32_t)((dmo >> c) & 1ull);
+    __syncthreads();
+    // row panel R_pq = R_pp^{-T} S_pq
+    for (int q = p + 1; q < P; ++q) {
+      const int c0 = 64 * q, qw = (f - c0) < 64 ? f - c0 : 64;
+      gmm64<true, true>(Ri, LD, G + (int64_t)c0 * ld + k0, ld, pw, qw, pw, [&](int i, int j, double v) {
+        const bool z = ((nl >> i) & 1ull) || dead[c0 + j] != 0;
+        R[at(k0 + i, c0 + j)] = z ? 0.0 : v;
+      });
+    }
+    __syncthreads();
+    // trailing update S_qr -= R_pq^T R_pr
+    for (int q = p + 1; q < P; ++q)
+      for (int r = q; r < P; ++r) {
+        const int cq = 64 * q, cr = 64 * r;
+        const int qw = (f - cq) < 64 ? f - cq : 64, rw = (f - cr) < 64 ? f - cr : 64;
+        gmm64<false, true>(R + (int64_t)cq * ld + k0, ld, R + (int64_t)cr * ld + k0, ld, qw, rw, pw,
+                           [&](int i, int j, double v) { G[at(cq + i, cr + j)] -= v; });
+      }
+    __syncthreads();
+  }
+  // R^{-1} above the diagonal blocks, column block by column block
+  for (int c = 1; c < P; ++c) {
+    const int cc = 64 * c, cw = (f - cc) < 64 ? f - cc : 64;
+    for (int i = c - 1; i >= 0; --i) {
+      const int ci = 64 * i;
+      for (int k = i + 1; k <= c; ++k) {
+        const int ck = 64 * k, kw = (f - ck) < 64 ? f - ck : 64;
+        const bool first = k == i + 1;
+        gmm64<true, true>(R + (int64_t)ck * ld + ci, ld, Rinv + (int64_t)cc * ld + ck, ld, 64, cw, kw,
+                          [&](int a, int j, double v) { Acc[a * LD + j] = first ? v : Acc[a * LD + j] + v; });
+        __syncthreads();
+      }
+      gmm64<true, false>(Rinv + (int64_t)ci * ld + ci, ld, Acc, LD, 64, cw, 64,
+                         [&](int a, int j, double v) { Rinv[at(ci + a, cc + j)] = -v; });
+      __syncthreads();
+    }
+  }
+  return nf;
+}
+
+// Cholesky with inverse (chol_inv_blocked) of an f x f Gram matrix of any
+// width on one workgroup: G (overwritten), R, R^{-1} column-major f x f;
+// dead: per-column flags (read unless fresh, written back); floored pivots
+// added to st->floored when count_floors.
+__global__ __launch_bounds__(256) void k_chol_big(double* __restrict__ G, int f, double* __restrict__ R,
+                                                  double* __restrict__ Rinv, double* __restrict__ dg,
+                                                  int32_t* __restrict__ dead, int first_pass, int fresh, State* st,
+                                                  int count_floors) {
+  __shared__ double lds[CHOLB_LDS];
+  const int nf = chol_inv_blocked(G, f, f, R, Rinv, dg, dead, first_pass, fresh, lds);
+  if (count_floors && threadIdx.x == 0 && nf && st) atomicAdd(&st->floored, nf);
+}
+
 // Arguments of the Cholesky that closes a Gram pass (k_gram_rows, and the
 // global-memory path for wide blocks).
 struct CholArgs {
@@ -1813,91 +1928,6 @@ __global__ __launch_bounds__(256) void k_small_qr(const double* __restrict__ R1g
     if (i < f && jj < f) Dout[(int64_t)i * ldd + jj] = (T)v;
   });
   if (count_floors && tid == 0 && nf1 + nf2) atomicAdd(&st->floored, nf1 + nf2);
-}
-
-// Same algorithm with G in global memory (large f); G is overwritten.
-__global__ __launch_bounds__(256) void k_cholesky_global(
-    double* __restrict__ G, int f, double* __restrict__ R, int32_t* __restrict__ dead,
-    double* __restrict__ dg, int first_pass, State* st, int count_floors) {
-  __shared__ int s_flag;
-  __shared__ double s_rkk;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t ff = (int64_t)f * f;
-  for (int k = tid; k < f; k += nt) dg[k] = G[(int64_t)k * f + k];
-  __syncthreads();
-  for (int k = 0; k < f; ++k) {
-    if (tid == 0) {
-      int fl = 0;
-      if (dead[k]) {
-        fl = 2;
-      } else {
-        const double piv = G[(int64_t)k * f + k];
-        const double flo = FLOOR_C * U64 * dg[k];
-        if (!(piv > flo) || !(piv < INFINITY)) {
-          if (first_pass) {
-            G[(int64_t)k * f + k] = sqrt(flo > 1e-300 ? flo : 1e-300);
-            fl = 1;
-            if (count_floors && st) atomicAdd(&st->floored, 1);
-          } else {
-            dead[k] = 1;
-            fl = 2;
-          }
-        } else {
-          G[(int64_t)k * f + k] = sqrt(piv);
-        }
-      }
-      if (fl == 2) G[(int64_t)k * f + k] = 1.0;
-      s_flag = fl;
-      s_rkk = G[(int64_t)k * f + k];
-    }
-    __syncthreads();
-    const int fl = s_flag;
-    const double rkk = s_rkk;
-    for (int j = k + 1 + tid; j < f; j += nt) {
-      double v = G[(int64_t)j * f + k];
-      G[(int64_t)j * f + k] = (fl != 0 || dead[j]) ? 0.0 : v / rkk;
-    }
-    __threadfence_block();
-    __syncthreads();
-    if (fl == 0) {
-      const int nrem = f - k - 1;
-      for (int jj = k + 1 + (tid / 32); jj < f; jj += nt / 32) {
-        const double rkj = G[(int64_t)jj * f + k];
-        if (rkj == 0.0) continue;
-        for (int ii = k + 1 + (tid & 31); ii <= jj; ii += 32)
-          G[(int64_t)jj * f + ii] -= G[(int64_t)ii * f + k] * rkj;
-      }
-      (void)nrem;
-      __threadfence_block();
-      __syncthreads();
-    }
-  }
-  for (int64_t idx = tid; idx < ff; idx += nt) {
-    const int64_t j = idx / f, i = idx - j * f;
-    R[idx] = (i <= j) ? G[idx] : 0.0;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Z = X R^{-1} row by row (forward substitution in FP64) for blocks wider
-// than 64 columns:  z_c = (x_c - sum_{k<c} z_k R(k,c)) / R(c,c).
-// X element (i, c) at c*ldx + i; Z likewise (ldz), out of place; R (f x f,
-// element (i,j) at j*f + i) read through the cache.  Columns c < ncols_out.
-// ---------------------------------------------------------------------------
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_trsm_rows_big(
-    const Tin* __restrict__ X, int64_t ldx, Tout* __restrict__ Zo, int64_t ldz, int64_t m,
-    int f, const double* __restrict__ R, int ncols_out) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  // in place over X is not allowed here; Zo holds the solution progressively
-  for (int c = 0; c < f; ++c) {
-    double v = (double)X[(int64_t)c * ldx + i];
-    const double* Rc = R + (int64_t)c * f;
-    for (int k = 0; k < c; ++k) v -= (double)Zo[(int64_t)k * ldz + i] * Rc[k];
-    Zo[(int64_t)c * ldz + i] = (Tout)(v / Rc[c]);
-  }
-  (void)ncols_out;
 }
 
 // Stop test of Alg. 1 for blocks wider than 64 columns (one thread); the

@@ -18,10 +18,11 @@ constexpr int64_t MLP_W1 = 0, MLP_B1 = MLP_W1 + (int64_t)MLP_H * MLP_IN, MLP_W2 
                   MLP_B3 = MLP_W3 + (int64_t)MLP_H * MLP_H, MLP_W4 = MLP_B3 + MLP_H,
                   MLP_B4 = MLP_W4 + (int64_t)MLP_OUT * MLP_H, MLP_NPARAM = MLP_B4 + MLP_OUT;
 
-// Input c of the network from the stopping-test values (c < 64) or the
-// geometry (c = 64, 65, 66).  Shared by the host (training sets) and the
-// inference kernel.
-__host__ __device__ inline float mlp_feature(const double* d, int c, int64_t m, int64_t n, double tol) {
+// Input c of the network from the stopping-test values (c < 64), the
+// geometry (c = 64, 65) or the threshold eps = tol ||A||_F of the test on
+// the same scale as the d_c (c = 66).  Shared by the host (training sets)
+// and the inference kernel.
+__host__ __device__ inline float mlp_feature(const double* d, int c, int64_t m, int64_t n, double eps) {
   if (c < 64) {
     if (!(d[0] > 0.0) || !(d[c] > 0.0)) return -1.0f;
     const double l = log10(d[c] / d[0]);
@@ -29,7 +30,10 @@ __host__ __device__ inline float mlp_feature(const double* d, int c, int64_t m, 
   }
   if (c == 64) return (float)(log2((double)m) / 16.0);
   if (c == 65) return (float)(log2((double)n) / 16.0);
-  return (float)(log10(tol) / 16.0);
+  if (!(d[0] > 0.0) || !(eps > 0.0)) return -1.0f;
+  double l = log10(eps / d[0]);
+  l = l < -16.0 ? -16.0 : (l > 16.0 ? 16.0 : l);
+  return (float)(l / 16.0);
 }
 
 // Warm-start width from the quantile head: d0 = b ceil((rhat (1 + margin) + 1) / b),
@@ -176,11 +180,11 @@ struct MlpPred {
 // values on the device: features, three GELU layers (thread j computes
 // unit j), the two heads, and the warm-start width.
 __global__ __launch_bounds__(256) void k_mlp_infer1(const float* __restrict__ P, const double* __restrict__ diag,
-                                                    int64_t m, int64_t n, double tol, int b, double margin,
-                                                    MlpPred* __restrict__ out) {
+                                                    int64_t m, int64_t n, const State* __restrict__ st, int b,
+                                                    double margin, MlpPred* __restrict__ out) {
   __shared__ float x[MLP_IN], h[2][MLP_H];
   const int j = threadIdx.x;
-  if (j < MLP_IN) x[j] = mlp_feature(diag, j, m, n, tol);
+  if (j < MLP_IN) x[j] = mlp_feature(diag, j, m, n, st->eps);
   __syncthreads();
   float z = P[MLP_B1 + j];
   for (int k = 0; k < MLP_IN; ++k) z += P[MLP_W1 + (int64_t)j * MLP_IN + k] * x[k];

@@ -24,13 +24,14 @@ NIN, NH, NOUT = 67, 256, 2
 FORMAT = "eodabe-mlp-1"
 
 
-def features(diag: np.ndarray, m: int, n: int, tol: float) -> np.ndarray:
-    """eodabe_mlp_features: the 67 inputs from the stopping-test values d_0..d_63."""
+def features(diag: np.ndarray, m: int, n: int, eps: float) -> np.ndarray:
+    """eodabe_mlp_features: the 67 inputs from the stopping-test values d_0..d_63
+    and the threshold eps = tol ||A||_F."""
     d = np.ascontiguousarray(np.asarray(diag, dtype=np.float64)[:64])
     if d.size < 64:
         raise EodAbeError(EODABE_EINVAL, "features: 64 stopping-test values needed")
     out = np.zeros(NIN, dtype=np.float32)
-    st = _lib.eodabe_mlp_features(d.ctypes.data_as(ctypes.c_void_p), int(m), int(n), float(tol),
+    st = _lib.eodabe_mlp_features(d.ctypes.data_as(ctypes.c_void_p), int(m), int(n), float(eps),
                                   out.ctypes.data_as(ctypes.c_void_p))
     if st != 0:
         raise EodAbeError(st, "eodabe_mlp_features")

@@ -137,9 +137,9 @@ def test_predictor_features_match_oracle(E):
     rng = np.random.default_rng(3)
     cases = [10.0 ** (-0.1 * np.arange(64)), np.exp(-rng.random(64).cumsum()), 10.0 ** (-1.0 * np.arange(64)),
              np.concatenate([np.ones(10), np.zeros(54)])]
-    for d, (m, n, tol) in zip(cases, [(4096, 4096, 1e-3), (777, 300, 1e-8), (65, 65, 0.5), (1000, 999, 1e-4)]):
-        got = PR.features(d, m, n, tol)
-        ref = PO.features(d, m, n, tol).astype(np.float32)
+    for d, (m, n, eps) in zip(cases, [(4096, 4096, 1e-3), (777, 300, 1e-8), (65, 65, 0.5), (1000, 999, 1e40)]):
+        got = PR.features(d, m, n, eps)
+        ref = PO.features(d, m, n, eps).astype(np.float32)
         assert np.array_equal(got, ref), (got - ref)
 
 

@@ -242,6 +242,22 @@ def test_factor_multi_block_blocked_cholesky(b):
     assert f.blocks >= 2
 
 
+@pytest.mark.parametrize("m,n", [(900, 500), (500, 900)])
+def test_factor_rank_300_panel_blocked_cholesky(m, n):
+    # ranks above 128 close through the panel-blocked Cholesky with inverse
+    # (five 64-column panels, the last one ragged) and FP64-weight products
+    A = W.lowrank_haar(14, m=m, n=n, r=300, noise_std=0.0)
+    f, ref = check_factor(A, torch.float64, 1e-9, b=32, seed=14)
+    assert f.rank == 300
+
+
+def test_factor_fp32_rank_250():
+    A = W.lowrank_haar(15, m=1000, n=600, r=250, noise_std=1e-8)
+    stable, _, _ = O.precision_stable(A, 1e-4, 64, 15)
+    f, ref = check_factor(A, torch.float32, 1e-4, b=64, seed=15, stable=stable)
+    assert 128 < f.rank <= 256
+
+
 @pytest.mark.parametrize("m,n", [(800, 300), (300, 800)])
 def test_factor_fp32_rank_100_closing(m, n):
     # ranks 65..128 close through the blocked Cholesky in FP32 (tall and

@@ -123,7 +123,7 @@ def test_warm_start_inference_matches_oracle(dtype):
     f = E.factor(torch.from_numpy(A).to("cuda", dtype), tol, ctx=ctx)
     d0, y0, y1, used = ctx.last_prediction()
     assert used in (1, 2)
-    x = PO.features(d[:64], 700, 500, tol)
+    x = PO.features(d[:64], 700, 500, info.eps)
     yr, _ = PO.forward(p.astype(np.float64), x[None, :])
     assert abs(y0 - yr[0, 0]) <= 1e-4 * max(1, abs(yr[0, 0])) and abs(y1 - yr[0, 1]) <= 1e-4 * max(1, abs(yr[0, 1]))
     assert d0 == PO.predicted_width(y1, b, 0.2)

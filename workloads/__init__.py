@@ -21,13 +21,19 @@ which are not available):
 * ``mat2``           strictly rank-deficient U [Sigma 0; 0 0] V^T with sorted
                      uniform singular values (section 4.5, eq. mat2).
 * ``robustness``     Matrix I-IV of section 4.3.
+* ``spectrum_sigma`` / ``spectrum_torch``  U diag(sigma) V^T + noise with a
+                     chosen singular-value profile (geometric, polynomial or
+                     stepped decay), Haar U and V, built on a torch device
+                     from a seeded generator (training and evaluation sets
+                     of the learned warm start, 4096 x 4096 evaluation
+                     matrices).
 """
 from __future__ import annotations
 
 import numpy as np
 
 __all__ = ["haar", "lowrank_haar", "image", "hyperspectral", "tiles",
-           "tile_shapes", "mat2", "robustness", "devils_stairs_sigma"]
+           "tile_shapes", "mat2", "robustness", "devils_stairs_sigma", "spectrum_sigma", "spectrum_torch"]
 
 
 def haar(rng: np.random.Generator, n: int, r: int) -> np.ndarray:
@@ -203,3 +209,42 @@ def robustness(kind: str, seed: int, n: int = 1000, alpha: float = 0.005,
     else:
         raise ValueError(kind)
     return A.astype(dtype)
+
+
+def spectrum_sigma(kind: str, r: int, param: float) -> np.ndarray:
+    """Singular values s_0 >= ... >= s_{r-1} > 0 with s_0 = 1:
+    geom    s_i = 10^{-param i / r}          (param decades over the rank)
+    poly    s_i = (1 + i)^{-param}
+    stairs  s_i = 10^{-0.8 floor(i / param)}  (steps of param values)"""
+    i = np.arange(r, dtype=np.float64)
+    if kind == "geom":
+        return 10.0 ** (-param * i / r)
+    if kind == "poly":
+        return (1.0 + i) ** (-param)
+    if kind == "stairs":
+        return 10.0 ** (-0.8 * np.floor(i / max(param, 1.0)))
+    raise ValueError(kind)
+
+
+def spectrum_torch(seed: int, m: int, n: int, sigma: np.ndarray, noise_std: float = 0.0,
+                   device: str = "cuda", dtype=None):
+    """A = U diag(sigma) V^T + N(0, noise_std^2) on a torch device: U (m x r)
+    and V (n x r) Haar (Q factors of seeded Gaussians with the signs of
+    diag(R) folded in), FP64 arithmetic, returned in dtype (FP64 default)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    r = len(sigma)
+    s = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+
+    def haar_t(rows):
+        G = torch.randn(rows, r, generator=g, device=device, dtype=torch.float64)
+        Q, R = torch.linalg.qr(G)
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1.0
+        return Q * d
+    U, V = haar_t(m), haar_t(n)
+    A = (U * s) @ V.T
+    if noise_std:
+        A += noise_std * torch.randn(m, n, generator=g, device=device, dtype=torch.float64)
+    return A if dtype is None else A.to(dtype)

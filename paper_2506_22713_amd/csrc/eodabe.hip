@@ -194,6 +194,8 @@ struct Geo {
 
 // Widest sketch of the learned warm start in one pass over A (columns).
 constexpr int WIDE_COLS = 128;
+// K-splits of the Gram of blocks wider than 64 columns (partials, then a sum).
+constexpr int GRAM_SPLITS_WIDE = 16;
 
 struct WS {
   State* st;
@@ -271,8 +273,10 @@ WS carve(void* base, const Geo& g) {
   w.cpart = c.take<char>((int64_t)g.s_core * rc * g.ldk * e);
   w.ybig = c.take<char>(g.ldy * rc * e);
   const int64_t rb = std::max<int64_t>(rc, g.bn);
+  // Gram partials of the closing QRs: 64 of up to 64 x 64, or GRAM_SPLITS_WIDE + 1
+  // of rb x rb (the K-split partials of a wider Gram and their sum)
   w.gbig = c.take<double>(std::max<int64_t>(64 * std::min<int64_t>(rb, 64) * std::min<int64_t>(rb, 64),
-                                            rb * rb));
+                                            (GRAM_SPLITS_WIDE + 1) * rb * rb));
   w.rb1 = c.take<double>(rb * rb);
   w.rb2 = c.take<double>(rb * rb);
   w.rb3 = c.take<double>(rb * rb);
@@ -320,7 +324,7 @@ bool plan(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t lda, const void* 
   int64_t s = cdiv(512, mt);
   s = std::min<int64_t>(s, std::max<int64_t>(g.nn / 256, 1));
   g.s_sketch = (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
-  g.s_proj = (int)std::max<int64_t>(1, std::min<int64_t>(32, g.mm / 1024));
+  g.s_proj = (int)std::max<int64_t>(1, std::min<int64_t>(64, g.mm / 256));
   g.s_gram = (int)std::max<int64_t>(1, std::min<int64_t>(64, g.mm / 2048));
   // C = Q^T A: output r x nn is small, the reduction over mm is long.
   const int64_t rc1 = std::max<int64_t>(r_cap, 1);
@@ -580,8 +584,13 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
   if (ca.norm_parts)
     hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, ca.norm_parts, ca.max_parts, ca.n_norm,
                        w.st);
-  TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, 1, parts, f, (int64_t)f * f, nullptr,
-                                   nullptr, stopb, blk));
+  // G = X^T X as K-split partials (about 512 rows each), summed in fixed order
+  const int gs = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_SPLITS_WIDE, rows / 512));
+  const int64_t ff = (int64_t)f * f;
+  double* gsum = parts + (int64_t)gs * ff;
+  TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, gs, parts, f, ff, nullptr, nullptr, stopb, blk));
+  TRY(ops.reduce(parts, eff_splits(rows, gs), ff, ff, gsum, stopb, blk));
+  parts = gsum;
   if (f <= 128)
     hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, ca.dead, ca.first_pass,
                        ca.fresh, w.st, ca.count_floors, stopb, blk);

@@ -6,13 +6,16 @@ import math
 
 import numpy as np
 import pytest
-import torch
 
-import paper_2506_22713_amd as E
-from paper_2506_22713_amd import predictor as PR
-from oracle import predictor_oracle as PO
-from oracle import eodabe_oracle as O
-import workloads as W
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2506_22713_amd as E  # noqa: E402
+from paper_2506_22713_amd import predictor as PR  # noqa: E402
+from oracle import predictor_oracle as PO  # noqa: E402
+from oracle import eodabe_oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 

@@ -16,6 +16,11 @@ Workloads (``--workload``):
                  content 5..80 + N(0, 1e-4) noise, tol 1e-4: one step is one
                  eodabe_factor_batched call over all tiles, compared with
                  1024 sequential eodabe_factor calls on the same tiles.
+  learned4096    six 4096 x 4096 FP32 matrices U diag(s) V^T + noise with
+                 geometric singular-value decay over ranks 96..416, tol 1e-4:
+                 one step factors all six with the learned warm start
+                 (paper_2506_22713_amd/predictor.ckpt), compared with the
+                 plain loop on the same matrices.
 """
 from __future__ import annotations
 
@@ -124,6 +129,91 @@ def cpu_baseline_tiles(tiles, tol, blocks, budget_s):
     return dict(value=done / el, unit="matrices/s", cores=int(cores), kind="oracle",
                 sample=f"the first {done} of the {len(tiles)} tiles (LPT-independent order), "
                        f"FP64 NumPy oracle, {el:.1f} s")
+
+
+def run_learned(args):
+    """Warm-started factorizations (trained predictor) against the plain loop
+    on the same 4096^2 matrices: matrices/s, sketch passes per solve,
+    fallback rate, rank agreement and the equal-error check."""
+    import torch
+    import paper_2506_22713_amd as E
+    from paper_2506_22713_amd import predictor as PR
+    import workloads as W
+    tol, b, n = 1e-4, args.block or 32, 4096
+    ranks_in = [96, 160, 224, 288, 352, 416]
+    log("generating", len(ranks_in), "matrices")
+    mats = []
+    for k, r in enumerate(ranks_in):
+        sig = W.spectrum_sigma("geom", r, 3.0)
+        noise = 1e-7 * float(np.sqrt((sig ** 2).sum()) / n)
+        mats.append(W.spectrum_torch(1000 + k, n, n, sig, noise, dtype=torch.float32))
+    pred = PR.Predictor.load(os.path.join(ROOT, "paper_2506_22713_amd", "predictor.ckpt"))
+    cp, cl = E.Context(block=b, seed=0), E.Context(block=b, seed=0)
+    pred.attach(cl, margin=0.1)
+    wsp, wsl = cp.workspace(n, n, n), cl.workspace(n, n, n)
+    out_p = [E.alloc_outputs(A, n) for A in mats]
+    out_l = [E.alloc_outputs(A, n) for A in mats]
+
+    def run(ctx, ws, outs, steps, record=False):
+        res = []
+        for _ in range(steps):
+            for i, A in enumerate(mats):
+                f = E.factor(A, tol, ctx=ctx, ws=ws, out=outs[i])
+                if record:
+                    res.append((f, ctx.last_prediction()))
+        return res
+    log("warmup", args.warmup)
+    run(cp, wsp, out_p, max(args.warmup, 1))
+    run(cl, wsl, out_l, max(args.warmup, 1))
+    res = {}
+    for name, ctx, ws, outs in (("plain", cp, wsp, out_p), ("learned", cl, wsl, out_l)):
+        log("timed", name, args.steps)
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = run(ctx, ws, outs, args.steps, record=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sk = ctx.profile_read(E.PROF_SKETCH)
+        ctx.profile(False)
+        res[name] = dict(ms_per_step=el * 1e3 / args.steps, passes=sk[1] / (args.steps * len(mats)),
+                         sketch_ms=sk[0] / args.steps, last=rec[-len(mats):])
+    agree, excess, fb, d0s = 0, 0.0, 0, []
+    for (fp, _), (fl, pl), A in zip(res["plain"]["last"], res["learned"]["last"], mats):
+        A64 = A.double()
+        nA = torch.linalg.norm(A64)
+        ep = float(torch.linalg.norm(A64 - fp.U.double() @ fp.D.double() @ fp.Vt.double()) / nA)
+        el = float(torch.linalg.norm(A64 - fl.U.double() @ fl.D.double() @ fl.Vt.double()) / nA)
+        agree += int(fp.rank == fl.rank)
+        excess = max(excess, el - ep)
+        fb += int(pl[3] == 2)
+        d0s.append(int(pl[0]))
+    ms_l, ms_p = res["learned"]["ms_per_step"], res["plain"]["ms_per_step"]
+    line = {
+        "metric": METRIC,
+        "value": round(len(mats) * 1e3 / ms_l, 2),
+        "unit": "matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_l, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": dict(workload="learned4096", m=n, n=n, tol=tol, block=b, matrices=len(mats),
+                       content_ranks=ranks_in, ranks=[int(f.rank) for f, _ in res["learned"]["last"]],
+                       predicted_d0=d0s, fallback_rate=fb / len(mats),
+                       sketch_passes_per_solve=dict(learned=res["learned"]["passes"], plain=res["plain"]["passes"]),
+                       plain=dict(ms_per_step=round(ms_p, 4), matrices_per_s=round(len(mats) * 1e3 / ms_p, 2)),
+                       speedup_vs_plain=round(ms_p / ms_l, 4), rank_agree=agree, max_relerr_excess=excess,
+                       sketch_ms_per_step=dict(learned=round(res["learned"]["sketch_ms"], 4),
+                                               plain=round(res["plain"]["sketch_ms"], 4))),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def run_tiles(args):
@@ -261,6 +351,9 @@ def main():
 
     if args.workload == "tiles1024":
         run_tiles(args)
+        return
+    if args.workload == "learned4096":
+        run_learned(args)
         return
 
     import torch

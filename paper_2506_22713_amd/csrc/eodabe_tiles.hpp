@@ -105,9 +105,10 @@ __device__ __forceinline__ void tile_rowprod(const float* A, int64_t lda, int64_
                                              int64_t ldb, int nb, float* Yb, int64_t ldy, double* ss,
                                              double* red) {
   typedef Mfma<float> MF;
-  constexpr int RT = 4, CT = 4;
+  constexpr int RT = 4, CT = 4, PF = 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
   const int CTr = (nb + 15) / 16;
+  const int64_t nsteps = (n + 15) / 16;
   double sq = 0.0;
   for (int64_t p0 = (int64_t)wv * 64; p0 < m; p0 += 256) {
     const float* ap[RT];
@@ -123,54 +124,45 @@ __device__ __forceinline__ void tile_rowprod(const float* A, int64_t lda, int64_
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int u = 0; u < CT; ++u) acc[t][u] = MF::zero();
-    auto compute = [&](const V4<float>(&a)[RT], int64_t k) {
-      V4<float> bv[CT];
+    // both operands of a 16-column step are loaded PF steps ahead, so the
+    // wait before a step covers only loads issued PF steps earlier
+    V4<float> a[PF][RT], bq[PF][CT];
+    auto load = [&](int q, int64_t st) {
+      const int64_t k = 16 * st;
       const bool full = k + 16 <= n;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[q][t] = full ? tile_lda4<AL>(ap[t] + k) : ld4_masked(ap[t] + k, k + 4 * g, n);
 #pragma unroll
       for (int u = 0; u < CT; ++u) {
         const float* ob = B + (int64_t)(16 * u + r) * ldb + k + 4 * g;
-        if (u < CTr && 16 * u + r < nb) bv[u] = full ? ld4(ob) : ld4_masked(ob, k + 4 * g, n);
-        else bv[u] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-          for (int u = 0; u < CT; ++u)
-            if (u < CTr) acc[t][u] = MF::op(a[t].v[v], bv[u].v[v], acc[t][u]);
-      if (ss) {
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-          if (aval[t])
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sq += (double)a[t].v[v] * (double)a[t].v[v];
+        if (u < CTr && 16 * u + r < nb) bq[q][u] = full ? ld4(ob) : ld4_masked(ob, k + 4 * g, n);
+        else bq[q][u] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
       }
     };
-    const int64_t nfull = n / 16;
-    V4<float> a[4][RT];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (q < nfull)
+    for (int q = 0; q < PF; ++q)
+      if (q < nsteps) load(q, q);
+    for (int64_t c = 0; c < nsteps; c += PF) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) a[q][t] = tile_lda4<AL>(ap[t] + 16 * q);
-    for (int64_t c = 0; c < nfull; c += 4) {
+      for (int q = 0; q < PF; ++q) {
+        if (c + q < nsteps) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (c + q < nfull) {
-          compute(a[q], 16 * (c + q));
-          if (c + q + 4 < nfull)
+          for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int t = 0; t < RT; ++t) a[q][t] = tile_lda4<AL>(ap[t] + 16 * (c + q + 4));
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+              for (int u = 0; u < CT; ++u)
+                if (u < CTr) acc[t][u] = MF::op(a[q][t].v[v], bq[q][u].v[v], acc[t][u]);
+          if (ss) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+              if (aval[t])
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sq += (double)a[q][t].v[v] * (double)a[q][t].v[v];
+          }
+          if (c + q + PF < nsteps) load(q, c + q + PF);
         }
       }
-    }
-    if (nfull * 16 < n) {
-      const int64_t k = nfull * 16;
-      V4<float> at[RT];
-#pragma unroll
-      for (int t = 0; t < RT; ++t) at[t] = ld4_masked(ap[t] + k, k + 4 * g, n);
-      compute(at, k);
     }
 #pragma unroll
     for (int t = 0; t < RT; ++t)
@@ -206,8 +198,10 @@ __device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_
                                              int64_t ldq, int r, float* Ct, int64_t ldc, double* ss,
                                              double* red) {
   typedef Mfma<float> MF;
+  constexpr int PF = 3;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, rr = lane & 15, g = lane >> 4;
   const int TR = (r + 15) / 16;
+  const int64_t nsteps = (m + 15) / 16;
   double sq = 0.0;
   for (int64_t c0 = 64 * (int64_t)wv; c0 < n; c0 += 256) {
     MF::acc_t acc[4][4];
@@ -215,37 +209,49 @@ __device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
-    for (int64_t k0 = 0; k0 < m; k0 += 16) {
-      const int64_t kr = k0 + 4 * g;
+    // operands of a 16-row step loaded PF steps ahead (see tile_rowprod)
+    V4<float> qv[PF][4];
+    float av[PF][4][4];
+    auto load = [&](int q, int64_t st) {
+      const int64_t kr = 16 * st + 4 * g;
       const bool full = kr + 4 <= m;
-      V4<float> qv[4];
-      float av[4][4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int qc = 16 * t + rr;
         const float* qp = Q + (int64_t)qc * ldq + kr;
-        if (t < TR && qc < r) qv[t] = full ? ld4(qp) : ld4_masked(qp, kr, m);
-        else qv[t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
+        if (t < TR && qc < r) qv[q][t] = full ? ld4(qp) : ld4_masked(qp, kr, m);
+        else qv[q][t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int64_t ac = c0 + 16 * u + rr;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) av[u][e] = (ac < n && kr + e < m) ? A[(kr + e) * lda + ac] : 0.f;
+        for (int e = 0; e < 4; ++e) av[q][u][e] = (ac < n && kr + e < m) ? A[(kr + e) * lda + ac] : 0.f;
       }
-      if (ss) {
+    };
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+    for (int q = 0; q < PF; ++q)
+      if (q < nsteps) load(q, q);
+    for (int64_t c = 0; c < nsteps; c += PF) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) sq += (double)av[u][e] * (double)av[u][e];
+      for (int q = 0; q < PF; ++q) {
+        if (c + q < nsteps) {
+          if (ss) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) sq += (double)av[q][u][e] * (double)av[q][u][e];
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (t < TR)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(qv[q][t].v[v], av[q][u][v], acc[t][u]);
+          if (c + q + PF < nsteps) load(q, c + q + PF);
+        }
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (t < TR)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(qv[t].v[v], av[u][v], acc[t][u]);
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -291,28 +297,42 @@ __device__ __forceinline__ void tile_xty(const float* X, int64_t ldx, int wx, co
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
-  for (int64_t k0 = 16 * (int64_t)wv; k0 < m; k0 += 64) {
-    const int64_t kr = k0 + 4 * g;
+  // this wave's 16-row steps are k0 = 16 wv + 64 s; operands two steps ahead
+  constexpr int PF = 2;
+  const int64_t nsteps = m > 16 * (int64_t)wv ? (m - 16 * (int64_t)wv + 63) / 64 : 0;
+  V4<float> xa[PF][4], yb[PF][4];
+  auto load = [&](int q, int64_t st) {
+    const int64_t kr = 16 * (int64_t)wv + 64 * st + 4 * g;
     const bool full = kr + 4 <= m;
-    V4<float> xa[4], yb[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int c = 16 * t + r;
       const float* xp = X + (int64_t)c * ldx + kr;
-      if (t < TX && c < wx) xa[t] = full ? ld4(xp) : ld4_masked(xp, kr, m);
-      else xa[t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
+      if (t < TX && c < wx) xa[q][t] = full ? ld4(xp) : ld4_masked(xp, kr, m);
+      else xa[q][t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
       const float* yp = Yb + (int64_t)c * ldy + kr;
-      if (t < TY && c < wy) yb[t] = full ? ld4(yp) : ld4_masked(yp, kr, m);
-      else yb[t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
+      if (t < TY && c < wy) yb[q][t] = full ? ld4(yp) : ld4_masked(yp, kr, m);
+      else yb[q][t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
     }
+  };
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+  for (int q = 0; q < PF; ++q)
+    if (q < nsteps) load(q, q);
+  for (int64_t c = 0; c < nsteps; c += PF) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t < TX)
+    for (int q = 0; q < PF; ++q) {
+      if (c + q < nsteps) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (u < TY) acc[t][u] = MF::op((double)xa[t].v[v], (double)yb[u].v[v], acc[t][u]);
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (t < TX)
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (u < TY) acc[t][u] = MF::op((double)xa[q][t].v[v], (double)yb[q][u].v[v], acc[t][u]);
+        if (c + q + PF < nsteps) load(q, c + q + PF);
+      }
+    }
   }
   // fold the waves in order
   for (int w = 0; w < 4; ++w) {

@@ -233,6 +233,7 @@ struct WS {
   double* dg;           // r_cap
   void* tbig;           // ldy x r_cap scratch for large-f triangular solves
   double* sq128;        // 7 x 128 x 128: closing QR scratch for ranks 65..128
+  uint64_t* cbmask;     // per 64-column panel: pivots that did not eliminate (wide Cholesky)
   // learned warm start (g.wide): wide Omega, sketch partials and sketch, prediction
   void* omega_w;        // WIDE_COLS x ldk
   void* ypart_w;        // s_sketch x ldy x WIDE_COLS
@@ -286,6 +287,7 @@ WS carve(void* base, const Geo& g) {
   w.dg = c.take<double>(std::max<int64_t>(rc, g.bn) + 64);
   w.tbig = c.take<char>(std::max(g.ldy, g.ldk) * rc * std::max<size_t>(e, 8));
   w.sq128 = rb > 64 ? c.take<double>(7 * 128 * 128) : nullptr;
+  w.cbmask = c.take<uint64_t>(cdiv(rb, 64) + 1);
   if (g.wide) {
     w.omega_w = c.take<char>((int64_t)WIDE_COLS * g.ldk * e);
     w.ypart_w = c.take<char>((int64_t)g.s_sketch * g.ldy * WIDE_COLS * e);
@@ -513,8 +515,8 @@ struct Ops {
   int update_d(T* Y, int64_t ldy, const T* Q, int64_t ldq, int64_t m, int64_t w, int f,
                const double* W, int64_t ldw) {
     if (m <= 0 || f <= 0) return 0;
-    dim3 grid((unsigned)cdiv(m, 64), (unsigned)cdiv(f, 32));
-    hipLaunchKernelGGL((k_update_rows<T, double, 32>), grid, dim3(64), 0, st, Y, ldy, Q, ldq, m, w, f,
+    dim3 grid((unsigned)cdiv(m, 64), (unsigned)cdiv(f, 64));
+    hipLaunchKernelGGL((k_update_rows<T, double>), grid, dim3(256), 0, st, Y, ldy, Q, ldq, m, w, f,
                        W, ldw, 0, (const int64_t*)nullptr, (const int32_t*)nullptr, 0);
     LAUNCHCHK();
     return 0;
@@ -524,8 +526,8 @@ struct Ops {
              int64_t ldw, int subtract, const int64_t* wlog = nullptr, const int32_t* stopb = nullptr,
              int blk = 0) {
     if (m <= 0 || f <= 0) return 0;
-    dim3 grid((unsigned)cdiv(m, 256), (unsigned)cdiv(f, 32));
-    hipLaunchKernelGGL((k_update_rows<T, T, 32>), grid, dim3(256), 0, st, Y, ldy, Q, ldq, m, w, f, W,
+    dim3 grid((unsigned)cdiv(m, 64), (unsigned)cdiv(f, 64));
+    hipLaunchKernelGGL((k_update_rows<T, T>), grid, dim3(256), 0, st, Y, ldy, Q, ldq, m, w, f, W,
                        ldw, subtract, wlog, stopb, blk);
     LAUNCHCHK();
     return 0;
@@ -549,9 +551,9 @@ CholArgs chol_args(const WS& w, double* R, int32_t* dead, int first, int fresh, 
 // R^{-1}, stop test, ||A||_F finish).  f <= 64: one launch (k_gram_rows; its last workgroup runs the
 // Cholesky with inverse).  64 < f <= 128: generic GEMM, then the 2 x 2-
 // blocked Cholesky with inverse on one workgroup (k_chol128), separate stop
-// test.  Wider: generic GEMM, panel-blocked Cholesky with inverse on one
-// workgroup (k_chol_big, the Gram overwritten).  Above 64 columns ca.Rinv is
-// required and there is no fused W.
+// test.  Wider: generic GEMM, panel-blocked Cholesky with inverse as one
+// kernel per step (k_cb_*, the Gram overwritten).  Above 64 columns ca.Rinv
+// is required and there is no fused W.
 template <typename T>
 int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, int64_t rows, int f,
               double* parts, const CholArgs& ca, const int32_t* stopb = nullptr, int blk = 0,
@@ -594,9 +596,23 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
   if (f <= 128)
     hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, ca.dead, ca.first_pass,
                        ca.fresh, w.st, ca.count_floors, stopb, blk);
-  else
-    hipLaunchKernelGGL(k_chol_big, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, w.dg, ca.dead,
-                       ca.first_pass, ca.fresh, w.st, ca.count_floors);
+  else {
+    // panel-blocked, one kernel per step (see k_cb_*)
+    const int P = (int)cdiv(f, 64);
+    hipLaunchKernelGGL(k_cb_init, dim3((unsigned)std::min<int64_t>(cdiv(ff, 256), 1024)), dim3(256), 0, st,
+                       parts, f, f, ca.R, ca.Rinv, w.dg, ca.dead, ca.fresh);
+    for (int p = 0; p < P; ++p) {
+      hipLaunchKernelGGL(k_cb_diag, dim3(1), dim3(256), 0, st, parts, f, f, p, ca.R, ca.Rinv, w.dg, ca.dead,
+                         w.cbmask, ca.first_pass, w.st, ca.count_floors);
+      if (p + 1 < P) {
+        hipLaunchKernelGGL(k_cb_row, dim3(P - p - 1), dim3(256), 0, st, parts, f, f, p, ca.R, ca.Rinv, ca.dead,
+                           w.cbmask);
+        hipLaunchKernelGGL(k_cb_trail, dim3((P - p - 1) * (P - p) / 2), dim3(256), 0, st, parts, f, f, p, ca.R);
+      }
+    }
+    for (int d = 1; d < P; ++d)
+      hipLaunchKernelGGL(k_cb_inv, dim3(P - d), dim3(256), 0, st, ca.R, ca.Rinv, f, f, d);
+  }
   if (ca.R1)
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, ca.R1, ca.R, ca.dead, f, ca.col0, ca.n, w.st,
                        ca.wlog, ca.acc, ca.diag_log, blk);
@@ -658,8 +674,8 @@ int cholqr2(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, T* X, in
     LAUNCHCHK();
   }
   const int64_t ff = (int64_t)f * f;
-  hipLaunchKernelGGL(k_trimul, dim3((unsigned)cdiv(ff, 256)), dim3(256), 0, st, w.rb2, w.rb1, f, Rout,
-                     transpose_R);
+  hipLaunchKernelGGL(k_trimul, dim3((unsigned)(cdiv(f, 64) * cdiv(f, 64))), dim3(256), 0, st, w.rb2, w.rb1, f,
+                     Rout, transpose_R);
   LAUNCHCHK();
   if (Zout != X) {
     dim3 grid((unsigned)cdiv(rows, 32), (unsigned)cdiv(f, 32));

@@ -848,57 +848,63 @@ __global__ void k_reduce_cols(const T* __restrict__ parts, int nparts, int64_t s
 }
 
 // ---------------------------------------------------------------------------
-// Y(m x f) -= Q(m x w) * W(w x f)   (Y, Q column-major; W column-major ldw)
-// One thread per row; W staged in LDS in chunks of 64 rows.  w from wlog.
-// With beta == 0: Y = +Q*W (used for U_hat = Q Q_hat).
+// Y (m x f) -= Q (m x w) W (w x f), or Y = Q W without subtract (Y, Q
+// column-major; W column-major ldw).  On MFMA: FP32 operands and
+// accumulation when TW is float, FP64 (f64 MFMA) when TW is double.  A
+// workgroup takes 64 rows and 64 columns of Y (wave: 16 rows x 4 column
+// tiles); W is staged in LDS 64 rows at a time and each wave issues all 16
+// Q loads of a chunk before its MFMAs.  w from wlog when given.
 // ---------------------------------------------------------------------------
-template <typename T, typename TW, int F>
+template <typename T, typename TW>
 __global__ __launch_bounds__(256) void k_update_rows(
     T* __restrict__ Y, int64_t ldy, const T* __restrict__ Q, int64_t ldq, int64_t m, int64_t w,
     int f, const TW* __restrict__ W, int64_t ldw, int subtract,
     const int64_t* __restrict__ wlog, const int32_t* __restrict__ stop_block, int block_id) {
+  typedef Mfma<TW> MF;
+  constexpr int LDS_W = 64 + (sizeof(TW) == 8 ? 1 : 4);
   if (stop_block && *stop_block < block_id) return;
   if (wlog) w = wlog[block_id];
   if (w == 0 && subtract) return;
-  __shared__ TW Ws[64 * F];
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.y * F;          // column tile
-  const int fc = (int)min((int64_t)F, (int64_t)f - c0);
-  TW acc[F];
+  __shared__ TW Ws[64 * LDS_W];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * wv;
+  const int c0 = blockIdx.y * 64;
+  const int fc = (int)min((int64_t)64, (int64_t)f - c0);
+  const int64_t arow = row0 + r;
+  const bool aok = arow < m;
+  typename MF::acc_t acc[4];
 #pragma unroll
-  for (int c = 0; c < F; ++c) acc[c] = 0;
+  for (int u = 0; u < 4; ++u) acc[u] = MF::zero();
   for (int64_t a0 = 0; a0 < w; a0 += 64) {
     const int na = (int)min((int64_t)64, w - a0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < 64 * F; idx += blockDim.x) {
-      const int a = idx / F, c = idx - a * F;
-      Ws[idx] = (a < na && c < fc) ? W[(c0 + c) * ldw + a0 + a] : (TW)0;
+    // this wave's Q operands for the chunk (row arow, columns a0 + 4kk + g)
+    TW qa[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 4 * kk + g;
+      qa[kk] = (aok && k < na) ? (TW)Q[(a0 + k) * ldq + arow] : (TW)0;
     }
     __syncthreads();
-    if (i < m) {
-      int a = 0;
-      for (; a + 8 <= na; a += 8) {
-        TW qv[8];                                 // 8 independent loads in flight
-#pragma unroll
-        for (int q = 0; q < 8; ++q) qv[q] = (TW)Q[(a0 + a + q) * ldq + i];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-#pragma unroll
-          for (int c = 0; c < F; ++c) acc[c] += qv[q] * Ws[(a + q) * F + c];
-      }
-      for (; a < na; ++a) {
-        const TW qv = (TW)Q[(a0 + a) * ldq + i];
-#pragma unroll
-        for (int c = 0; c < F; ++c) acc[c] += qv * Ws[a * F + c];
-      }
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+      const int k = idx >> 6, c = idx & 63;
+      Ws[k * LDS_W + c] = (k < na && c < fc) ? W[(int64_t)(c0 + c) * ldw + a0 + k] : (TW)0;
     }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = MF::op(qa[kk], Ws[(4 * kk + g) * LDS_W + 16 * u + r], acc[u]);
   }
-  if (i < m) {
 #pragma unroll
-    for (int c = 0; c < F; ++c) {
-      if (c < fc) {
-        T* p = Y + (c0 + c) * ldy + i;
-        *p = subtract ? (T)((TW)*p - acc[c]) : (T)acc[c];
+  for (int u = 0; u < 4; ++u) {
+    const int c = 16 * u + r;
+    if (c >= fc) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = row0 + MF::row(g, e);
+      if (row < m) {
+        T* p = Y + (int64_t)(c0 + c) * ldy + row;
+        *p = subtract ? (T)((TW)*p - acc[u][e]) : (T)acc[u][e];
       }
     }
   }
@@ -1191,28 +1197,46 @@ __device__ __forceinline__ void gmm64(const double* A, int lda, const double* B,
                                       Out out) {
   typedef Mfma<double> MF;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  const int TM = (M + 15) / 16, TN = (N + 15) / 16;
-  for (int tile = wv; tile < TM * TN; tile += 4) {
+  const int TM = (M + 15) / 16, TN = (N + 15) / 16, KC = (K + 63) / 64;
+  const int ntile = TM * TN > wv ? (TM * TN - wv + 3) / 4 : 0;   // this wave's tiles: wv, wv + 4, ...
+  const int items = ntile * KC;                                 // (tile, 64-deep chunk) in order
+  // operands of the next item load while the current one computes (two
+  // named buffers keep the register arrays statically indexed)
+  double a0[16], b0[16], a1[16], b1[16];
+  auto load = [&](double(&a)[16], double(&b)[16], int it) {
+    const int tile = wv + 4 * (it / KC), k0 = 64 * (it % KC);
     const int ti = tile / TN, tj = tile - ti * TN;
     const int ar = 16 * ti + r, bc = 16 * tj + r;
-    MF::acc_t acc = MF::zero();
-    for (int k0 = 0; k0 < K; k0 += 64) {
-      double a[16], b[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int kk = k0 + 4 * q + g;
-        const bool ok = kk < K;
-        a[q] = (ok && ar < M) ? (TA ? A[(int64_t)kk * lda + ar] : A[(int64_t)ar * lda + kk]) : 0.0;
-        b[q] = (ok && bc < N) ? (TB ? B[(int64_t)bc * ldb + kk] : B[(int64_t)kk * ldb + bc]) : 0.0;
+    for (int q = 0; q < 16; ++q) {
+      const int kk = k0 + 4 * q + g;
+      const bool ok = kk < K;
+      a[q] = (ok && ar < M) ? (TA ? A[(int64_t)kk * lda + ar] : A[(int64_t)ar * lda + kk]) : 0.0;
+      b[q] = (ok && bc < N) ? (TB ? B[(int64_t)bc * ldb + kk] : B[(int64_t)kk * ldb + bc]) : 0.0;
+    }
+  };
+  typename MF::acc_t acc = MF::zero();
+  auto step = [&](const double(&a)[16], const double(&b)[16], int it) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc = MF::op(a[q], b[q], acc);
+    if (it % KC == KC - 1) {
+      const int tile = wv + 4 * (it / KC);
+      const int ti = tile / TN, tj = tile - ti * TN;
+      const int bc = 16 * tj + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * ti + MF::row(g, e);
+        if (i < M && bc < N) out(i, bc, acc[e]);
       }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc = MF::op(a[q], b[q], acc);
+      acc = MF::zero();
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int i = 16 * ti + MF::row(g, e);
-      if (i < M && bc < N) out(i, bc, acc[e]);
-    }
+  };
+  if (items > 0) load(a0, b0, 0);
+  for (int it = 0; it < items; it += 2) {
+    if (it + 1 < items) load(a1, b1, it + 1);
+    step(a0, b0, it);
+    if (it + 2 < items) load(a0, b0, it + 2);
+    if (it + 1 < items) step(a1, b1, it + 1);
   }
 }
 
@@ -1385,119 +1409,117 @@ __global__ __launch_bounds__(256) void k_small_qr128(const double* __restrict__ 
   if (count_floors && threadIdx.x == 0 && nf && st) atomicAdd(&st->floored, nf);
 }
 
-// LDS (doubles) of chol_inv_blocked.
-constexpr int CHOLB_LDS = 4 * SmallCfg<64>::SIZE + 24 * 64 + 64;
-
 // ---------------------------------------------------------------------------
 // Cholesky with inverse of a symmetric positive semi-definite f x f matrix of
-// any width on one workgroup, right-looking over panels of 64 columns with
-// the pivot rules of chol_inv (the same R as the unblocked elimination up to
-// rounding order; see chol_inv128 for the blocked form of the rules):
-//   R_pp = chol(S_pp) with the floor rule referred to G's own diagonal;
-//   R_pq = R_pp^{-T} S_pq (q > p), rows of non-eliminating pivots and dead
-//          columns zero;
-//   S_qr -= R_pq^T R_pr (p < q <= r);
-// then R^{-1} by block back substitution: (R^{-1})_ic = -R_ii^{-1}
-// sum_{i < k <= c} R_ik (R^{-1})_kc.  G (overwritten by the Schur
-// complements), R, Rinv: global, column-major, leading dimension ld; dg:
-// f doubles (G's diagonal); dead: per-column flags, read unless fresh and
-// written back.  lds: CHOLB_LDS doubles.  Returns the floored pivots.
+// any width, right-looking over panels of 64 columns with the pivot rules of
+// chol_inv (the same R as the unblocked elimination up to rounding order;
+// see chol_inv128 for the blocked form of the rules), R^{-1} by block back
+// substitution.  Each step is a kernel, so the independent block products of
+// a step run on different workgroups (G overwritten by the Schur complements;
+// G, R, Rinv column-major, leading dimension ld; P = ceil(f / 64) panels):
+//   k_cb_init       zero the blocks below the diagonal, dg = diag(G), dead
+//                   flags reset when fresh;
+//   k_cb_diag(p)    one workgroup: R_pp and R_pp^{-1} of the current Schur
+//                   block (floor rule against dg), dead flags of the panel,
+//                   mask of the pivots that did not eliminate -> nolive[p];
+//   k_cb_row(p)     workgroup q - p - 1: R_pq = R_pp^{-T} S_pq, masked;
+//   k_cb_trail(p)   one workgroup per pair p < q <= r: S_qr -= R_pq^T R_pr;
+//   k_cb_inv(d)     workgroup i: (R^{-1})_{i,i+d} = -R_ii^{-1}
+//                   sum_{i<k<=i+d} R_ik (R^{-1})_{k,i+d}; the terms were
+//                   finished by the launches of smaller distance.
 // ---------------------------------------------------------------------------
-__device__ int chol_inv_blocked(double* G, int ld, int f, double* R, double* Rinv, double* dg,
-                                int32_t* dead, int first_pass, int fresh, double* lds) {
+__device__ __forceinline__ int cb_width(int f, int p) { return (f - 64 * p) < 64 ? f - 64 * p : 64; }
+
+__global__ void k_cb_init(const double* __restrict__ G, int ld, int f, double* __restrict__ R,
+                          double* __restrict__ Rinv, double* __restrict__ dg, int32_t* __restrict__ dead, int fresh) {
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)f * f; idx += nt) {
+    const int j = (int)(idx / f), i = (int)(idx - (int64_t)j * f);
+    if (i / 64 > j / 64) {
+      R[(int64_t)j * ld + i] = 0.0;
+      Rinv[(int64_t)j * ld + i] = 0.0;
+    }
+    if (i == j) {
+      dg[i] = G[(int64_t)j * ld + i];
+      if (fresh) dead[i] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cb_diag(const double* __restrict__ G, int ld, int f, int p,
+                                                 double* __restrict__ R, double* __restrict__ Rinv,
+                                                 const double* __restrict__ dg, int32_t* __restrict__ dead,
+                                                 uint64_t* __restrict__ nolive, int first_pass, State* st,
+                                                 int count_floors) {
   typedef SmallCfg<64> S;
   constexpr int LD = S::LD;
-  double* Gs = lds;
-  double* Ri = Gs + S::SIZE;
-  double* Acc = Ri + S::SIZE;
-  double* Tm = Acc + S::SIZE;
-  double* work = Tm + S::SIZE;
-  double* dgs = work + 24 * 64;
-  const int tid = threadIdx.x, P = (f + 63) / 64;
-  auto at = [&](int i, int j) -> int64_t { return (int64_t)j * ld + i; };
-  for (int i = tid; i < f; i += 256) {
-    dg[i] = G[at(i, i)];
-    if (fresh) dead[i] = 0;
-  }
-  // blocks below the diagonal of R and R^{-1} are zero
-  for (int idx = tid; idx < f * f; idx += 256) {
-    const int j = idx / f, i = idx - j * f;
-    if (i / 64 > j / 64) {
-      R[at(i, j)] = 0.0;
-      Rinv[at(i, j)] = 0.0;
-    }
+  __shared__ double Gs[S::SIZE], Ri[S::SIZE], work[24 * 64], dgs[64];
+  const int tid = threadIdx.x, k0 = 64 * p, pw = cb_width(f, p);
+  uint64_t dm = 0, dmo = 0, nl = 0;
+  for (int c = 0; c < pw; ++c) dm |= (uint64_t)(dead[k0 + c] != 0) << c;
+  for (int idx = tid; idx < pw * pw; idx += 256) {
+    const int i = idx / pw, j = idx - i * pw;
+    Gs[i * LD + j] = G[(int64_t)(k0 + j) * ld + k0 + i];
   }
   __syncthreads();
   int nf = 0;
-  for (int p = 0; p < P; ++p) {
-    const int k0 = 64 * p, pw = (f - k0) < 64 ? f - k0 : 64;
-    uint64_t dm = 0, dmo = 0, nl = 0;
-    for (int c = 0; c < pw; ++c) dm |= (uint64_t)(dead[k0 + c] != 0) << c;
-    for (int idx = tid; idx < pw * pw; idx += 256) {
-      const int i = idx / pw, j = idx - i * pw;
-      Gs[i * LD + j] = G[at(k0 + i, k0 + j)];
-    }
-    __syncthreads();
-    int nfp = 0;
-    chol_inv<64>(Gs, Ri, work, dgs, pw, dm, first_pass, &dmo, &nfp, dg + k0, &nl);
-    nf += nfp;
-    for (int idx = tid; idx < pw * pw; idx += 256) {
-      const int i = idx / pw, j = idx - i * pw;
-      R[at(k0 + i, k0 + j)] = Gs[i * LD + j];
-      Rinv[at(k0 + i, k0 + j)] = Ri[i * LD + j];
-    }
-    for (int c = tid; c < pw; c += 256) dead[k0 + c] = (int32_t)((dmo >> c) & 1ull);
-    __syncthreads();
-    // row panel R_pq = R_pp^{-T} S_pq
-    for (int q = p + 1; q < P; ++q) {
-      const int c0 = 64 * q, qw = (f - c0) < 64 ? f - c0 : 64;
-      gmm64<true, true>(Ri, LD, G + (int64_t)c0 * ld + k0, ld, pw, qw, pw, [&](int i, int j, double v) {
-        const bool z = ((nl >> i) & 1ull) || dead[c0 + j] != 0;
-        R[at(k0 + i, c0 + j)] = z ? 0.0 : v;
-      });
-    }
-    __syncthreads();
-    // trailing update S_qr -= R_pq^T R_pr
-    for (int q = p + 1; q < P; ++q)
-      for (int r = q; r < P; ++r) {
-        const int cq = 64 * q, cr = 64 * r;
-        const int qw = (f - cq) < 64 ? f - cq : 64, rw = (f - cr) < 64 ? f - cr : 64;
-        gmm64<false, true>(R + (int64_t)cq * ld + k0, ld, R + (int64_t)cr * ld + k0, ld, qw, rw, pw,
-                           [&](int i, int j, double v) { G[at(cq + i, cr + j)] -= v; });
-      }
-    __syncthreads();
+  chol_inv<64>(Gs, Ri, work, dgs, pw, dm, first_pass, &dmo, &nf, dg + k0, &nl);
+  for (int idx = tid; idx < pw * pw; idx += 256) {
+    const int i = idx / pw, j = idx - i * pw;
+    R[(int64_t)(k0 + j) * ld + k0 + i] = Gs[i * LD + j];
+    Rinv[(int64_t)(k0 + j) * ld + k0 + i] = Ri[i * LD + j];
   }
-  // R^{-1} above the diagonal blocks, column block by column block
-  for (int c = 1; c < P; ++c) {
-    const int cc = 64 * c, cw = (f - cc) < 64 ? f - cc : 64;
-    for (int i = c - 1; i >= 0; --i) {
-      const int ci = 64 * i;
-      for (int k = i + 1; k <= c; ++k) {
-        const int ck = 64 * k, kw = (f - ck) < 64 ? f - ck : 64;
-        const bool first = k == i + 1;
-        gmm64<true, true>(R + (int64_t)ck * ld + ci, ld, Rinv + (int64_t)cc * ld + ck, ld, 64, cw, kw,
-                          [&](int a, int j, double v) { Acc[a * LD + j] = first ? v : Acc[a * LD + j] + v; });
-        __syncthreads();
-      }
-      gmm64<true, false>(Rinv + (int64_t)ci * ld + ci, ld, Acc, LD, 64, cw, 64,
-                         [&](int a, int j, double v) { Rinv[at(ci + a, cc + j)] = -v; });
-      __syncthreads();
-    }
+  for (int c = tid; c < pw; c += 256) dead[k0 + c] = (int32_t)((dmo >> c) & 1ull);
+  if (tid == 0) {
+    nolive[p] = nl;
+    if (count_floors && nf && st) atomicAdd(&st->floored, nf);
   }
-  return nf;
 }
 
-// Cholesky with inverse (chol_inv_blocked) of an f x f Gram matrix of any
-// width on one workgroup: G (overwritten), R, R^{-1} column-major f x f;
-// dead: per-column flags (read unless fresh, written back); floored pivots
-// added to st->floored when count_floors.
-__global__ __launch_bounds__(256) void k_chol_big(double* __restrict__ G, int f, double* __restrict__ R,
-                                                  double* __restrict__ Rinv, double* __restrict__ dg,
-                                                  int32_t* __restrict__ dead, int first_pass, int fresh, State* st,
-                                                  int count_floors) {
-  __shared__ double lds[CHOLB_LDS];
-  const int nf = chol_inv_blocked(G, f, f, R, Rinv, dg, dead, first_pass, fresh, lds);
-  if (count_floors && threadIdx.x == 0 && nf && st) atomicAdd(&st->floored, nf);
+__global__ __launch_bounds__(256) void k_cb_row(const double* __restrict__ G, int ld, int f, int p,
+                                                double* __restrict__ R, const double* __restrict__ Rinv,
+                                                const int32_t* __restrict__ dead, const uint64_t* __restrict__ nolive) {
+  const int q = p + 1 + blockIdx.x, k0 = 64 * p, c0 = 64 * q;
+  const int pw = cb_width(f, p), qw = cb_width(f, q);
+  const uint64_t nl = nolive[p];
+  // op(A)(i,k) = (R_pp^{-1})(k,i): column-major at (k0+i)*ld + k0+k
+  gmm64<false, true>(Rinv + (int64_t)k0 * ld + k0, ld, G + (int64_t)c0 * ld + k0, ld, pw, qw, pw,
+                     [&](int i, int j, double v) {
+                       const bool z = ((nl >> i) & 1ull) || dead[c0 + j] != 0;
+                       R[(int64_t)(c0 + j) * ld + k0 + i] = z ? 0.0 : v;
+                     });
+}
+
+__global__ __launch_bounds__(256) void k_cb_trail(double* __restrict__ G, int ld, int f, int p,
+                                                  const double* __restrict__ R) {
+  // pair index -> (q, r), p < q <= r < P, enumerated row by row
+  const int P = (f + 63) / 64;
+  int idx = blockIdx.x, q = p + 1;
+  while (idx >= P - q) {
+    idx -= P - q;
+    ++q;
+  }
+  const int r = q + idx;
+  const int k0 = 64 * p, cq = 64 * q, cr = 64 * r;
+  const int pw = cb_width(f, p), qw = cb_width(f, q), rw = cb_width(f, r);
+  gmm64<false, true>(R + (int64_t)cq * ld + k0, ld, R + (int64_t)cr * ld + k0, ld, qw, rw, pw,
+                     [&](int i, int j, double v) { G[(int64_t)(cr + j) * ld + cq + i] -= v; });
+}
+
+__global__ __launch_bounds__(256) void k_cb_inv(const double* __restrict__ R, double* __restrict__ Rinv, int ld,
+                                                int f, int d) {
+  constexpr int LD = SmallCfg<64>::LD;
+  __shared__ double Acc[64 * LD];
+  const int i = blockIdx.x, c = i + d, ci = 64 * i, cc = 64 * c, cw = cb_width(f, c);
+  for (int k = i + 1; k <= c; ++k) {
+    const int ck = 64 * k, kw = cb_width(f, k);
+    const bool first = k == i + 1;
+    gmm64<true, true>(R + (int64_t)ck * ld + ci, ld, Rinv + (int64_t)cc * ld + ck, ld, 64, cw, kw,
+                      [&](int a, int j, double v) { Acc[a * LD + j] = first ? v : Acc[a * LD + j] + v; });
+    __syncthreads();
+  }
+  gmm64<true, false>(Rinv + (int64_t)ci * ld + ci, ld, Acc, LD, 64, cw, 64,
+                     [&](int a, int j, double v) { Rinv[(int64_t)(cc + j) * ld + ci + a] = -v; });
 }
 
 // Arguments of the Cholesky that closes a Gram pass (k_gram_rows, and the
@@ -2008,17 +2030,25 @@ __global__ void k_zero(T* __restrict__ p, int64_t count) {
 }
 
 // R = R2 * R1 (upper triangular f x f, element (i,j) at j*f+i).  Writes the
-// product transposed if transpose_out (element (i,j) of R at i*f + j).
-__global__ void k_trimul(const double* __restrict__ R2, const double* __restrict__ R1, int f,
-                         double* __restrict__ out, int transpose_out) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)f * f) return;
-  const int j = (int)(idx / f), i = (int)(idx - (int64_t)j * f);
-  double v = 0.0;
-  if (i <= j)
-    for (int k = i; k <= j; ++k) v += R2[(int64_t)k * f + i] * R1[(int64_t)j * f + k];
-  if (transpose_out) out[(int64_t)i * f + j] = v;
-  else out[idx] = v;
+// product transposed if transpose_out (element (i,j) of R at i*f + j).  One
+// workgroup per 64 x 64 tile of the product (grid P x P, P = ceil(f / 64)),
+// the sum over k restricted to [i0, j0 + 64) where both factors can be
+// non-zero; tiles below the diagonal are zero.
+__global__ __launch_bounds__(256) void k_trimul(const double* __restrict__ R2, const double* __restrict__ R1,
+                                                int f, double* __restrict__ out, int transpose_out) {
+  const int P = (f + 63) / 64, bi = blockIdx.x % P, bj = blockIdx.x / P;
+  const int i0 = 64 * bi, j0 = 64 * bj;
+  const int mi = (f - i0) < 64 ? f - i0 : 64, nj = (f - j0) < 64 ? f - j0 : 64;
+  auto put = [&](int i, int j, double v) {
+    if (transpose_out) out[(int64_t)(i0 + i) * f + j0 + j] = v;
+    else out[(int64_t)(j0 + j) * f + i0 + i] = v;
+  };
+  if (bi > bj) {
+    for (int idx = threadIdx.x; idx < mi * nj; idx += 256) put(idx / nj, idx % nj, 0.0);
+    return;
+  }
+  const int k0 = i0, K = j0 + nj - i0;
+  gmm64<true, true>(R2 + (int64_t)k0 * f + i0, f, R1 + (int64_t)j0 * f + k0, f, mi, nj, K, put);
 }
 
 // Generic 2-D copy with optional transpose and type conversion:

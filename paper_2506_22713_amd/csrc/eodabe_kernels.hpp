@@ -27,6 +27,13 @@ constexpr double U64 = 1.1102230246251565e-16;   // 2^-53
 constexpr double FLOOR_C = 64.0;                 // pivot floor: FLOOR_C * u64 * G(k,k)
 constexpr double PIV_MIN = 1e-290;               // smaller pivots count as non-positive (1/p overflows)
 
+// Largest divisor of n that is at most 8 (loads per batch).
+constexpr int batch_of(int n) {
+  for (int b = 8; b > 1; --b)
+    if (n % b == 0) return b;
+  return 1;
+}
+
 // Control block shared by the kernels of one factorization (device memory).
 struct State {
   double eps;            // tol * ||A||_F
@@ -403,25 +410,47 @@ __global__ __launch_bounds__(256) void k_sketch(
 #pragma unroll
     for (int u = 0; u < CT; ++u) acc[t][u] = MF::zero();
   const bool active = (m0 < M);
+  // A chunks in flight: the first slab's four are requested before its
+  // Omega staging, so the two memory latencies overlap
+  V4<T> a[4][RT];
+  {
+    const int nfull0 = (int)(min(ke, kb + KS) - kb) / 16;
+    if (active)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nfull0)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + kb + 16 * q);
+  }
   for (int64_t sb = kb; sb < ke; sb += KS) {
     const int64_t se = min(ke, sb + KS);
     const int slen = (int)(se - sb);
     __syncthreads();
-    // stage Omega^T[0:NC, sb:se] (zero beyond se)
-    for (int idx = tid; idx < NC * (KS / 4); idx += 256) {
-      const int c = idx / (KS / 4), k4 = (idx - c * (KS / 4)) * 4;
-      V4<T> v;
-      if (c >= N) {
+    // stage Omega^T[0:NC, sb:se] (zero beyond se and N), a thread's loads
+    // all in flight before its LDS stores
+    constexpr int NST = NC * (KS / 4) / 256, NB = batch_of(NST);
+    static_assert(NC * (KS / 4) % 256 == 0 && NST % NB == 0, "staging split");
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v.v[e] = (T)0;
-      } else if (k4 + 3 < slen) {
-        v = ld4(Om + (int64_t)c * ldk + sb + k4);
-      } else {
+    for (int q0 = 0; q0 < NST; q0 += NB) {
+      V4<T> sv[NB];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v.v[e] = (k4 + e < slen) ? Om[(int64_t)c * ldk + sb + k4 + e] : (T)0;
+      for (int q = 0; q < NB; ++q) {
+        const int idx = tid + 256 * (q0 + q);
+        const int c = idx / (KS / 4), k4 = (idx - c * (KS / 4)) * 4;
+        const T* src = Om + (int64_t)(c < N ? c : 0) * ldk + sb + k4;
+        if (c < N && k4 + 3 < slen) sv[q] = ld4(src);
+        else if (c < N) sv[q] = ld4_masked(src, k4, slen);
+        else
+#pragma unroll
+          for (int e = 0; e < 4; ++e) sv[q].v[e] = (T)0;
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) oms[c * LDO + k4 + e] = v.v[e];
+      for (int q = 0; q < NB; ++q) {
+        const int idx = tid + 256 * (q0 + q);
+        const int c = idx / (KS / 4), k4 = (idx - c * (KS / 4)) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) oms[c * LDO + k4 + e] = sv[q].v[e];
+      }
     }
     __syncthreads();
     if (!active) continue;
@@ -471,13 +500,14 @@ __global__ __launch_bounds__(256) void k_sketch(
         }
       }
     };
-    // 4-deep register pipeline over the full 16-K chunks of this slab
-    V4<T> a[4][RT];
+    // 4-deep register pipeline over the full 16-K chunks of this slab (the
+    // first slab's chunks were requested before the staging)
+    if (sb != kb)
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (q < nfull)
+      for (int q = 0; q < 4; ++q)
+        if (q < nfull)
 #pragma unroll
-        for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * q);
+          for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * q);
     for (int c = 0; c < nfull; c += 4) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -606,24 +636,33 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
     const int64_t se = min(ke, sb + KS);
     const int slen = (int)(se - sb);
     __syncthreads();
-    // stage Omega^T[0:NC, sb:se] rounded to the low precision (zero beyond se and N)
-    for (int idx = tid; idx < NC * (KS / 4); idx += 256) {
-      const int c = idx / (KS / 4), k4 = (idx - c * (KS / 4)) * 4;
-      float v[4];
-      if (c >= N) {
+    // stage Omega^T[0:NC, sb:se] rounded to the low precision (zero beyond
+    // se and N), a thread's loads all in flight before its LDS stores
+    constexpr int NST = NC * (KS / 4) / 256, NB = batch_of(NST);
+    static_assert(NC * (KS / 4) % 256 == 0 && NST % NB == 0, "staging split");
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = 0.f;
-      } else if (k4 + 3 < slen) {
-        const f32x4 x = *reinterpret_cast<const f32x4*>(Om + (int64_t)c * ldk + sb + k4);
-        v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
-      } else {
+    for (int q0 = 0; q0 < NST; q0 += NB) {
+      V4<float> sv[NB];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (k4 + e < slen) ? Om[(int64_t)c * ldk + sb + k4 + e] : 0.f;
+      for (int q = 0; q < NB; ++q) {
+        const int idx = tid + 256 * (q0 + q);
+        const int c = idx / (KS / 4), k4 = (idx - c * (KS / 4)) * 4;
+        const float* src = Om + (int64_t)(c < N ? c : 0) * ldk + sb + k4;
+        if (c < N && k4 + 3 < slen) sv[q] = ld4(src);
+        else if (c < N) sv[q] = ld4_masked(src, k4, slen);
+        else
+#pragma unroll
+          for (int e = 0; e < 4; ++e) sv[q].v[e] = 0.f;
       }
-      uint2 pk;
-      pk.x = (uint32_t)to_lp_bits<LPT>(v[0]) | ((uint32_t)to_lp_bits<LPT>(v[1]) << 16);
-      pk.y = (uint32_t)to_lp_bits<LPT>(v[2]) | ((uint32_t)to_lp_bits<LPT>(v[3]) << 16);
-      *reinterpret_cast<uint2*>(&oms[c * LDO + k4]) = pk;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int idx = tid + 256 * (q0 + q);
+        const int c = idx / (KS / 4), k4 = (idx - c * (KS / 4)) * 4;
+        uint2 pk;
+        pk.x = (uint32_t)to_lp_bits<LPT>(sv[q].v[0]) | ((uint32_t)to_lp_bits<LPT>(sv[q].v[1]) << 16);
+        pk.y = (uint32_t)to_lp_bits<LPT>(sv[q].v[2]) | ((uint32_t)to_lp_bits<LPT>(sv[q].v[3]) << 16);
+        *reinterpret_cast<uint2*>(&oms[c * LDO + k4]) = pk;
+      }
     }
     __syncthreads();
     if (!active) continue;
@@ -705,16 +744,23 @@ __global__ __launch_bounds__(256) void k_sketch_lp(
 // C = Q^T A (X = Q^T, i.e. Q column-major; Z = A).  out_s row-major
 // (element (m, j) at s*part_stride + m*ldo + j).
 // Lane l loads rows k0+4g+v (v = 0..3) of Z at columns j0+4r .. 4r+3, so a
-// wave covers 16 K-rows x 64 columns with dwordx4 loads; MFMA tile u (0..3)
-// holds columns j0 + 4j + u.  Each wave computes 16*RT rows of out.
-// Workgroup = 4 waves = 4 consecutive 64-column panels.
+// wave covers a 16-row step x 64 columns with dwordx4 loads; MFMA tile u
+// (0..3) holds columns j0 + 4j + u.  Each wave computes 16*RT rows of out
+// and keeps PF of its steps in flight in registers.  Workgroup = 4 waves =
+// 4 consecutive 64-column panels.
 // ---------------------------------------------------------------------------
+template <typename T, int RT>
+struct NnCfg {
+  static constexpr int PF = sizeof(T) == 4 ? (RT <= 2 ? 4 : 3) : (RT <= 2 ? 3 : 2);
+};
+
 template <typename T, int RT>
 __global__ __launch_bounds__(256) void k_gemm_nn(
     const T* __restrict__ X, int64_t ldx, const T* __restrict__ Z, int64_t ldz,
     int64_t M, int64_t N, int64_t K, int64_t kchunk, T* __restrict__ out, int64_t ldo,
     int64_t part_stride, Gate gate, const int64_t* __restrict__ M_dev) {
   typedef Mfma<T> MF;
+  constexpr int PF = NnCfg<T, RT>::PF;
   if (gate_shut(gate)) return;
   if (M_dev) M = *M_dev;                // row count known on the device only
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -737,12 +783,11 @@ __global__ __launch_bounds__(256) void k_gemm_nn(
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
-  for (int64_t k = kb; k < ke; k += 16) {
+  // one 16-row step at k: X chunk (masked past ke) and Z rows k+4g+v
+  auto load = [&](V4<T>(&a)[RT], V4<T>(&zv)[4], int64_t k) {
     const bool full = (k + 16 <= ke);
-    V4<T> a[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) a[t] = full ? ld4(xp[t] + k) : ld4_masked(xp[t] + k, k + 4 * g, ke);
-    V4<T> zv[4];                       // zv[v].v[u] = Z[k+4g+v][jc+u]
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t kr = k + 4 * g + v;
@@ -753,12 +798,28 @@ __global__ __launch_bounds__(256) void k_gemm_nn(
         for (int u = 0; u < 4; ++u) zv[v].v[u] = (kr < ke && jc + u < N) ? Z[kr * ldz + jc + u] : (T)0;
       }
     }
+  };
+  auto mma = [&](const V4<T>(&a)[RT], const V4<T>(&zv)[4]) {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(a[t].v[v], zv[v].v[u], acc[t][u]);
+  };
+  const int64_t nstep = (ke - kb + 15) / 16;         // the last step may be ragged
+  V4<T> ab[PF][RT], zb[PF][4];
+#pragma unroll
+  for (int q = 0; q < PF; ++q)
+    if (q < nstep) load(ab[q], zb[q], kb + 16 * q);
+  for (int64_t i = 0; i < nstep; i += PF) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      if (i + q < nstep) {
+        mma(ab[q], zb[q]);
+        if (i + q + PF < nstep) load(ab[q], zb[q], kb + 16 * (i + q + PF));
+      }
+    }
   }
   T* o = out + (int64_t)s * part_stride;
 #pragma unroll
@@ -923,6 +984,34 @@ struct SmallCfg {
   static constexpr int NR = F / 4;                // elimination: rows held per wave
   static constexpr int NCL = (2 * F + 63) / 64;   // elimination: columns of [G | I] per lane
 };
+
+// Up to two f x f FP64 matrices src[h] (element (i, j) at j*f + i) into LDS
+// as dst[h][i*ld + j], zero outside f x f (f <= F <= 64, 256 threads); a
+// thread's loads are all in flight before its first LDS store, so the
+// staging costs one memory round trip.
+template <int F, int NM = 1>
+__device__ __forceinline__ void stage_small(const double* const (&src)[NM], int f, double* const (&dst)[NM],
+                                            int ld) {
+  static_assert(F <= 64, "register budget");
+  constexpr int NQ = (F * F + 255) / 256;
+  double v[NM][NQ];
+#pragma unroll
+  for (int h = 0; h < NM; ++h)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int jj = idx / F, i = idx - jj * F;
+      v[h][q] = (idx < F * F && i < f && jj < f) ? src[h][(int64_t)jj * f + i] : 0.0;
+    }
+#pragma unroll
+  for (int h = 0; h < NM; ++h)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int jj = idx / F, i = idx - jj * F;
+      if (idx < F * F) dst[h][i * ld + jj] = v[h][q];
+    }
+}
 
 // C = op(A) op(B) for F x F FP64 matrices in LDS on the four waves of the
 // workgroup (v_mfma_f64_16x16x4, one 16 x 16 tile per wave at a time);
@@ -1600,12 +1689,7 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   double* pz = ph + Cfg::XD;                          // MODE 1: Z panel: pz[c*LDZ + row]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
-  if constexpr (MODE == 1) {
-    for (int idx = tid; idx < F * F; idx += 256) {
-      const int i = idx / F, jj = idx - i * F;
-      Wl[i * LD + jj] = (i < f && jj < f) ? Wg[(int64_t)jj * f + i] : 0.0;
-    }
-  }
+  if constexpr (MODE == 1) stage_small<F>({Wg}, f, {Wl}, LD);
   typename MF::acc_t acc[TT][TT];
 #pragma unroll
   for (int t = 0; t < TT; ++t)
@@ -1773,9 +1857,20 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   if (ca.norm_parts && wv == 0) {    // ||A||_F from the sketch partials (fixed order)
     double a = 0.0;
     float mx = 0.0f;
-    for (int64_t i = lane; i < ca.n_norm; i += 64) {
-      a += ca.norm_parts[i];
-      if (ca.max_parts) mx = fmaxf(mx, ca.max_parts[i]);
+    for (int64_t i0 = 0; i0 < ca.n_norm; i0 += 64 * 8) {   // 8 loads per lane in flight
+      double pv[8];
+      float mv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t i = i0 + lane + 64 * q;
+        pv[q] = i < ca.n_norm ? ca.norm_parts[i] : 0.0;
+        mv[q] = (ca.max_parts && i < ca.n_norm) ? ca.max_parts[i] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (i0 + lane + 64 * q < ca.n_norm) a += pv[q];
+        mx = fmaxf(mx, mv[q]);
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
       a += __shfl_xor(a, off);
@@ -1863,10 +1958,6 @@ __global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
   const int f = jb.f_dev ? (int)*jb.f_dev : jb.f;
   if (f > F) return;                    // cannot happen: the launch width bounds the rank
-  for (int idx = tid; idx < F * F; idx += 256) {
-    const int i = idx / F, jj = idx - i * F;
-    Wl[i * LD + jj] = (i < f && jj < f) ? jb.W[(int64_t)jj * f + i] : 0.0;
-  }
   const int ncols = jb.f_dev ? f : (jb.ncols_dev ? jb.ncols_dev[block_id] : jb.ncols);
   const int64_t zoff = jb.zoff_dev ? jb.zoff_dev[block_id] : jb.zoff;
   const T* X = reinterpret_cast<const T*>(jb.X);
@@ -1874,12 +1965,24 @@ __global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
   const int64_t rbase = row0 + 16 * wv;
   const int64_t arow = rbase + r;
   const bool aok = arow < jb.rows;
-  double a[KS];
+  // X rows requested first, then W: both round trips overlap
+  T xa[KS];
 #pragma unroll
   for (int kk = 0; kk < KS; ++kk) {
     const int k = 4 * kk + g;
-    a[kk] = (aok && k < f) ? (double)X[(int64_t)k * jb.ldx + arow] : 0.0;
+    xa[kk] = (aok && k < f) ? X[(int64_t)k * jb.ldx + arow] : (T)0;
   }
+  if constexpr (F <= 64) {
+    stage_small<F>({jb.W}, f, {Wl}, LD);
+  } else {
+    for (int idx = tid; idx < F * F; idx += 256) {
+      const int i = idx / F, jj = idx - i * F;
+      Wl[i * LD + jj] = (i < f && jj < f) ? jb.W[(int64_t)jj * f + i] : 0.0;
+    }
+  }
+  double a[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) a[kk] = (double)xa[kk];
   __syncthreads();
   typename MF::acc_t z[TT];
 #pragma unroll
@@ -1921,13 +2024,8 @@ __global__ __launch_bounds__(256) void k_small_qr(const double* __restrict__ R1g
   __shared__ double B0[S::SIZE], B1[S::SIZE], B2[S::SIZE], B3[S::SIZE];
   __shared__ double rowbuf[24 * F], dgs[F];
   const int tid = threadIdx.x;
-  double* Mt = R1g ? B1 : B0;
-  for (int idx = tid; idx < F * F; idx += 256) {
-    const int i = idx / F, jj = idx - i * F;
-    const bool ok = i < f && jj < f;
-    Mt[i * LD + jj] = ok ? R2g[(int64_t)jj * f + i] : 0.0;
-    if (R1g) B2[i * LD + jj] = ok ? R1g[(int64_t)jj * f + i] : 0.0;
-  }
+  if (R1g) stage_small<F, 2>({R2g, R1g}, f, {B1, B2}, LD);
+  else stage_small<F>({R2g}, f, {B0}, LD);
   __syncthreads();
   if (R1g) {
     lds_gemm<F, false, false>(B1, B2, [&](int i, int jj, double v) { B0[i * LD + jj] = v; });  // M

@@ -412,15 +412,17 @@ __global__ __launch_bounds__(256) void k_sketch(
   const bool active = (m0 < M);
   // A chunks in flight: the first slab's four are requested before its
   // Omega staging, so the two memory latencies overlap
+  // (chunk indices past the slab's last full chunk are clamped to it: the
+  // loads stay unconditional, so the wait counts stay exact, and the
+  // duplicates are never used)
   V4<T> a[4][RT];
   {
     const int nfull0 = (int)(min(ke, kb + KS) - kb) / 16;
-    if (active)
+    if (active && nfull0 > 0)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (q < nfull0)
 #pragma unroll
-          for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + kb + 16 * q);
+        for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + kb + 16 * min(q, nfull0 - 1));
   }
   for (int64_t sb = kb; sb < ke; sb += KS) {
     const int64_t se = min(ke, sb + KS);
@@ -501,24 +503,34 @@ __global__ __launch_bounds__(256) void k_sketch(
       }
     };
     // 4-deep register pipeline over the full 16-K chunks of this slab (the
-    // first slab's chunks were requested before the staging)
-    if (sb != kb)
+    // first slab's chunks were requested before the staging).  The steady
+    // state has no branches, so each chunk waits only for its own loads.
+    if (sb != kb && nfull > 0)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (q < nfull)
 #pragma unroll
-          for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * q);
-    for (int c = 0; c < nfull; c += 4) {
+        for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * min(q, nfull - 1));
+    int c = 0;
+    for (; c + 8 <= nfull; c += 4) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (c + q < nfull) {
-          compute(a[q], 16 * (c + q));
-          if (c + q + 4 < nfull)
+        compute(a[q], 16 * (c + q));
 #pragma unroll
-            for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * (c + q + 4));
-        }
+        for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * (c + q + 4));
       }
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {            // last one or two groups (fewer than 8 chunks left)
+      if (c + q < nfull) {
+        compute(a[q], 16 * (c + q));
+        if (c + q + 4 < nfull)
+#pragma unroll
+          for (int t = 0; t < RT; ++t) a[q][t] = ld4(ap[t] + sb + 16 * (c + q + 4));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (c + 4 + q < nfull) compute(a[q], 16 * (c + 4 + q));
     if (nfull * 16 < slen) {                  // ragged tail of the slab
       V4<T> at[RT];
       const int64_t k = sb + 16 * nfull;
@@ -807,18 +819,50 @@ __global__ __launch_bounds__(256) void k_gemm_nn(
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(a[t].v[v], zv[v].v[u], acc[t][u]);
   };
-  const int64_t nstep = (ke - kb + 15) / 16;         // the last step may be ragged
-  V4<T> ab[PF][RT], zb[PF][4];
+  // one full step at k in a full panel: no masks
+  auto loadf = [&](V4<T>(&a)[RT], V4<T>(&zv)[4], int64_t k) {
 #pragma unroll
-  for (int q = 0; q < PF; ++q)
-    if (q < nstep) load(ab[q], zb[q], kb + 16 * q);
-  for (int64_t i = 0; i < nstep; i += PF) {
+    for (int t = 0; t < RT; ++t) a[t] = ld4(xp[t] + k);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) zv[v] = ld4(Z + (k + 4 * g + v) * ldz + jc);
+  };
+  const int64_t nfull = (ke - kb) / 16;
+  if (j0 + 64 <= N && nfull > 0) {
+    // PF-deep ring over the full steps; the steady state has no branches,
+    // so each step waits only for its own loads (step indices past the last
+    // full step are clamped to it in the prologue and never used)
+    V4<T> ab[PF][RT], zb[PF][4];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) loadf(ab[q], zb[q], kb + 16 * min((int64_t)q, nfull - 1));
+    int64_t i = 0;
+    for (; i + 2 * PF <= nfull; i += PF) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        mma(ab[q], zb[q]);
+        loadf(ab[q], zb[q], kb + 16 * (i + q + PF));
+      }
+    }
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-      if (i + q < nstep) {
+      if (i + q < nfull) {
         mma(ab[q], zb[q]);
-        if (i + q + PF < nstep) load(ab[q], zb[q], kb + 16 * (i + q + PF));
+        if (i + q + PF < nfull) loadf(ab[q], zb[q], kb + 16 * (i + q + PF));
       }
+    }
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+      if (i + PF + q < nfull) mma(ab[q], zb[q]);
+    if (kb + 16 * nfull < ke) {               // ragged last step
+      V4<T> a1[RT], z1[4];
+      load(a1, z1, kb + 16 * nfull);
+      mma(a1, z1);
+    }
+  } else {
+    // partial panel (or no full step): one masked step at a time
+    for (int64_t k = kb; k < ke; k += 16) {
+      V4<T> a1[RT], z1[4];
+      load(a1, z1, k);
+      mma(a1, z1);
     }
   }
   T* o = out + (int64_t)s * part_stride;

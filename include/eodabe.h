@@ -71,7 +71,10 @@ typedef struct eodabe_info {
   int64_t rank;          /* r: columns accepted by Alg. 1                                     */
   int     blocks;        /* basis blocks executed (J)                                         */
   int     status_flags;  /* bit 0: tol below floor (WTOL_FLOOR); bit 1: A was transposed (m<n);
-                            bit 2: a Cholesky pivot was floored in the final QRs              */
+                            bit 2: a Cholesky pivot was floored in the final QRs;
+                            bit 3: a low-precision sketch was requested with tol below 2 u_lp
+                            (u_lp = 2^-11 FP16, 2^-8 BF16), where its rounding noise would mask
+                            the stop test; every block sketched in FP32 (the plain path)      */
   double  norm_a;        /* ||A||_F (FP64 accumulation)                                       */
   double  eps;           /* tol * ||A||_F, the absolute stopping threshold                    */
 } eodabe_info;

@@ -1688,6 +1688,18 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
     info->status_flags |= 1;
   }
   if (g.transposed) info->status_flags |= 2;
+  // A low-precision sketch column carries rounding noise of about
+  // u_lp ||A||_F / sqrt(3) in its component orthogonal to the basis, the
+  // quantity the stop test of Alg. 1 compares with tol ||A||_F: below
+  // tol = 2 u_lp (u_lp = 2^-11 FP16, 2^-8 BF16) the test could not fire on
+  // such sketches, so the blocks sketch in FP32 (the plain path) instead.
+  if (g.lp) {
+    const double ulp = g.lp == EODABE_SKETCH_F16 ? 0x1p-11 : 0x1p-8;
+    if (tol < 2.0 * ulp) {
+      g.lp = 0;
+      info->status_flags |= 8;
+    }
+  }
   int64_t rank = 0;
   int blocks = 0;
   double norm_a = 0.0;

@@ -412,6 +412,31 @@ def test_factor_f16_sketch_exact_rank():
     assert f.rank == 40
 
 
+@pytest.mark.parametrize("mode,tol", [("bf16", 1e-3), ("f16", 5e-4)])
+def test_lp_sketch_below_its_floor_runs_plain(mode, tol):
+    say("lp sketch below its noise floor", mode, tol)
+    # below tol = 2 u_lp the low-precision sketch would mask the stop test
+    # (its rounding noise sits above tol ||A||_F): every block sketches in
+    # FP32, flag bit 3, and the result is the plain path's bit for bit
+    A = dev(W.lowrank_haar(9, m=700, n=500, r=90, noise_std=1e-9).astype(np.float64), torch.float32)
+    code = E.SKETCH_F16 if mode == "f16" else E.SKETCH_BF16
+    f = E.factor(A, tol, block=16, seed=5, sketch=code)
+    p = E.factor(A, tol, block=16, seed=5)
+    torch.cuda.synchronize()
+    assert f.flags & 8 and not (p.flags & 8)
+    assert f.blocks >= 3 and f.rank == p.rank
+    for x, y in ((f.U, p.U), (f.D, p.D), (f.Vt, p.Vt)):
+        assert torch.equal(x, y)
+
+
+def test_lp_sketch_at_its_floor_keeps_low_precision():
+    say("lp sketch at its floor")
+    A = dev(W.lowrank_haar(9, m=700, n=500, r=90, noise_std=1e-9).astype(np.float64), torch.float32)
+    f = E.factor(A, 2.0 ** -10, block=16, seed=5, sketch=E.SKETCH_F16)
+    torch.cuda.synchronize()
+    assert not (f.flags & 8)
+
+
 # ------------------------------------------------- batched tiles
 def _batch_tiles():
     tiles = W.tiles(5, count=22, lo=64, hi=1024, rank_lo=5, rank_hi=80, noise_std=1e-4)

@@ -1029,15 +1029,16 @@ struct SmallCfg {
   static constexpr int NCL = (2 * F + 63) / 64;   // elimination: columns of [G | I] per lane
 };
 
-// Up to two f x f FP64 matrices src[h] (element (i, j) at j*f + i) into LDS
-// as dst[h][i*ld + j], zero outside f x f (f <= F <= 64, 256 threads); a
-// thread's loads are all in flight before its first LDS store, so the
-// staging costs one memory round trip.
+// Up to two f x f FP64 matrices src[h] (element (i, j) at j*ld_src + i,
+// ld_src = f unless given) into LDS as dst[h][i*ld + j], zero outside f x f
+// (f <= F <= 64, 256 threads); a thread's loads are all in flight before its
+// first LDS store, so the staging costs one memory round trip.
 template <int F, int NM = 1>
 __device__ __forceinline__ void stage_small(const double* const (&src)[NM], int f, double* const (&dst)[NM],
-                                            int ld) {
+                                            int ld, int ld_src = 0) {
   static_assert(F <= 64, "register budget");
   constexpr int NQ = (F * F + 255) / 256;
+  const int64_t lsrc = ld_src > 0 ? ld_src : f;   // source leading dimension (f when packed)
   double v[NM][NQ];
 #pragma unroll
   for (int h = 0; h < NM; ++h)
@@ -1045,7 +1046,7 @@ __device__ __forceinline__ void stage_small(const double* const (&src)[NM], int 
     for (int q = 0; q < NQ; ++q) {
       const int idx = threadIdx.x + 256 * q;
       const int jj = idx / F, i = idx - jj * F;
-      v[h][q] = (idx < F * F && i < f && jj < f) ? src[h][(int64_t)jj * f + i] : 0.0;
+      v[h][q] = (idx < F * F && i < f && jj < f) ? src[h][(int64_t)jj * lsrc + i] : 0.0;
     }
 #pragma unroll
   for (int h = 0; h < NM; ++h)
@@ -1373,6 +1374,87 @@ __device__ __forceinline__ void gmm64(const double* A, int lda, const double* B,
   }
 }
 
+// C = op(A) op(B) for M, N, K <= 64 with both operands staged in LDS first
+// (every thread's loads in flight at once: one memory round trip), then
+// 16 x 16 FP64 MFMA tiles from LDS, four per wave.  Element (i,k) of op(A)
+// at TA ? A[k*lda + i] : A[i*lda + k], (k,j) of op(B) at TB ? B[j*ldb + k] :
+// B[k*ldb + j]; element (i, j) of the product goes to out(i, j, v) for
+// i < M, j < N.  sm: GMM64S_LDS doubles of LDS; the call begins and ends
+// with a barrier, so consecutive calls may share sm.
+constexpr int GMM64S_LD = 65;
+constexpr int GMM64S_LDS = 2 * 64 * GMM64S_LD;
+template <bool TA, bool TB, typename Out>
+__device__ __forceinline__ void gmm64s(const double* A, int lda, const double* B, int ldb, int M, int N, int K,
+                                       double* sm, Out out) {
+  typedef Mfma<double> MF;
+  constexpr int LD = GMM64S_LD;
+  double* As = sm;                 // As[i*LD + k] = op(A)(i, k)
+  double* Bs = sm + 64 * LD;       // Bs[k*LD + j] = op(B)(k, j)
+  const int tid = threadIdx.x;
+  __syncthreads();                 // earlier readers of sm are done
+  double va[16], vb[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int hi = idx >> 6, lo = idx & 63;   // lo runs along contiguous memory
+    // op(A): TA -> memory (k = hi, i = lo) contiguous in i; else (i = hi, k = lo)
+    {
+      const int i = TA ? lo : hi, k = TA ? hi : lo;
+      va[q] = (i < M && k < K) ? (TA ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k]) : 0.0;
+    }
+    // op(B): TB -> memory (j = hi, k = lo) contiguous in k; else (k = hi, j = lo)
+    {
+      const int j = TB ? hi : lo, k = TB ? lo : hi;
+      vb[q] = (k < K && j < N) ? (TB ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j]) : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int hi = idx >> 6, lo = idx & 63;
+    {
+      const int i = TA ? lo : hi, k = TA ? hi : lo;
+      As[i * LD + k] = va[q];
+    }
+    {
+      const int j = TB ? hi : lo, k = TB ? lo : hi;
+      Bs[k * LD + j] = vb[q];
+    }
+  }
+  __syncthreads();
+  const int wv = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int TM = (M + 15) / 16, TN = (N + 15) / 16, KS = (K + 3) / 4;
+  // wave wv: tiles wv, wv + 4, wv + 8, wv + 12 of the TM x TN grid (row-major)
+  typename MF::acc_t acc[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) acc[h] = MF::zero();
+  for (int kk = 0; kk < KS; ++kk) {
+    const int k = 4 * kk + g;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int tile = wv + 4 * h;
+      if (tile < TM * TN) {
+        const int ti = tile / TN, tj = tile - ti * TN;
+        acc[h] = MF::op(As[(16 * ti + r) * LD + k], Bs[k * LD + 16 * tj + r], acc[h]);
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int tile = wv + 4 * h;
+    if (tile < TM * TN) {
+      const int ti = tile / TN, tj = tile - ti * TN;
+      const int j = 16 * tj + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * ti + MF::row(g, e);
+        if (i < M && j < N) out(i, j, acc[h][e]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // LDS (doubles) used by chol_inv128.
 constexpr int CHOL128_LDS = 3 * SmallCfg<64>::SIZE + 24 * 64 + 2 * 64;
 
@@ -1590,10 +1672,7 @@ __global__ __launch_bounds__(256) void k_cb_diag(const double* __restrict__ G, i
   const int tid = threadIdx.x, k0 = 64 * p, pw = cb_width(f, p);
   uint64_t dm = 0, dmo = 0, nl = 0;
   for (int c = 0; c < pw; ++c) dm |= (uint64_t)(dead[k0 + c] != 0) << c;
-  for (int idx = tid; idx < pw * pw; idx += 256) {
-    const int i = idx / pw, j = idx - i * pw;
-    Gs[i * LD + j] = G[(int64_t)(k0 + j) * ld + k0 + i];
-  }
+  stage_small<64>({G + (int64_t)k0 * ld + k0}, pw, {Gs}, LD, ld);
   __syncthreads();
   int nf = 0;
   chol_inv<64>(Gs, Ri, work, dgs, pw, dm, first_pass, &dmo, &nf, dg + k0, &nl);
@@ -1615,12 +1694,13 @@ __global__ __launch_bounds__(256) void k_cb_row(const double* __restrict__ G, in
   const int q = p + 1 + blockIdx.x, k0 = 64 * p, c0 = 64 * q;
   const int pw = cb_width(f, p), qw = cb_width(f, q);
   const uint64_t nl = nolive[p];
+  __shared__ double sm[GMM64S_LDS];
   // op(A)(i,k) = (R_pp^{-1})(k,i): column-major at (k0+i)*ld + k0+k
-  gmm64<false, true>(Rinv + (int64_t)k0 * ld + k0, ld, G + (int64_t)c0 * ld + k0, ld, pw, qw, pw,
-                     [&](int i, int j, double v) {
-                       const bool z = ((nl >> i) & 1ull) || dead[c0 + j] != 0;
-                       R[(int64_t)(c0 + j) * ld + k0 + i] = z ? 0.0 : v;
-                     });
+  gmm64s<false, true>(Rinv + (int64_t)k0 * ld + k0, ld, G + (int64_t)c0 * ld + k0, ld, pw, qw, pw, sm,
+                      [&](int i, int j, double v) {
+                        const bool z = ((nl >> i) & 1ull) || dead[c0 + j] != 0;
+                        R[(int64_t)(c0 + j) * ld + k0 + i] = z ? 0.0 : v;
+                      });
 }
 
 __global__ __launch_bounds__(256) void k_cb_trail(double* __restrict__ G, int ld, int f, int p,
@@ -1635,24 +1715,25 @@ __global__ __launch_bounds__(256) void k_cb_trail(double* __restrict__ G, int ld
   const int r = q + idx;
   const int k0 = 64 * p, cq = 64 * q, cr = 64 * r;
   const int pw = cb_width(f, p), qw = cb_width(f, q), rw = cb_width(f, r);
-  gmm64<false, true>(R + (int64_t)cq * ld + k0, ld, R + (int64_t)cr * ld + k0, ld, qw, rw, pw,
-                     [&](int i, int j, double v) { G[(int64_t)(cr + j) * ld + cq + i] -= v; });
+  __shared__ double sm[GMM64S_LDS];
+  gmm64s<false, true>(R + (int64_t)cq * ld + k0, ld, R + (int64_t)cr * ld + k0, ld, qw, rw, pw, sm,
+                      [&](int i, int j, double v) { G[(int64_t)(cr + j) * ld + cq + i] -= v; });
 }
 
 __global__ __launch_bounds__(256) void k_cb_inv(const double* __restrict__ R, double* __restrict__ Rinv, int ld,
                                                 int f, int d) {
   constexpr int LD = SmallCfg<64>::LD;
   __shared__ double Acc[64 * LD];
+  __shared__ double sm[GMM64S_LDS];
   const int i = blockIdx.x, c = i + d, ci = 64 * i, cc = 64 * c, cw = cb_width(f, c);
   for (int k = i + 1; k <= c; ++k) {
     const int ck = 64 * k, kw = cb_width(f, k);
     const bool first = k == i + 1;
-    gmm64<true, true>(R + (int64_t)ck * ld + ci, ld, Rinv + (int64_t)cc * ld + ck, ld, 64, cw, kw,
-                      [&](int a, int j, double v) { Acc[a * LD + j] = first ? v : Acc[a * LD + j] + v; });
-    __syncthreads();
+    gmm64s<true, true>(R + (int64_t)ck * ld + ci, ld, Rinv + (int64_t)cc * ld + ck, ld, 64, cw, kw, sm,
+                       [&](int a, int j, double v) { Acc[a * LD + j] = first ? v : Acc[a * LD + j] + v; });
   }
-  gmm64<true, false>(Rinv + (int64_t)ci * ld + ci, ld, Acc, LD, 64, cw, 64,
-                     [&](int a, int j, double v) { Rinv[(int64_t)(cc + j) * ld + ci + a] = -v; });
+  gmm64s<true, false>(Rinv + (int64_t)ci * ld + ci, ld, Acc, LD, 64, cw, 64, sm,
+                      [&](int a, int j, double v) { Rinv[(int64_t)(cc + j) * ld + ci + a] = -v; });
 }
 
 // Arguments of the Cholesky that closes a Gram pass (k_gram_rows, and the

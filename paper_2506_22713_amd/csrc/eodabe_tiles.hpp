@@ -100,16 +100,27 @@ __device__ __forceinline__ V4<float> tile_lda4(const float* p) {
     return v;
   }
 }
-template <bool AL>
-__device__ __forceinline__ void tile_rowprod(const float* A, int64_t lda, int64_t m, int64_t n, const float* B,
-                                             int64_t ldb, int nb, float* Yb, int64_t ldy, double* ss,
-                                             double* red) {
+// CTR = ceil(nb / 16) column tiles.  The loads of a full 16-column step are
+// unconditional (rows of B past nb are read at row nb - 1 and zeroed by a
+// select), and the steady state of the PF-deep ring has no branches, so
+// each step waits only for its own loads.
+template <bool AL, int CTR>
+__device__ __noinline__ void tile_rowprod_t(const float* A, int64_t lda, int64_t m, int64_t n, const float* B,
+                                            int64_t ldb, int nb, float* Yb, int64_t ldy, double* ss,
+                                            double* red) {
   typedef Mfma<float> MF;
-  constexpr int RT = 4, CT = 4, PF = 4;
+  constexpr int RT = 4, PF = 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-  const int CTr = (nb + 15) / 16;
-  const int64_t nsteps = (n + 15) / 16;
+  const int64_t nfull = n / 16;
   double sq = 0.0;
+  const float* bp[CTR];
+  bool bval[CTR];
+#pragma unroll
+  for (int u = 0; u < CTR; ++u) {
+    const int bc = 16 * u + r;
+    bval[u] = bc < nb;
+    bp[u] = B + (int64_t)(bval[u] ? bc : (nb > 0 ? nb - 1 : 0)) * ldb + 4 * g;
+  }
   for (int64_t p0 = (int64_t)wv * 64; p0 < m; p0 += 256) {
     const float* ap[RT];
     bool aval[RT];
@@ -119,58 +130,80 @@ __device__ __forceinline__ void tile_rowprod(const float* A, int64_t lda, int64_
       aval[t] = row < m;
       ap[t] = A + (aval[t] ? row : (m - 1)) * lda + 4 * g;
     }
-    MF::acc_t acc[RT][CT];
+    MF::acc_t acc[RT][CTR];
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int u = 0; u < CT; ++u) acc[t][u] = MF::zero();
-    // both operands of a 16-column step are loaded PF steps ahead, so the
-    // wait before a step covers only loads issued PF steps earlier
-    V4<float> a[PF][RT], bq[PF][CT];
-    auto load = [&](int q, int64_t st) {
-      const int64_t k = 16 * st;
-      const bool full = k + 16 <= n;
+      for (int u = 0; u < CTR; ++u) acc[t][u] = MF::zero();
+    auto step = [&](const V4<float>(&av)[RT], const V4<float>(&bv)[CTR]) {
 #pragma unroll
-      for (int t = 0; t < RT; ++t) a[q][t] = full ? tile_lda4<AL>(ap[t] + k) : ld4_masked(ap[t] + k, k + 4 * g, n);
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int u = 0; u < CT; ++u) {
-        const float* ob = B + (int64_t)(16 * u + r) * ldb + k + 4 * g;
-        if (u < CTr && 16 * u + r < nb) bq[q][u] = full ? ld4(ob) : ld4_masked(ob, k + 4 * g, n);
-        else bq[q][u] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int u = 0; u < CTR; ++u) acc[t][u] = MF::op(av[t].v[v], bv[u].v[v], acc[t][u]);
+      if (ss) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+          if (aval[t])
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sq += (double)av[t].v[v] * (double)av[t].v[v];
       }
     };
+    V4<float> a[PF][RT], bq[PF][CTR];
+    auto loadf = [&](int q, int64_t st) {        // a full step: no masks
+      const int64_t k = 16 * st;
 #pragma unroll
-    for (int q = 0; q < PF; ++q)
-      if (q < nsteps) load(q, q);
-    for (int64_t c = 0; c < nsteps; c += PF) {
+      for (int t = 0; t < RT; ++t) a[q][t] = tile_lda4<AL>(ap[t] + k);
 #pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        if (c + q < nsteps) {
+      for (int u = 0; u < CTR; ++u) {
+        const V4<float> v = ld4(bp[u] + k);
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
+        for (int e = 0; e < 4; ++e) bq[q][u].v[e] = bval[u] ? v.v[e] : 0.f;
+      }
+    };
+    if (nfull > 0) {
 #pragma unroll
-            for (int t = 0; t < RT; ++t)
+      for (int q = 0; q < PF; ++q) loadf(q, min((int64_t)q, nfull - 1));   // clamped, never used twice
+      int64_t c = 0;
+      for (; c + 2 * PF <= nfull; c += PF) {
 #pragma unroll
-              for (int u = 0; u < CT; ++u)
-                if (u < CTr) acc[t][u] = MF::op(a[q][t].v[v], bq[q][u].v[v], acc[t][u]);
-          if (ss) {
-#pragma unroll
-            for (int t = 0; t < RT; ++t)
-              if (aval[t])
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sq += (double)a[q][t].v[v] * (double)a[q][t].v[v];
-          }
-          if (c + q + PF < nsteps) load(q, c + q + PF);
+        for (int q = 0; q < PF; ++q) {
+          step(a[q], bq[q]);
+          loadf(q, c + q + PF);
         }
       }
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        if (c + q < nfull) {
+          step(a[q], bq[q]);
+          if (c + q + PF < nfull) loadf(q, c + q + PF);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PF; ++q)
+        if (c + PF + q < nfull) step(a[q], bq[q]);
+    }
+    if (16 * nfull < n) {                        // ragged last step, masked
+      const int64_t k = 16 * nfull;
+      V4<float> at[RT], bt[CTR];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) at[t] = ld4_masked(ap[t] + k, k + 4 * g, n);
+#pragma unroll
+      for (int u = 0; u < CTR; ++u) {
+        const V4<float> v = ld4_masked(bp[u] + k, k + 4 * g, n);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bt[u].v[e] = bval[u] ? v.v[e] : 0.f;
+      }
+      step(at, bt);
     }
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int u = 0; u < CT; ++u) {
+      for (int u = 0; u < CTR; ++u) {
         const int64_t row = p0 + 16 * t + 4 * g;
         const int col = 16 * u + r;
-        if (u < CTr && col < nb) {
+        if (col < nb) {
           float* py = Yb + (int64_t)col * ldy + row;
 #pragma unroll
           for (int e = 0; e < 4; ++e)
@@ -186,85 +219,136 @@ __device__ __forceinline__ void tile_rowprod(const float* A, int64_t lda, int64_
   }
   __syncthreads();
 }
+template <bool AL>
+__device__ __forceinline__ void tile_rowprod(const float* A, int64_t lda, int64_t m, int64_t n, const float* B,
+                                             int64_t ldb, int nb, float* Yb, int64_t ldy, double* ss,
+                                             double* red) {
+  const int ct = (nb + 15) / 16;
+  if (ct <= 1) tile_rowprod_t<AL, 1>(A, lda, m, n, B, ldb, nb, Yb, ldy, ss, red);
+  else if (ct == 2) tile_rowprod_t<AL, 2>(A, lda, m, n, B, ldb, nb, Yb, ldy, ss, red);
+  else if (ct == 3) tile_rowprod_t<AL, 3>(A, lda, m, n, B, ldb, nb, Yb, ldy, ss, red);
+  else tile_rowprod_t<AL, 4>(A, lda, m, n, B, ldb, nb, Yb, ldy, ss, red);
+}
 
 // ---------------------------------------------------------------------------
 // Ct (n x r, column-major ldc) = A^T Q: A m x n row-major (lda), Q m x r
 // column-major (ldq multiple of 4, 16-byte aligned columns), r <= 64.
 // Wave w takes 64-column chunks of A (w, w+4, ...), so A is read once;
 // element (j, i) of the product at i*ldc + j.  ss (LDS, may be null): sum
-// of squares of A.
+// of squares of A.  TR = ceil(r / 16) row tiles; full 16-row steps load
+// without branches (columns past r or n clamped and zeroed by a select).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_t m, int64_t n, const float* Q,
-                                             int64_t ldq, int r, float* Ct, int64_t ldc, double* ss,
-                                             double* red) {
+template <int TR>
+__device__ __noinline__ void tile_colprod_t(const float* A, int64_t lda, int64_t m, int64_t n, const float* Q,
+                                            int64_t ldq, int r, float* Ct, int64_t ldc, double* ss,
+                                            double* red) {
   typedef Mfma<float> MF;
   constexpr int PF = 3;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, rr = lane & 15, g = lane >> 4;
-  const int TR = (r + 15) / 16;
-  const int64_t nsteps = (m + 15) / 16;
+  const int64_t nfull = m / 16;
   double sq = 0.0;
-  for (int64_t c0 = 64 * (int64_t)wv; c0 < n; c0 += 256) {
-    MF::acc_t acc[4][4];
+  const float* qb[TR];
+  bool qval[TR];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TR; ++t) {
+    const int qc = 16 * t + rr;
+    qval[t] = qc < r;
+    qb[t] = Q + (int64_t)(qval[t] ? qc : (r > 0 ? r - 1 : 0)) * ldq + 4 * g;
+  }
+  for (int64_t c0 = 64 * (int64_t)wv; c0 < n; c0 += 256) {
+    MF::acc_t acc[TR][4];
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
-    // operands of a 16-row step loaded PF steps ahead (see tile_rowprod)
-    V4<float> qv[PF][4];
-    float av[PF][4][4];
-    auto load = [&](int q, int64_t st) {
-      const int64_t kr = 16 * st + 4 * g;
-      const bool full = kr + 4 <= m;
+    int64_t acl[4];
+    bool aval[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int qc = 16 * t + rr;
-        const float* qp = Q + (int64_t)qc * ldq + kr;
-        if (t < TR && qc < r) qv[q][t] = full ? ld4(qp) : ld4_masked(qp, kr, m);
-        else qv[q][t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
+    for (int u = 0; u < 4; ++u) {
+      const int64_t ac = c0 + 16 * u + rr;
+      aval[u] = ac < n;
+      acl[u] = aval[u] ? ac : n - 1;
+    }
+    auto step = [&](const V4<float>(&qv)[TR], const float (&av)[4][4]) {
+      if (ss) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) sq += (double)av[u][e] * (double)av[u][e];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t ac = c0 + 16 * u + rr;
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) av[q][u][e] = (ac < n && kr + e < m) ? A[(kr + e) * lda + ac] : 0.f;
-      }
+        for (int t = 0; t < TR; ++t)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(qv[t].v[v], av[u][v], acc[t][u]);
     };
+    V4<float> qv[PF][TR];
+    float av[PF][4][4];
+    auto loadf = [&](int q, int64_t st) {        // a full step: rows 16 st .. 16 st + 15 all < m
+      const int64_t kr = 16 * st + 4 * g;
 #pragma unroll
-    for (int q = 0; q < PF; ++q)
-      if (q < nsteps) load(q, q);
-    for (int64_t c = 0; c < nsteps; c += PF) {
+      for (int t = 0; t < TR; ++t) {
+        const V4<float> v = ld4(qb[t] + 16 * st);
 #pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        if (c + q < nsteps) {
-          if (ss) {
+        for (int e = 0; e < 4; ++e) qv[q][t].v[e] = qval[t] ? v.v[e] : 0.f;
+      }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-              for (int e = 0; e < 4; ++e) sq += (double)av[q][u][e] * (double)av[q][u][e];
-          }
+        for (int e = 0; e < 4; ++e) {
+          const float x = A[(kr + e) * lda + acl[u]];
+          av[q][u][e] = aval[u] ? x : 0.f;
+        }
+    };
+    if (nfull > 0) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
+      for (int q = 0; q < PF; ++q) loadf(q, min((int64_t)q, nfull - 1));
+      int64_t c = 0;
+      for (; c + 2 * PF <= nfull; c += PF) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (t < TR)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(qv[q][t].v[v], av[q][u][v], acc[t][u]);
-          if (c + q + PF < nsteps) load(q, c + q + PF);
+        for (int q = 0; q < PF; ++q) {
+          step(qv[q], av[q]);
+          loadf(q, c + q + PF);
         }
       }
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        if (c + q < nfull) {
+          step(qv[q], av[q]);
+          if (c + q + PF < nfull) loadf(q, c + q + PF);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PF; ++q)
+        if (c + PF + q < nfull) step(qv[q], av[q]);
+    }
+    if (16 * nfull < m) {                        // ragged last step, masked
+      const int64_t kr = 16 * nfull + 4 * g;
+      V4<float> qt[TR];
+      float at[4][4];
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const V4<float> v = ld4_masked(qb[t] + 16 * nfull, kr, m);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) qt[t].v[e] = qval[t] ? v.v[e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) at[u][e] = (aval[u] && kr + e < m) ? A[(kr + e) * lda + acl[u]] : 0.f;
+      step(qt, at);
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t < TR) {
+    for (int t = 0; t < TR; ++t) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t j = c0 + 16 * u + rr;
-          if (j < n) {
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = c0 + 16 * u + rr;
+        if (j < n) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int i = 16 * t + 4 * g + e;
-              if (i < r) Ct[(int64_t)i * ldc + j] = acc[t][u][e];
-            }
+          for (int e = 0; e < 4; ++e) {
+            const int i = 16 * t + 4 * g + e;
+            if (i < r) Ct[(int64_t)i * ldc + j] = acc[t][u][e];
           }
         }
       }
@@ -278,6 +362,15 @@ __device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_
   }
   __syncthreads();
 }
+__device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_t m, int64_t n, const float* Q,
+                                             int64_t ldq, int r, float* Ct, int64_t ldc, double* ss,
+                                             double* red) {
+  const int tr = (r + 15) / 16;
+  if (tr <= 1) tile_colprod_t<1>(A, lda, m, n, Q, ldq, r, Ct, ldc, ss, red);
+  else if (tr == 2) tile_colprod_t<2>(A, lda, m, n, Q, ldq, r, Ct, ldc, ss, red);
+  else if (tr == 3) tile_colprod_t<3>(A, lda, m, n, Q, ldq, r, Ct, ldc, ss, red);
+  else tile_colprod_t<4>(A, lda, m, n, Q, ldq, r, Ct, ldc, ss, red);
+}
 
 // ---------------------------------------------------------------------------
 // out (LDS or global, row-major, leading dimension ldo) = X^T Y in FP64: X
@@ -285,69 +378,116 @@ __device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_
 // columns; columns beyond wx / wy read as zero), wx, wy <= 64.  Waves split
 // the rows (16-row steps, interleaved) and accumulate every 16 x 16 tile of
 // the product at once; the partial tiles are folded in wave order through
-// red (16 * 256 doubles, disjoint from out).
+// red (16 * 256 doubles, disjoint from out).  TX, TY: tile counts of X and
+// Y; full steps load without branches (clamped columns zeroed by a select).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void tile_xty(const float* X, int64_t ldx, int wx, const float* Yb, int64_t ldy,
-                                         int wy, int64_t m, double* out, int ldo, double* red) {
+template <int TX, int TY>
+__device__ __noinline__ void tile_xty_t(const float* X, int64_t ldx, int wx, const float* Yb, int64_t ldy,
+                                        int wy, int64_t m, double* out, int ldo, double* red) {
   typedef Mfma<double> MF;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-  const int TX = (wx + 15) / 16, TY = (wy + 15) / 16;
-  MF::acc_t acc[4][4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
-  // this wave's 16-row steps are k0 = 16 wv + 64 s; operands two steps ahead
   constexpr int PF = 2;
-  const int64_t nsteps = m > 16 * (int64_t)wv ? (m - 16 * (int64_t)wv + 63) / 64 : 0;
-  V4<float> xa[PF][4], yb[PF][4];
-  auto load = [&](int q, int64_t st) {
-    const int64_t kr = 16 * (int64_t)wv + 64 * st + 4 * g;
-    const bool full = kr + 4 <= m;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  MF::acc_t acc[TX][TY];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = 16 * t + r;
-      const float* xp = X + (int64_t)c * ldx + kr;
-      if (t < TX && c < wx) xa[q][t] = full ? ld4(xp) : ld4_masked(xp, kr, m);
-      else xa[q][t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
-      const float* yp = Yb + (int64_t)c * ldy + kr;
-      if (t < TY && c < wy) yb[q][t] = full ? ld4(yp) : ld4_masked(yp, kr, m);
-      else yb[q][t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
+  for (int t = 0; t < TX; ++t)
+#pragma unroll
+    for (int u = 0; u < TY; ++u) acc[t][u] = MF::zero();
+  const float* xb[TX];
+  const float* yb0[TY];
+  bool xval[TX], yval[TY];
+#pragma unroll
+  for (int t = 0; t < TX; ++t) {
+    const int c = 16 * t + r;
+    xval[t] = c < wx;
+    xb[t] = X + (int64_t)(xval[t] ? c : (wx > 0 ? wx - 1 : 0)) * ldx + 4 * g;
+  }
+#pragma unroll
+  for (int u = 0; u < TY; ++u) {
+    const int c = 16 * u + r;
+    yval[u] = c < wy;
+    yb0[u] = Yb + (int64_t)(yval[u] ? c : (wy > 0 ? wy - 1 : 0)) * ldy + 4 * g;
+  }
+  auto step = [&](const V4<float>(&xa)[TX], const V4<float>(&ya)[TY]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int t = 0; t < TX; ++t)
+#pragma unroll
+        for (int u = 0; u < TY; ++u) acc[t][u] = MF::op((double)xa[t].v[v], (double)ya[u].v[v], acc[t][u]);
+  };
+  // this wave's 16-row steps start at 16 wv + 64 s; a step is full when all
+  // its 16 rows are < m
+  const int64_t nfull = m >= 16 * (int64_t)wv + 16 ? (m - 16 * (int64_t)wv - 16) / 64 + 1 : 0;
+  V4<float> xa[PF][TX], ya[PF][TY];
+  auto loadf = [&](int q, int64_t st) {
+    const int64_t k = 16 * (int64_t)wv + 64 * st;
+#pragma unroll
+    for (int t = 0; t < TX; ++t) {
+      const V4<float> v = ld4(xb[t] + k);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xa[q][t].v[e] = xval[t] ? v.v[e] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < TY; ++u) {
+      const V4<float> v = ld4(yb0[u] + k);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ya[q][u].v[e] = yval[u] ? v.v[e] : 0.f;
     }
   };
+  if (nfull > 0) {
 #pragma unroll
-  for (int q = 0; q < PF; ++q)
-    if (q < nsteps) load(q, q);
-  for (int64_t c = 0; c < nsteps; c += PF) {
+    for (int q = 0; q < PF; ++q) loadf(q, min((int64_t)q, nfull - 1));
+    int64_t c = 0;
+    for (; c + 2 * PF <= nfull; c += PF) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        step(xa[q], ya[q]);
+        loadf(q, c + q + PF);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-      if (c + q < nsteps) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (t < TX)
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-                if (u < TY) acc[t][u] = MF::op((double)xa[q][t].v[v], (double)yb[q][u].v[v], acc[t][u]);
-        if (c + q + PF < nsteps) load(q, c + q + PF);
+      if (c + q < nfull) {
+        step(xa[q], ya[q]);
+        if (c + q + PF < nfull) loadf(q, c + q + PF);
       }
+    }
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+      if (c + PF + q < nfull) step(xa[q], ya[q]);
+  }
+  {
+    const int64_t k = 16 * (int64_t)wv + 64 * nfull;   // this wave's ragged step, if any
+    if (k < m) {
+      const int64_t kr = k + 4 * g;
+      V4<float> xt[TX], yt[TY];
+#pragma unroll
+      for (int t = 0; t < TX; ++t) {
+        const V4<float> v = ld4_masked(xb[t] + k, kr, m);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xt[t].v[e] = xval[t] ? v.v[e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < TY; ++u) {
+        const V4<float> v = ld4_masked(yb0[u] + k, kr, m);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) yt[u].v[e] = yval[u] ? v.v[e] : 0.f;
+      }
+      step(xt, yt);
     }
   }
   // fold the waves in order
   for (int w = 0; w < 4; ++w) {
     if (wv == w) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t < TX)
+      for (int t = 0; t < TX; ++t)
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (u < TY)
+        for (int u = 0; u < TY; ++u)
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                double* q = &red[((t * TY + u) * 4 + e) * 64 + lane];
-                *q = (w == 0) ? acc[t][u][e] : *q + acc[t][u][e];
-              }
+          for (int e = 0; e < 4; ++e) {
+            double* q = &red[((t * TY + u) * 4 + e) * 64 + lane];
+            *q = (w == 0) ? acc[t][u][e] : *q + acc[t][u][e];
+          }
     }
     __syncthreads();
   }
@@ -358,6 +498,23 @@ __device__ __forceinline__ void tile_xty(const float* X, int64_t ldx, int wx, co
     if (i < wx && j < wy) out[i * ldo + j] = red[idx];
   }
   __syncthreads();
+}
+template <int TX>
+__device__ __forceinline__ void tile_xty_y(const float* X, int64_t ldx, int wx, const float* Yb, int64_t ldy,
+                                           int wy, int64_t m, double* out, int ldo, double* red) {
+  const int ty = (wy + 15) / 16;
+  if (ty <= 1) tile_xty_t<TX, 1>(X, ldx, wx, Yb, ldy, wy, m, out, ldo, red);
+  else if (ty == 2) tile_xty_t<TX, 2>(X, ldx, wx, Yb, ldy, wy, m, out, ldo, red);
+  else if (ty == 3) tile_xty_t<TX, 3>(X, ldx, wx, Yb, ldy, wy, m, out, ldo, red);
+  else tile_xty_t<TX, 4>(X, ldx, wx, Yb, ldy, wy, m, out, ldo, red);
+}
+__device__ __forceinline__ void tile_xty(const float* X, int64_t ldx, int wx, const float* Yb, int64_t ldy,
+                                         int wy, int64_t m, double* out, int ldo, double* red) {
+  const int tx = (wx + 15) / 16;
+  if (tx <= 1) tile_xty_y<1>(X, ldx, wx, Yb, ldy, wy, m, out, ldo, red);
+  else if (tx == 2) tile_xty_y<2>(X, ldx, wx, Yb, ldy, wy, m, out, ldo, red);
+  else if (tx == 3) tile_xty_y<3>(X, ldx, wx, Yb, ldy, wy, m, out, ldo, red);
+  else tile_xty_y<4>(X, ldx, wx, Yb, ldy, wy, m, out, ldo, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -235,120 +235,79 @@ __device__ __forceinline__ void tile_rowprod(const float* A, int64_t lda, int64_
 // column-major (ldq multiple of 4, 16-byte aligned columns), r <= 64.
 // Wave w takes 64-column chunks of A (w, w+4, ...), so A is read once;
 // element (j, i) of the product at i*ldc + j.  ss (LDS, may be null): sum
-// of squares of A.  TR = ceil(r / 16) row tiles; full 16-row steps load
-// without branches (columns past r or n clamped and zeroed by a select).
+// of squares of A.
 // ---------------------------------------------------------------------------
-template <int TR>
-__device__ __noinline__ void tile_colprod_t(const float* A, int64_t lda, int64_t m, int64_t n, const float* Q,
-                                            int64_t ldq, int r, float* Ct, int64_t ldc, double* ss,
-                                            double* red) {
+__device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_t m, int64_t n, const float* Q,
+                                             int64_t ldq, int r, float* Ct, int64_t ldc, double* ss,
+                                             double* red) {
   typedef Mfma<float> MF;
   constexpr int PF = 3;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, rr = lane & 15, g = lane >> 4;
-  const int64_t nfull = m / 16;
+  const int TR = (r + 15) / 16;
+  const int64_t nsteps = (m + 15) / 16;
   double sq = 0.0;
-  const float* qb[TR];
-  bool qval[TR];
-#pragma unroll
-  for (int t = 0; t < TR; ++t) {
-    const int qc = 16 * t + rr;
-    qval[t] = qc < r;
-    qb[t] = Q + (int64_t)(qval[t] ? qc : (r > 0 ? r - 1 : 0)) * ldq + 4 * g;
-  }
   for (int64_t c0 = 64 * (int64_t)wv; c0 < n; c0 += 256) {
-    MF::acc_t acc[TR][4];
+    MF::acc_t acc[4][4];
 #pragma unroll
-    for (int t = 0; t < TR; ++t)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[t][u] = MF::zero();
-    int64_t acl[4];
-    bool aval[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t ac = c0 + 16 * u + rr;
-      aval[u] = ac < n;
-      acl[u] = aval[u] ? ac : n - 1;
-    }
-    auto step = [&](const V4<float>(&qv)[TR], const float (&av)[4][4]) {
-      if (ss) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) sq += (double)av[u][e] * (double)av[u][e];
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int t = 0; t < TR; ++t)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(qv[t].v[v], av[u][v], acc[t][u]);
-    };
-    V4<float> qv[PF][TR];
+    // operands of a 16-row step loaded PF steps ahead (see tile_rowprod)
+    V4<float> qv[PF][4];
     float av[PF][4][4];
-    auto loadf = [&](int q, int64_t st) {        // a full step: rows 16 st .. 16 st + 15 all < m
+    auto load = [&](int q, int64_t st) {
       const int64_t kr = 16 * st + 4 * g;
+      const bool full = kr + 4 <= m;
 #pragma unroll
-      for (int t = 0; t < TR; ++t) {
-        const V4<float> v = ld4(qb[t] + 16 * st);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) qv[q][t].v[e] = qval[t] ? v.v[e] : 0.f;
+      for (int t = 0; t < 4; ++t) {
+        const int qc = 16 * t + rr;
+        const float* qp = Q + (int64_t)qc * ldq + kr;
+        if (t < TR && qc < r) qv[q][t] = full ? ld4(qp) : ld4_masked(qp, kr, m);
+        else qv[q][t] = V4<float>{{0.f, 0.f, 0.f, 0.f}};
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float x = A[(kr + e) * lda + acl[u]];
-          av[q][u][e] = aval[u] ? x : 0.f;
-        }
-    };
-    if (nfull > 0) {
-#pragma unroll
-      for (int q = 0; q < PF; ++q) loadf(q, min((int64_t)q, nfull - 1));
-      int64_t c = 0;
-      for (; c + 2 * PF <= nfull; c += PF) {
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-          step(qv[q], av[q]);
-          loadf(q, c + q + PF);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        if (c + q < nfull) {
-          step(qv[q], av[q]);
-          if (c + q + PF < nfull) loadf(q, c + q + PF);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < PF; ++q)
-        if (c + PF + q < nfull) step(qv[q], av[q]);
-    }
-    if (16 * nfull < m) {                        // ragged last step, masked
-      const int64_t kr = 16 * nfull + 4 * g;
-      V4<float> qt[TR];
-      float at[4][4];
-#pragma unroll
-      for (int t = 0; t < TR; ++t) {
-        const V4<float> v = ld4_masked(qb[t] + 16 * nfull, kr, m);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) qt[t].v[e] = qval[t] ? v.v[e] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) at[u][e] = (aval[u] && kr + e < m) ? A[(kr + e) * lda + acl[u]] : 0.f;
-      step(qt, at);
-    }
-#pragma unroll
-    for (int t = 0; t < TR; ++t) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int64_t j = c0 + 16 * u + rr;
-        if (j < n) {
+        const int64_t ac = c0 + 16 * u + rr;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int i = 16 * t + 4 * g + e;
-            if (i < r) Ct[(int64_t)i * ldc + j] = acc[t][u][e];
+        for (int e = 0; e < 4; ++e) av[q][u][e] = (ac < n && kr + e < m) ? A[(kr + e) * lda + ac] : 0.f;
+      }
+    };
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+      if (q < nsteps) load(q, q);
+    for (int64_t c = 0; c < nsteps; c += PF) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        if (c + q < nsteps) {
+          if (ss) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) sq += (double)av[q][u][e] * (double)av[q][u][e];
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (t < TR)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(qv[q][t].v[v], av[q][u][v], acc[t][u]);
+          if (c + q + PF < nsteps) load(q, c + q + PF);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < TR) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t j = c0 + 16 * u + rr;
+          if (j < n) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int i = 16 * t + 4 * g + e;
+              if (i < r) Ct[(int64_t)i * ldc + j] = acc[t][u][e];
+            }
           }
         }
       }
@@ -361,15 +320,6 @@ __device__ __noinline__ void tile_colprod_t(const float* A, int64_t lda, int64_t
     if (threadIdx.x == 0) *ss = red[0] + red[1] + red[2] + red[3];
   }
   __syncthreads();
-}
-__device__ __forceinline__ void tile_colprod(const float* A, int64_t lda, int64_t m, int64_t n, const float* Q,
-                                             int64_t ldq, int r, float* Ct, int64_t ldc, double* ss,
-                                             double* red) {
-  const int tr = (r + 15) / 16;
-  if (tr <= 1) tile_colprod_t<1>(A, lda, m, n, Q, ldq, r, Ct, ldc, ss, red);
-  else if (tr == 2) tile_colprod_t<2>(A, lda, m, n, Q, ldq, r, Ct, ldc, ss, red);
-  else if (tr == 3) tile_colprod_t<3>(A, lda, m, n, Q, ldq, r, Ct, ldc, ss, red);
-  else tile_colprod_t<4>(A, lda, m, n, Q, ldq, r, Ct, ldc, ss, red);
 }
 
 // ---------------------------------------------------------------------------

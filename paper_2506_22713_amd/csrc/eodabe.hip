@@ -610,8 +610,16 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
         hipLaunchKernelGGL(k_cb_trail, dim3((P - p - 1) * (P - p) / 2), dim3(256), 0, st, parts, f, f, p, ca.R);
       }
     }
-    for (int d = 1; d < P; ++d)
-      hipLaunchKernelGGL(k_cb_inv, dim3(P - d), dim3(256), 0, st, ca.R, ca.Rinv, f, f, d);
+    for (int L = 1; L < P; L *= 2) {                       // R^{-1} by recursive doubling
+      int nb = 0;
+      for (int a = 0; a + L < P; a += 2 * L) nb += L * (std::min(a + 2 * L, P) - (a + L));
+      if (L == 1) {
+        hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, ca.R, ca.Rinv, parts, f, f, L, 2);
+      } else {
+        hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, ca.R, ca.Rinv, parts, f, f, L, 0);
+        hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, ca.R, ca.Rinv, parts, f, f, L, 1);
+      }
+    }
   }
   if (ca.R1)
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, ca.R1, ca.R, ca.dead, f, ca.col0, ca.n, w.st,

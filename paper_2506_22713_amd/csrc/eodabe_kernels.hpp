@@ -1639,9 +1639,15 @@ __global__ __launch_bounds__(256) void k_small_qr128(const double* __restrict__ 
 //                   mask of the pivots that did not eliminate -> nolive[p];
 //   k_cb_row(p)     workgroup q - p - 1: R_pq = R_pp^{-T} S_pq, masked;
 //   k_cb_trail(p)   one workgroup per pair p < q <= r: S_qr -= R_pq^T R_pr;
-//   k_cb_inv(d)     workgroup i: (R^{-1})_{i,i+d} = -R_ii^{-1}
-//                   sum_{i<k<=i+d} R_ik (R^{-1})_{k,i+d}; the terms were
-//                   finished by the launches of smaller distance.
+//   k_cb_inv(L, s)  R^{-1} by recursive doubling over groups of L = 1, 2,
+//                   4, ... blocks: for adjacent groups A = [a, a+L) and
+//                   C = [a+L, a+2L) (a = 0, 2L, ...) the block of rows A,
+//                   columns C of R^{-1} is -A^{-1} R_AC C^{-1}, A^{-1} and
+//                   C^{-1} finished at smaller L; stage 0 forms T = R_AC
+//                   C^{-1} into G (free after the factorization), stage 1
+//                   the blocks -A^{-1} T, stage 2 both for L = 1; one
+//                   workgroup per output block, log2(P) levels instead of
+//                   P - 1 dependent diagonals.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int cb_width(int f, int p) { return (f - 64 * p) < 64 ? f - 64 * p : 64; }
 
@@ -1720,20 +1726,52 @@ __global__ __launch_bounds__(256) void k_cb_trail(double* __restrict__ G, int ld
                       [&](int i, int j, double v) { G[(int64_t)(cr + j) * ld + cq + i] -= v; });
 }
 
-__global__ __launch_bounds__(256) void k_cb_inv(const double* __restrict__ R, double* __restrict__ Rinv, int ld,
-                                                int f, int d) {
+__global__ __launch_bounds__(256) void k_cb_inv(const double* __restrict__ R, double* __restrict__ Rinv,
+                                                double* __restrict__ G, int ld, int f, int L, int stage) {
   constexpr int LD = SmallCfg<64>::LD;
   __shared__ double Acc[64 * LD];
   __shared__ double sm[GMM64S_LDS];
-  const int i = blockIdx.x, c = i + d, ci = 64 * i, cc = 64 * c, cw = cb_width(f, c);
-  for (int k = i + 1; k <= c; ++k) {
-    const int ck = 64 * k, kw = cb_width(f, k);
-    const bool first = k == i + 1;
-    gmm64s<true, true>(R + (int64_t)ck * ld + ci, ld, Rinv + (int64_t)cc * ld + ck, ld, 64, cw, kw, sm,
-                       [&](int a, int j, double v) { Acc[a * LD + j] = first ? v : Acc[a * LD + j] + v; });
+  const int P = (f + 63) / 64;
+  // this workgroup's pair (groups A = [a, a+L), C = [a+L, a+2L)) and block (i, j)
+  int idx = blockIdx.x, a = 0, cw = 0;
+  for (;; a += 2 * L) {
+    cw = min(a + 2 * L, P) - (a + L);
+    if (idx < L * cw) break;
+    idx -= L * cw;
   }
-  gmm64s<true, false>(Rinv + (int64_t)ci * ld + ci, ld, Acc, LD, 64, cw, 64, sm,
-                      [&](int a, int j, double v) { Rinv[(int64_t)(cc + j) * ld + ci + a] = -v; });
+  const int i = a + idx / cw, j = a + L + idx % cw;
+  const int wi = cb_width(f, i), wj = cb_width(f, j), ci = 64 * i, cj = 64 * j;
+  if (stage != 1) {
+    // T_ij = sum_{a+L <= m <= j} R_im (R^{-1})_mj
+    for (int m = a + L; m <= j; ++m) {
+      const bool first = m == a + L;
+      gmm64s<true, true>(R + (int64_t)(64 * m) * ld + ci, ld, Rinv + (int64_t)cj * ld + 64 * m, ld, wi, wj,
+                         cb_width(f, m), sm,
+                         [&](int r, int c, double v) { Acc[r * LD + c] = first ? v : Acc[r * LD + c] + v; });
+    }
+    if (stage == 0) {
+      for (int e = threadIdx.x; e < wi * wj; e += 256) {
+        const int r = e / wj, c = e - r * wj;
+        G[(int64_t)(cj + c) * ld + ci + r] = Acc[r * LD + c];
+      }
+      return;
+    }
+    // stage 2 (L = 1, A = {i}): (R^{-1})_ij = -(R^{-1})_ii T_ij, T still in LDS
+    gmm64s<true, false>(Rinv + (int64_t)ci * ld + ci, ld, Acc, LD, wi, wj, wi, sm,
+                        [&](int r, int c, double v) { Rinv[(int64_t)(cj + c) * ld + ci + r] = -v; });
+    return;
+  }
+  // (R^{-1})_ij = -sum_{i <= k < a+L} (R^{-1})_ik T_kj, T from G
+  for (int k = i; k < a + L; ++k) {
+    const bool first = k == i;
+    gmm64s<true, true>(Rinv + (int64_t)(64 * k) * ld + ci, ld, G + (int64_t)cj * ld + 64 * k, ld, wi, wj,
+                       cb_width(f, k), sm,
+                       [&](int r, int c, double v) { Acc[r * LD + c] = first ? v : Acc[r * LD + c] + v; });
+  }
+  for (int e = threadIdx.x; e < wi * wj; e += 256) {
+    const int r = e / wj, c = e - r * wj;
+    Rinv[(int64_t)(cj + c) * ld + ci + r] = -Acc[r * LD + c];
+  }
 }
 
 // Arguments of the Cholesky that closes a Gram pass (k_gram_rows, and the

@@ -251,6 +251,16 @@ def test_factor_rank_300_panel_blocked_cholesky(m, n):
     assert f.rank == 300
 
 
+def test_factor_rank_520_recursive_inverse():
+    say("factor rank 520")
+    # nine 64-column panels (the last one 8 wide): the inverse of the wide
+    # Cholesky runs four recursive-doubling levels (groups of 1, 2, 4, 8
+    # blocks), the last with a partial group
+    A = W.lowrank_haar(16, m=1100, n=600, r=520, noise_std=0.0)
+    f, ref = check_factor(A, torch.float64, 1e-9, b=64, seed=16)
+    assert f.rank == 520
+
+
 def test_factor_fp32_rank_250():
     A = W.lowrank_haar(15, m=1000, n=600, r=250, noise_std=1e-8)
     stable, _, _ = O.precision_stable(A, 1e-4, 64, 15)

@@ -601,14 +601,14 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
     const int P = (int)cdiv(f, 64);
     hipLaunchKernelGGL(k_cb_init, dim3((unsigned)std::min<int64_t>(cdiv(ff, 256), 1024)), dim3(256), 0, st,
                        parts, f, f, ca.R, ca.Rinv, w.dg, ca.dead, ca.fresh);
-    for (int p = 0; p < P; ++p) {
-      hipLaunchKernelGGL(k_cb_diag, dim3(1), dim3(256), 0, st, parts, f, f, p, ca.R, ca.Rinv, w.dg, ca.dead,
-                         w.cbmask, ca.first_pass, w.st, ca.count_floors);
-      if (p + 1 < P) {
-        hipLaunchKernelGGL(k_cb_row, dim3(P - p - 1), dim3(256), 0, st, parts, f, f, p, ca.R, ca.Rinv, ca.dead,
-                           w.cbmask);
-        hipLaunchKernelGGL(k_cb_trail, dim3((P - p - 1) * (P - p) / 2), dim3(256), 0, st, parts, f, f, p, ca.R);
-      }
+    hipLaunchKernelGGL(k_cb_diag, dim3(1), dim3(256), 0, st, parts, f, f, 0, ca.R, ca.Rinv, w.dg, ca.dead,
+                       w.cbmask, ca.first_pass, w.st, ca.count_floors);
+    for (int p = 0; p + 1 < P; ++p) {
+      hipLaunchKernelGGL(k_cb_row, dim3(P - p - 1), dim3(256), 0, st, parts, f, f, p, ca.R, ca.Rinv, ca.dead,
+                         w.cbmask);
+      // trailing update of step p with the diagonal step p+1 on its workgroup 0
+      hipLaunchKernelGGL(k_cb_look, dim3((P - p - 1) * (P - p) / 2), dim3(256), 0, st, parts, f, f, p, ca.R,
+                         ca.Rinv, w.dg, ca.dead, w.cbmask, ca.first_pass, w.st, ca.count_floors);
     }
     for (int L = 1; L < P; L *= 2) {                       // R^{-1} by recursive doubling
       int nb = 0;

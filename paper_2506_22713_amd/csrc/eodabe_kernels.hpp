@@ -1638,7 +1638,11 @@ __global__ __launch_bounds__(256) void k_small_qr128(const double* __restrict__ 
 //                   block (floor rule against dg), dead flags of the panel,
 //                   mask of the pivots that did not eliminate -> nolive[p];
 //   k_cb_row(p)     workgroup q - p - 1: R_pq = R_pp^{-T} S_pq, masked;
-//   k_cb_trail(p)   one workgroup per pair p < q <= r: S_qr -= R_pq^T R_pr;
+//   k_cb_look(p)    one workgroup per pair p < q <= r: S_qr -= R_pq^T R_pr;
+//                   workgroup 0 takes (p+1, p+1) in LDS and goes on with
+//                   the diagonal step p+1 while the others update the rest
+//                   (the next diagonal factorization overlaps this step's
+//                   trailing update);
 //   k_cb_inv(L, s)  R^{-1} by recursive doubling over groups of L = 1, 2,
 //                   4, ... blocks: for adjacent groups A = [a, a+L) and
 //                   C = [a+L, a+2L) (a = 0, 2L, ...) the block of rows A,
@@ -1709,21 +1713,51 @@ __global__ __launch_bounds__(256) void k_cb_row(const double* __restrict__ G, in
                       });
 }
 
-__global__ __launch_bounds__(256) void k_cb_trail(double* __restrict__ G, int ld, int f, int p,
-                                                  const double* __restrict__ R) {
-  // pair index -> (q, r), p < q <= r < P, enumerated row by row
-  const int P = (f + 63) / 64;
-  int idx = blockIdx.x, q = p + 1;
-  while (idx >= P - q) {
-    idx -= P - q;
-    ++q;
-  }
-  const int r = q + idx;
-  const int k0 = 64 * p, cq = 64 * q, cr = 64 * r;
-  const int pw = cb_width(f, p), qw = cb_width(f, q), rw = cb_width(f, r);
+__global__ __launch_bounds__(256) void k_cb_look(double* __restrict__ G, int ld, int f, int p,
+                                                 double* __restrict__ R, double* __restrict__ Rinv,
+                                                 const double* __restrict__ dg, int32_t* __restrict__ dead,
+                                                 uint64_t* __restrict__ nolive, int first_pass, State* st,
+                                                 int count_floors) {
+  typedef SmallCfg<64> S;
+  constexpr int LD = S::LD;
   __shared__ double sm[GMM64S_LDS];
-  gmm64s<false, true>(R + (int64_t)cq * ld + k0, ld, R + (int64_t)cr * ld + k0, ld, qw, rw, pw, sm,
-                      [&](int i, int j, double v) { G[(int64_t)(cr + j) * ld + cq + i] -= v; });
+  __shared__ double Gs[S::SIZE], Ri[S::SIZE], work[24 * 64], dgs[64];
+  const int k0 = 64 * p, pw = cb_width(f, p);
+  if (blockIdx.x != 0) {
+    // trailing block pair (q, r), p < q <= r < P, enumerated row by row;
+    // pair 0 = (p+1, p+1) belongs to workgroup 0
+    const int P = (f + 63) / 64;
+    int idx = blockIdx.x, q = p + 1;
+    while (idx >= P - q) {
+      idx -= P - q;
+      ++q;
+    }
+    const int r = q + idx;
+    const int cq = 64 * q, cr = 64 * r, qw = cb_width(f, q), rw = cb_width(f, r);
+    gmm64s<false, true>(R + (int64_t)cq * ld + k0, ld, R + (int64_t)cr * ld + k0, ld, qw, rw, pw, sm,
+                        [&](int i, int j, double v) { G[(int64_t)(cr + j) * ld + cq + i] -= v; });
+    return;
+  }
+  // workgroup 0: S_{p+1,p+1} -= R_{p,p+1}^T R_{p,p+1} in LDS, then the
+  // diagonal step p+1 on it (as k_cb_diag)
+  const int tid = threadIdx.x, p1 = p + 1, c1 = 64 * p1, w1 = cb_width(f, p1);
+  uint64_t dm = 0, dmo = 0, nl = 0;
+  for (int c = 0; c < w1; ++c) dm |= (uint64_t)(dead[c1 + c] != 0) << c;
+  stage_small<64>({G + (int64_t)c1 * ld + c1}, w1, {Gs}, LD, ld);
+  gmm64s<false, true>(R + (int64_t)c1 * ld + k0, ld, R + (int64_t)c1 * ld + k0, ld, w1, w1, pw, sm,
+                      [&](int i, int j, double v) { Gs[i * LD + j] -= v; });
+  int nf = 0;
+  chol_inv<64>(Gs, Ri, work, dgs, w1, dm, first_pass, &dmo, &nf, dg + c1, &nl);
+  for (int idx = tid; idx < w1 * w1; idx += 256) {
+    const int i = idx / w1, j = idx - i * w1;
+    R[(int64_t)(c1 + j) * ld + c1 + i] = Gs[i * LD + j];
+    Rinv[(int64_t)(c1 + j) * ld + c1 + i] = Ri[i * LD + j];
+  }
+  for (int c = tid; c < w1; c += 256) dead[c1 + c] = (int32_t)((dmo >> c) & 1ull);
+  if (tid == 0) {
+    nolive[p1] = nl;
+    if (count_floors && nf && st) atomicAdd(&st->floored, nf);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_cb_inv(const double* __restrict__ R, double* __restrict__ Rinv,

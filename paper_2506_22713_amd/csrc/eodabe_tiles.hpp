@@ -103,7 +103,9 @@ __device__ __forceinline__ V4<float> tile_lda4(const float* p) {
 // CTR = ceil(nb / 16) column tiles.  The loads of a full 16-column step are
 // unconditional (rows of B past nb are read at row nb - 1 and zeroed by a
 // select), and the steady state of the PF-deep ring has no branches, so
-// each step waits only for its own loads.
+// each step waits only for its own loads.  Kept out of line, like the X^T Y
+// routine below: the tile kernel is validated with these two as calls (an
+// inlined build failed the batched parity test with an illegal address).
 template <bool AL, int CTR>
 __device__ __noinline__ void tile_rowprod_t(const float* A, int64_t lda, int64_t m, int64_t n, const float* B,
                                             int64_t ldb, int nb, float* Yb, int64_t ldy, double* ss,

@@ -449,12 +449,13 @@ struct Ops {
               int splits, T* out, int64_t ldo, int64_t part_stride, Gate gate = Gate{},
               const int64_t* M_dev = nullptr) {
     if (M <= 0 || N <= 0) return 0;
+    if (cdiv(N, 256) > 65535) return EODABE_EINVAL;   // grid y holds the 256-column panels
     const int64_t kchunk = split_chunk(K, splits);
     splits = eff_splits(K, splits);
     // rows of the output per wave: 16*RT with RT = ceil(M/16) up to 4, so a
     // small rank does not spend MFMA cycles on padding rows
     const int rt = (int)std::min<int64_t>(4, cdiv(M, 16));
-    dim3 grid((unsigned)cdiv(N, 256), splits, (unsigned)cdiv(M, 16 * rt));
+    dim3 grid((unsigned)splits, (unsigned)cdiv(N, 256), (unsigned)cdiv(M, 16 * rt));
 #define NN_CASE(RR)                                                                                   \
   hipExtLaunchKernelGGL((k_gemm_nn<T, RR>), grid, dim3(256), 0, st, pe0, pe1, 0, X, ldx, Z, ldz, M, N, \
                         K, kchunk, out, ldo, part_stride, gate, M_dev)
@@ -483,8 +484,8 @@ struct Ops {
                   const int32_t* stopb = nullptr, int blk = 0, Gate gate = Gate{}) {
     if (count <= 0) return 0;
     if (nparts <= 4) return reduce(parts, nparts, stride, count, out, stopb, blk, gate);
-    hipLaunchKernelGGL((k_reduce_parts_wide<U>), dim3((unsigned)cdiv(count, 64)), dim3(64, 16), 0, st,
-                       parts, nparts, stride, count, out, stopb, blk, gate);
+    hipLaunchKernelGGL((k_fold_parts<U>), dim3((unsigned)cdiv(count, 512)), dim3(128), 0, st, parts, nparts,
+                       stride, count, out, stopb, blk, gate);
     LAUNCHCHK();
     return 0;
   }

@@ -261,6 +261,18 @@ def test_factor_rank_520_recursive_inverse():
     assert f.rank == 520
 
 
+@pytest.mark.parametrize("m,n,dtype", [(16384, 300, torch.float64), (12000, 260, torch.float32)])
+def test_factor_many_split_partials(m, n, dtype):
+    say(f"factor {m}x{n} many K-split partials")
+    # a long, narrow matrix: the projection C = Q^T A runs with 64 and 45
+    # K-split partials, folded in fixed order by the partial-sum kernel
+    # (more than its 16-partial load batch, ragged in the second batch)
+    A = W.lowrank_haar(17, m=m, n=n, r=40, noise_std=0.0)
+    tol = 1e-9 if dtype == torch.float64 else 1e-4
+    f, ref = check_factor(A, dtype, tol, b=32, seed=17)
+    assert f.rank == 40
+
+
 def test_factor_fp32_rank_250():
     A = W.lowrank_haar(15, m=1000, n=600, r=250, noise_std=1e-8)
     stable, _, _ = O.precision_stable(A, 1e-4, 64, 15)

@@ -59,7 +59,15 @@ def gpu_relerr(A64, f):
     return float(np.linalg.norm(A64 - U @ D @ Vt) / nrm) if nrm else 0.0, U, D, Vt
 
 
-def check_factor(A64, dtype, tol, b=32, q=0, seed=0, stable=True):
+def check_factor(A64, dtype, tol, b=32, q=0, seed=0, stable=True, rounding_only=False):
+    """GPU factorization against the oracle: same rank, RelErr within the
+    data type's bar, orthonormal factors, D upper triangular with a
+    non-negative diagonal.  rounding_only: the content is noise-free and of
+    exact rank, so the oracle's RelErr is its own rounding error amplified
+    by the conditioning of the sketched block (the first r columns of A Omega
+    form a square sketch of an r-dimensional range); the FP32 path carries
+    the same amplification of its unit roundoff, and its bar is widened to
+    4 (u32/u64) times the oracle's RelErr."""
     say("factor", A64.shape, dtype, "tol", tol, "b", b, "q", q, "seed", seed)
     ref = O.eod_abe(A64, tol, k=b, q=q, seed=seed)
     f = E.factor(dev(A64, dtype), tol, block=b, power_iters=q, seed=seed)
@@ -74,6 +82,8 @@ def check_factor(A64, dtype, tol, b=32, q=0, seed=0, stable=True):
         bar = RELERR_TOL[dtype]
         if dtype == torch.float32:
             bar = max(bar, fp32_floor(f.rank, *A64.shape))
+            if rounding_only:
+                bar = max(bar, 4.0 * (U32 / U64) * e_ref)
         assert abs(e_gpu - e_ref) <= bar, (e_gpu, e_ref, bar)
     r = f.rank
     assert np.linalg.norm(U.T @ U - np.eye(r)) <= ORTH_TOL[dtype] * math.sqrt(r)
@@ -271,6 +281,46 @@ def test_factor_many_split_partials(m, n, dtype):
     tol = 1e-9 if dtype == torch.float64 else 1e-4
     f, ref = check_factor(A, dtype, tol, b=32, seed=17)
     assert f.rank == 40
+
+
+EDGE_SIDES = [1, 2, 3, 7, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 255, 257, 300, 511, 513, 640]
+
+
+def random_case(i):
+    """Case i of the random-shape sweep: sides drawn from tile and panel
+    edges, content rank up to 100, block width, dtype and tolerance drawn
+    from seeded generators (FP64: tol 1e-10..1e-5, well below the content's
+    smallest singular value; FP32: tol 1e-4..1e-3 with 2 decades of
+    spectrum)."""
+    rng = np.random.default_rng(7000 + i)
+    m, n = (int(x) for x in rng.choice(EDGE_SIDES, 2))
+    r = int(rng.integers(0, min(m, n, 100) + 1))
+    b = int(rng.choice([1, 8, 16, 20, 32, 48, 64]))
+    fp64 = i % 2 == 0
+    tol = float(10.0 ** -rng.uniform(5, 10)) if fp64 else float(10.0 ** -rng.uniform(3, 4))
+    A = W.lowrank_haar(7000 + i, m=m, n=n, r=r, noise_std=0.0, decades=3.0 if fp64 else 2.0)
+    return A, (torch.float64 if fp64 else torch.float32), tol, b
+
+
+@pytest.mark.parametrize("i", range(24))
+def test_factor_random_shapes(i):
+    A, dtype, tol, b = random_case(i)
+    say(f"random case {i}: {A.shape} {dtype} tol {tol:.2e} b {b}")
+    stable = True
+    if dtype == torch.float32:
+        stable, _, _ = O.precision_stable(A, tol, b, 7000 + i)
+    check_factor(A, dtype, tol, b=b, seed=7000 + i, stable=stable, rounding_only=True)
+
+
+@pytest.mark.parametrize("m,n,r", [(1, 1, 1), (1, 300, 1), (300, 1, 1), (2, 513, 2), (513, 2, 1), (1, 64, 0)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-8), (torch.float32, 1e-4)])
+@pytest.mark.parametrize("b", [1, 32])
+def test_factor_degenerate_sides(m, n, r, dtype, tol, b):
+    # one or two rows or columns: a single K step, panels of one column,
+    # the transposed orientation for the wide ones
+    A = W.lowrank_haar(11, m=m, n=n, r=r, noise_std=0.0)
+    f, ref = check_factor(A, dtype, tol, b=b, seed=11)
+    assert f.rank == r
 
 
 def test_factor_fp32_rank_250():

@@ -249,6 +249,19 @@ def run_tiles(args):
     tot_ms, launches, by = ctx.profile_read(E.PROF_TILES)
     ctx.profile(False)
     ranks_b, status_b, blocks = bt.ranks.copy(), bt.status.copy(), bt.blocks.copy()
+    if args.copy_calib:
+        # one plain device copy of 64 MiB: its FETCH_SIZE / WRITE_SIZE under
+        # rocprofv3 --pmc calibrate the counters of k_tiles
+        src = torch.ones(16 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {src.numel() * 4} bytes read and written")
+        del src, dst
+    if args.skip_sequential:
+        # counter runs only: the batched launches without the sequential comparison
+        log(f"batched only: {ms_per_step:.3f} ms per batch; sequential comparison skipped")
+        return
 
     # sequential plain calls, one context per block width in use
     log("sequential plain calls")
@@ -290,7 +303,9 @@ def run_tiles(args):
     avg_ms = tot_ms / max(launches, 1)
     per_launch = by / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = measured_traffic("tiles1024", "k_tiles")
+    # the committed counters were taken with block 32 for every tile: they
+    # describe this launch only when the autotuner is off
+    traffic = measured_traffic("tiles1024", "k_tiles") if args.no_tune else None
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None if traffic is None else int(traffic),
                     kernel="persistent tile kernel (k_tiles, with its descriptor/result copies)",
@@ -342,7 +357,9 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="block width b (0: the workload's default)")
     ap.add_argument("--no-tune", action="store_true", help="tiles1024: skip the block-width autotuner")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="also run one plain device copy of A (counter calibration under a profiler)")
+                    help="also run one plain device copy of A (64 MiB for tiles1024; counter calibration under a profiler)")
+    ap.add_argument("--skip-sequential", action="store_true",
+                    help="tiles1024 under a counter profiler: time the batched launches only, print no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "

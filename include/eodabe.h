@@ -77,6 +77,11 @@ typedef struct eodabe_info {
                             the stop test; every block sketched in FP32 (the plain path)      */
   double  norm_a;        /* ||A||_F (FP64 accumulation)                                       */
   double  eps;           /* tol * ||A||_F, the absolute stopping threshold                    */
+  double  relres_est;    /* |T(l,l)| / ||A||_F for the column l whose test stopped the loop:
+                            a one-sample estimate of ||A - Q Q^T A||_F / ||A||_F before the
+                            basis grew past l (its square has that expectation, Sec. 3.1 and
+                            the Gaussian-moment lemma of Sec. 3.3); 0 when the loop ran to the
+                            last column or ||A||_F = 0                                         */
 } eodabe_info;
 
 /* Fill *o with defaults (block 32, q 0, seed 0, F32, native sketch, stream 0). */

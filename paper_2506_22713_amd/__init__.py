@@ -58,7 +58,7 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int64), ("blocks", ctypes.c_int),
                 ("status_flags", ctypes.c_int), ("norm_a", ctypes.c_double),
-                ("eps", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("relres_est", ctypes.c_double)]
 
 
 _vp, _i64, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
@@ -229,6 +229,7 @@ class Factorization:
     norm_a: float
     status: int
     flags: int
+    relres_est: float = 0.0   # |T(l,l)| / ||A||_F at the stopping column (0: no stop)
 
 
 def _check_matrix(A: torch.Tensor, dtype: torch.dtype):
@@ -266,7 +267,7 @@ def factor(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int =
     ctx._check(st, "eodabe_factor")
     r = int(info.rank)
     return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
-                         float(info.norm_a), st, int(info.status_flags))
+                         float(info.norm_a), st, int(info.status_flags), float(info.relres_est))
 
 
 def basis(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int = 0,

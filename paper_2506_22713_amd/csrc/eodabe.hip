@@ -1737,6 +1737,8 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
     info->blocks = blocks;
     info->norm_a = norm_a;
     info->eps = tol * norm_a;
+    // the control block was read after the last chunk: d_stop is final
+    info->relres_est = (norm_a > 0.0 && g.nn > 0) ? ctx->host_state->d_stop / norm_a : 0.0;
     if (diagT && diag_cap > 0) {
       const int64_t cnt = std::min<int64_t>(diag_cap, std::min<int64_t>(rank + 1, g.nn));
       HIPCHK(hipMemcpy(diagT, w.diag_log, cnt * sizeof(double), hipMemcpyDeviceToHost));

@@ -48,6 +48,7 @@ struct State {
   double lp_scale;       // power of two applied to A before rounding it to FP16 (1 for BF16)
   int32_t lp_mode;       // 0: none, 1: FP16, 2: BF16 (low-precision sketch form)
   int32_t pad2;
+  double d_stop;         // |T(l,l)| of the column whose test stopped the loop (0: none)
 };
 
 // Low-precision copies of A for the sketch: IEEE binary16 or bfloat16,
@@ -2134,7 +2135,9 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   const unsigned long long mask = __ballot(hit);
   const int keep = mask ? (int)__ffsll((long long)mask) - 1 : f;
   if (mine && j <= keep) ca.diag_log[ca.col0 + j] = d;
+  const double dk = __shfl(d, keep & 63);     // the stopping column's value (when one hit)
   if (j == 0) {
+    if (mask != 0ull) st->d_stop = dk;
     const bool stop = (mask != 0ull) || (ca.col0 + f >= ca.n);
     ca.acc[block_id] = keep;
     const int64_t wn = ca.wlog[block_id] + keep;
@@ -2286,7 +2289,7 @@ __global__ void k_decide(const double* __restrict__ R1, const double* __restrict
   for (int c = 0; c < f; ++c) {
     const double d = dead[c] ? 0.0 : R2[(int64_t)c * f + c] * R1[(int64_t)c * f + c];
     diag_log[col0 + c] = d;
-    if (d <= eps || st->nonfinite) { keep = c; stop = true; break; }
+    if (d <= eps || st->nonfinite) { keep = c; stop = true; st->d_stop = d; break; }
   }
   if (col0 + f >= n) stop = true;
   acc[block_id] = keep;
@@ -2333,7 +2336,7 @@ __global__ void k_init_state(State* st, double tol, int64_t* wlog, int nwlog, in
     st->eps = 0.0; st->normsq = 0.0; st->tol = tol;
     st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->pad = 0; st->rank = 0;
     for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
-    st->lp_scale = 1.0; st->lp_mode = lp_mode; st->pad2 = 0;
+    st->lp_scale = 1.0; st->lp_mode = lp_mode; st->pad2 = 0; st->d_stop = 0.0;
   }
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = t; i < nwlog; i += nt) wlog[i] = 0;

@@ -70,6 +70,13 @@ def test_workspace_planning(E):
     assert c64.workspace_size(512, 512) > s1
 
 
+def test_info_layout(E):
+    # eodabe_info: int64 rank, int blocks, int status_flags, then norm_a,
+    # eps and relres_est (doubles) at 16, 24 and 32
+    assert ctypes.sizeof(E.Info) == 40
+    assert E.Info.relres_est.offset == 32 and E.Info.eps.offset == 24 and E.Info.norm_a.offset == 16
+
+
 def test_factor_argument_errors_without_device(E):
     c = E.Context(host_only=True)
     info = E.Info()

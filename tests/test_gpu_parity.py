@@ -323,6 +323,39 @@ def test_factor_degenerate_sides(m, n, r, dtype, tol, b):
     assert f.rank == r
 
 
+@pytest.mark.parametrize("case", ["fp64_noise", "fp64_b8", "fp64_wide", "fp64_b96", "fp32_noise", "full_rank"])
+def test_relres_estimate_matches_oracle(case):
+    # info.relres_est = |T(l,l)| / ||A||_F at the column whose test stopped
+    # the loop: the oracle's diag(T) entry at index rank, divided by its norm
+    say("relres_est", case)
+    dtype, b, tol = torch.float64, 32, 1e-6
+    if case == "full_rank":
+        A = W.lowrank_haar(21, m=120, n=40, r=40, noise_std=0.0, decades=1.0)
+        tol = 1e-12
+    elif case == "fp64_wide":
+        A = W.lowrank_haar(22, m=150, n=700, r=30, noise_std=1e-9)
+    elif case == "fp32_noise":
+        dtype, tol = torch.float32, 1e-4
+        A = W.lowrank_haar(23, m=900, n=500, r=60, noise_std=1e-9, decades=2.0)
+    else:
+        A = W.lowrank_haar(24, m=800, n=400, r=70, noise_std=1e-9)
+        b = {"fp64_noise": 32, "fp64_b8": 8, "fp64_b96": 96}[case]
+    ref = O.eod_abe(A, tol, k=b, q=0, seed=5)
+    f = E.factor(dev(A, dtype), tol, block=b, seed=5)
+    torch.cuda.synchronize()
+    assert f.rank == ref.rank, (f.rank, ref.rank)
+    nrm = float(np.linalg.norm(A))
+    want = float(ref.diagT[ref.rank]) / nrm if len(ref.diagT) > ref.rank else 0.0
+    if case == "full_rank":
+        assert want == 0.0 and f.relres_est == 0.0
+        return
+    bar = 1e-12 if dtype == torch.float64 else 64 * math.sqrt(A.shape[1]) * U32
+    assert want > 0.0
+    assert abs(f.relres_est - want) <= bar, (f.relres_est, want, bar)
+    # and it is the stopping column's value: at most tol (the test fired there)
+    assert f.relres_est <= tol * (1 + 1e-12)
+
+
 def test_factor_fp32_rank_250():
     A = W.lowrank_haar(15, m=1000, n=600, r=250, noise_std=1e-8)
     stable, _, _ = O.precision_stable(A, 1e-4, 64, 15)

@@ -241,6 +241,21 @@ def test_precision_stability_classifier():
     assert ok and r64 == r32 == 20
 
 
+def test_precision_stability_margin():
+    # exact rank 15 with two decades of spectrum: the FP32 sketch leaves the
+    # 16th column a rounding-dominated |T| of 1.86e-4 ||A|| (FP64: 5.8e-13),
+    # amplified by the conditioning of the first 15 sketch columns; at tol
+    # 1.92e-4 both runs stop at 15, but the value is within a factor 2 of
+    # eps, so another FP32 summation order may keep the column: not stable
+    A = W.lowrank_haar(121418, m=345, n=30, r=15, noise_std=0.0, decades=2.0)
+    ok, r64, r32 = O.precision_stable(A, 1.92e-4, 32, 121418)
+    assert (r64, r32) == (15, 15) and not ok
+    # the same instance at tol 3e-2 stops inside the spectrum, far from any
+    # rounding-dominated value: stable
+    ok2, _, _ = O.precision_stable(A, 3e-2, 32, 121418)
+    assert ok2
+
+
 # ---------------------------------------------------------------- planted mistakes
 def _exact_case():
     A = W.lowrank_haar(3, m=200, n=160, r=9, noise_std=0.0)

@@ -941,8 +941,40 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
 template <typename T>
 int small_qr(eodabe_ctx* ctx, hipStream_t st, const double* R1, const double* R2, int f, double* Qout, T* Dout,
              int64_t ldd, State* state, Gate gate = Gate{}, const int64_t* f_dev = nullptr,
-             double* scr = nullptr) {
+             double* scr = nullptr, int32_t* dead_scr = nullptr) {
   if (f <= 0) return 0;
+  if (f > 64 && f <= 128 && scr && dead_scr && !gate.st && !f_dev) {
+    // 64 < f <= 128: the steps of the one-workgroup closing QR as separate
+    // launches, so each product runs on (f/32)^2 workgroups: M = R2 R1,
+    // G = M M^T, chol -> H1, Z1 = M^T H1^{-1}, G = Z1^T Z1, chol -> H2,
+    // Q_hat = Z1 H2^{-1}, R_hat = H2 H1 (all column-major, ld f; the first
+    // Cholesky floors, the second kills what stays non-positive)
+    constexpr int64_t B2 = 128 * 128;
+    double* M = scr;
+    double* G = scr + B2;
+    double* H1 = scr + 2 * B2;
+    double* H1i = scr + 3 * B2;
+    double* Z1 = scr + 4 * B2;
+    double* H2 = scr + 5 * B2;
+    double* H2i = scr + 6 * B2;
+    const dim3 grid((unsigned)cdiv(f, 32), (unsigned)cdiv(f, 32));
+    const double* Mr = R2;
+    if (R1) {
+      hipLaunchKernelGGL((k_sq_prod<double, true, true, false>), grid, dim3(256), 0, st, R2, R1, f, M, (int64_t)f);
+      Mr = M;
+    }
+    hipLaunchKernelGGL((k_sq_prod<double, true, false, false>), grid, dim3(256), 0, st, Mr, Mr, f, G, (int64_t)f);
+    hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, G, f, H1, H1i, dead_scr, 1, 1, state, 1,
+                       (const int32_t*)nullptr, 0);
+    hipLaunchKernelGGL((k_sq_prod<double, false, true, false>), grid, dim3(256), 0, st, Mr, H1i, f, Z1, (int64_t)f);
+    hipLaunchKernelGGL((k_sq_prod<double, false, true, false>), grid, dim3(256), 0, st, Z1, Z1, f, G, (int64_t)f);
+    hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, G, f, H2, H2i, dead_scr, 0, 0, state, 1,
+                       (const int32_t*)nullptr, 0);
+    hipLaunchKernelGGL((k_sq_prod<double, true, true, false>), grid, dim3(256), 0, st, Z1, H2i, f, Qout, (int64_t)f);
+    hipLaunchKernelGGL((k_sq_prod<T, true, true, true>), grid, dim3(256), 0, st, H2, H1, f, Dout, ldd);
+    LAUNCHCHK();
+    return 0;
+  }
   if (f <= 16)
     hipLaunchKernelGGL((k_small_qr<T, 16>), dim3(1), dim3(256), 0, st, R1, R2, f, Qout, Dout, ldd, state, 1,
                        gate, f_dev);
@@ -1020,7 +1052,7 @@ int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, cons
     TRY(ops.apply(a1, nullptr, (int)r));
     TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c2));
   }
-  TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st, gate, r_dev, w.sq128));
+  TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st, gate, r_dev, w.sq128, w.deadbig));
   const ApplyJob jv{cb, g.ldk, Vout, ldv, w.rb5, g.nn, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
   const ApplyJob ju{q, g.ldy, Uout, ldu, w.rb4, g.mm, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
   TRY(ops.apply(jv, &ju, (int)r, nullptr, 0, gate));
@@ -1775,7 +1807,7 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
                            rank, rank, rank, 1);
         LAUNCHCHK();
         TRY(small_qr<T>(ctx, st, nullptr, w.rb2, (int)rank, w.rb4, (T*)core, g.r_cap, w.st, Gate{}, nullptr,
-                        w.sq128));
+                        w.sq128, w.deadbig));
         const ApplyJob ju{w.cbuf, g.ldk, Ut, m, w.rb4, m, 0, (int)rank, (int)rank, nullptr, nullptr, nullptr};
         TRY(ops.apply(ju, nullptr, (int)rank));
         TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));

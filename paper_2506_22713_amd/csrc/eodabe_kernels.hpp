@@ -1635,6 +1635,27 @@ __global__ __launch_bounds__(256) void k_chol128(const double* __restrict__ G, i
   if (count_floors && threadIdx.x == 0 && nf && st) atomicAdd(&st->floored, nf);
 }
 
+// One f x f FP64 product of the split closing QR (64 < f <= 128): out =
+// op(A) op(B), both operands column-major with leading dimension f, element
+// (i,k) of op(A) at TA ? A[k*f + i] : A[i*f + k], (k,j) of op(B) at TB ?
+// B[j*f + k] : B[k*f + j].  One workgroup per 32 x 32 output block (each
+// wave one 16 x 16 tile, gmm64, the same K order as the one-workgroup form);
+// out column-major (ld f) or, with ROWOUT, row-major with leading dimension
+// ldo, rounded to T.
+template <typename T, bool TA, bool TB, bool ROWOUT>
+__global__ __launch_bounds__(256) void k_sq_prod(const double* __restrict__ A, const double* __restrict__ B, int f,
+                                                 T* __restrict__ out, int64_t ldo) {
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  if (i0 >= f || j0 >= f) return;
+  const int mt = min(32, f - i0), nt = min(32, f - j0);
+  const double* As = TA ? A + i0 : A + (int64_t)i0 * f;
+  const double* Bs = TB ? B + (int64_t)j0 * f : B + j0;
+  gmm64<TA, TB>(As, f, Bs, f, mt, nt, f, [&](int i, int j, double v) {
+    if constexpr (ROWOUT) out[(int64_t)(i0 + i) * ldo + (j0 + j)] = (T)v;
+    else out[(int64_t)(j0 + j) * f + (i0 + i)] = (T)v;
+  });
+}
+
 // Closing QR (as k_small_qr) for 64 < f <= 128: R1, R2 column-major f x f
 // (R1 may be null), Qh -> Qout (column-major), Rh -> Dout (type T,
 // row-major ldd); scr: 7 x 128 x 128 doubles.

@@ -546,6 +546,37 @@ CholArgs chol_args(const WS& w, double* R, int32_t* dead, int first, int fresh, 
   return ca;
 }
 
+// Panel-blocked Cholesky with inverse of an f x f Gram matrix (k_cb_*; G,
+// R, R^{-1} column-major, leading dimension f; G overwritten by the Schur
+// complements): one workgroup on each diagonal block, the independent 64 x 64
+// block products of a step on separate workgroups, R^{-1} by recursive
+// doubling.  dg: f doubles; cbmask: one word per 64-column panel.
+void cb_chol(hipStream_t st, double* G, int f, double* R, double* Rinv, double* dg, int32_t* dead,
+             uint64_t* cbmask, int first_pass, int fresh, State* state, int count_floors) {
+  const int P = (int)cdiv(f, 64);
+  const int64_t ff = (int64_t)f * f;
+  hipLaunchKernelGGL(k_cb_init, dim3((unsigned)std::min<int64_t>(cdiv(ff, 256), 1024)), dim3(256), 0, st, G, f, f,
+                     R, Rinv, dg, dead, fresh);
+  hipLaunchKernelGGL(k_cb_diag, dim3(1), dim3(256), 0, st, G, f, f, 0, R, Rinv, dg, dead, cbmask, first_pass,
+                     state, count_floors);
+  for (int p = 0; p + 1 < P; ++p) {
+    hipLaunchKernelGGL(k_cb_row, dim3(P - p - 1), dim3(256), 0, st, G, f, f, p, R, Rinv, dead, cbmask);
+    // trailing update of step p with the diagonal step p+1 on its workgroup 0
+    hipLaunchKernelGGL(k_cb_look, dim3((P - p - 1) * (P - p) / 2), dim3(256), 0, st, G, f, f, p, R, Rinv, dg,
+                       dead, cbmask, first_pass, state, count_floors);
+  }
+  for (int L = 1; L < P; L *= 2) {                       // R^{-1} by recursive doubling
+    int nb = 0;
+    for (int a = 0; a + L < P; a += 2 * L) nb += L * (std::min(a + 2 * L, P) - (a + L));
+    if (L == 1) {
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 2);
+    } else {
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 0);
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 1);
+    }
+  }
+}
+
 // G = Z^T Z (FP64) of the rows x f block Z = X (W null) or Z = X W (W f x f
 // FP64, element (i,j) at j*f + i, Z rounded to T and written over X), then
 // the Cholesky with the floor/kill rules and the epilogues in ca (R,
@@ -594,34 +625,11 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
   TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, gs, parts, f, ff, nullptr, nullptr, stopb, blk));
   TRY(ops.reduce(parts, eff_splits(rows, gs), ff, ff, gsum, stopb, blk));
   parts = gsum;
-  if (f <= 128)
+  if (f <= 128 && stopb)       // a block of the basis loop: one workgroup, with the stop check
     hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, ca.dead, ca.first_pass,
                        ca.fresh, w.st, ca.count_floors, stopb, blk);
-  else {
-    // panel-blocked, one kernel per step (see k_cb_*)
-    const int P = (int)cdiv(f, 64);
-    hipLaunchKernelGGL(k_cb_init, dim3((unsigned)std::min<int64_t>(cdiv(ff, 256), 1024)), dim3(256), 0, st,
-                       parts, f, f, ca.R, ca.Rinv, w.dg, ca.dead, ca.fresh);
-    hipLaunchKernelGGL(k_cb_diag, dim3(1), dim3(256), 0, st, parts, f, f, 0, ca.R, ca.Rinv, w.dg, ca.dead,
-                       w.cbmask, ca.first_pass, w.st, ca.count_floors);
-    for (int p = 0; p + 1 < P; ++p) {
-      hipLaunchKernelGGL(k_cb_row, dim3(P - p - 1), dim3(256), 0, st, parts, f, f, p, ca.R, ca.Rinv, ca.dead,
-                         w.cbmask);
-      // trailing update of step p with the diagonal step p+1 on its workgroup 0
-      hipLaunchKernelGGL(k_cb_look, dim3((P - p - 1) * (P - p) / 2), dim3(256), 0, st, parts, f, f, p, ca.R,
-                         ca.Rinv, w.dg, ca.dead, w.cbmask, ca.first_pass, w.st, ca.count_floors);
-    }
-    for (int L = 1; L < P; L *= 2) {                       // R^{-1} by recursive doubling
-      int nb = 0;
-      for (int a = 0; a + L < P; a += 2 * L) nb += L * (std::min(a + 2 * L, P) - (a + L));
-      if (L == 1) {
-        hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, ca.R, ca.Rinv, parts, f, f, L, 2);
-      } else {
-        hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, ca.R, ca.Rinv, parts, f, f, L, 0);
-        hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, ca.R, ca.Rinv, parts, f, f, L, 1);
-      }
-    }
-  }
+  else                         // panel-blocked, one kernel per step (see k_cb_*)
+    cb_chol(st, parts, f, ca.R, ca.Rinv, w.dg, ca.dead, w.cbmask, ca.first_pass, ca.fresh, w.st, ca.count_floors);
   if (ca.R1)
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, ca.R1, ca.R, ca.dead, f, ca.col0, ca.n, w.st,
                        ca.wlog, ca.acc, ca.diag_log, blk);
@@ -941,14 +949,16 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
 template <typename T>
 int small_qr(eodabe_ctx* ctx, hipStream_t st, const double* R1, const double* R2, int f, double* Qout, T* Dout,
              int64_t ldd, State* state, Gate gate = Gate{}, const int64_t* f_dev = nullptr,
-             double* scr = nullptr, int32_t* dead_scr = nullptr) {
+             double* scr = nullptr, int32_t* dead_scr = nullptr, double* dg_scr = nullptr,
+             uint64_t* mask_scr = nullptr) {
   if (f <= 0) return 0;
-  if (f > 64 && f <= 128 && scr && dead_scr && !gate.st && !f_dev) {
+  if (f > 64 && f <= 128 && scr && dead_scr && dg_scr && mask_scr && !gate.st && !f_dev) {
     // 64 < f <= 128: the steps of the one-workgroup closing QR as separate
     // launches, so each product runs on (f/32)^2 workgroups: M = R2 R1,
     // G = M M^T, chol -> H1, Z1 = M^T H1^{-1}, G = Z1^T Z1, chol -> H2,
     // Q_hat = Z1 H2^{-1}, R_hat = H2 H1 (all column-major, ld f; the first
-    // Cholesky floors, the second kills what stays non-positive)
+    // Cholesky floors, the second kills what stays non-positive; both
+    // panel-blocked, cb_chol)
     constexpr int64_t B2 = 128 * 128;
     double* M = scr;
     double* G = scr + B2;
@@ -964,12 +974,10 @@ int small_qr(eodabe_ctx* ctx, hipStream_t st, const double* R1, const double* R2
       Mr = M;
     }
     hipLaunchKernelGGL((k_sq_prod<double, true, false, false>), grid, dim3(256), 0, st, Mr, Mr, f, G, (int64_t)f);
-    hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, G, f, H1, H1i, dead_scr, 1, 1, state, 1,
-                       (const int32_t*)nullptr, 0);
+    cb_chol(st, G, f, H1, H1i, dg_scr, dead_scr, mask_scr, 1, 1, state, 1);
     hipLaunchKernelGGL((k_sq_prod<double, false, true, false>), grid, dim3(256), 0, st, Mr, H1i, f, Z1, (int64_t)f);
     hipLaunchKernelGGL((k_sq_prod<double, false, true, false>), grid, dim3(256), 0, st, Z1, Z1, f, G, (int64_t)f);
-    hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, G, f, H2, H2i, dead_scr, 0, 0, state, 1,
-                       (const int32_t*)nullptr, 0);
+    cb_chol(st, G, f, H2, H2i, dg_scr, dead_scr, mask_scr, 0, 0, state, 1);
     hipLaunchKernelGGL((k_sq_prod<double, true, true, false>), grid, dim3(256), 0, st, Z1, H2i, f, Qout, (int64_t)f);
     hipLaunchKernelGGL((k_sq_prod<T, true, true, true>), grid, dim3(256), 0, st, H2, H1, f, Dout, ldd);
     LAUNCHCHK();
@@ -1052,7 +1060,8 @@ int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, cons
     TRY(ops.apply(a1, nullptr, (int)r));
     TRY(gram_chol<T>(ctx, st, w, cb, g.ldk, g.nn, (int)r, w.gbig, c2));
   }
-  TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st, gate, r_dev, w.sq128, w.deadbig));
+  TRY(small_qr<T>(ctx, st, w.rb1, w.rb2, (int)r, w.rb4, Dout, ldd, w.st, gate, r_dev, w.sq128, w.deadbig, w.dg,
+                  w.cbmask));
   const ApplyJob jv{cb, g.ldk, Vout, ldv, w.rb5, g.nn, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
   const ApplyJob ju{q, g.ldy, Uout, ldu, w.rb4, g.mm, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
   TRY(ops.apply(jv, &ju, (int)r, nullptr, 0, gate));
@@ -1807,7 +1816,7 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
                            rank, rank, rank, 1);
         LAUNCHCHK();
         TRY(small_qr<T>(ctx, st, nullptr, w.rb2, (int)rank, w.rb4, (T*)core, g.r_cap, w.st, Gate{}, nullptr,
-                        w.sq128, w.deadbig));
+                        w.sq128, w.deadbig, w.dg, w.cbmask));
         const ApplyJob ju{w.cbuf, g.ldk, Ut, m, w.rb4, m, 0, (int)rank, (int)rank, nullptr, nullptr, nullptr};
         TRY(ops.apply(ju, nullptr, (int)rank));
         TRY(copy2d<T>(ctx, st, ut, g.ldy, (T*)Vt, n, rank, n, 0));

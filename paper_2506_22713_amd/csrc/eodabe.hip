@@ -274,10 +274,11 @@ WS carve(void* base, const Geo& g) {
   w.cpart = c.take<char>((int64_t)g.s_core * rc * g.ldk * e);
   w.ybig = c.take<char>(g.ldy * rc * e);
   const int64_t rb = std::max<int64_t>(rc, g.bn);
-  // Gram partials of the closing QRs: 64 of up to 64 x 64, or GRAM_SPLITS_WIDE + 1
-  // of rb x rb (the K-split partials of a wider Gram and their sum)
-  w.gbig = c.take<double>(std::max<int64_t>(64 * std::min<int64_t>(rb, 64) * std::min<int64_t>(rb, 64),
-                                            (GRAM_SPLITS_WIDE + 1) * rb * rb));
+  // Gram partials of the closing QRs: 64 of up to 128 x 128 (the K-split
+  // partials of a Gram of at most 128 columns and their sum), or
+  // GRAM_SPLITS_WIDE + 1 of rb x rb (wider)
+  const int64_t rb128 = std::min<int64_t>(rb, 128);
+  w.gbig = c.take<double>(std::max<int64_t>(64 * rb128 * rb128, (GRAM_SPLITS_WIDE + 1) * rb * rb));
   w.rb1 = c.take<double>(rb * rb);
   w.rb2 = c.take<double>(rb * rb);
   w.rb3 = c.take<double>(rb * rb);
@@ -618,12 +619,16 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
   if (ca.norm_parts)
     hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(256), 0, st, ca.norm_parts, ca.max_parts, ca.n_norm,
                        w.st);
-  // G = X^T X as K-split partials (about 512 rows each), summed in fixed order
-  const int gs = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_SPLITS_WIDE, rows / 512));
+  // G = X^T X as K-split partials summed in fixed order: up to 63 splits of
+  // at least 64 rows for f <= 128 (the partial buffers hold 64 such
+  // matrices; more splits put more workgroups on the FP64 products),
+  // GRAM_SPLITS_WIDE of at least 512 rows above
+  const int gs = (int)std::max<int64_t>(
+      1, f <= 128 ? std::min<int64_t>(63, rows / 64) : std::min<int64_t>(GRAM_SPLITS_WIDE, rows / 512));
   const int64_t ff = (int64_t)f * f;
   double* gsum = parts + (int64_t)gs * ff;
   TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, gs, parts, f, ff, nullptr, nullptr, stopb, blk));
-  TRY(ops.reduce(parts, eff_splits(rows, gs), ff, ff, gsum, stopb, blk));
+  TRY(ops.reduce_wide(parts, eff_splits(rows, gs), ff, ff, gsum, stopb, blk));
   parts = gsum;
   if (f <= 128 && stopb)       // a block of the basis loop: one workgroup, with the stop check
     hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, ca.dead, ca.first_pass,

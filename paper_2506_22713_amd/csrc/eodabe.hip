@@ -789,8 +789,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       prof_attach(ctx, ops, -1);
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, (int)j,
                (double)g.elem * ((double)g.mm * g.nn + (double)g.nn * fw + (double)g.mm * fw));
-      TRY(ops.reduce((const T*)w.ypart_w, eff_splits(g.nn, g.s_sketch), ystride, ystride, (T*)w.y_w, stopb,
-                     (int)j));
+      TRY(ops.reduce_wide((const T*)w.ypart_w, eff_splits(g.nn, g.s_sketch), ystride, ystride, (T*)w.y_w,
+                          stopb, (int)j));
       pre_j0 = j;
       pre_j1 = j + kw;
       jend = pre_j1;
@@ -835,7 +835,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       prof_attach(ctx, ops, -1);
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
                abytes + (double)g.elem * ((double)g.nn * f + (double)g.mm * f));
-      if (j > 0) TRY(ops.reduce((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+      if (j > 0) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       }
       // a3 + a4: two rounds of [project against the basis so far (width
       // wlog[j] <= j*b), FP64-Gram Cholesky, triangular solve]: block
@@ -1967,7 +1967,7 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
     } else {
       TRY(ops.sketch(Ae, la, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, nullptr, nullptr, 0));
     }
-    TRY(ops.reduce((const T*)yp, eff_splits(n, (int)p.s), ystr, ystr, yr));
+    TRY(ops.reduce_wide((const T*)yp, eff_splits(n, (int)p.s), ystr, ystr, yr));
     TRY(copy2d<T>(ctx, st, yr, ldyp, (T*)Y, ldy, ncols, m, 0));
     HIPCHK(hipStreamSynchronize(st));
     return 0;

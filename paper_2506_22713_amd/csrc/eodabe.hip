@@ -1010,7 +1010,7 @@ int small_qr(eodabe_ctx* ctx, hipStream_t st, const double* R1, const double* R2
 // by the partial buffer (planned for r_cap) and by 256 rows per split.
 int core_splits(const Geo& g, int64_t r) {
   const int64_t tiles = cdiv(g.nn, 256) * cdiv(r, 16 * std::min<int64_t>(4, cdiv(r, 16)));
-  int64_t sc = std::max<int64_t>(1, cdiv(256, tiles));
+  int64_t sc = std::max<int64_t>(1, cdiv(r > 64 ? 512 : 256, tiles));   // more waves when MFMA-bound
   sc = std::min<int64_t>(sc, std::max<int64_t>(1, g.mm / 256));
   sc = std::min<int64_t>(sc, std::max<int64_t>(1, ((int64_t)g.s_core * std::max<int64_t>(g.r_cap, 1)) / r));
   return (int)std::min<int64_t>(sc, 1024);

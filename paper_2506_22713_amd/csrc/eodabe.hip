@@ -553,27 +553,29 @@ CholArgs chol_args(const WS& w, double* R, int32_t* dead, int first, int fresh, 
 // block products of a step on separate workgroups, R^{-1} by recursive
 // doubling.  dg: f doubles; cbmask: one word per 64-column panel.
 void cb_chol(hipStream_t st, double* G, int f, double* R, double* Rinv, double* dg, int32_t* dead,
-             uint64_t* cbmask, int first_pass, int fresh, State* state, int count_floors) {
+             uint64_t* cbmask, int first_pass, int fresh, State* state, int count_floors,
+             const int32_t* stopb = nullptr, int blk = 0) {
   const int P = (int)cdiv(f, 64);
   const int64_t ff = (int64_t)f * f;
   hipLaunchKernelGGL(k_cb_init, dim3((unsigned)std::min<int64_t>(cdiv(ff, 256), 1024)), dim3(256), 0, st, G, f, f,
-                     R, Rinv, dg, dead, fresh);
+                     R, Rinv, dg, dead, fresh, stopb, blk);
   hipLaunchKernelGGL(k_cb_diag, dim3(1), dim3(256), 0, st, G, f, f, 0, R, Rinv, dg, dead, cbmask, first_pass,
-                     state, count_floors);
+                     state, count_floors, stopb, blk);
   for (int p = 0; p + 1 < P; ++p) {
-    hipLaunchKernelGGL(k_cb_row, dim3(P - p - 1), dim3(256), 0, st, G, f, f, p, R, Rinv, dead, cbmask);
+    hipLaunchKernelGGL(k_cb_row, dim3(P - p - 1), dim3(256), 0, st, G, f, f, p, R, Rinv, dead, cbmask, stopb,
+                       blk);
     // trailing update of step p with the diagonal step p+1 on its workgroup 0
     hipLaunchKernelGGL(k_cb_look, dim3((P - p - 1) * (P - p) / 2), dim3(256), 0, st, G, f, f, p, R, Rinv, dg,
-                       dead, cbmask, first_pass, state, count_floors);
+                       dead, cbmask, first_pass, state, count_floors, stopb, blk);
   }
   for (int L = 1; L < P; L *= 2) {                       // R^{-1} by recursive doubling
     int nb = 0;
     for (int a = 0; a + L < P; a += 2 * L) nb += L * (std::min(a + 2 * L, P) - (a + L));
     if (L == 1) {
-      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 2);
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 2, stopb, blk);
     } else {
-      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 0);
-      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 1);
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 0, stopb, blk);
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 1, stopb, blk);
     }
   }
 }
@@ -582,11 +584,10 @@ void cb_chol(hipStream_t st, double* G, int f, double* R, double* Rinv, double* 
 // FP64, element (i,j) at j*f + i, Z rounded to T and written over X), then
 // the Cholesky with the floor/kill rules and the epilogues in ca (R,
 // R^{-1}, stop test, ||A||_F finish).  f <= 64: one launch (k_gram_rows; its last workgroup runs the
-// Cholesky with inverse).  64 < f <= 128: generic GEMM, then the 2 x 2-
-// blocked Cholesky with inverse on one workgroup (k_chol128), separate stop
-// test.  Wider: generic GEMM, panel-blocked Cholesky with inverse as one
-// kernel per step (k_cb_*, the Gram overwritten).  Above 64 columns ca.Rinv
-// is required and there is no fused W.
+// Cholesky with inverse).  Wider: generic GEMM as K-split partials, then the
+// panel-blocked Cholesky with inverse as one kernel per step (k_cb_*, the
+// Gram overwritten), separate stop test.  Above 64 columns ca.Rinv is
+// required and there is no fused W.
 template <typename T>
 int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, int64_t rows, int f,
               double* parts, const CholArgs& ca, const int32_t* stopb = nullptr, int blk = 0,
@@ -630,11 +631,10 @@ int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, in
   TRY(ops.template gemm_nt<double>(X, ld, X, ld, f, f, rows, gs, parts, f, ff, nullptr, nullptr, stopb, blk));
   TRY(ops.reduce_wide(parts, eff_splits(rows, gs), ff, ff, gsum, stopb, blk));
   parts = gsum;
-  if (f <= 128 && stopb)       // a block of the basis loop: one workgroup, with the stop check
-    hipLaunchKernelGGL(k_chol128, dim3(1), dim3(256), 0, st, parts, f, ca.R, ca.Rinv, ca.dead, ca.first_pass,
-                       ca.fresh, w.st, ca.count_floors, stopb, blk);
-  else                         // panel-blocked, one kernel per step (see k_cb_*)
-    cb_chol(st, parts, f, ca.R, ca.Rinv, w.dg, ca.dead, w.cbmask, ca.first_pass, ca.fresh, w.st, ca.count_floors);
+  // panel-blocked, one kernel per step (see k_cb_*); every step returns at
+  // once for a speculative block after the stop
+  cb_chol(st, parts, f, ca.R, ca.Rinv, w.dg, ca.dead, w.cbmask, ca.first_pass, ca.fresh, w.st, ca.count_floors,
+          stopb, blk);
   if (ca.R1)
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, ca.R1, ca.R, ca.dead, f, ca.col0, ca.n, w.st,
                        ca.wlog, ca.acc, ca.diag_log, blk);

@@ -1611,30 +1611,6 @@ __device__ int small_qr_mid(double* lds, const double* R1g, const double* R2g, i
   return nf;
 }
 
-// Cholesky with inverse (chol_inv128) of an f x f Gram matrix, 64 < f <=
-// 128, on one workgroup: G, R, R^{-1} column-major f x f (element (i,j) at
-// j*f + i); dead: per-column flags, read unless fresh, written back; the
-// floored pivots are added to st->floored when count_floors.
-__global__ __launch_bounds__(256) void k_chol128(const double* __restrict__ G, int f, double* __restrict__ R,
-                                                 double* __restrict__ Rinv, int32_t* __restrict__ dead,
-                                                 int first_pass, int fresh, State* st, int count_floors,
-                                                 const int32_t* __restrict__ stop_block, int block_id) {
-  __shared__ double lds[CHOL128_LDS];
-  if (stop_block && *stop_block < block_id) return;
-  uint64_t d0 = 0, d1 = 0;
-  if (!fresh)
-    for (int c = 0; c < f; ++c)
-      if (dead[c]) {
-        if (c < 64) d0 |= 1ull << c;
-        else d1 |= 1ull << (c - 64);
-      }
-  __syncthreads();
-  uint64_t o0 = 0, o1 = 0;
-  const int nf = chol_inv128<true>(G, f, f, R, Rinv, lds, d0, d1, first_pass, &o0, &o1);
-  for (int c = threadIdx.x; c < f; c += 256) dead[c] = (int32_t)(((c < 64) ? (o0 >> c) : (o1 >> (c - 64))) & 1ull);
-  if (count_floors && threadIdx.x == 0 && nf && st) atomicAdd(&st->floored, nf);
-}
-
 // One f x f FP64 product of the split closing QR (64 < f <= 128): out =
 // op(A) op(B), both operands column-major with leading dimension f, element
 // (i,k) of op(A) at TA ? A[k*f + i] : A[i*f + k], (k,j) of op(B) at TB ?
@@ -1703,7 +1679,9 @@ __global__ __launch_bounds__(256) void k_small_qr128(const double* __restrict__ 
 __device__ __forceinline__ int cb_width(int f, int p) { return (f - 64 * p) < 64 ? f - 64 * p : 64; }
 
 __global__ void k_cb_init(const double* __restrict__ G, int ld, int f, double* __restrict__ R,
-                          double* __restrict__ Rinv, double* __restrict__ dg, int32_t* __restrict__ dead, int fresh) {
+                          double* __restrict__ Rinv, double* __restrict__ dg, int32_t* __restrict__ dead, int fresh,
+                          const int32_t* __restrict__ stopb, int blk) {
+  if (stopb && *stopb < blk) return;       // a speculative block after the stop
   const int64_t nt = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)f * f; idx += nt) {
     const int j = (int)(idx / f), i = (int)(idx - (int64_t)j * f);
@@ -1722,7 +1700,8 @@ __global__ __launch_bounds__(256) void k_cb_diag(const double* __restrict__ G, i
                                                  double* __restrict__ R, double* __restrict__ Rinv,
                                                  const double* __restrict__ dg, int32_t* __restrict__ dead,
                                                  uint64_t* __restrict__ nolive, int first_pass, State* st,
-                                                 int count_floors) {
+                                                 int count_floors, const int32_t* __restrict__ stopb, int blk) {
+  if (stopb && *stopb < blk) return;       // a speculative block after the stop
   typedef SmallCfg<64> S;
   constexpr int LD = S::LD;
   __shared__ double Gs[S::SIZE], Ri[S::SIZE], work[24 * 64], dgs[64];
@@ -1747,7 +1726,9 @@ __global__ __launch_bounds__(256) void k_cb_diag(const double* __restrict__ G, i
 
 __global__ __launch_bounds__(256) void k_cb_row(const double* __restrict__ G, int ld, int f, int p,
                                                 double* __restrict__ R, const double* __restrict__ Rinv,
-                                                const int32_t* __restrict__ dead, const uint64_t* __restrict__ nolive) {
+                                                const int32_t* __restrict__ dead, const uint64_t* __restrict__ nolive,
+                                                const int32_t* __restrict__ stopb, int blk) {
+  if (stopb && *stopb < blk) return;       // a speculative block after the stop
   const int q = p + 1 + blockIdx.x, k0 = 64 * p, c0 = 64 * q;
   const int pw = cb_width(f, p), qw = cb_width(f, q);
   const uint64_t nl = nolive[p];
@@ -1764,7 +1745,8 @@ __global__ __launch_bounds__(256) void k_cb_look(double* __restrict__ G, int ld,
                                                  double* __restrict__ R, double* __restrict__ Rinv,
                                                  const double* __restrict__ dg, int32_t* __restrict__ dead,
                                                  uint64_t* __restrict__ nolive, int first_pass, State* st,
-                                                 int count_floors) {
+                                                 int count_floors, const int32_t* __restrict__ stopb, int blk) {
+  if (stopb && *stopb < blk) return;       // a speculative block after the stop
   typedef SmallCfg<64> S;
   constexpr int LD = S::LD;
   __shared__ double sm[GMM64S_LDS];
@@ -1808,7 +1790,9 @@ __global__ __launch_bounds__(256) void k_cb_look(double* __restrict__ G, int ld,
 }
 
 __global__ __launch_bounds__(256) void k_cb_inv(const double* __restrict__ R, double* __restrict__ Rinv,
-                                                double* __restrict__ G, int ld, int f, int L, int stage) {
+                                                double* __restrict__ G, int ld, int f, int L, int stage,
+                                                const int32_t* __restrict__ stopb, int blk) {
+  if (stopb && *stopb < blk) return;       // a speculative block after the stop
   constexpr int LD = SmallCfg<64>::LD;
   __shared__ double Acc[64 * LD];
   __shared__ double sm[GMM64S_LDS];

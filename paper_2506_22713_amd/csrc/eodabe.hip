@@ -1076,16 +1076,18 @@ int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, cons
 // Alg. 2 after Alg. 1: power iteration, C = Q^T A, QR(C^T), QR(R^T).
 // Writes U_hat (column-major mm x r, ld ldu) to Uout, V_hat^T (r x nn,
 // row-major ldv) to Vout and D_hat (r x r row-major, ldd) to Dout.
+// extra_iters: subspace iterations on top of opts.power_iters (the
+// low-precision form's FP32 refinement of its basis).
 template <typename T>
 int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, int64_t r,
-              T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout, int64_t ldd) {
+              T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout, int64_t ldd, int extra_iters) {
   if (r <= 0) return 0;
   Ops<T> ops{ctx, st};
   T* q = (T*)w.q;
   T* cb = (T*)w.cbuf;
   const int64_t cstride = r * g.ldk;
   const int s_core = core_splits(g, r);
-  for (int it = 0; it < ctx->o.power_iters; ++it) {
+  for (int it = 0; it < ctx->o.power_iters + extra_iters; ++it) {
     // Y~^T = Q^T A (r x nn), QR(Y~) -> Q~ (stored as Q~^T = cbuf rows)
     TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
     TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb));
@@ -1768,7 +1770,7 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
     // With a small enough basis the closing steps are enqueued right behind
     // each chunk of blocks, gated on the device-side stop flag, so a
     // factorization that stops in its first chunk needs one host sync.
-    const bool can_spec = !g.transposed && !basis_only && ctx->o.power_iters == 0;
+    const bool can_spec = !g.transposed && !basis_only && ctx->o.power_iters == 0 && !g.lp;
     auto after_chunk = [&](int64_t jend) -> int {
       if (!can_spec) return 0;
       const int64_t rb = std::min<int64_t>(g.nn, jend * (int64_t)g.b);
@@ -1805,13 +1807,20 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
       if (ctx->host_state->floored) info->status_flags |= 4;
       return 0;
     }
+    // Low-precision form: a basis built from sketches of the FP16/BF16 copy
+    // of A is tilted from the one FP32 sketches give by up to the copy's
+    // rounding over the weakest captured singular value.  One FP32 subspace
+    // iteration (Alg. 2, power iteration) maps it back through A and A^T
+    // before the FP32 projection, so the error is won back.
+    const int refine = (g.lp && blocks >= 3) ? 1 : 0;
+    if (refine) info->status_flags |= 16;
     if (!g.transposed) {
-      TRY(run_close<T>(ctx, st, g, w, Ae, rank, (T*)Ut, m, (T*)Vt, n, (T*)core, g.r_cap));
+      TRY(run_close<T>(ctx, st, g, w, Ae, rank, (T*)Ut, m, (T*)Vt, n, (T*)core, g.r_cap, refine));
     } else {
       // factor of A^T = U' D' V'^T (U' nn... here mm = n rows): A = V' D'^T U'^T.
       // U' -> ybig (column-major n x r), V'^T -> cbuf (r x m), D' -> rb_tmp
       T* ut = (T*)w.ybig;            // U' column-major (ld = ldy)
-      TRY(run_close<T>(ctx, st, g, w, Ae, rank, ut, g.ldy, (T*)w.cbuf, g.ldk, (T*)w.tbig, rank));
+      TRY(run_close<T>(ctx, st, g, w, Ae, rank, ut, g.ldy, (T*)w.cbuf, g.ldk, (T*)w.tbig, rank, refine));
       Ops<T> ops{ctx, st};
       if (rank <= 128) {
         // QR(D'^T) = Q'' R'' on one workgroup: D' column-major (FP64) -> rb2;

@@ -68,23 +68,28 @@ def check_factor(A64, dtype, tol, b=32, q=0, seed=0, stable=True, rounding_only=
     form a square sketch of an r-dimensional range); the FP32 path carries
     the same amplification of its unit roundoff, and its bar is widened to
     4 (u32/u64) times the oracle's RelErr."""
-    say("factor", A64.shape, dtype, "tol", tol, "b", b, "q", q, "seed", seed)
+    say("factor", A64.shape, dtype, "tol", tol, "b", b, "q", q, "seed", seed, "stable", stable)
     ref = O.eod_abe(A64, tol, k=b, q=q, seed=seed)
     f = E.factor(dev(A64, dtype), tol, block=b, power_iters=q, seed=seed)
     torch.cuda.synchronize()
+    cmp = ref
     if stable:
         assert f.rank == ref.rank, (f.rank, ref.rank)
+    elif f.rank != ref.rank:
+        # a precision-unstable rank decision: the GPU must land on the other
+        # side's rank, that of the oracle's FP32-data emulation, and is
+        # compared with that run
+        cmp = O.eod_abe(A64, tol, k=b, q=q, seed=seed, sketch_dtype=np.float32)
+        assert f.rank == cmp.rank, (f.rank, ref.rank, cmp.rank)
     if f.rank == 0:
         return f, ref
     e_gpu, U, D, Vt = gpu_relerr(A64, f)
-    e_ref = O.rel_err(A64, ref.U, ref.D, ref.V)
-    if f.rank == ref.rank:
-        bar = RELERR_TOL[dtype]
-        if dtype == torch.float32:
-            bar = max(bar, fp32_floor(f.rank, *A64.shape))
-            if rounding_only:
-                bar = max(bar, 4.0 * (U32 / U64) * e_ref)
-        assert abs(e_gpu - e_ref) <= bar, (e_gpu, e_ref, bar)
+    e_ref = O.rel_err(A64, cmp.U, cmp.D, cmp.V)
+    bar = RELERR_TOL[dtype]
+    if dtype == torch.float32 and rounding_only:
+        bar = max(bar, fp32_floor(f.rank, *A64.shape), 4.0 * (U32 / U64) * e_ref)
+    say(f"  rank {f.rank} relerr gpu {e_gpu:.3e} oracle {e_ref:.3e} diff {abs(e_gpu - e_ref):.2e} bar {bar:.1e}")
+    assert abs(e_gpu - e_ref) <= bar, (e_gpu, e_ref, bar)
     r = f.rank
     assert np.linalg.norm(U.T @ U - np.eye(r)) <= ORTH_TOL[dtype] * math.sqrt(r)
     assert np.linalg.norm(Vt @ Vt.T - np.eye(r)) <= ORTH_TOL[dtype] * math.sqrt(r)
@@ -221,6 +226,16 @@ def test_factor_power_iteration(q):
     assert abs(e - ey) <= 1e-10
 
 
+@pytest.mark.parametrize("m,n", [(700, 400), (300, 650)])
+def test_factor_power_iteration_fp32(m, n):
+    # q = 1 in FP32, tall and wide (the wide one iterates on A^T): noisy
+    # content with a decaying spectrum, compared with the oracle at q = 1
+    A = W.lowrank_haar(31, m=m, n=n, r=60, noise_std=1e-6, decades=3.0).astype(np.float32).astype(np.float64)
+    stable, _, _ = O.precision_stable(A, 1e-4, 16, 31)
+    f, ref = check_factor(A, torch.float32, 1e-4, b=16, q=1, seed=31, stable=stable)
+    assert f.rank > 16
+
+
 def test_factor_wide_matrix():
     A = W.lowrank_haar(4, m=150, n=420, r=12, noise_std=0.0)
     check_factor(A, torch.float64, 1e-9, b=8, seed=4)
@@ -279,7 +294,7 @@ def test_factor_many_split_partials(m, n, dtype):
     # (more than its 16-partial load batch, ragged in the second batch)
     A = W.lowrank_haar(17, m=m, n=n, r=40, noise_std=0.0)
     tol = 1e-9 if dtype == torch.float64 else 1e-4
-    f, ref = check_factor(A, dtype, tol, b=32, seed=17)
+    f, ref = check_factor(A, dtype, tol, b=32, seed=17, rounding_only=True)
     assert f.rank == 40
 
 
@@ -319,7 +334,7 @@ def test_factor_degenerate_sides(m, n, r, dtype, tol, b):
     # one or two rows or columns: a single K step, panels of one column,
     # the transposed orientation for the wide ones
     A = W.lowrank_haar(11, m=m, n=n, r=r, noise_std=0.0)
-    f, ref = check_factor(A, dtype, tol, b=b, seed=11)
+    f, ref = check_factor(A, dtype, tol, b=b, seed=11, rounding_only=True)
     assert f.rank == r
 
 
@@ -444,6 +459,16 @@ def test_hyperspectral_small_fp32():
     check_factor(A, torch.float32, 1e-2, b=16, seed=0, stable=stable)
 
 
+def test_hyperspectral_full_size_fp32():
+    # the full 262144 x 200 hyperspectral workload (512 x 512 pixels x 200
+    # bands, 15 endmembers) at tol 1e-2 and b = 16, against the oracle
+    say("hyperspectral 262144 x 200")
+    A = W.hyperspectral(0).astype(np.float64)
+    stable, _, _ = O.precision_stable(A, 1e-2, 16, 0)
+    f, ref = check_factor(A, torch.float32, 1e-2, b=16, seed=0, stable=stable)
+    assert 10 <= f.rank <= 20
+
+
 def test_mat2_fp64():
     A = W.mat2(1, 600, 240)
     check_factor(A, torch.float64, 1e-12, b=32, seed=1)
@@ -466,55 +491,93 @@ def test_sketch_lp_kernel(mode):
     assert np.all(np.abs(Y - ref) <= bound + 1e-30)
 
 
-# Error bars of the low-precision form, as absolute differences of RelErr
-# from the FP64 oracle: FP16 (2^-11 relative rounding of A) within 1e-3;
-# BF16 (2^-8, about 1.6e-3 RMS relative rounding of A) within 2e-3.
-LP_ERR = {"f16": 1e-3, "bf16": 2e-3}
+# Error bar of the low-precision form (FP16 and BF16 alike): its RelErr
+# within 1e-3 of the oracle's emulation of the same form, absolute, and
+# never more than 1e-3 above the plain FP64 oracle's (the equal-error rule).
+# The emulation sketches blocks 3, 4, ... with the rounded copies of A and
+# Omega and then runs one subspace iteration on A, as the form is defined.
+LP_ERR = 1e-3
 
 
-def _check_lp_factor(A, tol, b, seed, mode, err_tol=None):
+def _check_lp_factor(A, tol, b, seed, mode):
+    say("lp factor", A.shape, mode, "tol", tol, "b", b, "seed", seed)
     code = E.SKETCH_F16 if mode == "f16" else E.SKETCH_BF16
     f = E.factor(dev(A, torch.float32), tol, block=b, seed=seed, sketch=code)
     torch.cuda.synchronize()
     ref = O.eod_abe(A, tol, k=b, q=0, seed=seed)
+    emu = O.eod_abe(A, tol, k=b, q=0, seed=seed, sketch_dtype=mode)
     stable, r64, rlp = O.precision_stable(A, tol, b, seed, mode)
     assert f.blocks >= 3                       # the low-precision blocks did run
+    assert f.flags & 16                        # ... and the FP32 refinement with them
     if stable:
-        assert f.rank == r64, (f.rank, r64, rlp)
+        assert f.rank == r64 == emu.rank, (f.rank, r64, rlp)
     else:
         assert f.rank in (r64, rlp), (f.rank, r64, rlp)
     e_gpu, U, D, Vt = gpu_relerr(A, f)
     e_ref = O.rel_err(A, ref.U, ref.D, ref.V)
-    if err_tol is None:
-        assert abs(e_gpu - e_ref) <= LP_ERR[mode], (e_gpu, e_ref)
-    else:
-        assert e_gpu <= err_tol, (e_gpu, e_ref)
+    e_emu = O.rel_err(A, emu.U, emu.D, emu.V)
+    say(f"  rank {f.rank} relerr gpu {e_gpu:.3e} form-oracle {e_emu:.3e} plain-oracle {e_ref:.3e}")
+    if f.rank == emu.rank:
+        assert abs(e_gpu - e_emu) <= LP_ERR, (e_gpu, e_emu)
+    assert e_gpu <= e_ref + LP_ERR, (e_gpu, e_ref)
     r = f.rank
     assert np.linalg.norm(U.T @ U - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
     assert np.linalg.norm(Vt @ Vt.T - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
-    return f, ref
+    assert np.all(np.tril(D, -1) == 0) and np.all(np.diag(D) >= 0)
+    return f, ref, e_gpu, e_emu
 
 
 def test_factor_f16_sketch_image():
-    say("factor f16 sketch image 1024")
     A = W.image(0, 1024, 0.05).astype(np.float64)
     _check_lp_factor(A, 1e-3, 8, 0, "f16")
 
 
 @pytest.mark.parametrize("mode", ["f16", "bf16"])
 def test_factor_lp_sketch_hyperspectral(mode):
-    say("factor lp sketch hyperspectral 16384", mode)
     A = W.hyperspectral(0, pixels=16384).astype(np.float64)
     _check_lp_factor(A, 1e-2, 4, 0, mode)
 
 
-def test_factor_f16_sketch_exact_rank():
-    say("factor f16 sketch exact rank")
-    # exact rank 40 with sigma_40 = sigma_1 / 10: the rank is exact, and the
-    # subspace tilt by ||A - A_f16|| / sigma_40 keeps RelErr under tol
+@pytest.mark.parametrize("mode", ["f16", "bf16"])
+def test_factor_lp_sketch_exact_rank(mode):
+    # exact rank 40 with sigma_40 = sigma_1 / 10.  FP16 rounding (2^-11)
+    # keeps the rank exact; BF16 (2^-8) tilts the sketched subspace by about
+    # ||A - A_bf16|| / sigma_40, which can keep a few rounding columns (the
+    # oracle's emulation gives 40..48).  Either way the refined error is the
+    # FP32 path's own, compared with the form's oracle.
     A = W.lowrank_haar(4, m=400, n=300, r=40, noise_std=0.0, decades=1.0).astype(np.float32).astype(np.float64)
-    f, ref = _check_lp_factor(A, 1e-2, 8, 4, "f16", err_tol=1e-2)
-    assert f.rank == 40
+    f, ref, e_gpu, e_emu = _check_lp_factor(A, 1e-2, 8, 4, mode)
+    if mode == "f16":
+        assert f.rank == 40
+    else:
+        assert 40 <= f.rank <= 48
+    assert abs(e_gpu - e_emu) <= 1e-5
+
+
+# Exact-rank instances (FP32-rounded, so their error is FP32 rounding) on
+# which a basis from the rounded sketches alone misses the oracle's RelErr
+# by 3.7e-3 .. 1.7e-2 at the same rank (found by a seeded sweep of the
+# oracle's emulation): the refinement brings the error back to the plain
+# path's.  (mode, sweep index, m, n, content rank, decades, tol, b)
+LP_SWEEP_CASES = [
+    ("f16", 201, 380, 538, 39, 1.449, 0.00309, 4),
+    ("f16", 229, 465, 267, 56, 1.998, 0.0011, 8),
+    ("f16", 145, 470, 474, 157, 0.712, 0.00746, 16),
+    ("f16", 155, 218, 478, 114, 0.842, 0.0099, 8),
+    ("bf16", 252, 359, 63, 20, 0.666, 0.011, 8),
+    ("bf16", 380, 558, 413, 73, 0.734, 0.0156, 8),
+    ("bf16", 358, 295, 499, 183, 0.622, 0.0453, 4),
+    ("bf16", 152, 598, 34, 17, 1.552, 0.0239, 4),
+]
+
+
+@pytest.mark.parametrize("case", LP_SWEEP_CASES, ids=lambda c: f"{c[0]}-{c[1]}")
+def test_factor_lp_sketch_sweep_cases(case):
+    mode, i, m, n, r, dec, tol, b = case
+    A = W.lowrank_haar(5000 + i, m=m, n=n, r=r, noise_std=0.0, decades=dec).astype(np.float32).astype(np.float64)
+    f, ref, e_gpu, e_emu = _check_lp_factor(A, tol, b, i, mode)
+    e_ref = O.rel_err(A, ref.U, ref.D, ref.V)
+    assert abs(e_gpu - e_ref) <= max(1e-5, fp32_floor(f.rank, m, n))
 
 
 @pytest.mark.parametrize("mode,tol", [("bf16", 1e-3), ("f16", 5e-4)])
@@ -544,7 +607,11 @@ def test_lp_sketch_at_its_floor_keeps_low_precision():
 
 # ------------------------------------------------- batched tiles
 def _batch_tiles():
+    """Tiles of the batched parity test and, per tile, whether its content is
+    noise-free (exact rank, or a full-rank Gaussian that the loop never
+    stops on), where the FP32 error is rounding alone."""
     tiles = W.tiles(5, count=22, lo=64, hi=1024, rank_lo=5, rank_hi=80, noise_std=1e-4)
+    clean = [False] * len(tiles)
     rng = np.random.default_rng(11)
     wide = (W.lowrank_haar(6, m=90, n=700, r=17, noise_std=0.0) * 100).astype(np.float32)
     tiles += [wide, np.zeros((64, 80), dtype=np.float32)]
@@ -554,18 +621,20 @@ def _batch_tiles():
     tiles += [(W.lowrank_haar(7, m=150, n=403, r=100, noise_std=0.0) * 50).astype(np.float32)]
     tiles += [(W.lowrank_haar(8, m=517, n=260, r=121, noise_std=0.0) * 50).astype(np.float32)]
     tiles += [(rng.standard_normal((300, 190)) * 3).astype(np.float32)]    # rank 190 > 128: regular path
-    return tiles
+    clean += [True] * (len(tiles) - len(clean))
+    return tiles, clean
 
 
 def test_batched_tiles_against_oracle():
     say("batched tiles")
-    tiles = _batch_tiles()
+    tiles, clean = _batch_tiles()
     c = E.Context(seed=3, block=32)
     dtiles = [dev(T.astype(np.float64), torch.float32) for T in tiles]
     bt = E.Batch(c, dtiles)
     bt.run(1e-4)
     torch.cuda.synchronize()
     assert set(bt.status.tolist()) <= {0}, bt.status
+    exempt = 0
     for t, T in enumerate(tiles):
         A = T.astype(np.float64)
         U, D, Vt, r, st = bt.result(t)
@@ -574,15 +643,25 @@ def test_batched_tiles_against_oracle():
         if not np.any(A):
             assert r == 0
             continue
-        stable, r64, _ = O.precision_stable(A, 1e-4, b, 3)
+        stable, r64, r32 = O.precision_stable(A, 1e-4, b, 3)
         if stable:
             assert r == ref.rank, (t, T.shape, r, ref.rank)
+        else:
+            exempt += 1
+            assert r in (r64, r32), (t, T.shape, r, r64, r32)
         Un, Dn, Vn = (x.double().cpu().numpy() for x in (U, D, Vt))
         e_gpu = np.linalg.norm(A - Un @ Dn @ Vn) / np.linalg.norm(A)
-        e_ref = O.rel_err(A, ref.U, ref.D, ref.V)
-        if r == ref.rank:
-            bar = max(RELERR_TOL[torch.float32], fp32_floor(r, *A.shape))
-            assert abs(e_gpu - e_ref) <= bar, (t, T.shape, e_gpu, e_ref, bar)
+        # the oracle run with the rank the GPU returned: FP64 when it agrees
+        # with it, else the oracle's FP32-data emulation (the other side of a
+        # precision-unstable rank decision)
+        cmp = ref if r == ref.rank else O.eod_abe(A, 1e-4, k=b, q=0, seed=3, sketch_dtype=np.float32)
+        assert cmp.rank == r, (t, T.shape, r, cmp.rank)
+        e_ref = O.rel_err(A, cmp.U, cmp.D, cmp.V)
+        bar = RELERR_TOL[torch.float32]
+        if clean[t]:
+            bar = max(bar, fp32_floor(r, *A.shape), 4.0 * (U32 / U64) * e_ref)
+        say(f"  tile {t} {T.shape} b {b} rank {r} relerr gpu {e_gpu:.3e} oracle {e_ref:.3e} bar {bar:.1e}")
+        assert abs(e_gpu - e_ref) <= bar, (t, T.shape, e_gpu, e_ref, bar)
         # equal error with the single-matrix FP32 path on the same tile
         f = E.factor(dtiles[t], 1e-4, ctx=E.Context(seed=3, block=b))
         e_one = float(torch.linalg.norm(dtiles[t].double() - f.U.double() @ f.D.double() @ f.Vt.double())
@@ -592,6 +671,7 @@ def test_batched_tiles_against_oracle():
         assert np.linalg.norm(Un.T @ Un - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
         assert np.linalg.norm(Vn @ Vn.T - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
         assert np.all(np.tril(Dn, -1) == 0) and np.all(np.diag(Dn) >= 0)
+    say(f"  precision-unstable tiles (rank checked against both sides): {exempt} of {len(tiles)}")
 
 
 def test_batched_replay_deterministic_and_tuner():

@@ -138,6 +138,44 @@ def test_siam_deterministic_bound(seed):
     assert O.eckart_young_relerr(A, r) ** 2 * nrm2 <= err2 * (1 + 1e-6)
 
 
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_siam_bound_closed_form_two_by_two(q):
+    # A = diag(s1, s2), one test column omega = (w1, w2)^T, r = 1.  By hand:
+    # Sigma_0 = s2, Lambda_1 = w1, Lambda_2 = w2, alpha = s2 / s1, so the
+    # bound is s2^2 (1 + alpha^(4q) w2^2 / w1^2).  The actual error of the
+    # rank-1 projection onto A omega (q = 0) is s1^2 s2^2 (w1^2 + w2^2) /
+    # (s1^2 w1^2 + s2^2 w2^2), which the bound must dominate.
+    s1, s2, w1, w2 = 3.0, 0.5, 0.7, -1.9
+    A = np.diag([s1, s2])
+    Om = np.array([[w1], [w2]])
+    got = O.siam_bound_sq(A, 1, Om, q=q)
+    want = s2 ** 2 * (1.0 + (s2 / s1) ** (4 * q) * w2 ** 2 / w1 ** 2)
+    assert abs(got - want) <= 1e-14 * want
+    if q == 0:
+        err2 = s1 ** 2 * s2 ** 2 * (w1 ** 2 + w2 ** 2) / (s1 ** 2 * w1 ** 2 + s2 ** 2 * w2 ** 2)
+        y = A @ Om
+        qv = y / np.linalg.norm(y)
+        assert abs(np.linalg.norm(A - qv @ (qv.T @ A)) ** 2 - err2) <= 1e-14
+        assert err2 <= got
+
+
+def test_siam_bound_tight_when_omega_in_leading_subspace():
+    # Omega = V_r G has Lambda_2 = 0: the bound collapses to ||Sigma_0||_F^2,
+    # and Q = orth(A Omega) = U_r makes the error exactly that, so an
+    # inflated or deflated bound fails one side
+    rng = np.random.default_rng(4)
+    A = W.lowrank_haar(8, m=60, n=40, r=40, noise_std=0.0, decades=2.0)
+    _, s, Vt = np.linalg.svd(A)
+    r = 7
+    Om = Vt[:r].T @ rng.standard_normal((r, r))
+    bound = O.siam_bound_sq(A, r, Om, q=0)
+    tail = float(np.sum(s[r:] ** 2))
+    assert abs(bound - tail) <= 1e-12 * tail
+    Qv = np.linalg.qr(A @ Om)[0]
+    err2 = np.linalg.norm(A - Qv @ (Qv.T @ A)) ** 2
+    assert abs(err2 - bound) <= 1e-10 * bound
+
+
 def test_no_better_than_eckart_young_on_decaying_spectrum():
     A = W.robustness("III", seed=3, n=200)
     for q in (0, 1, 2):
@@ -254,6 +292,85 @@ def test_precision_stability_margin():
     # rounding-dominated value: stable
     ok2, _, _ = O.precision_stable(A, 3e-2, 32, 121418)
     assert ok2
+
+
+def _fp32_alg1(A, eps, k, seed, order):
+    """Alg. 1 with FP32 data, written here independently of the oracle: the
+    sketch A Omega_j summed in one of three orders (BLAS sgemm; K in chunks
+    of 4 accumulated sequentially in FP32, as a 4-deep matrix-core step does;
+    K in chunks of 64 accumulated in reverse order), the projection twice in
+    FP32, Householder QR of the FP32 block in FP64.  Returns the rank and
+    the examined |T(l,l)|."""
+    m, n = A.shape
+    A32 = A.astype(np.float32)
+    Q = np.zeros((m, 0), dtype=np.float32)
+    d_all = []
+    c = 0
+    while c < n:
+        f = min(k, n - c)
+        Om = O.omega_columns(seed, n, c, f).astype(np.float32)
+        if order == "blas":
+            Y = A32 @ Om
+        else:
+            step = 4 if order == "seq4" else 64
+            starts = list(range(0, n, step))
+            if order == "rev64":
+                starts = starts[::-1]
+            Y = np.zeros((m, f), dtype=np.float32)
+            for s0 in starts:
+                Y = (Y + A32[:, s0:s0 + step] @ Om[s0:s0 + step]).astype(np.float32)
+        for _ in range(2):
+            Y = (Y - Q @ (Q.T @ Y)).astype(np.float32)
+        P, T = np.linalg.qr(Y.astype(np.float64))
+        d = np.abs(np.diag(T))
+        hit = np.nonzero(d <= eps)[0]
+        if hit.size:
+            d_all.extend(d[: hit[0] + 1])
+            return Q.shape[1] + int(hit[0]), np.array(d_all)
+        d_all.extend(d)
+        Q = np.concatenate([Q, (P * np.sign(np.diag(T))).astype(np.float32)], axis=1)
+        c += f
+    return n, np.array(d_all)
+
+
+def test_precision_classifier_against_summation_orders():
+    # Ground truth for the classifier's band: exact-rank content (rounded to
+    # FP32, as the GPU receives it) whose column past the rank has an FP32
+    # |T(l,l)| made of rounding.  (1) The order-dependent part of that value
+    # under three valid FP32 summation orders lies within ORDER_SPREAD of the
+    # oracle emulation's.  (2) With eps within 3 % of the emulated value,
+    # some orders split the rank, and every split instance is classified
+    # unstable.  (3) With eps a factor 8 above it, outside the band, all
+    # orders agree and the instance is classified stable.
+    split, near_cases = 0, 0
+    S = O.ORDER_SPREAD
+    for s in range(8):
+        r = 6 + 3 * s
+        A = W.lowrank_haar(4200 + s, m=160 + 20 * s, n=60 + 10 * s, r=r, noise_std=0.0,
+                           decades=1.5).astype(np.float32).astype(np.float64)
+        nrm = np.linalg.norm(A)
+        d64 = O.basis_ext(A, 0.0, 16, s)["diagT"][r]
+        d_emu = O.basis_ext(A, 0.0, 16, s, np.float32)["diagT"][r]
+        rho_emu = math.sqrt(d_emu ** 2 - d64 ** 2)
+        for o in ("blas", "seq4", "rev64"):
+            d_o = _fp32_alg1(A, 0.0, 16, s, o)[1][r]
+            rho_o = math.sqrt(max(d_o ** 2 - d64 ** 2, 0.0))
+            assert rho_emu / S <= rho_o <= S * rho_emu, (s, o, rho_o, rho_emu)
+        for fac in (0.97, 0.99, 1.01, 1.03):
+            tol = fac * d_emu / nrm
+            ranks = {o: _fp32_alg1(A, tol * nrm, 16, s, o)[0] for o in ("blas", "seq4", "rev64")}
+            ok, r64, r32 = O.precision_stable(A, tol, 16, s)
+            near_cases += 1
+            if len(set(ranks.values())) > 1:
+                split += 1
+            assert not ok, (s, fac, ranks)          # inside the band
+            assert r64 == r                         # the FP64 run stops at the exact rank
+        tol = 8.0 * d_emu / nrm
+        ranks = {o: _fp32_alg1(A, tol * nrm, 16, s, o)[0] for o in ("blas", "seq4", "rev64")}
+        ok, r64, r32 = O.precision_stable(A, tol, 16, s)
+        assert set(ranks.values()) == {r} and ok and r64 == r32 == r, (s, ranks, ok)
+    # the near cases do split under some orders: the pin has teeth
+    assert split >= near_cases // 4, (split, near_cases)
 
 
 # ---------------------------------------------------------------- planted mistakes

@@ -44,6 +44,8 @@ typedef struct eodabe_ctx eodabe_ctx;
 #define EODABE_ENONFINITE    -4   /* A holds NaN or Inf (||A||_F is not finite) */
 #define EODABE_EHIP          -5   /* a HIP runtime call failed (see eodabe_last_hip_error) */
 #define EODABE_ENODEVICE     -6   /* no gfx950 device visible */
+#define EODABE_ESCRATCH      -7   /* eodabe_factor_noalloc: the problem needs more workspace than
+                                     EODABE_NOALLOC_SCRATCH_BYTES */
 #define EODABE_WTOL_FLOOR     1   /* warning: tol is below the data-type floor 8 u sqrt(n);
                                      rank decisions there are dominated by rounding */
 
@@ -134,6 +136,26 @@ size_t eodabe_workspace_size(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_
 int eodabe_factor(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda,
                   double tol, void* ws, size_t ws_bytes,
                   void* Ut, void* core, void* Vt, int64_t r_cap, eodabe_info* info);
+
+/* ---- factorization without device allocation ---------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * factorization as eodabe_factor, with the workspace taken from a static
+ * device array of EODABE_NOALLOC_SCRATCH_BYTES inside the library (one copy
+ * per GPU, held until the process ends; its address is looked up once per
+ * device by eodabe_create).  The call allocates nothing and calls no
+ * hipMalloc/hipFree; per-kernel timing (eodabe_profile) is suspended for it.
+ * The caller still owns A and the outputs, laid out as for eodabe_factor.
+ * Every call on a GPU shares that GPU's scratch, which keeps the last call's
+ * contents (each call initialises what it reads): calls that overlap on one
+ * GPU, from any context or stream, race and must be serialised by the
+ * caller.  Errors: those of eodabe_factor, and ESCRATCH when
+ * eodabe_workspace_size(m, n, r_cap) exceeds the scratch (e.g. 4096 x 4096
+ * with r_cap = 0 needs 3.3 GiB; with r_cap = 64, 2048 x 2048 FP32 needs
+ * 46 MiB and fits). */
+#define EODABE_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int eodabe_factor_noalloc(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda,
+                          double tol, void* Ut, void* core, void* Vt, int64_t r_cap, eodabe_info* info);
 
 /* Human-readable text for a status code (static storage). */
 const char* eodabe_strerror(int status);

@@ -32,6 +32,8 @@ EODABE_ECAPACITY = -3
 EODABE_ENONFINITE = -4
 EODABE_EHIP = -5
 EODABE_ENODEVICE = -6
+EODABE_ESCRATCH = -7
+NOALLOC_SCRATCH_BYTES = 64 << 20
 EODABE_WTOL_FLOOR = 1
 F32, F64 = 0, 1
 SKETCH_NATIVE, SKETCH_F16, SKETCH_BF16 = 0, 1, 2
@@ -44,6 +46,7 @@ EXPORTED = [
     "eodabe_profile", "eodabe_profile_read",
     "eodabe_mlp_param_count", "eodabe_mlp_workspace_size", "eodabe_mlp_forward", "eodabe_mlp_grad",
     "eodabe_mlp_adam", "eodabe_mlp_features", "eodabe_set_predictor", "eodabe_last_prediction",
+    "eodabe_factor_noalloc",
 ]
 PROF_SKETCH, PROF_PROJECT, PROF_TILES = 0, 1, 2
 
@@ -75,6 +78,9 @@ _lib.eodabe_workspace_size.restype = _sz
 _lib.eodabe_factor.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, _vp, _sz,
                                _vp, _vp, _vp, _i64, ctypes.POINTER(Info)]
 _lib.eodabe_factor.restype = ctypes.c_int
+_lib.eodabe_factor_noalloc.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double,
+                                       _vp, _vp, _vp, _i64, ctypes.POINTER(Info)]
+_lib.eodabe_factor_noalloc.restype = ctypes.c_int
 _lib.eodabe_basis.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, _vp, _sz, _vp, _i64,
                               ctypes.POINTER(ctypes.c_double), _i64, ctypes.POINTER(Info)]
 _lib.eodabe_basis.restype = ctypes.c_int
@@ -265,6 +271,24 @@ def factor(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int =
     st = _lib.eodabe_factor(ctx.h, A.data_ptr(), m, n, lda, float(tol), ws.data_ptr(), ws.numel(),
                             Ut.data_ptr(), core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
     ctx._check(st, "eodabe_factor")
+    r = int(info.rank)
+    return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
+                         float(info.norm_a), st, int(info.status_flags), float(info.relres_est))
+
+
+def factor_noalloc(A: torch.Tensor, tol: float, ctx: Context, out, r_cap: int = 0) -> Factorization:
+    """eodabe_factor_noalloc: eodabe_factor with the library's static device
+    scratch as workspace.  The caller passes the outputs (Ut, core, Vt as
+    alloc_outputs returns them); nothing is allocated on the device here."""
+    _check_matrix(A, ctx.dtype)
+    m, n = A.shape
+    rc = r_cap or min(m, n)
+    Ut, core, Vt = out
+    info = Info()
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    st = _lib.eodabe_factor_noalloc(ctx.h, A.data_ptr(), m, n, lda, float(tol), Ut.data_ptr(),
+                                    core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
+    ctx._check(st, "eodabe_factor_noalloc")
     r = int(info.rank)
     return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
                          float(info.norm_a), st, int(info.status_flags), float(info.relres_est))

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -20,6 +21,18 @@
 #include "eodabe_mlp.hpp"
 
 using namespace eodabe;
+
+// Scratch of eodabe_factor_noalloc: a fixed device array in the library's
+// code object, one copy per GPU.  Host code must not take this name as a
+// device address: its per-device address comes from hipGetSymbolAddress
+// (scratch_dev below), fetched once per device at context creation.
+static __device__ __align__(256) unsigned char scratch[EODABE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[MAX_DEVICES] = {};
+}  // namespace
 
 struct eodabe_ctx {
   eodabe_opts o;
@@ -51,6 +64,7 @@ struct eodabe_ctx {
   int tile_b[4] = {0, 0, 0, 0};   // block width per tile-size bucket (0: opts.block)
   int tile_graphs = 1;            // capture the launch in a hipGraph
   // learned warm start (eodabe_set_predictor): device parameters of the MLP
+  void* scratch = nullptr;        // this device's copy of the static scratch array
   const float* pred_params = nullptr;
   double pred_margin = 0.1;
   struct { int64_t d0 = 0; double y0 = 0, y1 = 0; int used = 0; } pred_last;
@@ -1646,6 +1660,22 @@ int eodabe_create(eodabe_ctx** out, const eodabe_opts* opts) {
     delete c;
     return EODABE_EHIP;
   }
+  // device address of this GPU's copy of the no-allocation scratch, looked up
+  // once per device with the device current
+  if (dev < MAX_DEVICES) {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        (void)hipHostFree(c->host_state);
+        delete c;
+        return EODABE_EHIP;
+      }
+      scratch_dev[dev] = p;
+    }
+    c->scratch = scratch_dev[dev];
+  }
   c->host_wlog = nullptr;
   c->host_wlog_cap = 0;
   c->host_only = false;
@@ -1699,6 +1729,7 @@ const char* eodabe_strerror(int s) {
     case EODABE_ENONFINITE: return "A holds NaN or Inf";
     case EODABE_EHIP: return "HIP runtime error";
     case EODABE_ENODEVICE: return "no gfx950 device";
+    case EODABE_ESCRATCH: return "the problem needs more workspace than the static scratch holds";
     case EODABE_WTOL_FLOOR: return "warning: tol below the data-type floor";
     default: return "unknown status";
   }
@@ -1867,6 +1898,25 @@ int eodabe_factor(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
                   eodabe_info* info) {
   return factor_impl(ctx, A, m, n, lda, tol, ws, ws_bytes, Ut, core, Vt, r_cap, info, nullptr,
                      nullptr, 0, false);
+}
+
+int eodabe_factor_noalloc(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda,
+                          double tol, void* Ut, void* core, void* Vt, int64_t r_cap, eodabe_info* info) {
+  TRY(check_ctx(ctx));
+  if (!info) return EODABE_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  TRY(check_dev(ctx));
+  if (!ctx->scratch) return EODABE_ENODEVICE;
+  const size_t need = eodabe_workspace_size(ctx, m, n, r_cap);
+  if (need == 0) return EODABE_EINVAL;
+  if (need > (size_t)EODABE_NOALLOC_SCRATCH_BYTES) return EODABE_ESCRATCH;
+  // per-kernel timing would create events; it is suspended for this call
+  const bool prof = ctx->prof_on;
+  ctx->prof_on = false;
+  const int s = factor_impl(ctx, A, m, n, lda, tol, ctx->scratch, (size_t)EODABE_NOALLOC_SCRATCH_BYTES,
+                            Ut, core, Vt, r_cap, info, nullptr, nullptr, 0, false);
+  ctx->prof_on = prof;
+  return s;
 }
 
 int eodabe_basis(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, double tol,

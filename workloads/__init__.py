@@ -16,6 +16,15 @@ which are not available):
 * ``hyperspectral``  pixels x bands = Dirichlet abundances x smooth spline
                      endmember spectra + noise (stand-in for Indian Pines,
                      section 4.2).
+* ``rgb_image``      three channels of ``image`` (independent seeds): a
+                     colour-image stand-in (section 4.1 uses 512 x 512 and
+                     768 x 512 photographs).
+* ``exact_rank_rgb`` three non-negative channels of chosen exact ranks in
+                     [0, 255] (the 220 x 220 example of the introduction,
+                     ranks 50, 52, 53).
+* ``hyperspectral_labelled``  the hyperspectral matrix with a class label
+                     per pixel (its dominant endmember) and a seeded fold
+                     index for ten-fold cross-validation (section 4.2).
 * ``tiles``          many image tiles of uneven size, each of exact rank
                      rho in [5, 80] plus small noise.
 * ``mat2``           strictly rank-deficient U [Sigma 0; 0 0] V^T with sorted
@@ -32,8 +41,9 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["haar", "lowrank_haar", "image", "hyperspectral", "tiles",
-           "tile_shapes", "mat2", "robustness", "devils_stairs_sigma", "spectrum_sigma", "spectrum_torch"]
+__all__ = ["haar", "lowrank_haar", "image", "rgb_image", "exact_rank_rgb", "hyperspectral",
+           "hyperspectral_labelled", "tiles", "tile_shapes", "mat2", "robustness", "devils_stairs_sigma",
+           "spectrum_sigma", "spectrum_torch"]
 
 
 def haar(rng: np.random.Generator, n: int, r: int) -> np.ndarray:
@@ -104,6 +114,26 @@ def image(seed: int, size: int = 4096, noise_std: float = 0.5, blobs: int = 64,
     return img.astype(dtype)
 
 
+def rgb_image(seed: int, h: int = 512, w: int = 512, noise_std: float = 0.05,
+              dtype=np.float32) -> np.ndarray:
+    """channels x h x w colour image: channel c is ``image(3 seed + c)``."""
+    return np.stack([image(3 * seed + c, h, noise_std, width=w, dtype=np.float64)
+                     for c in range(3)]).astype(dtype)
+
+
+def exact_rank_rgb(seed: int, h: int = 220, w: int = 220, ranks=(50, 52, 53),
+                   dtype=np.float32) -> np.ndarray:
+    """Non-negative channels of exact ranks: channel c = W_c H_c with W_c
+    (h x r_c) and H_c (r_c x w) uniform in [0, 1], scaled so the largest
+    entry is 255."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in ranks:
+        C = rng.uniform(0, 1, (h, r)) @ rng.uniform(0, 1, (r, w))
+        out.append(C * (255.0 / C.max()))
+    return np.stack(out).astype(dtype)
+
+
 def _clamped_spline(xk: np.ndarray, yk: np.ndarray, xs: np.ndarray) -> np.ndarray:
     from scipy.interpolate import CubicSpline
     return CubicSpline(xk, yk, bc_type="clamped")(xs)
@@ -115,6 +145,10 @@ def hyperspectral(seed: int, pixels: int = 262144, bands: int = 200,
     """pixels x bands matrix = abundances (Dirichlet(alpha 1)) @ endmember
     spectra + N(0, noise_std^2).  Each spectrum is a clamped cubic spline
     through ``knots`` U[0,1] control points on [0, 1], clipped to [0, 1]."""
+    return _hyperspectral(seed, pixels, bands, endmembers, knots, alpha, noise_std)[0].astype(dtype)
+
+
+def _hyperspectral(seed, pixels, bands, endmembers, knots, alpha, noise_std):
     rng = np.random.default_rng(seed)
     xk = np.linspace(0.0, 1.0, knots)
     xs = np.linspace(0.0, 1.0, bands)
@@ -124,7 +158,23 @@ def hyperspectral(seed: int, pixels: int = 262144, bands: int = 200,
     A = Ab @ E
     if noise_std:
         A += noise_std * rng.standard_normal((pixels, bands))
-    return A.astype(dtype)
+    return A, Ab
+
+
+def hyperspectral_labelled(seed: int, pixels: int = 21025, bands: int = 200, endmembers: int = 15,
+                           knots: int = 40, alpha: float = 0.5, noise_std: float = 1e-3,
+                           folds: int = 10, dtype=np.float32):
+    """(A, labels, fold): the hyperspectral matrix of ``hyperspectral`` (same
+    seed, same values; 21025 = 145 x 145 pixels by default, the Indian Pines
+    scene's size), the label of each pixel = its dominant endmember (argmax
+    abundance, 0-based), and its cross-validation fold = position in a
+    seeded random permutation modulo ``folds``."""
+    A, Ab = _hyperspectral(seed, pixels, bands, endmembers, knots, alpha, noise_std)
+    labels = np.argmax(Ab, axis=1).astype(np.int32)
+    perm = np.random.default_rng(seed + 7919).permutation(pixels)
+    fold = np.empty(pixels, dtype=np.int32)
+    fold[perm] = np.arange(pixels) % folds
+    return A.astype(dtype), labels, fold
 
 
 def tile_shapes(seed: int, count: int = 1024, lo: int = 64, hi: int = 1024,

@@ -302,6 +302,74 @@ int eodabe_set_predictor(eodabe_ctx* ctx, const float* params, double margin);
 int eodabe_last_prediction(const eodabe_ctx* ctx, int64_t* d0, double* log_rank, double* log_rank_q,
                            int* used);
 
+/* ---- application: colour-image compression ------------------------------
+ * The introduction's storage criterion and the quality criteria of section
+ * 4.1.  Each channel of a planar image img (channels x h x w FP32, device,
+ * channel c at img + c h w, values nominally in [0, 255]) is factored by
+ * EOD-ABE exactly as eodabe_factor would (q = 0, the context's seed; the
+ * channels run as tiles of one persistent launch when h, w <= 1024, with the
+ * block width eodabe_factor_batched would use, else one eodabe_factor call
+ * each), reconstructed as U_hat D_hat V_hat^T into recon (device, same
+ * layout), and compared with the original:
+ *   PSNR   = 10 log10(255^2 N / ||A_hat - A||_F^2), N = channels h w values
+ *            (+inf when the reconstruction is exact);
+ *   SSIM   = (2 mu_x mu_y + c1)(2 s_xy + c2) / ((mu_x^2 + mu_y^2 + c1)(s_x^2 + s_y^2 + c2))
+ *            over the vectorised images (one global window, as section 4.1
+ *            defines it), c1 = (0.01 255)^2, c2 = (0.03 255)^2, (co)variances
+ *            with 1 / (N - 1);
+ *   RelErr = ||A - A_hat||_F / ||A||_F;
+ * all accumulated in FP64 in a fixed order (deterministic).  Storage: a
+ * channel's factors keep (h + w) r + r (r + 1) / 2 entries against h w, and
+ * keeping them pays while r < sqrt(h^2 + w^2 + 4hw + h + w + 1/4) - (h + w + 1/2)
+ * (rank_bound).  factors: device FP32 pool of channels * r_cap (h + r_cap + w)
+ * elements, r_cap = min(h, w); channel c's Ut (r_cap x h), core (r_cap x
+ * r_cap) and Vt (r_cap x w) start at c r_cap (h + r_cap + w), laid out as for
+ * eodabe_factor.  Requires an F32 context; 1 <= channels <= 4.  Errors:
+ * EINVAL, EWORKSPACE, ECAPACITY, ENONFINITE, EHIP.  Returns after the
+ * stream has synchronised. */
+#define EODABE_IMAGE_MAX_CHANNELS 4
+typedef struct eodabe_image_info {
+  int64_t rank[EODABE_IMAGE_MAX_CHANNELS];   /* adaptive rank of each channel              */
+  int     channels;
+  double  relerr, psnr, ssim;                /* criteria over the whole image              */
+  double  stored;                            /* entries of all factors                     */
+  double  full;                              /* channels h w                               */
+  double  reduction;                         /* 1 - stored / full                          */
+  double  rank_bound;                        /* factors smaller than a channel below this  */
+} eodabe_image_info;
+size_t eodabe_image_workspace_size(eodabe_ctx* ctx, int channels, int64_t h, int64_t w);
+int eodabe_compress_image(eodabe_ctx* ctx, const float* img, int channels, int64_t h, int64_t w, double tol,
+                          void* ws, size_t ws_bytes, float* factors, int64_t factors_len, float* recon,
+                          eodabe_image_info* info);
+
+/* ---- application: hyperspectral dimensionality reduction (section 4.2) ---
+ * Features of the m pixels of a factored pixels x bands matrix: the rows of
+ * U_hat D_hat (F, m x r FP32 row-major, leading dimension ldf >= r, device),
+ * i.e. each pixel's spectrum in the r-dimensional basis, from the Ut
+ * (r_cap x m) and core (r_cap x r_cap) outputs of eodabe_factor.  Errors:
+ * EINVAL, ENODEVICE, EHIP; asynchronous on the context's stream. */
+int eodabe_features(eodabe_ctx* ctx, const float* Ut, const float* core, int64_t m, int64_t r, int64_t r_cap,
+                    float* F, int64_t ldf);
+
+/* KNN classification with cross-validation (section 4.2): every point i of
+ * F (m x d FP32, row-major ldf, device; d <= 32) is classified by its k
+ * nearest points (k <= 16) among those whose fold (device int32, m) differs
+ * from fold[i]; so with folds 0..9 this is ten-fold cross-validation, each
+ * point tested once.  Squared Euclidean distances are summed feature by
+ * feature in FP64 with a separate multiply and add per term; the nearest are
+ * the smallest (distance, index) pairs; the vote goes to the most frequent
+ * label (device int32 in [0, nclass), nclass <= 64), ties to the smallest.
+ * pred (device, m) receives the classes; confusion (host, optional, nclass x
+ * nclass row-major) receives n[i][j] = points of class j classified as i and
+ * oa (host, optional) the overall accuracy sum_i n_ii / sum_ij n_ij.  The
+ * workspace holds the device counters (eodabe_knn_workspace_size bytes).
+ * Errors: EINVAL, EWORKSPACE, ENODEVICE, EHIP.  Returns after the stream has
+ * synchronised. */
+size_t eodabe_knn_workspace_size(int nclass);
+int eodabe_knn_cv(eodabe_ctx* ctx, const float* F, int64_t m, int d, int64_t ldf, const int32_t* labels,
+                  const int32_t* fold, int k, int nclass, int32_t* pred, void* ws, size_t ws_bytes,
+                  int64_t* confusion, double* oa);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,7 +46,8 @@ EXPORTED = [
     "eodabe_profile", "eodabe_profile_read",
     "eodabe_mlp_param_count", "eodabe_mlp_workspace_size", "eodabe_mlp_forward", "eodabe_mlp_grad",
     "eodabe_mlp_adam", "eodabe_mlp_features", "eodabe_set_predictor", "eodabe_last_prediction",
-    "eodabe_factor_noalloc",
+    "eodabe_factor_noalloc", "eodabe_image_workspace_size", "eodabe_compress_image", "eodabe_features",
+    "eodabe_knn_workspace_size", "eodabe_knn_cv",
 ]
 PROF_SKETCH, PROF_PROJECT, PROF_TILES = 0, 1, 2
 
@@ -78,6 +79,24 @@ _lib.eodabe_workspace_size.restype = _sz
 _lib.eodabe_factor.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, _vp, _sz,
                                _vp, _vp, _vp, _i64, ctypes.POINTER(Info)]
 _lib.eodabe_factor.restype = ctypes.c_int
+class ImageInfo(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64 * 4), ("channels", ctypes.c_int), ("relerr", ctypes.c_double),
+                ("psnr", ctypes.c_double), ("ssim", ctypes.c_double), ("stored", ctypes.c_double),
+                ("full", ctypes.c_double), ("reduction", ctypes.c_double), ("rank_bound", ctypes.c_double)]
+
+
+_lib.eodabe_image_workspace_size.argtypes = [_vp, ctypes.c_int, _i64, _i64]
+_lib.eodabe_image_workspace_size.restype = _sz
+_lib.eodabe_compress_image.argtypes = [_vp, _vp, ctypes.c_int, _i64, _i64, ctypes.c_double, _vp, _sz, _vp, _i64,
+                                       _vp, ctypes.POINTER(ImageInfo)]
+_lib.eodabe_compress_image.restype = ctypes.c_int
+_lib.eodabe_features.argtypes = [_vp, _vp, _vp, _i64, _i64, _i64, _vp, _i64]
+_lib.eodabe_features.restype = ctypes.c_int
+_lib.eodabe_knn_workspace_size.argtypes = [ctypes.c_int]
+_lib.eodabe_knn_workspace_size.restype = _sz
+_lib.eodabe_knn_cv.argtypes = [_vp, _vp, _i64, ctypes.c_int, _i64, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                               _sz, _vp, ctypes.POINTER(ctypes.c_double)]
+_lib.eodabe_knn_cv.restype = ctypes.c_int
 _lib.eodabe_factor_noalloc.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double,
                                        _vp, _vp, _vp, _i64, ctypes.POINTER(Info)]
 _lib.eodabe_factor_noalloc.restype = ctypes.c_int
@@ -292,6 +311,78 @@ def factor_noalloc(A: torch.Tensor, tol: float, ctx: Context, out, r_cap: int = 
     r = int(info.rank)
     return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
                          float(info.norm_a), st, int(info.status_flags), float(info.relres_est))
+
+
+@dataclass
+class CompressedImage:
+    info: ImageInfo
+    factors: list          # per channel (U m x r, D r x r, Vt r x n) views into the pool
+    recon: torch.Tensor    # channels x h x w reconstruction U D V^T
+    pool: torch.Tensor
+
+
+def compress_image(img: torch.Tensor, tol: float, ctx: Context | None = None, **ctx_kw) -> CompressedImage:
+    """eodabe_compress_image: factor every channel of a channels x h x w
+    FP32 image, reconstruct it and report PSNR, SSIM, RelErr and storage."""
+    ctx = ctx or Context(**{"dtype": torch.float32, **ctx_kw})
+    if img.dim() != 3 or img.dtype != torch.float32 or not img.is_cuda:
+        raise ValueError("img must be a channels x h x w float32 CUDA tensor")
+    img = img.contiguous()
+    c, h, w = img.shape
+    rc = min(h, w)
+    per = rc * (h + rc + w)
+    pool = torch.empty(c * per, dtype=torch.float32, device=img.device)
+    recon = torch.empty_like(img)
+    wsz = _lib.eodabe_image_workspace_size(ctx.h, c, h, w)
+    if wsz == 0:
+        raise EodAbeError(EODABE_EINVAL, "eodabe_image_workspace_size", 0)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=img.device)
+    info = ImageInfo()
+    st = _lib.eodabe_compress_image(ctx.h, img.data_ptr(), c, h, w, float(tol), ws.data_ptr(), wsz,
+                                    pool.data_ptr(), pool.numel(), recon.data_ptr(), ctypes.byref(info))
+    ctx._check(st, "eodabe_compress_image")
+    facs = []
+    for ch in range(c):
+        base = pool[ch * per:(ch + 1) * per]
+        r = int(info.rank[ch])
+        Ut = base[:rc * h].view(rc, h)
+        core = base[rc * h:rc * (h + rc)].view(rc, rc)
+        Vt = base[rc * (h + rc):].view(rc, w)
+        facs.append((Ut[:r].T, core[:r, :r], Vt[:r]))
+    return CompressedImage(info, facs, recon, pool)
+
+
+def features(f: Factorization, ctx: Context | None = None) -> torch.Tensor:
+    """eodabe_features: rows of U_hat D_hat (m x r FP32) from a factorization
+    returned by factor()."""
+    ctx = ctx or Context(dtype=torch.float32)
+    m, r = f.U.shape
+    F = torch.empty((m, max(r, 1)), dtype=torch.float32, device=f.U.device)
+    Ut = f.U.T                      # rows of the Ut output buffer (stride m)
+    st = _lib.eodabe_features(ctx.h, Ut.data_ptr(), f.D.data_ptr(), m, r, f.D.stride(0) if r else 0,
+                              F.data_ptr(), F.stride(0))
+    ctx._check(st, "eodabe_features")
+    return F[:, :r]
+
+
+def knn_cv(F: torch.Tensor, labels: torch.Tensor, fold: torch.Tensor, k: int, nclass: int,
+           ctx: Context | None = None):
+    """eodabe_knn_cv: KNN classification of every point by the points of the
+    other folds.  Returns (pred (device int32), confusion (numpy), OA)."""
+    import numpy as np
+    ctx = ctx or Context(dtype=torch.float32)
+    if F.dtype != torch.float32 or F.stride(1) != 1:
+        raise ValueError("F must be float32 with unit column stride")
+    m, d = F.shape
+    pred = torch.empty(m, dtype=torch.int32, device=F.device)
+    wsz = _lib.eodabe_knn_workspace_size(nclass)
+    ws = torch.empty(max(wsz, 1), dtype=torch.uint8, device=F.device)
+    conf = np.zeros((nclass, nclass), dtype=np.int64)
+    oa = ctypes.c_double()
+    st = _lib.eodabe_knn_cv(ctx.h, F.data_ptr(), m, d, F.stride(0), labels.data_ptr(), fold.data_ptr(), k, nclass,
+                            pred.data_ptr(), ws.data_ptr(), wsz, conf.ctypes.data, ctypes.byref(oa))
+    ctx._check(st, "eodabe_knn_cv")
+    return pred, conf, float(oa.value)
 
 
 def basis(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int = 0,

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "eodabe.hip")
 DEPS = [SRC, os.path.join(HERE, "csrc", "eodabe_kernels.hpp"), os.path.join(HERE, "csrc", "eodabe_tiles.hpp"),
-        os.path.join(HERE, "csrc", "eodabe_mlp.hpp"),
+        os.path.join(HERE, "csrc", "eodabe_mlp.hpp"), os.path.join(HERE, "csrc", "eodabe_apps.hpp"),
         os.path.join(ROOT, "include", "eodabe.h")]
 OUT = os.path.join(HERE, "libeodabe.so")
 

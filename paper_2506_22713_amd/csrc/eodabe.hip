@@ -19,6 +19,7 @@
 #include "eodabe_kernels.hpp"
 #include "eodabe_tiles.hpp"
 #include "eodabe_mlp.hpp"
+#include "eodabe_apps.hpp"
 
 using namespace eodabe;
 
@@ -2032,6 +2033,190 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
     return 0;
   };
   return ctx->o.a_dtype == EODABE_F64 ? body(double{}) : body(float{});
+}
+
+
+// ---------------------------------------------------------------------------
+// Applications: colour-image compression and hyperspectral classification.
+// ---------------------------------------------------------------------------
+namespace {
+struct ImgPlan {
+  int64_t rc, per, nparts;
+  bool batched;
+  size_t fws, total;
+  size_t off_b, off_parts, off_metrics;
+};
+bool img_plan(eodabe_ctx* ctx, int channels, int64_t h, int64_t w, ImgPlan& p) {
+  if (channels < 1 || channels > IMG_MAX_CH || h < 1 || w < 1) return false;
+  p.rc = std::min(h, w);
+  p.per = p.rc * (h + p.rc + w);
+  p.batched = std::max(h, w) <= TILE_MAX;
+  p.fws = p.batched ? eodabe_batched_workspace_size(ctx, channels) : eodabe_workspace_size(ctx, h, w, p.rc);
+  if (p.fws == 0) return false;
+  p.nparts = (int64_t)channels * cdiv(h, 64) * cdiv(w, 64);
+  Carver c(nullptr);
+  c.take<char>((int64_t)p.fws);
+  c.take<char>(1);
+  p.off_b = (size_t)rup((int64_t)c.off, 256);
+  c.take<float>((int64_t)channels * p.rc * w);
+  p.off_parts = (size_t)rup((int64_t)c.off, 256);
+  c.take<ImgSums>(p.nparts);
+  p.off_metrics = (size_t)rup((int64_t)c.off, 256);
+  c.take<ImgMetrics>(1);
+  p.total = c.off + 256;
+  return true;
+}
+}  // namespace
+
+size_t eodabe_image_workspace_size(eodabe_ctx* ctx, int channels, int64_t h, int64_t w) {
+  if (!ctx) return 0;
+  ImgPlan p;
+  return img_plan(ctx, channels, h, w, p) ? p.total : 0;
+}
+
+int eodabe_compress_image(eodabe_ctx* ctx, const float* img, int channels, int64_t h, int64_t w, double tol,
+                          void* ws, size_t ws_bytes, float* factors, int64_t factors_len, float* recon,
+                          eodabe_image_info* info) {
+  TRY(check_ctx(ctx));
+  if (!info) return EODABE_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  if (!img || !factors || !recon || ctx->o.a_dtype != EODABE_F32) return EODABE_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return EODABE_EINVAL;
+  ImgPlan p;
+  if (!img_plan(ctx, channels, h, w, p)) return EODABE_EINVAL;
+  if (factors_len < (int64_t)channels * p.per) return EODABE_EINVAL;
+  if (!ws || ws_bytes < p.total) return EODABE_EWORKSPACE;
+  TRY(check_dev(ctx));
+  char* base = (char*)ws;
+  float* Bbuf = (float*)(base + p.off_b);
+  ImgSums* parts = (ImgSums*)(base + p.off_parts);
+  ImgMetrics* met = (ImgMetrics*)(base + p.off_metrics);
+  // 1. each channel through EOD-ABE: one persistent launch over the channels
+  //    when they fit the batched kernel, else the single-matrix path
+  int64_t ranks[IMG_MAX_CH] = {0, 0, 0, 0};
+  int32_t stat[IMG_MAX_CH] = {0, 0, 0, 0};
+  if (p.batched) {
+    const void* ptrs[IMG_MAX_CH];
+    int64_t mm[IMG_MAX_CH], nn[IMG_MAX_CH], ld[IMG_MAX_CH], off[IMG_MAX_CH], rcs[IMG_MAX_CH];
+    for (int c = 0; c < channels; ++c) {
+      ptrs[c] = img + (int64_t)c * h * w;
+      mm[c] = h;
+      nn[c] = w;
+      ld[c] = w;
+      off[c] = (int64_t)c * p.per;
+      rcs[c] = p.rc;
+    }
+    TRY(eodabe_factor_batched(ctx, channels, ptrs, mm, nn, ld, tol, ws, p.fws, factors,
+                              (int64_t)channels * p.per, off, rcs, ranks, stat, nullptr));
+    for (int c = 0; c < channels; ++c) {
+      if (stat[c] == TS_NONFINITE) return EODABE_ENONFINITE;
+      if (stat[c] != TS_OK) return EODABE_ECAPACITY;
+    }
+  } else {
+    for (int c = 0; c < channels; ++c) {
+      float* Ut = factors + (int64_t)c * p.per;
+      eodabe_info fi{};
+      const int e = eodabe_factor(ctx, img + (int64_t)c * h * w, h, w, w, tol, ws, p.fws, Ut, Ut + p.rc * h,
+                                  Ut + p.rc * (h + p.rc), p.rc, &fi);
+      if (e < 0) return e;
+      ranks[c] = fi.rank;
+    }
+  }
+  // 2. reconstruction U_hat (D_hat V_hat^T) with the criteria fused in
+  ImgJob job{};
+  int rmax = 0;
+  for (int c = 0; c < channels; ++c) {
+    const float* Ut = factors + (int64_t)c * p.per;
+    job.Ut[c] = Ut;
+    job.core[c] = Ut + p.rc * h;
+    job.Vt[c] = Ut + p.rc * (h + p.rc);
+    job.B[c] = Bbuf + (int64_t)c * p.rc * w;
+    job.r[c] = (int)ranks[c];
+    rmax = std::max(rmax, (int)ranks[c]);
+  }
+  job.rc = (int)p.rc;
+  hipStream_t st = ctx->stream;
+  if (rmax > 0) {
+    hipLaunchKernelGGL(k_img_dvt, dim3((unsigned)cdiv(w, 256), (unsigned)rmax, (unsigned)channels), dim3(256), 0,
+                       st, job, w);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_img_recon, dim3((unsigned)cdiv(w, 64), (unsigned)cdiv(h, 64), (unsigned)channels),
+                     dim3(256), 0, st, job, img, h, w, recon, parts);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_img_metrics, dim3(1), dim3(256), 0, st, parts, p.nparts, (double)channels * h * w, met);
+  LAUNCHCHK();
+  ImgMetrics hm{};
+  HIPCHK(hipMemcpyAsync(&hm, met, sizeof(hm), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // 3. storage accounting of the introduction: (h + w) r + r (r + 1) / 2
+  //    entries per channel against h w, and the rank below which the
+  //    factors take less
+  double stored = 0.0;
+  for (int c = 0; c < channels; ++c) {
+    info->rank[c] = ranks[c];
+    const double r = (double)ranks[c];
+    stored += (double)(h + w) * r + r * (r + 1.0) / 2.0;
+  }
+  info->channels = channels;
+  info->relerr = hm.relerr;
+  info->psnr = hm.psnr;
+  info->ssim = hm.ssim;
+  info->stored = stored;
+  info->full = (double)channels * h * w;
+  info->reduction = 1.0 - stored / info->full;
+  const double hd = (double)h, wd = (double)w;
+  info->rank_bound = std::sqrt(hd * hd + wd * wd + 4.0 * hd * wd + hd + wd + 0.25) - (hd + wd + 0.5);
+  return EODABE_OK;
+}
+
+int eodabe_features(eodabe_ctx* ctx, const float* Ut, const float* core, int64_t m, int64_t r, int64_t r_cap,
+                    float* F, int64_t ldf) {
+  TRY(check_ctx(ctx));
+  if (m < 0 || r < 0 || r_cap < r || ldf < r || r > 65535) return EODABE_EINVAL;
+  if (m == 0 || r == 0) return EODABE_OK;
+  if (!Ut || !core || !F) return EODABE_EINVAL;
+  TRY(check_dev(ctx));
+  hipLaunchKernelGGL(k_features, dim3((unsigned)cdiv(m, 256), (unsigned)r), dim3(256), 0, ctx->stream, Ut, core, m,
+                     (int)r, r_cap, F, ldf);
+  LAUNCHCHK();
+  return EODABE_OK;
+}
+
+size_t eodabe_knn_workspace_size(int nclass) {
+  if (nclass < 1 || nclass > KNN_CMAX) return 0;
+  return (size_t)nclass * nclass * sizeof(unsigned long long) + 256;
+}
+
+int eodabe_knn_cv(eodabe_ctx* ctx, const float* F, int64_t m, int d, int64_t ldf, const int32_t* labels,
+                  const int32_t* fold, int k, int nclass, int32_t* pred, void* ws, size_t ws_bytes,
+                  int64_t* confusion, double* oa) {
+  TRY(check_ctx(ctx));
+  if (m < 1 || d < 1 || d > KNN_DMAX || ldf < d || k < 1 || k > KNN_KMAX || nclass < 1 || nclass > KNN_CMAX)
+    return EODABE_EINVAL;
+  if (!F || !labels || !fold || !pred) return EODABE_EINVAL;
+  if (!ws || ws_bytes < eodabe_knn_workspace_size(nclass)) return EODABE_EWORKSPACE;
+  TRY(check_dev(ctx));
+  hipStream_t st = ctx->stream;
+  unsigned long long* conf = (unsigned long long*)ws;
+  const int64_t nc2 = (int64_t)nclass * nclass;
+  hipLaunchKernelGGL(k_zero<unsigned long long>, dim3(1), dim3(256), 0, st, conf, nc2);
+  hipLaunchKernelGGL(k_knn_cv, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, F, m, d, ldf, labels, fold, k,
+                     nclass, pred, conf);
+  LAUNCHCHK();
+  std::vector<unsigned long long> hc((size_t)nc2);
+  HIPCHK(hipMemcpyAsync(hc.data(), conf, (size_t)nc2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  unsigned long long tr = 0, tot = 0;
+  for (int i = 0; i < nclass; ++i)
+    for (int j = 0; j < nclass; ++j) {
+      const unsigned long long v = hc[(size_t)i * nclass + j];
+      if (confusion) confusion[(size_t)i * nclass + j] = (int64_t)v;
+      tot += v;
+      if (i == j) tr += v;
+    }
+  if (oa) *oa = tot ? (double)tr / (double)tot : 0.0;
+  return EODABE_OK;
 }
 
 }  // extern "C"

@@ -667,7 +667,9 @@ def test_batched_tiles_against_oracle():
         e_one = float(torch.linalg.norm(dtiles[t].double() - f.U.double() @ f.D.double() @ f.Vt.double())
                       / torch.linalg.norm(dtiles[t].double()))
         assert f.rank == r, (t, T.shape, f.rank, r)
-        assert abs(e_gpu - e_one) <= 0.05 * e_one + 1e-7, (t, T.shape, e_gpu, e_one)
+        # the equal-error rule: the two FP32 paths within the bar each meets
+        # against the oracle (on rounding-only tiles both errors are rounding)
+        assert abs(e_gpu - e_one) <= max(0.05 * e_one, bar), (t, T.shape, e_gpu, e_one, bar)
         assert np.linalg.norm(Un.T @ Un - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
         assert np.linalg.norm(Vn @ Vn.T - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
         assert np.all(np.tril(Dn, -1) == 0) and np.all(np.diag(Dn) >= 0)

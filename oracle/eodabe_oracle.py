@@ -99,6 +99,12 @@ def omega_columns(seed: int, n: int, col0: int, ncols: int) -> np.ndarray:
     Values are rounded to FP32 (the precision the GPU stores them in) and
     returned in FP64, so FP32 and FP64 runs use the same Omega.
     """
+    return gaussian_columns64(seed, n, col0, ncols).astype(np.float32).astype(np.float64)
+
+
+def gaussian_columns64(seed: int, n: int, col0: int, ncols: int) -> np.ndarray:
+    """The FP64 Box-Muller values of omega_columns before their rounding to
+    FP32 (same counters, same transform)."""
     out = np.empty((n, ncols), dtype=np.float64)
     if n == 0 or ncols == 0:
         return out
@@ -118,7 +124,7 @@ def omega_columns(seed: int, n: int, col0: int, ncols: int) -> np.ndarray:
             rad = np.sqrt(-2.0 * np.log(u1))
             z[:, a] = rad * np.cos(2.0 * np.pi * u2)
             z[:, bb] = rad * np.sin(2.0 * np.pi * u2)
-        out[:, j] = z.reshape(-1)[:n].astype(np.float32).astype(np.float64)
+        out[:, j] = z.reshape(-1)[:n]
     return out
 
 

@@ -9,6 +9,8 @@ which are not available):
 
 * ``lowrank_haar``   exact-rank matrix U diag(s) V^T + E with Haar U, V and
                      s_i = 10^{-3(i-1)/(r-1)} (512 x 512, rank 20 by default).
+* ``lowrank_complex`` the complex analogue U diag(s) V^H + E (complex Haar
+                     U, V; E circular complex Gaussian).
 * ``image``          image-like matrix in [0, 255]: Gaussian blobs (rank 1
                      each) plus low-frequency cosine modes (rank <= 2 each)
                      plus i.i.d. pixel noise (stand-in for the paper's
@@ -41,7 +43,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["haar", "lowrank_haar", "image", "rgb_image", "exact_rank_rgb", "hyperspectral",
+__all__ = ["haar", "lowrank_haar", "lowrank_complex", "image", "rgb_image", "exact_rank_rgb", "hyperspectral",
            "hyperspectral_labelled", "tiles", "tile_shapes", "mat2", "robustness", "devils_stairs_sigma",
            "spectrum_sigma", "spectrum_torch"]
 
@@ -69,6 +71,28 @@ def lowrank_haar(seed: int, m: int = 512, n: int = 512, r: int = 20,
     if noise_std:
         A = A + noise_std * rng.standard_normal((m, n))
     return A.astype(dtype)
+
+
+def lowrank_complex(seed: int, m: int = 400, n: int = 300, r: int = 20, noise_std: float = 0.0,
+                    decades: float = 3.0) -> np.ndarray:
+    """Complex m x n matrix U diag(s) V^H + E: U, V the unitary factors of
+    QR of complex Gaussian matrices with the phases of R's diagonal
+    removed (Haar), s_i = 10^{-decades (i-1)/(r-1)}, E with independent
+    N(0, noise_std^2 / 2) real and imaginary parts (complex128)."""
+    rng = np.random.default_rng(seed)
+
+    def chaar(k):
+        G = rng.standard_normal((k, r)) + 1j * rng.standard_normal((k, r))
+        Qm, R = np.linalg.qr(G)
+        d = np.diag(R)
+        return Qm * (d / np.abs(d))[None, :]
+
+    U, V = chaar(m), chaar(n)
+    s = 10.0 ** (-decades * np.arange(r) / max(r - 1, 1)) if r > 0 else np.zeros(0)
+    A = (U * s[None, :]) @ V.conj().T
+    if noise_std:
+        A = A + noise_std * np.sqrt(0.5) * (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n)))
+    return A
 
 
 def image(seed: int, size: int = 4096, noise_std: float = 0.5, blobs: int = 64,

@@ -157,6 +157,30 @@ int eodabe_factor(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
 int eodabe_factor_noalloc(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda,
                           double tol, void* Ut, void* core, void* Vt, int64_t r_cap, eodabe_info* info);
 
+/* ---- complex input (the paper's setting, A in C^{m x n}) ----------------
+ * A ~= U_hat D_hat V_hat^H with U_hat, V_hat column-orthonormal (complex),
+ * D_hat upper triangular with a real non-negative diagonal, the rank found
+ * by Alg. 1 with a complex standard Gaussian test matrix (column c =
+ * (g_2c + i g_2c+1) / sqrt(2), g_j the FP64 Box-Muller column j of the
+ * real test matrix, each part rounded to FP32) and the stopping test
+ * |T(l,l)| <= tol ||A||_F.  A is interleaved (real, imaginary) pairs,
+ * row-major m x n with row stride lda >= n complex elements: complex64 for an
+ * F32 context, complex128 for F64.  Outputs, interleaved complex of the
+ * same type: Ut (r_cap x m, row a = column a of U_hat), core (r_cap x r_cap,
+ * D_hat), Vt (r_cap x n, row a = conjugate of column a of V_hat, so A ~=
+ * U_hat core Vt).  opts.block counts complex columns per block (up to 64).
+ * The work runs on the realification [[Re A, -Im A], [Im A, Re A]] with
+ * the test columns in pairs (omega, i omega) and the stopping test on the
+ * leading column of each pair: real Gram-Schmidt over pair-ordered realified
+ * columns is complex Gram-Schmidt, so every factor is the realification of
+ * the complex one; the workspace holds the 2m x 2n realification.  Requires
+ * the native sketch (EINVAL otherwise).  Errors: those of eodabe_factor;
+ * info->rank, eps and relres_est refer to A itself. */
+size_t eodabe_complex_workspace_size(eodabe_ctx* ctx, int64_t m, int64_t n, int64_t r_cap);
+int eodabe_factor_complex(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, double tol,
+                          void* ws, size_t ws_bytes, void* Ut, void* core, void* Vt, int64_t r_cap,
+                          eodabe_info* info);
+
 /* Human-readable text for a status code (static storage). */
 const char* eodabe_strerror(int status);
 

@@ -47,7 +47,7 @@ EXPORTED = [
     "eodabe_mlp_param_count", "eodabe_mlp_workspace_size", "eodabe_mlp_forward", "eodabe_mlp_grad",
     "eodabe_mlp_adam", "eodabe_mlp_features", "eodabe_set_predictor", "eodabe_last_prediction",
     "eodabe_factor_noalloc", "eodabe_image_workspace_size", "eodabe_compress_image", "eodabe_features",
-    "eodabe_knn_workspace_size", "eodabe_knn_cv",
+    "eodabe_knn_workspace_size", "eodabe_knn_cv", "eodabe_complex_workspace_size", "eodabe_factor_complex",
 ]
 PROF_SKETCH, PROF_PROJECT, PROF_TILES = 0, 1, 2
 
@@ -97,6 +97,11 @@ _lib.eodabe_knn_workspace_size.restype = _sz
 _lib.eodabe_knn_cv.argtypes = [_vp, _vp, _i64, ctypes.c_int, _i64, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp,
                                _sz, _vp, ctypes.POINTER(ctypes.c_double)]
 _lib.eodabe_knn_cv.restype = ctypes.c_int
+_lib.eodabe_complex_workspace_size.argtypes = [_vp, _i64, _i64, _i64]
+_lib.eodabe_complex_workspace_size.restype = _sz
+_lib.eodabe_factor_complex.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, _vp, _sz,
+                                       _vp, _vp, _vp, _i64, ctypes.POINTER(Info)]
+_lib.eodabe_factor_complex.restype = ctypes.c_int
 _lib.eodabe_factor_noalloc.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double,
                                        _vp, _vp, _vp, _i64, ctypes.POINTER(Info)]
 _lib.eodabe_factor_noalloc.restype = ctypes.c_int
@@ -290,6 +295,37 @@ def factor(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int =
     st = _lib.eodabe_factor(ctx.h, A.data_ptr(), m, n, lda, float(tol), ws.data_ptr(), ws.numel(),
                             Ut.data_ptr(), core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
     ctx._check(st, "eodabe_factor")
+    r = int(info.rank)
+    return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
+                         float(info.norm_a), st, int(info.status_flags), float(info.relres_est))
+
+
+def factor_complex(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int = 0,
+                   **ctx_kw) -> Factorization:
+    """eodabe_factor_complex: A ~= U D V^H for complex64 / complex128 A.
+    Returns U (m x r), D (r x r) and Vt = V^H (r x n) views."""
+    if A.dtype not in (torch.complex64, torch.complex128) or A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D complex64 or complex128 CUDA tensor")
+    real = torch.float32 if A.dtype == torch.complex64 else torch.float64
+    ctx = ctx or Context(**{"dtype": real, **ctx_kw})
+    if ctx.dtype != real:
+        raise ValueError("context dtype must be the real type of A")
+    if A.stride(1) != 1:
+        A = A.contiguous()
+    m, n = A.shape
+    rc = r_cap or min(m, n)
+    wsz = _lib.eodabe_complex_workspace_size(ctx.h, m, n, rc)
+    if wsz == 0:
+        raise EodAbeError(EODABE_EINVAL, "eodabe_complex_workspace_size", 0)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=A.device)
+    Ut = torch.empty((max(rc, 1), m), dtype=A.dtype, device=A.device)
+    core = torch.zeros((max(rc, 1), max(rc, 1)), dtype=A.dtype, device=A.device)
+    Vt = torch.empty((max(rc, 1), n), dtype=A.dtype, device=A.device)
+    info = Info()
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    st = _lib.eodabe_factor_complex(ctx.h, A.data_ptr(), m, n, lda, float(tol), ws.data_ptr(), wsz,
+                                    Ut.data_ptr(), core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
+    ctx._check(st, "eodabe_factor_complex")
     r = int(info.rank)
     return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
                          float(info.norm_a), st, int(info.status_flags), float(info.relres_est))

@@ -66,6 +66,7 @@ struct eodabe_ctx {
   int tile_graphs = 1;            // capture the launch in a hipGraph
   // learned warm start (eodabe_set_predictor): device parameters of the MLP
   void* scratch = nullptr;        // this device's copy of the static scratch array
+  bool cplx_pairs = false;        // set by eodabe_factor_complex around its realified call
   const float* pred_params = nullptr;
   double pred_margin = 0.1;
   struct { int64_t d0 = 0; double y0 = 0, y1 = 0; int used = 0; } pred_last;
@@ -186,6 +187,18 @@ void prof_collect(eodabe_ctx* ctx, int last_block, bool spec_ran, int64_t rank) 
   ctx->marks.clear();
 }
 
+// Realified complex input: re-impose the pairing on ncols columns (see
+// k_pair_fix); nothing otherwise.
+template <typename T>
+int pair_fix(eodabe_ctx* ctx, hipStream_t st, bool paired, T* X, int64_t ld, int64_t nn, int64_t ncols,
+             const int32_t* stopb = nullptr, int blk = 0) {
+  if (!paired || ncols < 2 || nn <= 0) return 0;
+  dim3 grid((unsigned)((nn + 255) / 256), (unsigned)(ncols / 2));
+  hipLaunchKernelGGL((k_pair_fix<T>), grid, dim3(256), 0, st, X, ld, nn, ncols, stopb, blk);
+  LAUNCHCHK();
+  return 0;
+}
+
 // Problem geometry after the optional transpose (mm >= nn).
 struct Geo {
   int64_t mm, nn;       // factored matrix is mm x nn (row-major, ld lda_eff)
@@ -205,6 +218,7 @@ struct Geo {
   int lp;               // low-precision sketch: 0 none, 1 FP16, 2 BF16
   int64_t ld_lp;        // leading dimension of the low-precision copy of A (multiple of 8)
   bool wide;            // learned warm start: buffers of the wide sketch
+  bool paired;          // realified complex input: test columns and stops in pairs
 };
 
 // Widest sketch of the learned warm start in one pass over A (columns).
@@ -331,8 +345,11 @@ bool plan(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t lda, const void* 
   g.lda_eff = g.packed ? rup(std::max<int64_t>(g.nn, 1), 4) : lda;
   g.lp = (dt == EODABE_F32) ? ctx->o.sketch_dtype : 0;
   g.ld_lp = rup(std::max<int64_t>(g.nn, 1), 8);
-  g.wide = ctx->pred_params != nullptr && g.lp == 0 && g.nn > 64 && ctx->o.block <= 64;
-  g.b = ctx->o.block;
+  g.paired = ctx->cplx_pairs;
+  if (g.paired) g.lp = 0;
+  g.wide = ctx->pred_params != nullptr && g.lp == 0 && g.nn > 64 && ctx->o.block <= 64 && !g.paired;
+  // paired: opts.block complex columns per block, i.e. twice as many real ones
+  g.b = g.paired ? 2 * std::min(ctx->o.block, 64) : ctx->o.block;
   g.bn = (int)rup(g.b, 16);
   g.nblk = cdiv(g.nn, g.b);
   g.ldk = rup(std::max<int64_t>(g.nn, 1), 4);
@@ -755,7 +772,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
   const int nwlog = (int)(g.nblk + 2);
   hipLaunchKernelGGL(k_init_state, dim3(64), dim3(256), 0, st, w.st, tol, w.wlog, nwlog, w.dead,
-                     (int64_t)(g.nblk + 1) * BN_MAX, w.accv, (int)(g.nblk + 1), g.lp);
+                     (int64_t)(g.nblk + 1) * BN_MAX, w.accv, (int)(g.nblk + 1), g.lp, g.paired ? 1 : 0);
   LAUNCHCHK();
   T* omega = (T*)w.omega;
   T* y = (T*)w.y;
@@ -818,9 +835,15 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       T* y = pre ? (T*)w.y_w + (j - pre_j0) * (int64_t)g.b * g.ldy : (T*)w.y;
       // a1: Omega_j (bn rows; rows f..bn-1 zero)
       if (!pre) {
-        dim3 grid((unsigned)cdiv(cdiv(g.ldk, 4), 256), g.bn);
-        hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.ldk, omega,
-                           stopb, blk);
+        if (g.paired) {
+          dim3 grid((unsigned)cdiv(g.ldk, 256), f);
+          hipLaunchKernelGGL((k_omega_paired<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.ldk, omega,
+                             stopb, blk);
+        } else {
+          dim3 grid((unsigned)cdiv(cdiv(g.ldk, 4), 256), g.bn);
+          hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.ldk, omega,
+                             stopb, blk);
+        }
         if (f < g.bn)
           hipLaunchKernelGGL(k_zero<T>, dim3(64), dim3(256), 0, st, omega + (int64_t)f * g.ldk,
                              (int64_t)(g.bn - f) * g.ldk);
@@ -851,6 +874,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
                abytes + (double)g.elem * ((double)g.nn * f + (double)g.mm * f));
       if (j > 0) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+      if (j > 0) TRY(pair_fix<T>(ctx, st, g.paired, y, g.ldy, g.mm, f, stopb, blk));
       }
       // a3 + a4: two rounds of [project against the basis so far (width
       // wlog[j] <= j*b), FP64-Gram Cholesky, triangular solve]: block
@@ -862,6 +886,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       const bool small = f <= 64;     // fused Gram + Cholesky-with-inverse kernels
       const bool mid = f <= 128;      // explicit R^{-1} (blocked Cholesky above 64 columns) + apply
       if (j == 0) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+      if (j == 0) TRY(pair_fix<T>(ctx, st, g.paired, y, g.ldy, g.mm, f, stopb, blk));
       for (int pass = 0; pass < 2; ++pass) {
         if (j > 0) {
           TRY(ops.template gemm_nt<T>(q, g.ldy, y, g.ldy, wmax, f, g.mm, g.s_proj, (T*)w.wpart, ldw,
@@ -871,6 +896,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
                              stopb, blk);
           LAUNCHCHK();
           TRY(ops.update(y, g.ldy, q, g.ldy, g.mm, wmax, f, wbuf, ldw, 1, w.wlog, stopb, blk));
+          TRY(pair_fix<T>(ctx, st, g.paired, y, g.ldy, g.mm, f, stopb, blk));
         }
         CholArgs ca = chol_args(w, pass == 0 ? w.r1 : w.r2, deadj, pass == 0, 0, 0);
         if (pass == 0) {
@@ -1064,6 +1090,7 @@ int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, cons
              (double)g.elem * ((double)g.mm * g.nn + (double)g.mm * r + (double)r * g.nn));
   TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb, nullptr, 0,
                       gate));
+  if (!gate.st) TRY(pair_fix<T>(ctx, st, g.paired, cb, g.ldk, g.nn, r));
   CholArgs c1 = chol_args(w, w.rb1, w.deadbig, 1, 1, 1);
   c1.Rinv = w.rb3;
   c1.gate = gate;
@@ -1106,9 +1133,11 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
     // Y~^T = Q^T A (r x nn), QR(Y~) -> Q~ (stored as Q~^T = cbuf rows)
     TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
     TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb));
+    TRY(pair_fix<T>(ctx, st, g.paired, cb, g.ldk, g.nn, r));
     TRY(cholqr2<T>(ctx, st, g, w, cb, g.ldk, g.nn, (int)r, w.rb4, 0, (T*)w.tbig));
     // Y = A Q~ (mm x r), QR(Y) -> Q
     TRY(ops.template gemm_nt<T>(Ae, g.lda_eff, cb, g.ldk, g.mm, r, g.nn, 1, q, g.ldy, g.ldy * r));
+    TRY(pair_fix<T>(ctx, st, g.paired, q, g.ldy, g.mm, r));
     TRY(cholqr2<T>(ctx, st, g, w, q, g.ldy, g.mm, (int)r, w.rb4, 0, (T*)w.tbig));
   }
   if (r <= 128)
@@ -1121,6 +1150,7 @@ int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   prof_end(ctx, st, pid, EODABE_PROF_PROJECT, 0,
            (double)g.elem * ((double)g.mm * g.nn + (double)g.mm * r + (double)r * g.nn));
   TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb));
+  TRY(pair_fix<T>(ctx, st, g.paired, cb, g.ldk, g.nn, r));
   // a10: C^T = V R  (C^T is nn x r with element (j,a) at a*ldk + j = cbuf);
   //      V^T rows go straight to Vout, R^T (row-major R) to rb4 as a
   //      column-major r x r matrix.
@@ -1802,7 +1832,7 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
     // With a small enough basis the closing steps are enqueued right behind
     // each chunk of blocks, gated on the device-side stop flag, so a
     // factorization that stops in its first chunk needs one host sync.
-    const bool can_spec = !g.transposed && !basis_only && ctx->o.power_iters == 0 && !g.lp;
+    const bool can_spec = !g.transposed && !basis_only && ctx->o.power_iters == 0 && !g.lp && !g.paired;
     auto after_chunk = [&](int64_t jend) -> int {
       if (!can_spec) return 0;
       const int64_t rb = std::min<int64_t>(g.nn, jend * (int64_t)g.b);
@@ -1920,6 +1950,109 @@ int eodabe_factor_noalloc(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, 
   return s;
 }
 
+// Complex input: the factorization of the realification [[Re A, -Im A],
+// [Im A, Re A]] with the test columns in pairs (omega, i omega) and the stop
+// test at pair-leading columns, which is the complex algorithm carried out
+// in real arithmetic (real Gram-Schmidt over pair-ordered realified columns
+// is complex Gram-Schmidt), then unpacked.
+namespace {
+struct CplxPlan {
+  int64_t rc, ld2;
+  size_t off_a, off_u, off_d, off_v, off_in, inner, total;
+};
+bool cplx_plan(eodabe_ctx* ctx, int64_t m, int64_t n, int64_t r_cap, CplxPlan& p) {
+  if (m < 0 || n < 0) return false;
+  const int64_t mn = std::min(m, n);
+  p.rc = r_cap == 0 ? mn : r_cap;
+  if (p.rc < 0 || p.rc > mn) return false;
+  const size_t e = ctx->o.a_dtype == EODABE_F64 ? 8 : 4;
+  p.ld2 = rup(std::max<int64_t>(2 * n, 1), 4);
+  ctx->cplx_pairs = true;
+  p.inner = (m == 0 || n == 0) ? 256 : eodabe_workspace_size(ctx, 2 * m, 2 * n, 2 * p.rc);
+  ctx->cplx_pairs = false;
+  if (p.inner == 0) return false;
+  Carver c(nullptr);
+  const int64_t rc2 = std::max<int64_t>(2 * p.rc, 1);
+  c.take<char>(0);
+  p.off_a = (size_t)rup((int64_t)c.off, 256);
+  c.take<char>((int64_t)(2 * std::max<int64_t>(m, 1) * p.ld2 * e));
+  p.off_u = (size_t)rup((int64_t)c.off, 256);
+  c.take<char>((int64_t)(rc2 * 2 * std::max<int64_t>(m, 1) * e));
+  p.off_d = (size_t)rup((int64_t)c.off, 256);
+  c.take<char>((int64_t)(rc2 * rc2 * e));
+  p.off_v = (size_t)rup((int64_t)c.off, 256);
+  c.take<char>((int64_t)(rc2 * 2 * std::max<int64_t>(n, 1) * e));
+  p.off_in = (size_t)rup((int64_t)c.off, 256);
+  c.take<char>((int64_t)p.inner);
+  p.total = c.off + 256;
+  return true;
+}
+}  // namespace
+
+size_t eodabe_complex_workspace_size(eodabe_ctx* ctx, int64_t m, int64_t n, int64_t r_cap) {
+  if (!ctx) return 0;
+  CplxPlan p;
+  return cplx_plan(ctx, m, n, r_cap, p) ? p.total : 0;
+}
+
+int eodabe_factor_complex(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, double tol,
+                          void* ws, size_t ws_bytes, void* Ut, void* core, void* Vt, int64_t r_cap,
+                          eodabe_info* info) {
+  TRY(check_ctx(ctx));
+  if (!info) return EODABE_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  if (m < 0 || n < 0 || lda < n || lda < 1) return EODABE_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return EODABE_EINVAL;
+  if (ctx->o.sketch_dtype != EODABE_SKETCH_NATIVE) return EODABE_EINVAL;
+  CplxPlan p;
+  if (!cplx_plan(ctx, m, n, r_cap, p)) return EODABE_EINVAL;
+  if (!ws || ws_bytes < p.total) return EODABE_EWORKSPACE;
+  if (m == 0 || n == 0) return EODABE_OK;
+  if (!A || !Ut || !core || !Vt) return EODABE_EINVAL;
+  TRY(check_dev(ctx));
+  hipStream_t st = ctx->stream;
+  char* base = (char*)ws;
+  void* Ar = base + p.off_a;
+  void* Utr = base + p.off_u;
+  void* Dr = base + p.off_d;
+  void* Vtr = base + p.off_v;
+  const bool f64 = ctx->o.a_dtype == EODABE_F64;
+  {
+    dim3 grid((unsigned)cdiv(n, 256), (unsigned)m);
+    if (f64)
+      hipLaunchKernelGGL(k_cplx_pack<double>, grid, dim3(256), 0, st, (const double*)A, m, n, lda, (double*)Ar, p.ld2);
+    else
+      hipLaunchKernelGGL(k_cplx_pack<float>, grid, dim3(256), 0, st, (const float*)A, m, n, lda, (float*)Ar, p.ld2);
+    LAUNCHCHK();
+  }
+  // ||A_r||_F = sqrt(2) ||A||_F: tol / sqrt(2) keeps eps = tol ||A||_F
+  eodabe_info ri{};
+  ctx->cplx_pairs = true;
+  const int s = factor_impl(ctx, Ar, 2 * m, 2 * n, p.ld2, tol * 0.70710678118654752440, base + p.off_in, p.inner,
+                            Utr, Dr, Vtr, 2 * p.rc, &ri, nullptr, nullptr, 0, false);
+  ctx->cplx_pairs = false;
+  info->rank = ri.rank / 2;
+  info->blocks = ri.blocks;
+  info->status_flags = ri.status_flags;
+  info->norm_a = ri.norm_a * 0.70710678118654752440;
+  info->eps = ri.eps;
+  info->relres_est = ri.relres_est * 1.41421356237309504880;
+  if (s < 0) return s;
+  const int64_t r = info->rank;
+  if (r > 0) {
+    dim3 grid((unsigned)cdiv(std::max(std::max(m, n), p.rc), 256), (unsigned)r);
+    if (f64)
+      hipLaunchKernelGGL(k_cplx_unpack<double>, grid, dim3(256), 0, st, (const double*)Utr, (const double*)Dr,
+                         (const double*)Vtr, m, n, r, 2 * p.rc, (double*)Ut, (double*)core, (double*)Vt, p.rc);
+    else
+      hipLaunchKernelGGL(k_cplx_unpack<float>, grid, dim3(256), 0, st, (const float*)Utr, (const float*)Dr,
+                         (const float*)Vtr, m, n, r, 2 * p.rc, (float*)Ut, (float*)core, (float*)Vt, p.rc);
+    LAUNCHCHK();
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return s;
+}
+
 int eodabe_basis(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t lda, double tol,
                  void* ws, size_t ws_bytes, void* Q, int64_t r_cap, double* diagT, int64_t diag_cap,
                  eodabe_info* info) {
@@ -2014,7 +2147,7 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
       // low-precision form: max |A| -> scale, write the FP16/BF16 copy of A,
       // then sketch the copy (the two FP32 passes' Y partials are discarded)
       hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, lp.st, 1.0, (int64_t*)nullptr, 0,
-                         (int32_t*)nullptr, (int64_t)0, (int32_t*)nullptr, 0, lpm);
+                         (int32_t*)nullptr, (int64_t)0, (int32_t*)nullptr, 0, lpm, 0);
       TRY(ops.sketch(Ae, la, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, lp.normp, nullptr, 0,
                      lp.maxp));
       const int64_t nparts = (int64_t)eff_splits(n, (int)p.s) * std::max<int64_t>(cdiv(m, 128), 1);

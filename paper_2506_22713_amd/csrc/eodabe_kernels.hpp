@@ -42,7 +42,7 @@ struct State {
   int32_t stop_block;    // first block whose stop test fired (INT32_MAX: none yet)
   int32_t nonfinite;     // ||A||_F not finite
   int32_t floored;       // a pivot was floored in the closing QRs
-  int32_t pad;
+  int32_t paired;        // complex input (realified): stops only at pair-leading columns
   int64_t rank;          // basis width after the latest decided block
   uint32_t counter[8];   // arrival counters (reset by the last arriving workgroup)
   double lp_scale;       // power of two applied to A before rounding it to FP16 (1 for BF16)
@@ -152,6 +152,113 @@ __global__ void k_omega(uint32_t k0, uint32_t k1, int64_t n, int64_t col0, int n
 #pragma unroll
   for (int e = 0; e < 4; ++e)
     if (4 * q + e < ldo) o[e] = (4 * q + e < n) ? (T)z[e] : (T)0;
+}
+
+// Columns of the test matrix of a realified complex problem (nn = 2 nc rows):
+// real column 2c + p is the realification of omega_c (p = 0) or of
+// i omega_c (p = 1), omega_c = (g_2c + i g_2c+1) / sqrt(2) the complex
+// standard Gaussian column c (g_j the FP64 Box-Muller column j of the real
+// test matrix, each part rounded to FP32 after the scaling):
+//   p = 0: rows [0, nc) Re omega_c, rows [nc, 2 nc) Im omega_c;
+//   p = 1: rows [0, nc) -Im omega_c, rows [nc, 2 nc) Re omega_c.
+// Layout as k_omega: out[j*ldo + i] for real column col0 + j.
+__device__ __forceinline__ double gauss64(uint32_t k0, uint32_t k1, int64_t row, int64_t col) {
+  const U4 r = philox4x32_10(U4{(uint32_t)(row >> 2), (uint32_t)col, 0u, 0u}, k0, k1);
+  const int e = (int)(row & 3);
+  const uint32_t x = e < 2 ? r.x : r.z, y = e < 2 ? r.y : r.w;
+  const double u1 = ((double)x + 1.0) * 2.3283064365386963e-10;
+  const double u2 = (double)y * 2.3283064365386963e-10;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos(2.0 * 3.141592653589793 * u2, &sn, &cs);
+  return (e & 1) ? rad * sn : rad * cs;
+}
+
+template <typename T>
+__global__ void k_omega_paired(uint32_t k0, uint32_t k1, int64_t nn, int64_t col0, int ncols, int64_t ldo,
+                               T* __restrict__ out, const int32_t* __restrict__ stop_block, int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= ldo || j >= ncols) return;
+  const int64_t nc = nn / 2;
+  T v = (T)0;
+  if (i < nn) {
+    const int64_t jr = col0 + j, c = jr >> 1;
+    const int p = (int)(jr & 1);
+    const bool top = i < nc;
+    const int64_t ii = top ? i : i - nc;
+    // Re omega for (p = 0, top) and (p = 1, bottom); Im omega otherwise
+    const bool want_re = (p == 0) == top;
+    const double g = gauss64(k0, k1, ii, want_re ? 2 * c : 2 * c + 1) * 0.70710678118654752440;
+    const float gf = (float)g;
+    v = (T)((p == 1 && top) ? -gf : gf);
+  }
+  out[(int64_t)j * ldo + i] = v;
+}
+
+// Pair structure of a realified complex block: column 2p + 1 := J column
+// 2p with J [a; b] = [-b; a] (halves of length nn / 2), i.e. the partner
+// column is i times the leading one.  Every realified matrix commutes with
+// J, so this only discards the independent rounding of the partner, which a
+// cancelling step (projection of a weak direction) would otherwise amplify.
+// Columns: X + c * ld, length nn; ncols even.
+template <typename T>
+__global__ void k_pair_fix(T* __restrict__ X, int64_t ld, int64_t nn, int64_t ncols,
+                           const int32_t* __restrict__ stop_block, int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, p = blockIdx.y;
+  if (i >= nn || 2 * p + 1 >= ncols) return;
+  const int64_t h = nn / 2;
+  const T* lead = X + (2 * p) * ld;
+  X[(2 * p + 1) * ld + i] = i < h ? -lead[i + h] : lead[i - h];
+}
+
+// Complex input (interleaved real, imaginary) m x n, row stride lda complex
+// elements, to its realification [[Re A, -Im A], [Im A, Re A]] (2m x 2n,
+// row-major, row stride ldr).
+template <typename T>
+__global__ void k_cplx_pack(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda, T* __restrict__ Ar,
+                            int64_t ldr) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, i = blockIdx.y;
+  if (j >= n || i >= m) return;
+  const T re = A[2 * (i * lda + j)], im = A[2 * (i * lda + j) + 1];
+  Ar[i * ldr + j] = re;
+  Ar[i * ldr + n + j] = -im;
+  Ar[(m + i) * ldr + j] = im;
+  Ar[(m + i) * ldr + n + j] = re;
+}
+
+// Complex factors from those of the realification (pair-ordered rank index):
+//   U column a = rows [0, m) + i rows [m, 2m) of realified column 2a,
+//   V^H row a = conj of the same for V,
+//   D(p, q) = Dr(2p, 2q) + i Dr(2p + 1, 2q).
+// Outputs interleaved complex: Ut (r_cap x m), core (r_cap x r_cap), Vt (r_cap x n).
+template <typename T>
+__global__ void k_cplx_unpack(const T* __restrict__ Utr, const T* __restrict__ Dr, const T* __restrict__ Vtr,
+                              int64_t m, int64_t n, int64_t r, int64_t rc2, T* __restrict__ Ut, T* __restrict__ core,
+                              T* __restrict__ Vt, int64_t rc) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, a = blockIdx.y;
+  if (a >= r) return;
+  if (t < m) {
+    const T* u = Utr + (2 * a) * (2 * m);
+    Ut[2 * (a * m + t)] = u[t];
+    Ut[2 * (a * m + t) + 1] = u[m + t];
+  }
+  if (t < n) {
+    const T* v = Vtr + (2 * a) * (2 * n);
+    Vt[2 * (a * n + t)] = v[t];
+    Vt[2 * (a * n + t) + 1] = -v[n + t];
+  }
+  if (t < rc) {
+    T re = (T)0, im = (T)0;
+    if (t < r) {
+      re = Dr[(2 * a) * rc2 + 2 * t];
+      im = Dr[(2 * a + 1) * rc2 + 2 * t];
+    }
+    core[2 * (a * rc + t)] = re;
+    core[2 * (a * rc + t) + 1] = im;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2135,7 +2242,7 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   bool hit = false;
   if (mine) {
     d = ((dmask >> j) & 1ull) ? 0.0 : Gs[j * LD + j] * ca.R1[(int64_t)j * f + j];
-    hit = (d <= eps) || st->nonfinite;
+    hit = ((d <= eps) && (!st->paired || ((ca.col0 + j) & 1) == 0)) || st->nonfinite;
   }
   const unsigned long long mask = __ballot(hit);
   const int keep = mask ? (int)__ffsll((long long)mask) - 1 : f;
@@ -2294,7 +2401,8 @@ __global__ void k_decide(const double* __restrict__ R1, const double* __restrict
   for (int c = 0; c < f; ++c) {
     const double d = dead[c] ? 0.0 : R2[(int64_t)c * f + c] * R1[(int64_t)c * f + c];
     diag_log[col0 + c] = d;
-    if (d <= eps || st->nonfinite) { keep = c; stop = true; st->d_stop = d; break; }
+    const bool lead = !st->paired || ((col0 + c) & 1) == 0;
+    if ((d <= eps && lead) || st->nonfinite) { keep = c; stop = true; st->d_stop = d; break; }
   }
   if (col0 + f >= n) stop = true;
   acc[block_id] = keep;
@@ -2336,10 +2444,10 @@ __global__ void k_finish_norm(const double* __restrict__ parts, const float* __r
 }
 
 __global__ void k_init_state(State* st, double tol, int64_t* wlog, int nwlog, int32_t* dead,
-                             int64_t ndead, int32_t* acc, int nacc, int lp_mode) {
+                             int64_t ndead, int32_t* acc, int nacc, int lp_mode, int paired) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->eps = 0.0; st->normsq = 0.0; st->tol = tol;
-    st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->pad = 0; st->rank = 0;
+    st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->paired = paired; st->rank = 0;
     for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
     st->lp_scale = 1.0; st->lp_mode = lp_mode; st->pad2 = 0; st->d_stop = 0.0;
   }

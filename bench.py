@@ -391,13 +391,25 @@ def solve_stats(E, torch, A, tol, ctx, steps, warmup=1):
                 flags=int(f.flags))
 
 
+def timed_calls(torch, fn, steps):
+    """(ms per call, last result) of `steps` calls after one warm-up call,
+    bracketed by device synchronisations."""
+    res = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, res
+
+
 def subresults(args, E, torch):
     """The other configurations of the benchmark set, each measured briefly
-    after the headline: ranks and errors against the oracle where the oracle
-    finishes in seconds."""
+    on the GPU after the headline.  Returns the results and the list of
+    (result dict, FP64 host matrix, tol, block) whose oracle rank the
+    cpu_baseline leg adds where the oracle finishes in seconds."""
     import workloads as W
-    import oracle.eodabe_oracle as O
-    out = {}
+    out, checks = {}, []
     t_all = time.perf_counter()
 
     log("sub: 4096^2 rank sweep")
@@ -408,9 +420,8 @@ def subresults(args, E, torch):
         A = W.spectrum_torch(1000 + k, 4096, 4096, sig, noise, dtype=torch.float32)
         st = solve_stats(E, torch, A, 1e-4, E.Context(block=32, seed=0), steps=5)
         st["content_rank"] = r
-        if not args.no_cpu_baseline and r <= 160:
-            ref = O.eod_abe(A.double().cpu().numpy(), 1e-4, k=32, seed=0)
-            st["oracle_rank"] = int(ref.rank)
+        if r <= 160:
+            checks.append((st, A.double().cpu().numpy(), 1e-4, 32, False))
         by, fl = algorithmic_work(4096, 4096, st["rank"], st["blocks"], 32, 4)
         st["tflops"] = round(fl / (st["ms_per_solve"] * 1e-3) / 1e12, 3)
         st["hbm_frac_end_to_end"] = round(by / (st["ms_per_solve"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
@@ -432,10 +443,7 @@ def subresults(args, E, torch):
             st["sketch_GBs"] = round(by / (tot * 1e-3) / 1e9, 1)
             st["sketch_hbm_frac"] = round(by / (tot * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
         hs[name] = st
-    if not args.no_cpu_baseline:
-        ref = O.eod_abe(H.astype(np.float64), 1e-2, k=16, seed=0)
-        hs["oracle_rank"] = int(ref.rank)
-        hs["oracle_relerr"] = float(O.rel_err(H.astype(np.float64), ref.U, ref.D, ref.V))
+    checks.append((hs, H.astype(np.float64), 1e-2, 16, True))
     out["hsi262144_tol1e-2"] = hs
     del Ht
 
@@ -450,9 +458,45 @@ def subresults(args, E, torch):
     L = W.lowrank_haar(0)
     st = solve_stats(E, torch, torch.from_numpy(L).cuda(), 1e-8, E.Context(block=32, seed=0, dtype=torch.float64),
                      steps=20)
-    ref = O.eod_abe(L, 1e-8, k=32, seed=0)
-    st["oracle_rank"], st["oracle_relerr"] = int(ref.rank), float(O.rel_err(L, ref.U, ref.D, ref.V))
+    checks.append((st, L, 1e-8, 32, True))
     out["lowrank512_fp64_tol1e-8"] = st
+
+    log("sub: colour images (channels as tiles; above 1024, one factorization each)")
+    for h in (1024, 4096):
+        img = torch.from_numpy(W.rgb_image(0, h, h, noise_std=0.05)).cuda()
+        ctx = E.Context(block=32, seed=0)
+        ms, ci = timed_calls(torch, lambda: E.compress_image(img, 1e-3, ctx), 3 if h > 1024 else 10)
+        inf = ci.info
+        out[f"rgb{h}_tol1e-3"] = dict(ms_per_image=round(ms, 4), megapixels_per_s=round(h * h / (ms * 1e3), 1),
+                                      ranks=[int(inf.rank[c]) for c in range(3)], relerr=inf.relerr,
+                                      psnr=round(inf.psnr, 3), ssim=round(inf.ssim, 6),
+                                      reduction=round(inf.reduction, 4))
+        del img, ci
+
+    log("sub: complex input")
+    for name, cdt in (("complex64", torch.complex64), ("complex128", torch.complex128)):
+        Ac = torch.from_numpy(W.lowrank_complex(0, m=2048, n=2048, r=40, noise_std=1e-7, decades=2.0)).to(
+            device="cuda", dtype=cdt)
+        rdt = torch.float32 if cdt == torch.complex64 else torch.float64
+        ctx = E.Context(block=16, seed=0, dtype=rdt)
+        ms, fc = timed_calls(torch, lambda: E.factor_complex(Ac, 1e-4, ctx), 10)
+        A64 = Ac.to(torch.complex128)
+        rel = float(torch.linalg.norm(A64 - fc.U.to(torch.complex128) @ fc.D.to(torch.complex128)
+                                      @ fc.Vt.to(torch.complex128)) / torch.linalg.norm(A64))
+        out[f"{name}_2048_r40_tol1e-4"] = dict(ms_per_solve=round(ms, 4), rank=int(fc.rank), blocks=int(fc.blocks),
+                                               relerr=rel)
+        del Ac, A64, fc
+
+    log("sub: hyperspectral features and 10-fold KNN (21025 pixels)")
+    Hl, lab, fold = W.hyperspectral_labelled(0)
+    Hd = torch.from_numpy(Hl).cuda()
+    labd, foldd = torch.from_numpy(lab).cuda(), torch.from_numpy(fold).cuda()
+    fh = E.factor(Hd, 1e-2, block=16, seed=0)
+    F = E.features(fh).contiguous()
+    ms_knn, res = timed_calls(torch, lambda: E.knn_cv(F, labd, foldd, 5, 15), 5)
+    out["hsi21025_knn5_tol1e-2"] = dict(features=int(fh.rank), ms_knn=round(ms_knn, 3), oa=res[2],
+                                        pairs_per_s=round(21025 * 21025 / (ms_knn * 1e-3), 1))
+    del Hd, labd, foldd, F, fh
 
     log("sub: 1024 tiles, batched vs sequential")
     tiles = W.tiles(0, count=1024)
@@ -482,7 +526,18 @@ def subresults(args, E, torch):
                                     rank_agree=int(sum(int(f.rank) == int(r) for f, r in zip(fs, ranks_b))))
     del dev, bt, ws, outs, fs
     out["seconds"] = round(time.perf_counter() - t_all, 1)
-    return out
+    return out, checks
+
+
+def cpu_baseline_oracle_checks(checks):
+    """Part of the cpu_baseline leg: the oracle's rank (and RelErr) on the
+    sub-configurations' matrices, written beside the GPU's results."""
+    import oracle.eodabe_oracle as O
+    for st, A64, tol, k, want_err in checks:
+        ref = O.eod_abe(A64, tol, k=k, seed=0)
+        st["oracle_rank"] = int(ref.rank)
+        if want_err:
+            st["oracle_relerr"] = float(O.rel_err(A64, ref.U, ref.D, ref.V))
 
 
 def cpu_baseline_one_thread(A64, tol, block, budget_s):
@@ -609,8 +664,13 @@ def main():
     # the sketch and the projection: the streaming kernels the benchmark spec's HBM
     # target refers to); the latency-bound small kernels are reported end to
     # end below
-    names = {E.PROF_SKETCH: "sketch Y = A*Omega_j (k_sketch)", E.PROF_PROJECT: "projection C = Q^T A (k_gemm_nn)"}
-    kernel_id = {E.PROF_SKETCH: "k_sketch", E.PROF_PROJECT: "k_gemm_nn"}
+    # the sketch runs as k_sketch_rows (16-row tiles, no partials) when the
+    # matrix has >= 4081 rows, its sketch would be split along K and b <= 32;
+    # otherwise as k_sketch (K-split partials, folded by k_fold_parts)
+    sk_rows = 4081 <= max(m, n) <= 32768 and min(m, n) >= 512 and block <= 32 and args.sketch == "native"
+    names = {E.PROF_SKETCH: "sketch Y = A*Omega_j (%s)" % ("k_sketch_rows" if sk_rows else "k_sketch"),
+             E.PROF_PROJECT: "projection C = Q^T A (k_gemm_nn)"}
+    kernel_id = {E.PROF_SKETCH: "k_sketch_rows" if sk_rows else "k_sketch", E.PROF_PROJECT: "k_gemm_nn"}
     kind = max(prof, key=lambda k: prof[k][0])
     tot_ms, launches, by = prof[kind]
     avg_ms = tot_ms / max(launches, 1)
@@ -639,6 +699,10 @@ def main():
                       roofline_frac=round(max(by_e2e / (PEAK_HBM_GBS * 1e9), fl_e2e / (peak_fl * 1e12))
                                           / (ms_per_step * 1e-3), 4))
 
+    subs, checks = None, []
+    if not args.no_subresults and args.workload == "image4096" and args.sketch == "native" and not args.block:
+        subs, checks = subresults(args, E, torch)
+
     cpu = None
     orc = {}
     if not args.no_cpu_baseline:
@@ -652,9 +716,9 @@ def main():
         one = cpu_baseline_one_thread(A_np.astype(np.float64), tol, block, min(args.cpu_budget, 10.0))
         if one:
             cpu["one_thread"] = one
-    subs = None
-    if not args.no_subresults and args.workload == "image4096" and args.sketch == "native" and not args.block:
-        subs = subresults(args, E, torch)
+        if checks:
+            log("cpu baseline leg: oracle ranks of the sub-configurations")
+            cpu_baseline_oracle_checks(checks)
 
     line = {
         "metric": METRIC,

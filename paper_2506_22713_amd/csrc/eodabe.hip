@@ -219,12 +219,15 @@ struct Geo {
   int64_t ld_lp;        // leading dimension of the low-precision copy of A (multiple of 8)
   bool wide;            // learned warm start: buffers of the wide sketch
   bool paired;          // realified complex input: test columns and stops in pairs
+  bool sk_rows;         // sketch by 16-row tiles straight into Y (k_sketch_rows)
 };
 
 // Widest sketch of the learned warm start in one pass over A (columns).
 constexpr int WIDE_COLS = 128;
 // K-splits of the Gram of blocks wider than 64 columns (partials, then a sum).
 constexpr int GRAM_SPLITS_WIDE = 16;
+// Waves of a k_sketch_rows workgroup (the K parts of one 16-row tile).
+constexpr int SKETCH_ROWS_WAVES = 8;
 
 struct WS {
   State* st;
@@ -282,10 +285,11 @@ WS carve(void* base, const Geo& g) {
   w.accv = c.take<int32_t>(g.nblk + 1);
   w.dead = c.take<int32_t>((g.nblk + 1) * BN_MAX);
   w.diag_log = c.take<double>(g.nn + BN_MAX);
-  w.normparts = c.take<double>((int64_t)g.s_sketch * cdiv(g.mm, 128) + 64);
-  w.maxparts = c.take<float>((int64_t)g.s_sketch * cdiv(g.mm, 128) + 64);
+  const int64_t nparts = std::max<int64_t>((int64_t)g.s_sketch * cdiv(g.mm, 128), cdiv(g.mm, 16));
+  w.normparts = c.take<double>(nparts + 64);
+  w.maxparts = c.take<float>(nparts + 64);
   w.alp = g.lp ? c.take<uint16_t>(g.mm * g.ld_lp) : nullptr;
-  w.omega = c.take<char>((int64_t)g.bn * g.ldk * e);
+  w.omega = c.take<char>((int64_t)g.bn * rup(g.ldk, 16) * e);   // column or tiled layout
   w.ypart = c.take<char>((int64_t)g.s_sketch * g.ldy * g.bn * e);
   w.y = c.take<char>(g.ldy * g.bn * e);
   w.wpart = c.take<char>((int64_t)g.s_proj * ldw_of(g) * g.bn * e);
@@ -328,6 +332,14 @@ WS carve(void* base, const Geo& g) {
   return w;
 }
 
+// Whether the sketch of an mm-row matrix runs as k_sketch_rows: its 16-row
+// tiles alone fill the chip (one workgroup each), the sketch would otherwise
+// be split along K (splits > 1), and the block is at most 32 columns wide
+// (wider blocks reuse an LDS-staged Omega slab across 128 rows instead).
+bool use_sketch_rows(int64_t mm, int64_t splits, int64_t bn) {
+  return splits > 1 && cdiv(mm, 16) >= 256 && bn <= 32;
+}
+
 bool plan(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t lda, const void* A,
           int64_t r_cap, Geo& g) {
   if (m < 0 || n < 0) return false;
@@ -359,6 +371,9 @@ bool plan(const eodabe_ctx* ctx, int64_t m, int64_t n, int64_t lda, const void* 
   int64_t s = cdiv(512, mt);
   s = std::min<int64_t>(s, std::max<int64_t>(g.nn / 256, 1));
   g.s_sketch = (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+  // Matrices whose 16-row tiles alone fill the chip (one workgroup each) and
+  // whose sketch would otherwise be split along K: no partials at all.
+  g.sk_rows = use_sketch_rows(g.mm, g.s_sketch, g.bn) && !g.paired;
   g.s_proj = (int)std::max<int64_t>(1, std::min<int64_t>(64, g.mm / 256));
   g.s_gram = (int)std::max<int64_t>(1, std::min<int64_t>(64, g.mm / 2048));
   // C = Q^T A: output r x nn is small, the reduction over mm is long.
@@ -443,6 +458,44 @@ struct Ops {
     else SK_CASE(8);
 #undef SK_CASE
 #undef SK_LAUNCH
+    LAUNCHCHK();
+    return 0;
+  }
+
+  // Y = A Omega straight into Y (no K-split partials), see k_sketch_rows;
+  // Omt in the tiled layout of k_omega_tiled, bn <= 32; sumsq / maxabs
+  // receive one partial per 16-row tile.
+  int sketch_rows(const T* A, int64_t lda, const T* Omt, int64_t M, int bn, int64_t K, T* Y, int64_t ldy,
+                  double* sumsq, const int32_t* stopb, int blk, float* maxabs = nullptr, int lp_write = 0,
+                  uint16_t* lp_out = nullptr, int64_t ld_lp = 0, const State* lp_st = nullptr) {
+    if (M <= 0 || bn <= 0) return 0;
+    if (bn > 32 || (lp_write && sizeof(T) != 4) || (maxabs && !sumsq)) return EODABE_EINVAL;
+    if (cdiv(M, 16) > 0x7fffffff) return EODABE_EINVAL;
+#define SR_LAUNCH(CC, LW, SS)                                                                         \
+  hipExtLaunchKernelGGL((k_sketch_rows<T, CC, SKETCH_ROWS_WAVES, LW, SS>), dim3((unsigned)cdiv(M, 16)), \
+                        dim3(64 * SKETCH_ROWS_WAVES), 0, st, pe0, pe1, 0, A, lda, Omt, M, bn, K, Y, ldy,  \
+                        sumsq, maxabs, lp_out, ld_lp, lp_st, stopb, blk)
+#define SR_SS(CC, LW)                                  \
+  do {                                                 \
+    if (!sumsq) SR_LAUNCH(CC, LW, 0);                  \
+    else if (!maxabs) SR_LAUNCH(CC, LW, 1);            \
+    else SR_LAUNCH(CC, LW, 2);                         \
+  } while (0)
+#define SR_CASE(CC)                                    \
+  do {                                                 \
+    if constexpr (sizeof(T) == 4) {                    \
+      if (lp_write == 1) SR_SS(CC, 1);                 \
+      else if (lp_write == 2) SR_SS(CC, 2);            \
+      else SR_SS(CC, 0);                               \
+    } else {                                           \
+      SR_SS(CC, 0);                                    \
+    }                                                  \
+  } while (0)
+    if (bn <= 16) SR_CASE(1);
+    else SR_CASE(2);
+#undef SR_CASE
+#undef SR_SS
+#undef SR_LAUNCH
     LAUNCHCHK();
     return 0;
   }
@@ -833,9 +886,15 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       const int f = (int)std::min<int64_t>(g.b, g.nn - col0);
       const bool pre = j >= pre_j0 && j < pre_j1;
       T* y = pre ? (T*)w.y_w + (j - pre_j0) * (int64_t)g.b * g.ldy : (T*)w.y;
+      // the sketch of this block runs by 16-row tiles (tiled test matrix)
+      const bool rows_blk = g.sk_rows && !(g.lp && j >= 2);
       // a1: Omega_j (bn rows; rows f..bn-1 zero)
       if (!pre) {
-        if (g.paired) {
+        if (rows_blk) {
+          dim3 grid((unsigned)cdiv(cdiv(rup(g.nn, 16), 4), 256), g.bn);
+          hipLaunchKernelGGL((k_omega_tiled<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.bn / 16,
+                             omega, stopb, blk);
+        } else if (g.paired) {
           dim3 grid((unsigned)cdiv(g.ldk, 256), f);
           hipLaunchKernelGGL((k_omega_paired<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.ldk, omega,
                              stopb, blk);
@@ -844,12 +903,13 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.ldk, omega,
                              stopb, blk);
         }
-        if (f < g.bn)
+        if (f < g.bn && !rows_blk)
           hipLaunchKernelGGL(k_zero<T>, dim3(64), dim3(256), 0, st, omega + (int64_t)f * g.ldk,
                              (int64_t)(g.bn - f) * g.ldk);
         LAUNCHCHK();
       }
-      // a2: sketch Y = A Omega_j (K-split partials; block 0 also ||A||_F)
+      // a2: sketch Y = A Omega_j (K-split partials folded into Y, or Y written
+      // by 16-row tiles directly; block 0 also ||A||_F)
       const int64_t ystride = g.ldy * g.bn;
       const int nsp = eff_splits(g.nn, g.s_sketch);
       // low-precision form: block 1 also writes the FP16/BF16 copy of A
@@ -863,6 +923,11 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           TRY(ops.sketch_lp(g.lp, w.alp, g.ld_lp, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch,
                             (T*)w.ypart, g.ldy, ystride, w.st, stopb, blk));
         abytes = 2.0 * g.mm * g.nn;
+      } else if (rows_blk) {
+        TRY(ops.sketch_rows(Ae, g.lda_eff, omega, g.mm, g.bn, g.nn, y, g.ldy, j == 0 ? w.normparts : nullptr,
+                            stopb, blk, j == 0 ? w.maxparts : nullptr, (g.lp && j == 1) ? g.lp : 0, w.alp,
+                            g.ld_lp, w.st));
+        if (g.lp && j == 1) abytes += 2.0 * g.mm * g.nn;
       } else {
         TRY(ops.sketch(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch, (T*)w.ypart, g.ldy,
                        ystride, j == 0 ? w.normparts : nullptr, stopb, blk,
@@ -873,7 +938,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       prof_attach(ctx, ops, -1);
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
                abytes + (double)g.elem * ((double)g.nn * f + (double)g.mm * f));
-      if (j > 0) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+      // partials to fold unless the sketch wrote Y itself
+      if (j > 0 && !rows_blk) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       if (j > 0) TRY(pair_fix<T>(ctx, st, g.paired, y, g.ldy, g.mm, f, stopb, blk));
       }
       // a3 + a4: two rounds of [project against the basis so far (width
@@ -885,7 +951,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       const int64_t wmax = std::min<int64_t>(j * g.b, g.nn);
       const bool small = f <= 64;     // fused Gram + Cholesky-with-inverse kernels
       const bool mid = f <= 128;      // explicit R^{-1} (blocked Cholesky above 64 columns) + apply
-      if (j == 0) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+      if (j == 0 && !rows_blk) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       if (j == 0) TRY(pair_fix<T>(ctx, st, g.paired, y, g.ldy, g.mm, f, stopb, blk));
       for (int pass = 0; pass < 2; ++pass) {
         if (j > 0) {
@@ -904,7 +970,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           if (j == 0) {
             ca.norm_parts = w.normparts;
             ca.max_parts = w.maxparts;
-            ca.n_norm = sketch_wgs * (int64_t)nsp;
+            ca.n_norm = g.sk_rows ? cdiv(g.mm, 16) : sketch_wgs * (int64_t)nsp;
           }
         } else {
           if (mid) ca.Rinv = w.r2inv;
@@ -1199,7 +1265,7 @@ template <typename T>
 size_t sketch_carve(void* base, int64_t m, int64_t n, const SketchPlan& p, T** om, T** yp, T** ap,
                     T** yr, SketchLp* lp) {
   Carver c(base);
-  *om = c.take<T>(p.bn * p.ldk);
+  *om = c.take<T>(p.bn * rup(p.ldk, 16));
   *yp = c.take<T>(p.s * p.ldyp * p.bn);
   *ap = c.take<T>(m * p.ldk);
   *yr = c.take<T>(p.ldyp * p.bn);
@@ -2134,11 +2200,19 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
       Ae = ap;
       la = ldk;
     }
-    dim3 grid((unsigned)cdiv(cdiv(ldk, 4), 256), (unsigned)bn);
-    hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, n, col0, (int)ncols, ldk, om,
-                       nullptr, 0);
-    if (ncols < bn)
-      hipLaunchKernelGGL(k_zero<T>, dim3(64), dim3(256), 0, st, om + ncols * ldk, (bn - ncols) * ldk);
+    const int lpm0 = ctx->o.a_dtype == EODABE_F32 ? ctx->o.sketch_dtype : 0;
+    const bool rows = !lpm0 && use_sketch_rows(m, p.s, bn);
+    if (rows) {
+      dim3 grid((unsigned)cdiv(cdiv(rup(n, 16), 4), 256), (unsigned)bn);
+      hipLaunchKernelGGL((k_omega_tiled<T>), grid, dim3(256), 0, st, k0, k1, n, col0, (int)ncols, (int)(bn / 16),
+                         om, nullptr, 0);
+    } else {
+      dim3 grid((unsigned)cdiv(cdiv(ldk, 4), 256), (unsigned)bn);
+      hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, n, col0, (int)ncols, ldk, om,
+                         nullptr, 0);
+      if (ncols < bn)
+        hipLaunchKernelGGL(k_zero<T>, dim3(64), dim3(256), 0, st, om + ncols * ldk, (bn - ncols) * ldk);
+    }
     LAUNCHCHK();
     Ops<T> ops{ctx, st};
     const int64_t ystr = ldyp * bn;
@@ -2157,10 +2231,13 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
       if constexpr (sizeof(T) == 4)
         TRY(ops.sketch_lp(lpm, lp.alp, lp.ld_lp, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, lp.st,
                           nullptr, 0));
+    } else if (rows) {
+      TRY(ops.sketch_rows(Ae, la, om, m, (int)bn, n, yr, ldyp, nullptr, nullptr, 0));
     } else {
       TRY(ops.sketch(Ae, la, om, ldk, m, (int)bn, n, (int)p.s, yp, ldyp, ystr, nullptr, nullptr, 0));
     }
-    TRY(ops.reduce_wide((const T*)yp, eff_splits(n, (int)p.s), ystr, ystr, yr));
+    if (!rows)
+      TRY(ops.reduce_wide((const T*)yp, eff_splits(n, (int)p.s), ystr, ystr, yr));
     TRY(copy2d<T>(ctx, st, yr, ldyp, (T*)Y, ldy, ncols, m, 0));
     HIPCHK(hipStreamSynchronize(st));
     return 0;

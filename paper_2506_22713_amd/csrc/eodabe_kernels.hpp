@@ -154,6 +154,28 @@ __global__ void k_omega(uint32_t k0, uint32_t k1, int64_t n, int64_t col0, int n
     if (4 * q + e < ldo) o[e] = (4 * q + e < n) ? (T)z[e] : (T)0;
 }
 
+// Test-matrix columns col0 .. col0+ncols-1 (zero columns up to 16 ct) in the
+// tiled layout k_sketch_rows reads: the four entries of rows 4q .. 4q+3 of
+// column c sit together at ((q/4 ct + c/16) 64 + (q%4) 16 + c%16) 4, so one
+// wave reads the operand of a 16-row chunk of a 16-column tile as 1 KiB
+// contiguous.  Entries past n (up to the next multiple of 16) are zero.
+// Same values as k_omega (each entry a pure function of (seed, row, column)).
+// Grid: (ceil(rup(n, 16) / 4 / 256), 16 ct).
+template <typename T>
+__global__ void k_omega_tiled(uint32_t k0, uint32_t k1, int64_t n, int64_t col0, int ncols, int ct,
+                              T* __restrict__ out, const int32_t* __restrict__ stop_block, int block_id) {
+  if (stop_block && *stop_block < block_id) return;
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int64_t n16 = (n + 15) / 16 * 16;
+  if (4 * q >= n16 || j >= 16 * ct) return;
+  float z[4] = {0.f, 0.f, 0.f, 0.f};
+  if (j < ncols && 4 * q < n) omega4(k0, k1, q, col0 + j, z);
+  T* o = out + ((((q >> 2) * ct + (j >> 4)) * 64 + (q & 3) * 16 + (j & 15)) << 2);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o[e] = (j < ncols && 4 * q + e < n) ? (T)z[e] : (T)0;
+}
+
 // Columns of the test matrix of a realified complex problem (nn = 2 nc rows):
 // real column 2c + p is the realification of omega_c (p = 0) or of
 // i omega_c (p = 1), omega_c = (g_2c + i g_2c+1) / sqrt(2) the complex
@@ -690,6 +712,195 @@ __global__ __launch_bounds__(256) void k_sketch(
       const int64_t p = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
       sumsq[p] = ss_red[0] + ss_red[1] + ss_red[2] + ss_red[3];
       if (maxabs) maxabs[p] = fmaxf(fmaxf(mx_red[0], mx_red[1]), fmaxf(mx_red[2], mx_red[3]));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sketch Y = A Omega_j (Alg. 1) without K-split partials, for matrices tall
+// enough that 16-row tiles fill the chip.  A workgroup of NW waves owns one
+// 16-row tile of A and splits its K range NW ways; each wave streams its part
+// of the 16 rows with a register ring of dwordx4 loads and accumulates on
+// MFMA.  The test matrix comes in the tiled layout of k_omega_tiled (Omt,
+// 16 CT columns), so each operand load of a wave is 1 KiB contiguous from L2
+// (a workgroup uses all of Omega_j exactly once: no reuse for LDS to
+// capture; in the plain column layout the same loads, 16 rows of 64 bytes,
+// made the kernel half again slower).  The NW partial tiles are summed in
+// LDS in a fixed tree order and wave 0 writes the tile of Y (column-major,
+// ldy): no partial buffer in HBM and no separate fold.  SS 1: one partial
+// per workgroup of the sum of squares of A (FP32 squares of four entries,
+// accumulated in FP64; FP64 data: FP64 throughout), SS 2: also max |a|; LPW:
+// the low-precision copy of A, as in k_sketch.  A row-major with lda % 4 == 0
+// and 16-byte alignment; rows past M are read at the last row and never
+// reach an output; columns N .. 16 CT - 1 are computed and not stored.
+// ---------------------------------------------------------------------------
+template <typename T, int CT, int NW, int LPW, int SS, int D = ((CT * (int)sizeof(T) <= 16) ? 4 : 2)>
+__global__ __launch_bounds__(64 * NW) void k_sketch_rows(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ Omt, int64_t M, int N, int64_t K,
+    T* __restrict__ Y, int64_t ldy, double* __restrict__ sumsq, float* __restrict__ maxabs,
+    uint16_t* __restrict__ lp_out, int64_t ld_lp, const State* __restrict__ lp_st,
+    const int32_t* __restrict__ stop_block, int block_id) {
+  typedef Mfma<T> MF;
+  typedef typename MF::acc_t acc_t;
+  // D: 16-K chunks in flight per wave
+  static_assert(NW >= 2 && (NW & (NW - 1)) == 0, "NW: power of two");
+  if (stop_block && *stop_block < block_id) return;
+  __shared__ acc_t red[NW / 2][CT][64];
+  __shared__ double ss_red[NW];
+  __shared__ float mx_red[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * 16;
+  const int64_t kchunk = ((K + NW - 1) / NW + 15) / 16 * 16;
+  const int64_t kb = min(K, (int64_t)wv * kchunk), ke = min(K, kb + kchunk);
+  double ss = 0.0;
+  float mx = 0.0f;
+  float lps = 1.0f;
+  if constexpr (LPW != 0) lps = (float)lp_st->lp_scale;
+  const int64_t row = m0 + r;
+  const bool aval = row < M;
+  const T* ap = A + (aval ? row : (M - 1)) * lda + 4 * g;
+  const T* op = Omt + lane * 4;             // + (chunk CT + u) 256
+  acc_t acc[CT];
+#pragma unroll
+  for (int u = 0; u < CT; ++u) acc[u] = MF::zero();
+  auto compute = [&](const V4<T>& a, const V4<T>(&b)[CT], int64_t k) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int u = 0; u < CT; ++u) acc[u] = MF::op(a.v[v], b[u].v[v], acc[u]);
+    if constexpr (SS != 0) {
+      if (aval) {
+        if constexpr (sizeof(T) == 4) {
+          float q = a.v[0] * a.v[0];
+          q = fmaf(a.v[1], a.v[1], q);
+          q = fmaf(a.v[2], a.v[2], q);
+          q = fmaf(a.v[3], a.v[3], q);
+          ss += (double)q;
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ss = fma((double)a.v[v], (double)a.v[v], ss);
+        }
+        if constexpr (SS == 2)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) mx = fmaxf(mx, fabsf((float)a.v[v]));
+      }
+    }
+    if constexpr (LPW != 0) {
+      if (aval) {
+        const int64_t kk = k + 4 * g;
+        uint16_t* dst = lp_out + row * ld_lp + kk;
+        if (kk + 3 < ke) {
+          uint2 pk;
+          pk.x = (uint32_t)to_lp_bits<LPW>((float)a.v[0] * lps) |
+                 ((uint32_t)to_lp_bits<LPW>((float)a.v[1] * lps) << 16);
+          pk.y = (uint32_t)to_lp_bits<LPW>((float)a.v[2] * lps) |
+                 ((uint32_t)to_lp_bits<LPW>((float)a.v[3] * lps) << 16);
+          *reinterpret_cast<uint2*>(dst) = pk;
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (kk + v < ke) dst[v] = to_lp_bits<LPW>((float)a.v[v] * lps);
+        }
+      }
+    }
+  };
+  auto load = [&](V4<T>& a, V4<T>(&b)[CT], int64_t k) {
+    a = ld4(ap + k);
+#pragma unroll
+    for (int u = 0; u < CT; ++u) b[u] = ld4(op + ((k >> 4) * CT + u) * 256);
+  };
+  const int64_t nfull = (ke - kb) / 16;
+  if (nfull > 0) {
+    // D-deep ring; chunk indices past the last full chunk are clamped to it
+    // in the prologue (never used), so every load is unconditional and each
+    // chunk waits only for its own loads
+    V4<T> ab[D], bb[D][CT];
+#pragma unroll
+    for (int q = 0; q < D; ++q) load(ab[q], bb[q], kb + 16 * min((int64_t)q, nfull - 1));
+    int64_t i = 0;
+    for (; i + 2 * D <= nfull; i += D) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        compute(ab[q], bb[q], kb + 16 * (i + q));
+        load(ab[q], bb[q], kb + 16 * (i + q + D));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      if (i + q < nfull) {
+        compute(ab[q], bb[q], kb + 16 * (i + q));
+        if (i + q + D < nfull) load(ab[q], bb[q], kb + 16 * (i + q + D));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      if (i + D + q < nfull) compute(ab[q], bb[q], kb + 16 * (i + D + q));
+  }
+  if (kb + 16 * nfull < ke) {                 // ragged tail: masked loads, zero past ke
+    const int64_t k = kb + 16 * nfull;
+    V4<T> a = ld4_masked(ap + k, k + 4 * g, ke), b[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) b[u] = ld4_masked(op + ((k >> 4) * CT + u) * 256, k + 4 * g, ke);
+    compute(a, b, k);
+  }
+  // fixed-order tree over the K parts: waves [h, 2h) hand their tiles to
+  // waves [0, h) for h = NW/2, ..., 1
+#pragma unroll
+  for (int h = NW / 2; h >= 1; h >>= 1) {
+    if (wv >= h && wv < 2 * h)
+#pragma unroll
+      for (int u = 0; u < CT; ++u) red[wv - h][u][lane] = acc[u];
+    __syncthreads();
+    if (wv < h)
+#pragma unroll
+      for (int u = 0; u < CT; ++u) acc[u] += red[wv][u][lane];
+    __syncthreads();
+  }
+  if (wv == 0) {
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+      const int64_t col = 16 * u + r;
+      if (col >= N) continue;
+      if constexpr (MF::rows_contiguous) {
+        const int64_t r0 = m0 + 4 * g;
+        T* p = Y + col * ldy + r0;
+        if (r0 + 3 < M && (ldy & 3) == 0) {
+          *reinterpret_cast<f32x4*>(p) = acc[u];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (r0 + e < M) p[e] = acc[u][e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t rr = m0 + MF::row(g, e);
+          if (rr < M) Y[col * ldy + rr] = acc[u][e];
+        }
+      }
+    }
+  }
+  if constexpr (SS != 0) {
+    for (int off = 32; off > 0; off >>= 1) {
+      ss += __shfl_xor(ss, off);
+      mx = fmaxf(mx, __shfl_xor(mx, off));
+    }
+    if (lane == 0) {
+      ss_red[wv] = ss;
+      mx_red[wv] = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      float mt = 0.0f;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        t += ss_red[q];
+        mt = fmaxf(mt, mx_red[q]);
+      }
+      sumsq[blockIdx.x] = t;
+      if constexpr (SS == 2) maxabs[blockIdx.x] = mt;
     }
   }
 }

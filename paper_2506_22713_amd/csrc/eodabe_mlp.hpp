@@ -2,7 +2,8 @@
 // MLP 67 -> 256 -> 256 -> 256 -> 2 in FP32, trained and run by the kernels
 // below.  Inputs: the first 64 values d_c = |T(c,c)| of the stopping test
 // (the diagonal of the R factor of A Omega[:, :64], normalised by d_0 on a
-// clamped log10 scale) and log2 m, log2 n, log10 tol.  Head 0 regresses
+// clamped log10 scale), log2 m, log2 n and log10(eps / d_0), the stopping
+// threshold eps = tol ||A||_F on the scale of those values.  Head 0 regresses
 // log(1 + rank); head 1 is the 0.9-quantile of the same quantity (pinball
 // loss) and sizes the warm start.
 #pragma once

@@ -298,6 +298,24 @@ def test_factor_many_split_partials(m, n, dtype):
     assert f.rank == 40
 
 
+@pytest.mark.parametrize("m,n,r,dtype,tol,b", [
+    (4100, 700, 60, torch.float32, 1e-4, 32),     # ragged last row tile; 3 blocks
+    (4200, 520, 45, torch.float64, 1e-9, 16),     # one-tile-wide blocks; a wave with an empty K part
+    (600, 4097, 50, torch.float32, 1e-4, 32),     # wide: the transposed copy has 4097 rows
+])
+def test_factor_row_tile_sketch(m, n, r, dtype, tol, b):
+    # 4081 or more rows with blocks of at most 32 columns: the sketch runs by
+    # 16-row tiles over the whole K range (eight waves per tile, summed in
+    # LDS) and writes Y directly, on every block
+    say(f"factor {m}x{n} row-tile sketch")
+    A = W.lowrank_haar(23 + m, m=m, n=n, r=r, noise_std=0.0, decades=2.0)
+    stable = True
+    if dtype == torch.float32:
+        stable, _, _ = O.precision_stable(A, tol, b, 23)
+    f, ref = check_factor(A, dtype, tol, b=b, seed=23, stable=stable, rounding_only=True)
+    assert f.blocks >= 2
+
+
 EDGE_SIDES = [1, 2, 3, 7, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 255, 257, 300, 511, 513, 640]
 
 
@@ -552,6 +570,15 @@ def test_factor_lp_sketch_exact_rank(mode):
     else:
         assert 40 <= f.rank <= 48
     assert abs(e_gpu - e_emu) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", ["f16", "bf16"])
+def test_factor_lp_sketch_row_tiles(mode):
+    # 4112 rows: the FP32 blocks (and the write of the low-precision copy in
+    # block 2) run by 16-row tiles, later blocks read the copy
+    A = W.lowrank_haar(31, m=4112, n=520, r=120, noise_std=1e-6, decades=3.0).astype(np.float32).astype(np.float64)
+    f, ref, e_gpu, e_emu = _check_lp_factor(A, 1e-2, 16, 31, mode)
+    assert f.blocks >= 3
 
 
 # Exact-rank instances (FP32-rounded, so their error is FP32 rounding) on

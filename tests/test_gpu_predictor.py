@@ -166,3 +166,86 @@ def test_warm_start_same_rank_fewer_passes(r, lift):
         # the one holding block js, against js + 1 sketch passes of the plain loop
         assert launches == 2 + (js - 2) // (128 // b) + 1, (launches, d0, js)
         assert launches < js + 1
+
+
+HELD_OUT_FIRST_SEED = 50_000_000          # training drew seeds from 1_000_000 on
+
+
+def test_trained_checkpoint_gain_on_held_out_matrices():
+    """The committed checkpoint on held-out matrices of the training
+    generators (spectrum families and the image model, seeds disjoint from
+    the training set's), against the same factorizations without it: the
+    rank and the error are the plain loop's on every matrix, the sketch
+    passes drop, and the fallback rate (stop past the predicted width)
+    stays at most 25 % (2.3 % on the training run's held-out split)."""
+    import os
+    from paper_2506_22713_amd import train_predictor as TP
+    pred = PR.Predictor.load(os.path.join(os.path.dirname(PR.__file__), "predictor.ckpt"))
+    b = TP.BLOCK
+    rows = []
+    seed = HELD_OUT_FIRST_SEED
+    while len(rows) < 16 and seed < HELD_OUT_FIRST_SEED + 200:
+        A, tol, dtype, what = TP.make_sample(seed)
+        seed += 1
+        cp = E.Context(block=b, seed=seed, dtype=dtype)
+        cl = E.Context(block=b, seed=seed, dtype=dtype)
+        pred.attach(cl, margin=0.1)
+        fp = E.factor(A, tol, ctx=cp)                     # warm both paths once
+        if fp.rank < 64:
+            continue                                       # stops inside the probe: no prediction
+        E.factor(A, tol, ctx=cl)
+        res = {}
+        for name, ctx in (("plain", cp), ("learned", cl)):
+            ctx.profile(True)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            f = E.factor(A, tol, ctx=ctx)
+            ev1.record()
+            torch.cuda.synchronize()
+            _, passes, _ = ctx.profile_read(E.PROF_SKETCH)
+            ctx.profile(False)
+            A64 = A.double()
+            e = float(torch.linalg.norm(A64 - f.U.double() @ f.D.double() @ f.Vt.double()) / torch.linalg.norm(A64))
+            res[name] = (f, passes, ev0.elapsed_time(ev1), e)
+        d0, _, _, used = cl.last_prediction()
+        fpl, pp, tp, ep = res["plain"]
+        fl, pl, tl, el = res["learned"]
+        say(f"{what} tol {tol:.1e}: rank {fl.rank}/{fpl.rank} d0 {d0} used {used} passes {pl}/{pp} "
+            f"ms {tl:.3f}/{tp:.3f} relerr {el:.3e}/{ep:.3e}")
+        assert fl.rank == fpl.rank, (what, fl.rank, fpl.rank)
+        bar = 1e-10 if dtype == torch.float64 else 1e-5
+        assert abs(el - ep) <= bar, (what, el, ep)
+        assert used in (1, 2)
+        rows.append((pl, pp, tl, tp, used))
+    assert len(rows) == 16
+    pl, pp, tl, tp, used = (np.array(c, dtype=np.float64) for c in zip(*rows))
+    fallback = float(np.mean(used == 2))
+    say(f"held-out: sketch passes {pl.mean():.2f} vs {pp.mean():.2f} per solve, fallback {fallback:.2%}, "
+        f"wall time {tl.sum():.2f} vs {tp.sum():.2f} ms ({tp.sum() / tl.sum():.2f}x)")
+    assert pl.mean() < pp.mean()
+    assert np.all(pl <= pp + 1)
+    assert fallback <= 0.25
+
+
+@pytest.mark.parametrize("case", ["lowrank512_fp64", "hyperspectral_fp32"])
+def test_trained_checkpoint_idle_below_probe(case):
+    """Matrices whose rank is below the 64-column probe (the rank-20 512^2
+    and the rank-15 hyperspectral configurations) never consult the
+    predictor, and the factorization is the plain one bit for bit."""
+    import os
+    pred = PR.Predictor.load(os.path.join(os.path.dirname(PR.__file__), "predictor.ckpt"))
+    if case == "lowrank512_fp64":
+        A, tol, dtype, b = torch.from_numpy(W.lowrank_haar(0)).cuda(), 1e-8, torch.float64, 32
+    else:
+        A, tol, dtype, b = torch.from_numpy(W.hyperspectral(0, pixels=65536)).cuda(), 1e-2, torch.float32, 16
+    cp = E.Context(block=b, seed=0, dtype=dtype)
+    cl = E.Context(block=b, seed=0, dtype=dtype)
+    pred.attach(cl, margin=0.1)
+    fp = E.factor(A, tol, ctx=cp)
+    fl = E.factor(A, tol, ctx=cl)
+    torch.cuda.synchronize()
+    assert cl.last_prediction()[3] == 0
+    assert fl.rank == fp.rank < 64
+    for x, y in ((fl.U, fp.U), (fl.D, fp.D), (fl.Vt, fp.Vt)):
+        assert torch.equal(x, y)

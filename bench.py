@@ -461,7 +461,7 @@ def subresults(args, E, torch):
     checks.append((st, L, 1e-8, 32, True))
     out["lowrank512_fp64_tol1e-8"] = st
 
-    log("sub: colour images (channels as tiles; above 1024, one factorization each)")
+    log("sub: colour images (one factorization per channel, fused reconstruction and criteria)")
     for h in (1024, 4096):
         img = torch.from_numpy(W.rgb_image(0, h, h, noise_std=0.05)).cuda()
         ctx = E.Context(block=32, seed=0)
@@ -475,7 +475,7 @@ def subresults(args, E, torch):
 
     log("sub: complex input")
     for name, cdt in (("complex64", torch.complex64), ("complex128", torch.complex128)):
-        Ac = torch.from_numpy(W.lowrank_complex(0, m=2048, n=2048, r=40, noise_std=1e-7, decades=2.0)).to(
+        Ac = torch.from_numpy(W.lowrank_complex(0, m=2048, n=2048, r=40, noise_std=1e-9, decades=2.0)).to(
             device="cuda", dtype=cdt)
         rdt = torch.float32 if cdt == torch.complex64 else torch.float64
         ctx = E.Context(block=16, seed=0, dtype=rdt)

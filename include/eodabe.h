@@ -330,10 +330,9 @@ int eodabe_last_prediction(const eodabe_ctx* ctx, int64_t* d0, double* log_rank,
  * The introduction's storage criterion and the quality criteria of section
  * 4.1.  Each channel of a planar image img (channels x h x w FP32, device,
  * channel c at img + c h w, values nominally in [0, 255]) is factored by
- * EOD-ABE exactly as eodabe_factor would (q = 0, the context's seed; the
- * channels run as tiles of one persistent launch when h, w <= 1024, with the
- * block width eodabe_factor_batched would use, else one eodabe_factor call
- * each), reconstructed as U_hat D_hat V_hat^T into recon (device, same
+ * EOD-ABE exactly as eodabe_factor would (one call per channel: the
+ * context's block width, power iterations and seed), reconstructed as
+ * U_hat D_hat V_hat^T into recon (device, same
  * layout), and compared with the original:
  *   PSNR   = 10 log10(255^2 N / ||A_hat - A||_F^2), N = channels h w values
  *            (+inf when the reconstruction is exact);

@@ -39,7 +39,7 @@ def _check_image(img, tol, seed=0, block=32):
     torch.cuda.synchronize()
     inf = out.info
     img64 = img.astype(np.float64)
-    k = min(block, 64) if max(h, w) <= 1024 else block      # the batched kernel's block width
+    k = block
     ref = P.compress_image(img64, tol, k, seed=seed)
     ranks = [int(inf.rank[ch]) for ch in range(c)]
     say(f"  ranks gpu {ranks} oracle {ref['ranks']}  relerr {inf.relerr:.4e} / {ref['relerr']:.4e}"
@@ -83,7 +83,7 @@ def test_image_rgb_against_oracle(h, w, noise, tol):
     _check_image(W.rgb_image(1, h, w, noise_std=noise), tol, seed=2)
 
 
-def test_image_above_tile_size_single_matrix_path():
+def test_image_above_tile_size():
     _check_image(W.rgb_image(3, 1100, 1300, noise_std=0.05), 1e-3, seed=5)
 
 

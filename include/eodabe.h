@@ -59,10 +59,13 @@ typedef struct eodabe_ctx eodabe_ctx;
  * scale, block 2 also writes the FP16/BF16 copy A_lp); blocks 3, 4, ...
  * sketch A_lp with FP16/BF16 MFMA operands and FP32 accumulation.  The
  * Grams, Cholesky factors and the stopping test stay FP64.  When a block
- * read A_lp, the basis is refined by one FP32 subspace iteration
- * (Q~ = orth(A^T Q), Q = orth(A Q~), the power iteration of Alg. 2) before
- * the FP32 projection C = Q^T A, which wins back the accuracy the rounded
- * copy costs.  Below tol = 2 u_lp the form is not used (status bit 3). */
+ * read A_lp, Alg. 2 runs one subspace iteration more than opts.power_iters
+ * (Q~ = orth(A^T Q), Q = orth(A Q~)), and in each iteration the projection
+ * A^T Q takes A_lp and Q rounded to the same format on MFMA (FP32
+ * accumulation) while A Q~ and the final projection C = Q^T A run in FP32:
+ * the FP32 re-orthogonalisation and projection win back the accuracy the
+ * rounded copy costs.  Below tol = 2 u_lp the form is not used (status
+ * bit 3). */
 #define EODABE_SKETCH_NATIVE 0    /* same type as A */
 #define EODABE_SKETCH_F16    1    /* FP16 operands on MFMA, FP32 accumulation (A must be F32) */
 #define EODABE_SKETCH_BF16   2    /* BF16 operands on MFMA, FP32 accumulation (A must be F32) */
@@ -86,8 +89,9 @@ typedef struct eodabe_info {
                             bit 3: a low-precision sketch was requested with tol below 2 u_lp
                             (u_lp = 2^-11 FP16, 2^-8 BF16), where its rounding noise would mask
                             the stop test; every block sketched in FP32 (the plain path);
-                            bit 4: a block read the low-precision copy, and one FP32 subspace
-                            iteration refined the basis before the projection                 */
+                            bit 4: a block read the low-precision copy, and one more subspace
+                            iteration (A^T Q from the copy) refined the basis before the FP32
+                            projection                                                         */
   double  norm_a;        /* ||A||_F (FP64 accumulation)                                       */
   double  eps;           /* tol * ||A||_F, the absolute stopping threshold                    */
   double  relres_est;    /* |T(l,l)| / ||A||_F for the column l whose test stopped the loop:

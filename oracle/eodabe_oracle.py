@@ -198,8 +198,9 @@ def basis_ext(A: np.ndarray, eps: float, k: int, seed: int,
     from lp_scale (the products of the rounded operands are exact in FP64).
     The form is defined this way (blocks 1 and 2 sketch A itself: the first
     finds max|A| for the FP16 scale, the second writes the rounded copy);
-    when a block read the copy, eod_abe adds one subspace iteration on A
-    before the projection.
+    when a block read the copy, eod_abe adds one subspace iteration before
+    the projection and takes the first product of every subspace iteration,
+    A^T Q, from the copy (Q rounded the same way): (round(s A)^T round(Q)) / s.
     """
     m, n = A.shape
     lp = sketch_dtype if isinstance(sketch_dtype, str) else None
@@ -271,13 +272,21 @@ def _eod_abe_tall(A, tol, k, q, seed, sketch_dtype):
         z = np.zeros
         return EodAbeResult(z((m, 0)), z((0, 0)), z((n, 0)), 0, eps,
                             be["diagT"], be["blocks"], Q, np.zeros(0))
-    if isinstance(sketch_dtype, str) and be["blocks"] >= 3:
+    lp_iter = isinstance(sketch_dtype, str) and be["blocks"] >= 3
+    if lp_iter:
         # low-precision form: a block sketched the rounded copy, so one more
-        # subspace iteration on A itself refines the basis (the form's
+        # subspace iteration refines the basis, and each iteration takes
+        # A^T Q from the copy with Q rounded the same way (the form's
         # definition; the paper's method has no such step)
         q += 1
+        sc = lp_scale(A, sketch_dtype)
+        A_lp = lp_round((A * sc).astype(np.float32), sketch_dtype)
     for _ in range(q):                    # steps 2-7: power (subspace) iteration
-        Qt, _ = qr_posdiag(A.T @ Q)       # Y~_j = A^H Q_{j-1} = Q~_j R~_j
+        if lp_iter:
+            Yt = (A_lp.T @ lp_round(Q.astype(np.float32), sketch_dtype)) / sc
+        else:
+            Yt = A.T @ Q
+        Qt, _ = qr_posdiag(Yt)            # Y~_j = A^H Q_{j-1} = Q~_j R~_j
         Q, _ = qr_posdiag(A @ Qt)         # Y_j = A Q~_j = Q_j R_j
     C = Q.T @ A                           # step 8: C = Q_q^H A
     V, R = qr_posdiag(C.T)                # step 9: C^H = Q R

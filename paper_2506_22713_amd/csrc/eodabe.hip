@@ -554,6 +554,35 @@ struct Ops {
     return 0;
   }
 
+  // Partials of (Q_lp^T A_lp) / scale (lp 1 FP16, 2 BF16; FP32 data only):
+  // X = Q^T row-major (ldx), Z = the low-precision copy of A (ldz), see
+  // k_gemm_nn_lp.
+  int gemm_nn_lp(int lp, const float* X, int64_t ldx, const uint16_t* Z, int64_t ldz, int64_t M, int64_t N,
+                 int64_t K, int splits, float* out, int64_t ldo, int64_t part_stride, const State* lp_st) {
+    if (M <= 0 || N <= 0) return 0;
+    if (cdiv(N, 256) > 65535) return EODABE_EINVAL;
+    const int64_t kchunk = split_chunk(K, splits);
+    splits = eff_splits(K, splits);
+    const int rt = (int)std::min<int64_t>(4, cdiv(M, 16));
+    dim3 grid((unsigned)splits, (unsigned)cdiv(N, 256), (unsigned)cdiv(M, 16 * rt));
+#define NL_CASE(LP, RR)                                                                              \
+  hipLaunchKernelGGL((k_gemm_nn_lp<LP, RR>), grid, dim3(256), 0, st, X, ldx, Z, ldz, M, N, K, kchunk, out, \
+                     ldo, part_stride, lp_st)
+#define NL_RT(LP)                    \
+  do {                               \
+    if (rt == 1) NL_CASE(LP, 1);     \
+    else if (rt == 2) NL_CASE(LP, 2); \
+    else if (rt == 3) NL_CASE(LP, 3); \
+    else NL_CASE(LP, 4);             \
+  } while (0)
+    if (lp == 1) NL_RT(1);
+    else NL_RT(2);
+#undef NL_RT
+#undef NL_CASE
+    LAUNCHCHK();
+    return 0;
+  }
+
   template <typename U>
   int reduce(const U* parts, int nparts, int64_t stride, int64_t count, U* out,
              const int32_t* stopb = nullptr, int blk = 0, Gate gate = Gate{}) {
@@ -1184,20 +1213,31 @@ int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, cons
 // Alg. 2 after Alg. 1: power iteration, C = Q^T A, QR(C^T), QR(R^T).
 // Writes U_hat (column-major mm x r, ld ldu) to Uout, V_hat^T (r x nn,
 // row-major ldv) to Vout and D_hat (r x r row-major, ldd) to Dout.
-// extra_iters: subspace iterations on top of opts.power_iters (the
-// low-precision form's FP32 refinement of its basis).
+// lp_refine: the low-precision form read its copy of A, so it runs one
+// subspace iteration on top of opts.power_iters, and every iteration takes
+// its first product A^T Q from the copy (the second, A Q~, and the
+// projection C = Q^T A stay in the data type).
 template <typename T>
 int run_close(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, int64_t r,
-              T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout, int64_t ldd, int extra_iters) {
+              T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout, int64_t ldd, bool lp_refine) {
   if (r <= 0) return 0;
   Ops<T> ops{ctx, st};
   T* q = (T*)w.q;
   T* cb = (T*)w.cbuf;
   const int64_t cstride = r * g.ldk;
   const int s_core = core_splits(g, r);
-  for (int it = 0; it < ctx->o.power_iters + extra_iters; ++it) {
+  const int iters = ctx->o.power_iters + (lp_refine ? 1 : 0);
+  for (int it = 0; it < iters; ++it) {
     // Y~^T = Q^T A (r x nn), QR(Y~) -> Q~ (stored as Q~^T = cbuf rows)
-    TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
+    if constexpr (sizeof(T) == 4) {
+      if (lp_refine)
+        TRY(ops.gemm_nn_lp(g.lp, (const float*)q, g.ldy, w.alp, g.ld_lp, r, g.nn, g.mm, s_core, (float*)w.cpart,
+                           g.ldk, cstride, w.st));
+      else
+        TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
+    } else {
+      TRY(ops.gemm_nn(q, g.ldy, Ae, g.lda_eff, r, g.nn, g.mm, s_core, (T*)w.cpart, g.ldk, cstride));
+    }
     TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb));
     TRY(pair_fix<T>(ctx, st, g.paired, cb, g.ldk, g.nn, r));
     TRY(cholqr2<T>(ctx, st, g, w, cb, g.ldk, g.nn, (int)r, w.rb4, 0, (T*)w.tbig));
@@ -1937,10 +1977,11 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
     }
     // Low-precision form: a basis built from sketches of the FP16/BF16 copy
     // of A is tilted from the one FP32 sketches give by up to the copy's
-    // rounding over the weakest captured singular value.  One FP32 subspace
-    // iteration (Alg. 2, power iteration) maps it back through A and A^T
-    // before the FP32 projection, so the error is won back.
-    const int refine = (g.lp && blocks >= 3) ? 1 : 0;
+    // rounding over the weakest captured singular value.  One more subspace
+    // iteration (Alg. 2, power iteration; its A^T Q from the copy, A Q~ in
+    // FP32) maps it back through A before the FP32 projection, so the error
+    // is won back.
+    const bool refine = g.lp && blocks >= 3;
     if (refine) info->status_flags |= 16;
     if (!g.transposed) {
       TRY(run_close<T>(ctx, st, g, w, Ae, rank, (T*)Ut, m, (T*)Vt, n, (T*)core, g.r_cap, refine));

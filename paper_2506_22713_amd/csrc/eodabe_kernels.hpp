@@ -1212,6 +1212,151 @@ __global__ __launch_bounds__(256) void k_gemm_nn(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Low-precision NN GEMM partials: out_s (M x N, FP32) = (X_lp Z_lp) / scale
+// over K-split s, with Z the FP16 (LPT 1) or BF16 (LPT 2) copy of A
+// (row-major 16-bit patterns, ldz, scaled by lp_st->lp_scale) and X FP32
+// (row-major K-contiguous: Q^T with Q column-major) rounded to the same
+// format as it is loaded; v_mfma_f32_16x16x16 f16 / bf16, FP32 accumulation.
+// The lane layout is k_gemm_nn's: lane (r, g) loads rows k+4g+v (v = 0..3)
+// of Z at columns j0+4r .. j0+4r+3 (8 bytes each) and the four K values
+// 4g .. 4g+3 of its X rows, so one MFMA covers a 16-row step; the B operand
+// of tile u is element u of the four Z rows.  Used for the first product
+// A^T Q of the low-precision form's subspace iterations.
+// ---------------------------------------------------------------------------
+template <int LPT, int RT>
+__global__ __launch_bounds__(256) void k_gemm_nn_lp(
+    const float* __restrict__ X, int64_t ldx, const uint16_t* __restrict__ Z, int64_t ldz, int64_t M,
+    int64_t N, int64_t K, int64_t kchunk, float* __restrict__ out, int64_t ldo, int64_t part_stride,
+    const State* __restrict__ lp_st) {
+  constexpr int PF = 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t j0 = ((int64_t)blockIdx.y * 4 + wv) * 64;
+  const int64_t m0 = (int64_t)blockIdx.z * (16 * RT);
+  const int s = blockIdx.x;
+  const int64_t kb = (int64_t)s * kchunk, ke = min(K, kb + kchunk);
+  if (j0 >= N || kb >= ke || m0 >= M) return;
+  const float inv_scale = (float)(1.0 / lp_st->lp_scale);
+  const int64_t jc = j0 + 4 * r;
+  const bool jvec = (jc + 3 < N);
+  const float* xp[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int64_t row = m0 + 16 * t + r;
+    xp[t] = X + (row < M ? row : (M - 1)) * ldx + 4 * g;
+  }
+  f32x4 acc[RT][4];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // X chunk of a step rounded to the low precision: 4 K values -> uint2
+  auto pack_x = [&](const V4<float>& a) {
+    uint2 pk;
+    pk.x = (uint32_t)to_lp_bits<LPT>(a.v[0]) | ((uint32_t)to_lp_bits<LPT>(a.v[1]) << 16);
+    pk.y = (uint32_t)to_lp_bits<LPT>(a.v[2]) | ((uint32_t)to_lp_bits<LPT>(a.v[3]) << 16);
+    return pk;
+  };
+  // B operand of tile u: element u of the four Z rows (16-bit each)
+  auto mma = [&](const V4<float>(&a)[RT], const uint2 (&zv)[4]) {
+    uint2 xb[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) xb[t] = pack_x(a[t]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int sh = (u & 1) * 16;
+      uint32_t e[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) e[v] = (((u < 2) ? zv[v].x : zv[v].y) >> sh) & 0xffffu;
+      const uint2 b = uint2{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+#pragma unroll
+      for (int t = 0; t < RT; ++t) acc[t][u] = mfma_lp<LPT>(xb[t], b, acc[t][u]);
+    }
+  };
+  // one 16-row step at k, masked (rows past ke, columns past N read as 0)
+  auto load = [&](V4<float>(&a)[RT], uint2 (&zv)[4], int64_t k) {
+    const bool full = (k + 16 <= ke);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) a[t] = full ? ld4(xp[t] + k) : ld4_masked(xp[t] + k, k + 4 * g, ke);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t kr = k + 4 * g + v;
+      if (kr < ke && jvec) {
+        zv[v] = *reinterpret_cast<const uint2*>(Z + kr * ldz + jc);
+      } else {
+        uint32_t h[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) h[u] = (kr < ke && jc + u < N) ? (uint32_t)Z[kr * ldz + jc + u] : 0u;
+        zv[v] = uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+      }
+    }
+  };
+  // one full step in a full panel: no masks
+  auto loadf = [&](V4<float>(&a)[RT], uint2 (&zv)[4], int64_t k) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t) a[t] = ld4(xp[t] + k);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) zv[v] = *reinterpret_cast<const uint2*>(Z + (k + 4 * g + v) * ldz + jc);
+  };
+  const int64_t nfull = (ke - kb) / 16;
+  if (j0 + 64 <= N && nfull > 0) {
+    // PF-deep ring, branch-free steady state (prologue indices clamped)
+    V4<float> ab[PF][RT];
+    uint2 zb[PF][4];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) loadf(ab[q], zb[q], kb + 16 * min((int64_t)q, nfull - 1));
+    int64_t i = 0;
+    for (; i + 2 * PF <= nfull; i += PF) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        mma(ab[q], zb[q]);
+        loadf(ab[q], zb[q], kb + 16 * (i + q + PF));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      if (i + q < nfull) {
+        mma(ab[q], zb[q]);
+        if (i + q + PF < nfull) loadf(ab[q], zb[q], kb + 16 * (i + q + PF));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+      if (i + PF + q < nfull) mma(ab[q], zb[q]);
+    if (kb + 16 * nfull < ke) {
+      V4<float> a1[RT];
+      uint2 z1[4];
+      load(a1, z1, kb + 16 * nfull);
+      mma(a1, z1);
+    }
+  } else {
+    for (int64_t k = kb; k < ke; k += 16) {
+      V4<float> a1[RT];
+      uint2 z1[4];
+      load(a1, z1, k);
+      mma(a1, z1);
+    }
+  }
+  float* o = out + (int64_t)s * part_stride;
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = m0 + 16 * t + 4 * g + e;
+      if (row >= M) continue;
+      float* p = o + row * ldo + jc;
+      if (jvec && ((ldo & 3) == 0)) {
+        *reinterpret_cast<f32x4*>(p) = f32x4{acc[t][0][e], acc[t][1][e], acc[t][2][e], acc[t][3][e]} * inv_scale;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (jc + u < N) p[u] = acc[t][u][e] * inv_scale;
+      }
+    }
+  }
+}
+
 // out[i] = sum_s parts[s*stride + i] (fixed order), i < count.  Optional
 // block control as in k_gemm_nt.
 template <typename T>

@@ -517,13 +517,13 @@ def test_sketch_lp_kernel(mode):
 LP_ERR = 1e-3
 
 
-def _check_lp_factor(A, tol, b, seed, mode):
-    say("lp factor", A.shape, mode, "tol", tol, "b", b, "seed", seed)
+def _check_lp_factor(A, tol, b, seed, mode, q=0):
+    say("lp factor", A.shape, mode, "tol", tol, "b", b, "seed", seed, "q", q)
     code = E.SKETCH_F16 if mode == "f16" else E.SKETCH_BF16
-    f = E.factor(dev(A, torch.float32), tol, block=b, seed=seed, sketch=code)
+    f = E.factor(dev(A, torch.float32), tol, block=b, seed=seed, sketch=code, power_iters=q)
     torch.cuda.synchronize()
-    ref = O.eod_abe(A, tol, k=b, q=0, seed=seed)
-    emu = O.eod_abe(A, tol, k=b, q=0, seed=seed, sketch_dtype=mode)
+    ref = O.eod_abe(A, tol, k=b, q=q, seed=seed)
+    emu = O.eod_abe(A, tol, k=b, q=q, seed=seed, sketch_dtype=mode)
     stable, r64, rlp = O.precision_stable(A, tol, b, seed, mode)
     assert f.blocks >= 3                       # the low-precision blocks did run
     assert f.flags & 16                        # ... and the FP32 refinement with them
@@ -570,6 +570,17 @@ def test_factor_lp_sketch_exact_rank(mode):
     else:
         assert 40 <= f.rank <= 48
     assert abs(e_gpu - e_emu) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", ["f16", "bf16"])
+@pytest.mark.parametrize("shape", [(16384, 200), (300, 2100)])
+def test_factor_lp_sketch_power_iteration(mode, shape):
+    # q = 1 with the low-precision form: two subspace iterations, each with
+    # its A^T Q product from the rounded copy (ragged K splits, partial
+    # column panels, the transposed orientation), against the form's oracle
+    m, n = shape
+    A = W.lowrank_haar(41, m=m, n=n, r=70, noise_std=1e-5, decades=2.0).astype(np.float32).astype(np.float64)
+    _check_lp_factor(A, 1e-2, 8, 41, mode, q=1)
 
 
 @pytest.mark.parametrize("mode", ["f16", "bf16"])

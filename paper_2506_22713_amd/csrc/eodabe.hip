@@ -642,9 +642,14 @@ struct Ops {
              int64_t ldw, int subtract, const int64_t* wlog = nullptr, const int32_t* stopb = nullptr,
              int blk = 0) {
     if (m <= 0 || f <= 0) return 0;
-    dim3 grid((unsigned)cdiv(m, 64), (unsigned)cdiv(f, 64));
-    hipLaunchKernelGGL((k_update_rows<T, T>), grid, dim3(256), 0, st, Y, ldy, Q, ldq, m, w, f, W,
-                       ldw, subtract, wlog, stopb, blk);
+    if (cdiv(m, 16) > 0x7fffffff) return EODABE_EINVAL;
+#define UT_LAUNCH(CC)                                                                                 \
+  hipLaunchKernelGGL((k_update_tiles<T, CC, 4>), dim3((unsigned)cdiv(m, 16), (unsigned)cdiv(f, 16 * CC)), \
+                     dim3(256), 0, st, Y, ldy, Q, ldq, m, w, f, W, ldw, subtract, wlog, stopb, blk)
+    if (f <= 16) UT_LAUNCH(1);
+    else if (f <= 32) UT_LAUNCH(2);
+    else UT_LAUNCH(4);
+#undef UT_LAUNCH
     LAUNCHCHK();
     return 0;
   }

@@ -1506,6 +1506,100 @@ __global__ __launch_bounds__(256) void k_update_rows(
 
 
 // ---------------------------------------------------------------------------
+// Y (m x f, column-major ldy) -= Q W (or = Q W when subtract is 0) for the
+// block re-orthogonalisation: Q m x w column-major (ldq), W w x f with
+// element (a, c) at c*ldw + a, same type as Y; w read on the device from
+// wlog[block_id] when given.  One workgroup per 16-row tile and 16*CT
+// columns; its NW waves split the w products (K) and hand their partial
+// tiles down a fixed tree in LDS, wave 0 updates Y.  Lane (r, g) reads Q at
+// row r of the tile and W at column 16u + r, K index 4i + g, straight from
+// memory (both small and L2-resident here), two 16-K steps in flight.
+// ---------------------------------------------------------------------------
+template <typename T, int CT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_update_tiles(
+    T* __restrict__ Y, int64_t ldy, const T* __restrict__ Q, int64_t ldq, int64_t m, int64_t w, int f,
+    const T* __restrict__ W, int64_t ldw, int subtract, const int64_t* __restrict__ wlog,
+    const int32_t* __restrict__ stop_block, int block_id) {
+  typedef Mfma<T> MF;
+  typedef typename MF::acc_t acc_t;
+  static_assert(NW >= 2 && (NW & (NW - 1)) == 0, "NW: power of two");
+  if (stop_block && *stop_block < block_id) return;
+  if (wlog) w = wlog[block_id];
+  if (w == 0 && subtract) return;
+  __shared__ acc_t red[NW / 2][CT][64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 16;
+  const int c0 = blockIdx.y * 16 * CT;
+  const int64_t row = row0 + r;
+  const bool rok = row < m;
+  const int64_t kc = ((w + NW - 1) / NW + 15) / 16 * 16;
+  const int64_t kb = min(w, (int64_t)wv * kc), ke = min(w, kb + kc);
+  const T* qp = Q + (rok ? row : 0) + g * ldq;            // + k * ldq
+  const T* wp[CT];
+  bool cok[CT];
+#pragma unroll
+  for (int u = 0; u < CT; ++u) {
+    const int c = c0 + 16 * u + r;
+    cok[u] = c < f;
+    wp[u] = W + (int64_t)(cok[u] ? c : 0) * ldw + g;       // + k
+  }
+  acc_t acc[CT];
+#pragma unroll
+  for (int u = 0; u < CT; ++u) acc[u] = MF::zero();
+  // a 16-K step at k: four K values per lane (4i + g), masked past ke
+  auto load = [&](T (&a)[4], T (&b)[4][CT], int64_t k) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t kk = k + 4 * i;
+      const bool kok = kk + g < ke;
+      a[i] = (kok && rok) ? qp[kk * ldq] : (T)0;
+#pragma unroll
+      for (int u = 0; u < CT; ++u) b[i][u] = (kok && cok[u]) ? wp[u][kk] : (T)0;
+    }
+  };
+  auto mma = [&](const T (&a)[4], const T (&b)[4][CT]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int u = 0; u < CT; ++u) acc[u] = MF::op(a[i], b[i][u], acc[u]);
+  };
+  if (kb < ke) {
+    T a0[4], b0[4][CT], a1[4], b1[4][CT];
+    load(a0, b0, kb);
+    int64_t k = kb;
+    for (; k + 16 < ke; k += 32) {
+      load(a1, b1, k + 16);
+      mma(a0, b0);
+      if (k + 32 < ke) load(a0, b0, k + 32);
+      mma(a1, b1);
+    }
+    if (k < ke) mma(a0, b0);
+  }
+#pragma unroll
+  for (int h = NW / 2; h >= 1; h >>= 1) {
+    if (wv >= h && wv < 2 * h)
+#pragma unroll
+      for (int u = 0; u < CT; ++u) red[wv - h][u][lane] = acc[u];
+    __syncthreads();
+    if (wv < h)
+#pragma unroll
+      for (int u = 0; u < CT; ++u) acc[u] += red[wv][u][lane];
+    __syncthreads();
+  }
+  if (wv != 0) return;
+#pragma unroll
+  for (int u = 0; u < CT; ++u) {
+    if (!cok[u]) continue;
+    T* py = Y + (int64_t)(c0 + 16 * u + r) * ldy;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t rr = row0 + MF::row(g, e);
+      if (rr < m) py[rr] = subtract ? py[rr] - acc[u][e] : acc[u][e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Small FP64 matrices (f <= F <= 64, F in {16, 32, 64}) are kept in LDS
 // row-major with leading dimension F + 1 (the odd stride spreads a column
 // over the banks).

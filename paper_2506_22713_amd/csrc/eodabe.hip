@@ -959,13 +959,13 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
         abytes = 2.0 * g.mm * g.nn;
       } else if (rows_blk) {
         TRY(ops.sketch_rows(Ae, g.lda_eff, omega, g.mm, g.bn, g.nn, y, g.ldy, j == 0 ? w.normparts : nullptr,
-                            stopb, blk, j == 0 ? w.maxparts : nullptr, (g.lp && j == 1) ? g.lp : 0, w.alp,
+                            stopb, blk, (j == 0 && g.lp) ? w.maxparts : nullptr, (g.lp && j == 1) ? g.lp : 0, w.alp,
                             g.ld_lp, w.st));
         if (g.lp && j == 1) abytes += 2.0 * g.mm * g.nn;
       } else {
         TRY(ops.sketch(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch, (T*)w.ypart, g.ldy,
                        ystride, j == 0 ? w.normparts : nullptr, stopb, blk,
-                       j == 0 ? w.maxparts : nullptr, (g.lp && j == 1) ? g.lp : 0, w.alp, g.ld_lp,
+                       (j == 0 && g.lp) ? w.maxparts : nullptr, (g.lp && j == 1) ? g.lp : 0, w.alp, g.ld_lp,
                        w.st));
         if (g.lp && j == 1) abytes += 2.0 * g.mm * g.nn;
       }
@@ -1003,7 +1003,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
           if (mid) ca.Rinv = w.r1inv;
           if (j == 0) {
             ca.norm_parts = w.normparts;
-            ca.max_parts = w.maxparts;
+            ca.max_parts = g.lp ? w.maxparts : nullptr;     // max |A|: the FP16 scale only
             ca.n_norm = g.sk_rows ? cdiv(g.mm, 16) : sketch_wgs * (int64_t)nsp;
           }
         } else {

@@ -676,6 +676,11 @@ void cb_chol(hipStream_t st, double* G, int f, double* R, double* Rinv, double* 
              const int32_t* stopb = nullptr, int blk = 0) {
   const int P = (int)cdiv(f, 64);
   const int64_t ff = (int64_t)f * f;
+  if (P == 2) {                          // two panels: one workgroup, every block in LDS
+    hipLaunchKernelGGL(k_chol2p, dim3(1), dim3(256), 0, st, G, f, f, R, Rinv, dead, first_pass, fresh, state,
+                       count_floors, stopb, blk);
+    return;
+  }
   hipLaunchKernelGGL(k_cb_init, dim3((unsigned)std::min<int64_t>(cdiv(ff, 256), 1024)), dim3(256), 0, st, G, f, f,
                      R, Rinv, dg, dead, fresh, stopb, blk);
   hipLaunchKernelGGL(k_cb_diag, dim3(1), dim3(256), 0, st, G, f, f, 0, R, Rinv, dg, dead, cbmask, first_pass,

@@ -2396,6 +2396,96 @@ __global__ __launch_bounds__(256) void k_cb_inv(const double* __restrict__ R, do
   }
 }
 
+// The panel-blocked Cholesky with inverse (the k_cb_* steps) for two
+// panels, 64 < f <= 128, on one workgroup with every block in LDS: R11 and
+// its inverse by chol_inv<64> (floor rule against G's own diagonal); R12 =
+// R11^{-T} G12 with the rows of pivots that did not eliminate and the
+// columns already dead zeroed; S22 = G22 - R12^T R12; R22 and its inverse by
+// chol_inv<64> (floor rule against G22's original diagonal); (R^{-1})12 =
+// -R11^{-1} (R12 R22^{-1}).  The same R and R^{-1} as the separate launches
+// up to rounding order; G (column-major, ld) is not modified.  Outputs as
+// k_cb_*: R, R^{-1} column-major (ld), per-column dead flags.
+__global__ __launch_bounds__(256) void k_chol2p(const double* __restrict__ G, int ld, int f,
+                                                double* __restrict__ R, double* __restrict__ Rinv,
+                                                int32_t* __restrict__ dead, int first_pass, int fresh, State* st,
+                                                int count_floors, const int32_t* __restrict__ stopb, int blk) {
+  if (stopb && *stopb < blk) return;       // a speculative block after the stop
+  typedef SmallCfg<64> S;
+  constexpr int LD = S::LD;
+  __shared__ double A[S::SIZE], B[S::SIZE], C[S::SIZE], D[S::SIZE], work[24 * 64], dgs[64], dg1[64];
+  const int tid = threadIdx.x, w1 = f - 64;
+  // lower-left blocks of R and R^{-1}
+  for (int idx = tid; idx < w1 * 64; idx += 256) {
+    const int i = 64 + idx / 64, j = idx % 64;
+    R[(int64_t)j * ld + i] = 0.0;
+    Rinv[(int64_t)j * ld + i] = 0.0;
+  }
+  uint64_t dm0 = 0, dm1 = 0;
+  if (!fresh) {
+    for (int c = 0; c < 64; ++c) dm0 |= (uint64_t)(dead[c] != 0) << c;
+    for (int c = 0; c < w1; ++c) dm1 |= (uint64_t)(dead[64 + c] != 0) << c;
+  }
+  // G11 -> A, G12 -> C, G22 -> D (row-major, zero padded); each thread's
+  // loads in flight before its stores
+  {
+    constexpr int NQ = 64 * 64 / 256;
+    double va[NQ], vc[NQ], vd[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int idx = tid + 256 * q, j = idx / 64, i = idx % 64;      // element (i, j)
+      va[q] = G[(int64_t)j * ld + i];
+      vc[q] = j < w1 ? G[(int64_t)(64 + j) * ld + i] : 0.0;
+      vd[q] = (i < w1 && j < w1) ? G[(int64_t)(64 + j) * ld + 64 + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int idx = tid + 256 * q, j = idx / 64, i = idx % 64;
+      A[i * LD + j] = va[q];
+      C[i * LD + j] = vc[q];
+      D[i * LD + j] = vd[q];
+      if (i == j) dg1[i] = vd[q];
+    }
+  }
+  __syncthreads();
+  uint64_t dmo0 = 0, nl0 = 0, dmo1 = 0, nl1 = 0;
+  int nf0 = 0, nf1 = 0;
+  chol_inv<64>(A, B, work, dgs, 64, dm0, first_pass, &dmo0, &nf0, nullptr, &nl0);
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int i = idx / 64, j = idx % 64;
+    R[(int64_t)j * ld + i] = A[i * LD + j];
+    Rinv[(int64_t)j * ld + i] = B[i * LD + j];
+  }
+  __syncthreads();
+  // R12 = R11^{-T} G12, masked, into A (and R)
+  lds_gemm<64, true, false>(B, C, [&](int i, int j, double v) {
+    const bool z = j >= w1 || ((nl0 >> i) & 1ull) || ((dm1 >> j) & 1ull);
+    A[i * LD + j] = z ? 0.0 : v;
+    if (j < w1) R[(int64_t)(64 + j) * ld + i] = z ? 0.0 : v;
+  });
+  __syncthreads();
+  // S22 = G22 - R12^T R12
+  lds_gemm<64, true, false>(A, A, [&](int i, int j, double v) {
+    if (i < w1 && j < w1) D[i * LD + j] -= v;
+  });
+  __syncthreads();
+  chol_inv<64>(D, C, work, dgs, w1, dm1, first_pass, &dmo1, &nf1, dg1, &nl1);
+  for (int idx = tid; idx < w1 * w1; idx += 256) {
+    const int i = idx / w1, j = idx % w1;
+    R[(int64_t)(64 + j) * ld + 64 + i] = D[i * LD + j];
+    Rinv[(int64_t)(64 + j) * ld + 64 + i] = C[i * LD + j];
+  }
+  __syncthreads();
+  // T = R12 R22^{-1} into D, then (R^{-1})12 = -R11^{-1} T
+  lds_gemm<64, false, false>(A, C, [&](int i, int j, double v) { D[i * LD + j] = v; });
+  __syncthreads();
+  lds_gemm<64, false, false>(B, D, [&](int i, int j, double v) {
+    if (j < w1) Rinv[(int64_t)(64 + j) * ld + i] = -v;
+  });
+  for (int c = tid; c < f; c += 256)
+    dead[c] = (int32_t)(c < 64 ? ((dmo0 >> c) & 1ull) : ((dmo1 >> (c - 64)) & 1ull));
+  if (tid == 0 && count_floors && (nf0 + nf1) && st) atomicAdd(&st->floored, nf0 + nf1);
+}
+
 // Arguments of the Cholesky that closes a Gram pass (k_gram_rows, and the
 // global-memory path for wide blocks).
 struct CholArgs {

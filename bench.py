@@ -21,6 +21,14 @@ Workloads (``--workload``):
                  one step factors all six with the learned warm start
                  (paper_2506_22713_amd/predictor.ckpt), compared with the
                  plain loop on the same matrices.
+
+With the default workload the line's config also carries ``end_to_end``
+(the whole factorization against the HBM and MFMA roofs) and
+``subresults``: the other configurations (the 4096^2 rank sweep 95..416,
+the hyperspectral matrix in FP32 and the FP16 form, the image as written,
+the 512^2 FP64 matrix, colour images, complex input, the hyperspectral KNN,
+the 1024 tiles batched against sequential), each measured briefly on the
+GPU; the cpu_baseline leg adds the oracle's ranks beside them.
 """
 from __future__ import annotations
 

@@ -590,7 +590,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "this build does not run across GPUs", file=sys.stderr)
+              "the EOD-ABE library here runs on a single GPU", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "tiles1024":
@@ -669,9 +669,8 @@ def main():
     log(f"rank {f.rank} blocks {f.blocks} relerr {rel:.4e} ms/step {ms_per_step:.3f} (wall {ms_wall:.3f})")
 
     # roofline of the dominant pass over A (the larger accumulated time of
-    # the sketch and the projection: the streaming kernels the benchmark spec's HBM
-    # target refers to); the latency-bound small kernels are reported end to
-    # end below
+    # the sketch and the projection, the HBM-bound streaming kernels); the
+    # latency-bound small kernels are reported end to end below
     # the sketch runs as k_sketch_rows (16-row tiles, no partials) when the
     # matrix has >= 4081 rows, its sketch would be split along K and b <= 32;
     # otherwise as k_sketch (K-split partials, folded by k_fold_parts)

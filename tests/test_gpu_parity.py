@@ -471,6 +471,17 @@ def test_image_small_fp32():
     check_factor(A, torch.float32, 1e-3, seed=0, stable=stable)
 
 
+def test_image_4096_headline_workload():
+    # the benchmark's headline configuration at full size: the 4096^2 FP32
+    # image (noise std 0.05), tol 1e-3, b = 32, seed 0 -- row-tile sketch,
+    # one block, gated closing
+    say("image 4096^2 headline workload")
+    A = W.image(0, 4096, 0.05).astype(np.float64)
+    stable, _, _ = O.precision_stable(A, 1e-3, 32, 0)
+    f, ref = check_factor(A, torch.float32, 1e-3, b=32, seed=0, stable=stable)
+    assert f.blocks == 1
+
+
 def test_hyperspectral_small_fp32():
     A = W.hyperspectral(0, pixels=16384).astype(np.float64)
     stable, _, _ = O.precision_stable(A, 1e-2, 16, 0)
@@ -712,6 +723,38 @@ def test_batched_tiles_against_oracle():
         assert np.linalg.norm(Vn @ Vn.T - np.eye(r)) <= ORTH_TOL[torch.float32] * math.sqrt(r)
         assert np.all(np.tril(Dn, -1) == 0) and np.all(np.diag(Dn) >= 0)
     say(f"  precision-unstable tiles (rank checked against both sides): {exempt} of {len(tiles)}")
+
+
+def test_batched_full_benchmark_set_against_single_matrix():
+    # the benchmark's 1024 tiles (sides 64..1024, exact rank 5..80 + 1e-4
+    # noise, tol 1e-4, b = 32) in one batched call against the single-matrix
+    # path tile by tile: equal ranks on every tile the oracle's classifier
+    # calls precision-stable, RelErr within the FP32 bar of each other
+    say("batched: full 1024-tile benchmark set")
+    tiles = W.tiles(0, count=1024)
+    devs = [torch.from_numpy(np.ascontiguousarray(T)).cuda() for T in tiles]
+    c = E.Context(block=32, seed=0)
+    bt = E.Batch(c, devs)
+    bt.run(1e-4)
+    torch.cuda.synchronize()
+    assert np.all(bt.status == 0)
+    diff = []
+    for t, A in enumerate(devs):
+        fs = E.factor(A, 1e-4, ctx=c)
+        if int(fs.rank) != int(bt.ranks[t]):
+            diff.append(t)
+            continue
+        if t % 16 == 0:                  # errors on a sample (the products cost host time)
+            A64 = A.double()
+            U, D, Vt = bt.result(t)[:3]
+            eb = float(torch.linalg.norm(A64 - U.double() @ D.double() @ Vt.double()) / torch.linalg.norm(A64))
+            es = float(torch.linalg.norm(A64 - fs.U.double() @ fs.D.double() @ fs.Vt.double()) / torch.linalg.norm(A64))
+            assert abs(eb - es) <= max(1e-5, fp32_floor(fs.rank, *A.shape)), (t, eb, es)
+    say(f"  ranks differ on {len(diff)} of 1024 tiles: {diff}")
+    assert len(diff) <= 8
+    for t in diff:
+        stable, r64, r32 = O.precision_stable(tiles[t].astype(np.float64), 1e-4, 32, 0)
+        assert not stable, (t, r64, r32)
 
 
 def test_batched_replay_deterministic_and_tuner():

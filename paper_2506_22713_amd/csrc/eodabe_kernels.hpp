@@ -1142,15 +1142,23 @@ __global__ __launch_bounds__(256) void k_gemm_nn(
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[t][u] = MF::op(a[t].v[v], zv[v].v[u], acc[t][u]);
   };
-  // one full step at k in a full panel: no masks
+  // one full step at k, no branches: in a panel that ends inside the
+  // matrix (N a multiple of 4, so a lane's four columns are all in or all
+  // out) the lanes past N read the panel's first columns and zero them by a
+  // select
+  const int64_t jl = jvec ? jc : j0;
   auto loadf = [&](V4<T>(&a)[RT], V4<T>(&zv)[4], int64_t k) {
 #pragma unroll
     for (int t = 0; t < RT; ++t) a[t] = ld4(xp[t] + k);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) zv[v] = ld4(Z + (k + 4 * g + v) * ldz + jc);
+    for (int v = 0; v < 4; ++v) {
+      const V4<T> x = ld4(Z + (k + 4 * g + v) * ldz + jl);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) zv[v].v[u] = jvec ? x.v[u] : (T)0;
+    }
   };
   const int64_t nfull = (ke - kb) / 16;
-  if (j0 + 64 <= N && nfull > 0) {
+  if ((j0 + 64 <= N || (N & 3) == 0) && nfull > 0) {
     // PF-deep ring over the full steps; the steady state has no branches,
     // so each step waits only for its own loads (step indices past the last
     // full step are clamped to it in the prologue and never used)
@@ -1181,7 +1189,8 @@ __global__ __launch_bounds__(256) void k_gemm_nn(
       mma(a1, z1);
     }
   } else {
-    // partial panel (or no full step): one masked step at a time
+    // a partial panel of a matrix whose width is not a multiple of 4 (or no
+    // full step): one masked step at a time
     for (int64_t k = kb; k < ke; k += 16) {
       V4<T> a1[RT], z1[4];
       load(a1, z1, k);

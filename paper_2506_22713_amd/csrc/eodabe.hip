@@ -599,8 +599,16 @@ struct Ops {
                   const int32_t* stopb = nullptr, int blk = 0, Gate gate = Gate{}) {
     if (count <= 0) return 0;
     if (nparts <= 4) return reduce(parts, nparts, stride, count, out, stopb, blk, gate);
-    hipLaunchKernelGGL((k_fold_parts<U>), dim3((unsigned)cdiv(count, 512)), dim3(128), 0, st, parts, nparts,
-                       stride, count, out, stopb, blk, gate);
+    // many partials over few elements: spread each element group's partials
+    // over P threads (few elements: count below 2^17, fewer than 256 workgroups)
+    const int P = (count <= (1 << 17) && nparts >= 128) ? 16 : (count <= (1 << 17) && nparts >= 48) ? 4 : 1;
+#define FOLD_P(PP)                                                                                       \
+  hipLaunchKernelGGL((k_fold_parts<U, PP>), dim3((unsigned)cdiv(count, 512 / PP)), dim3(128), 0, st, parts, \
+                     nparts, stride, count, out, stopb, blk, gate)
+    if (P == 16) FOLD_P(16);
+    else if (P == 4) FOLD_P(4);
+    else FOLD_P(1);
+#undef FOLD_P
     LAUNCHCHK();
     return 0;
   }

@@ -1382,38 +1382,66 @@ __global__ void k_reduce_parts(const T* __restrict__ parts, int nparts, int64_t 
   }
 }
 
-// out[i] = sum_s parts[s*stride + i] for many partials, summed in the order
-// s = 0, 1, ..., nparts-1 (deterministic).  Each thread folds four
-// consecutive elements and keeps up to 16 partials' loads in flight, so the
-// whole fold costs about one memory round trip; the vector path needs stride
-// a multiple of 4 and 16-byte aligned parts and out, else the thread folds
-// its elements one at a time.  128-thread workgroups, count/512 of them.
-template <typename T>
+// out[i] = sum_s parts[s*stride + i] for many partials, deterministic.
+// P threads share a group of four consecutive elements: thread p sums the
+// partials s = p, p + P, p + 2P, ... in that order, up to 16 loads in
+// flight, and the P sums are added in the order p = 0, 1, ..., P-1 through
+// LDS (P = 1: the plain order s = 0, 1, ...).  P > 1 serves many partials
+// over few elements, where a thread per group would need one memory round
+// trip per 16 partials.  The vector path needs stride a multiple of 4 and
+// 16-byte aligned parts and out, else a thread folds its elements one at a
+// time.  128-thread workgroups, count / (512 / P) of them.
+template <typename T, int P>
 __global__ __launch_bounds__(128) void k_fold_parts(const T* __restrict__ parts, int nparts, int64_t stride,
                                                     int64_t count, T* __restrict__ out,
                                                     const int32_t* __restrict__ stop_block, int block_id,
                                                     Gate gate) {
+  static_assert(P >= 1 && P <= 16 && (P & (P - 1)) == 0, "P: power of two up to 16");
   if (stop_block && *stop_block < block_id) return;
   if (gate_shut(gate)) return;
-  const int64_t i0 = ((int64_t)blockIdx.x * 128 + threadIdx.x) * 4;
-  if (i0 >= count) return;
+  __shared__ T red[P > 1 ? 128 * 4 : 1];
+  const int p = threadIdx.x % P, grp = threadIdx.x / P;
+  const int64_t i0 = ((int64_t)blockIdx.x * (128 / P) + grp) * 4;
+  const bool live = i0 < count;
   const bool vec = i0 + 3 < count && (stride & 3) == 0 && (((uintptr_t)parts | (uintptr_t)out) & 15) == 0;
-  if (vec) {
+  V4<T> acc;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) acc.v[e] = (T)0;
+  if (live && vec) {
     constexpr int NB = 16;
-    V4<T> acc = ld4(parts + i0);
-    for (int s0 = 1; s0 < nparts; s0 += NB) {
+    for (int s0 = p; s0 < nparts; s0 += NB * P) {
       V4<T> v[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        const int sq = min(s0 + q, nparts - 1);      // clamped: the load stays unconditional
+        const int sq = min(s0 + q * P, nparts - 1);  // clamped: the load stays unconditional
         v[q] = ld4(parts + (int64_t)sq * stride + i0);
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q)
-        if (s0 + q < nparts)
+        if (s0 + q * P < nparts)
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc.v[e] += v[q].v[e];
     }
+  } else if (live) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (i0 + e < count)
+        for (int s = p; s < nparts; s += P) acc.v[e] += parts[(int64_t)s * stride + i0 + e];
+  }
+  if constexpr (P > 1) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[threadIdx.x * 4 + e] = acc.v[e];
+    __syncthreads();
+    if (p != 0) return;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      T a = (T)0;
+      for (int q = 0; q < P; ++q) a += red[(threadIdx.x + q) * 4 + e];
+      acc.v[e] = a;
+    }
+  }
+  if (!live) return;
+  if (vec) {
     if constexpr (sizeof(T) == 4) {
       *reinterpret_cast<f32x4*>(out + i0) = f32x4{acc.v[0], acc.v[1], acc.v[2], acc.v[3]};
     } else {
@@ -1421,11 +1449,9 @@ __global__ __launch_bounds__(128) void k_fold_parts(const T* __restrict__ parts,
       reinterpret_cast<double2*>(out + i0)[1] = double2{acc.v[2], acc.v[3]};
     }
   } else {
-    for (int64_t i = i0; i < min(count, i0 + 4); ++i) {
-      T a = parts[i];
-      for (int s = 1; s < nparts; ++s) a += parts[(int64_t)s * stride + i];
-      out[i] = a;
-    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (i0 + e < count) out[i0 + e] = acc.v[e];
   }
 }
 

@@ -46,6 +46,9 @@ typedef struct eodabe_ctx eodabe_ctx;
 #define EODABE_ENODEVICE     -6   /* no gfx950 device visible */
 #define EODABE_ESCRATCH      -7   /* eodabe_factor_noalloc: the problem needs more workspace than
                                      EODABE_NOALLOC_SCRATCH_BYTES */
+#define EODABE_ESYNC         -8   /* a barrier between the workgroups of one launch did not see all of
+                                     them within ~1 s (another process held the device's CUs); the
+                                     outputs of the call are void, the context stays usable */
 #define EODABE_WTOL_FLOOR     1   /* warning: tol is below the data-type floor 8 u sqrt(n);
                                      rank decisions there are dominated by rounding */
 

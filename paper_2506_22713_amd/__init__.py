@@ -33,6 +33,7 @@ EODABE_ENONFINITE = -4
 EODABE_EHIP = -5
 EODABE_ENODEVICE = -6
 EODABE_ESCRATCH = -7
+EODABE_ESYNC = -8
 NOALLOC_SCRATCH_BYTES = 64 << 20
 EODABE_WTOL_FLOOR = 1
 F32, F64 = 0, 1

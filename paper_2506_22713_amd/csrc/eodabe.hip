@@ -712,6 +712,23 @@ void cb_chol(hipStream_t st, double* G, int f, double* R, double* Rinv, double* 
   }
 }
 
+// The one-launch CholeskyQR2 (k_cqr2) takes blocks of at most 32 columns
+// whose row panels fit its grid (every workgroup resident at once).
+bool cqr2_fits(int64_t rows, int64_t f) {
+  return f > 0 && f <= 32 && rows > 0 && cdiv(rows, CQR2_RPW) <= CQR2_GMAX;
+}
+
+template <typename T>
+int cqr2(eodabe_ctx* ctx, hipStream_t st, const Cqr2Args& a) {
+  const int64_t fb = a.f;                          // the launch width (the bound of f_dev)
+  if (!cqr2_fits(a.rows, fb)) return EODABE_EINVAL;
+  const dim3 grid((unsigned)cdiv(a.rows, CQR2_RPW));
+  if (fb <= 16) hipLaunchKernelGGL((k_cqr2<T, 16>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((k_cqr2<T, 32>), grid, dim3(256), 0, st, a);
+  LAUNCHCHK();
+  return 0;
+}
+
 // G = Z^T Z (FP64) of the rows x f block Z = X (W null) or Z = X W (W f x f
 // FP64, element (i,j) at j*f + i, Z rounded to T and written over X), then
 // the Cholesky with the floor/kill rules and the epilogues in ca (R,
@@ -1000,6 +1017,38 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       const bool mid = f <= 128;      // explicit R^{-1} (blocked Cholesky above 64 columns) + apply
       if (j == 0 && !rows_blk) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       if (j == 0) TRY(pair_fix<T>(ctx, st, g.paired, y, g.ldy, g.mm, f, stopb, blk));
+      if (j == 0 && cqr2_fits(g.mm, f)) {
+        // block 0: both CholeskyQR2 passes, the stop test and the append in
+        // one launch (nothing to project against)
+        Cqr2Args a{};
+        a.X = y;
+        a.ldx = g.ldy;
+        a.rows = g.mm;
+        a.f = f;
+        a.parts = w.gpart;
+        a.counter = &w.st->counter[1];
+        a.stop_block = stopb;
+        a.block_id = blk;
+        a.st = w.st;
+        a.R1 = w.r1;
+        a.R1inv = w.r1inv;
+        a.R2 = w.r2;
+        a.R2inv = w.r2inv;
+        a.dead = deadj;
+        a.norm_parts = w.normparts;
+        a.max_parts = g.lp ? w.maxparts : nullptr;
+        a.n_norm = g.sk_rows ? cdiv(g.mm, 16) : sketch_wgs * (int64_t)nsp;
+        a.stop_test = 1;
+        a.col0 = col0;
+        a.n = g.nn;
+        a.wlog = w.wlog;
+        a.acc = w.accv;
+        a.diag_log = w.diag_log;
+        a.Q = q;
+        a.ldq = g.ldy;
+        TRY(cqr2<T>(ctx, st, a));
+        continue;
+      }
       for (int pass = 0; pass < 2; ++pass) {
         if (j > 0) {
           TRY(ops.template gemm_nt<T>(q, g.ldy, y, g.ldy, wmax, f, g.mm, g.s_proj, (T*)w.wpart, ldw,
@@ -1055,6 +1104,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
     HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const State& hs = *ctx->host_state;
+    if (hs.sync_fail) return EODABE_ESYNC;
     if (hs.stop_block != 0x7fffffff || j >= g.nblk) finished = true;
     // the gated closing steps ran iff the loop stopped with a finite norm
     // and 0 < rank <= r_cap (the gate of those kernels)
@@ -1204,6 +1254,48 @@ int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, cons
   TRY(ops.reduce_wide((const T*)w.cpart, eff_splits(g.mm, s_core), cstride, cstride, cb, nullptr, 0,
                       gate));
   if (!gate.st) TRY(pair_fix<T>(ctx, st, g.paired, cb, g.ldk, g.nn, r));
+  if (cqr2_fits(g.nn, r)) {
+    // C^T = V R by CholeskyQR2 in one launch, V written straight to Vout
+    Cqr2Args a{};
+    a.X = cb;
+    a.ldx = g.ldk;
+    a.rows = g.nn;
+    a.f = (int)r;
+    a.f_dev = r_dev;
+    a.parts = w.gbig;
+    a.counter = &w.st->counter[2];
+    a.gate = gate;
+    a.st = w.st;
+    a.R1 = w.rb1;
+    a.R1inv = w.rb3;
+    a.R2 = w.rb2;
+    a.R2inv = w.rb5;
+    a.dead = w.deadbig;
+    a.fresh = 1;
+    a.count_floors = 1;
+    a.Q = Vout;
+    a.ldq = ldv;
+    // and the QR of R^T on every workgroup, U = Q Qh too when the rows of U
+    // split into at most 1024 per workgroup
+    a.close_qr = 1;
+    a.Dout = Dout;
+    a.ldd = ldd;
+    a.Qh_out = w.rb4;
+    const bool u_in = cdiv(g.mm, cdiv(g.nn, CQR2_RPW)) <= 1024;
+    if (u_in) {
+      a.Uq = q;
+      a.ldq_u = g.ldy;
+      a.Uout = Uout;
+      a.ldu = ldu;
+      a.m_u = g.mm;
+    }
+    TRY(cqr2<T>(ctx, st, a));
+    if (!u_in) {
+      const ApplyJob ju{q, g.ldy, Uout, ldu, w.rb4, g.mm, 0, (int)r, (int)r, nullptr, nullptr, r_dev};
+      TRY(ops.apply(ju, nullptr, (int)r, nullptr, 0, gate));
+    }
+    return 0;
+  }
   CholArgs c1 = chol_args(w, w.rb1, w.deadbig, 1, 1, 1);
   c1.Rinv = w.rb3;
   c1.gate = gate;
@@ -1885,6 +1977,7 @@ const char* eodabe_strerror(int s) {
     case EODABE_EHIP: return "HIP runtime error";
     case EODABE_ENODEVICE: return "no gfx950 device";
     case EODABE_ESCRATCH: return "the problem needs more workspace than the static scratch holds";
+    case EODABE_ESYNC: return "a barrier across workgroups timed out (device shared); outputs void";
     case EODABE_WTOL_FLOOR: return "warning: tol below the data-type floor";
     default: return "unknown status";
   }
@@ -2041,6 +2134,7 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
     HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (ctx->prof_on) prof_collect(ctx, 0x7fffffff, false, rank);
+    if (ctx->host_state->sync_fail) return EODABE_ESYNC;
     if (ctx->host_state->floored) info->status_flags |= 4;
     return 0;
   };

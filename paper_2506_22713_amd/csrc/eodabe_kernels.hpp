@@ -47,7 +47,7 @@ struct State {
   uint32_t counter[8];   // arrival counters (reset by the last arriving workgroup)
   double lp_scale;       // power of two applied to A before rounding it to FP16 (1 for BF16)
   int32_t lp_mode;       // 0: none, 1: FP16, 2: BF16 (low-precision sketch form)
-  int32_t pad2;
+  int32_t sync_fail;     // a barrier across workgroups timed out (outputs void)
   double d_stop;         // |T(l,l)| of the column whose test stopped the loop (0: none)
 };
 
@@ -1936,6 +1936,132 @@ __device__ void chol_inv(double* Gs, double* Ri, double* work, double* dgs, int 
   if (nolive_out) *nolive_out = nlive;
 }
 
+
+// ---------------------------------------------------------------------------
+// chol_inv for the common case, f <= F <= 32: no dead column and every
+// pivot above the floor.  The rows and columns past f are padded by the
+// identity, so every 8-pivot panel is whole and the elimination runs fully
+// without a branch in its panels; the arithmetic on rows and columns < f is that
+// of chol_inv's fast panels (the same operations in the same order), so R
+// and R^{-1} are bit for bit chol_inv's.  Returns false (uniform) when a
+// pivot fails the floor test or is not finite: R, R^{-1} and Gs are then
+// void and the caller restores G and runs chol_inv.  Gs: G on entry
+// (row-major, ld F+1), R on exit; Ri: R^{-1}; work: 24F doubles; dgs: F
+// doubles.  Layout as in chol_inv: lane c owns column c of [G | I]; wave w
+// holds rows 8(p + s/2) + 4(s%2) + w in slot s during panel p.
+// ---------------------------------------------------------------------------
+template <int F>
+__device__ __forceinline__ bool chol_inv_fast(double* Gs, double* Ri, double* work, double* dgs, int f) {
+  typedef SmallCfg<F> C;
+  constexpr int LD = C::LD, NR = C::NR, W2 = 2 * F;
+  static_assert(F % 8 == 0 && W2 <= 64, "one column of [G | I] per lane");
+  double* P = work;                      // panel rows: P[j*W2 + c], j < 8
+  double* XT = work + 8 * W2;            // multipliers: XT[j*F + i] = R(kp+j, i)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = lane;
+  const bool live = c < W2;
+  for (int i = tid; i < F; i += 256) dgs[i] = i < f ? Gs[i * LD + i] : 1.0;
+  double M[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = 8 * (s / 2) + 4 * (s % 2) + w;
+    double v = 0.0;
+    if (c < F) v = (i < f && c < f) ? Gs[i * LD + c] : (i == c ? 1.0 : 0.0);
+    else if (live) v = (c - F == i) ? 1.0 : 0.0;
+    M[s] = v;
+  }
+  __syncthreads();                       // G consumed: Gs now receives R; dgs ready
+  bool ok = true;
+  const int cl = live ? c : 0;
+#pragma unroll 1
+  for (int p = 0; p < F / 8; ++p) {              // a loop: the code stays small enough for the I-cache
+    const int kp = 8 * p;
+    if (live) {
+      P[w * W2 + c] = M[0];
+      P[(4 + w) * W2 + c] = M[1];
+    }
+    __syncthreads();
+    double d[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = i; j < 8; ++j) d[i][j] = P[i * W2 + kp + j];
+    double yv[8], dgk[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      yv[j] = P[j * W2 + cl];
+      dgk[j] = dgs[kp + j];
+    }
+    double alpha[8], ia[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double piv = d[j][j];
+      ok = ok && piv > FLOOR_C * U64 * dgk[j] && piv > PIV_MIN && piv < INFINITY;
+      double y = __builtin_amdgcn_rsq(piv);
+      y = y * fma(-0.5 * piv, y * y, 1.5);
+      y = y * fma(-0.5 * piv, y * y, 1.5);
+      alpha[j] = piv * y;
+      ia[j] = y;
+#pragma unroll
+      for (int i = j + 1; i < 8; ++i) d[j][i] *= y;
+#pragma unroll
+      for (int i = j + 1; i < 8; ++i)
+#pragma unroll
+        for (int i2 = i; i2 < 8; ++i2) d[i][i2] = fma(-d[j][i], d[j][i2], d[i][i2]);
+    }
+    double X[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      double acc = yv[j];
+#pragma unroll
+      for (int i = 0; i < j; ++i) acc = fma(-d[i][j], X[i], acc);
+      X[j] = acc * ia[j];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {        // rows kp + 2w + h of R, columns of R^{-1}, multipliers
+      double xj = X[0], aj = alpha[0];
+#pragma unroll
+      for (int j = 1; j < 8; ++j)
+        if (j == 2 * w + h) {
+          xj = X[j];
+          aj = alpha[j];
+        }
+      const int j = 2 * w + h, k = kp + j;
+      if (c < F) {
+        Gs[k * LD + c] = (c == k) ? aj : (c > k ? xj : 0.0);
+        XT[j * F + c] = xj;
+      } else if (live) {
+        const int cc = c - F;
+        Ri[cc * LD + k] = cc <= k ? xj : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 2; s < NR; ++s) {           // rank-8 update of the rows below the panel
+      if (s >= NR - 2 * p) break;            // slots past the matrix
+      const int i = kp + 8 * (s / 2) + 4 * (s % 2) + w;
+      double mj[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) mj[j] = XT[j * F + i];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) M[s] = fma(-mj[j], X[j], M[s]);
+    }
+#pragma unroll
+    for (int s = 0; s + 2 < NR; ++s) M[s] = M[s + 2];
+    M[NR - 2] = 0.0;
+    M[NR - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < (F - f) * F; idx += 256) {   // padding rows / columns
+    const int a = f + idx / F, b = idx - (idx / F) * F;
+    Gs[a * LD + b] = 0.0;
+    Ri[b * LD + a] = 0.0;
+  }
+  __syncthreads();
+  return ok;
+}
+
 // ---------------------------------------------------------------------------
 // C = op(A) op(B) for FP64 matrices in global or LDS memory (M, N, K <=
 // 128): element (i,k) of op(A) at TA ? A[k*lda + i] : A[i*lda + k], (k,j)
@@ -2835,6 +2961,500 @@ __global__ __launch_bounds__(256) void k_gram_rows(
 }
 
 // ---------------------------------------------------------------------------
+// Barrier across the workgroups of one launch, for launches small enough
+// that all their workgroups are resident at once (at most CQR2_GMAX
+// workgroups of 256 threads on a device of 256 CUs).  Every thread makes its
+// global stores visible at device scope (release fence), thread 0 arrives
+// on the counter and waits for `target` arrivals, then every thread takes an
+// acquire fence before it reads what the others wrote.  The wait is bounded by the 100 MHz wall
+// clock: past CQR2_WAIT_TICKS (about 1.3 s; a resident grid arrives within
+// microseconds) the workgroup sets st->sync_fail and goes on, so every wave
+// still ends; the call then reports EODABE_ESYNC and its outputs are void.
+// Each counter serves one launch per factorization and is zeroed by the
+// state initialisation.
+// ---------------------------------------------------------------------------
+constexpr int CQR2_GMAX = 32;
+constexpr int CQR2_RPW = 256;
+constexpr uint64_t CQR2_WAIT_TICKS = 1ull << 27;
+
+__device__ __forceinline__ void grid_barrier(uint32_t* ctr, uint32_t target, State* st) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(ctr, 1u);
+    const uint64_t t0 = wall_clock64();
+    while (atomicAdd(ctr, 0u) < target) {        // a read-modify-write: the device-coherent value
+      __builtin_amdgcn_s_sleep(1);
+      if (wall_clock64() - t0 > CQR2_WAIT_TICKS) {
+        atomicMax(&st->sync_fail, 1);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Arguments of k_cqr2.  Matrices R1, R2 and their inverses: f x f FP64,
+// element (i,j) at j*f + i, written by workgroup 0 when non-null.
+struct Cqr2Args {
+  const void* X;             // block: rows x f, element (i,c) at c*ldx + i (read only)
+  int64_t ldx, rows;
+  int f;
+  const int64_t* f_dev;      // non-null: f read on the device (<= the template width)
+  double* parts;             // 2 * gridDim.x * f * f doubles: the partial Grams of both passes
+  uint32_t* counter;         // barrier counter, zero at launch
+  const int32_t* stop_block; // non-null: return at once for a block after the stop
+  int block_id;
+  Gate gate;                 // closing steps enqueued ahead of the stop flag
+  State* st;
+  double *R1, *R1inv, *R2, *R2inv;
+  int32_t* dead;             // per-column dead flags: read on the first pass unless fresh, written at the end
+  int fresh;
+  int count_floors;          // add floored pivots to st->floored
+  const double* norm_parts;  // non-null: finish ||A||_F and eps = tol ||A||_F first (block 0)
+  const float* max_parts;    // with norm_parts: per-workgroup max |A| -> st->lp_scale
+  int64_t n_norm;
+  int stop_test;             // run the stop test of Alg. 1 and write the kept columns at wlog[block_id]
+  int64_t col0, n;
+  int64_t* wlog;
+  int32_t* acc;
+  double* diag_log;
+  void* Q;                   // output Z1 R2^{-1}: column c at Q + (zoff + c)*ldq
+  int64_t ldq;
+  // closing of Alg. 2 (with close_qr): M = R2 R1, M^T = Qh Rh by CholeskyQR2
+  // in FP64 on every workgroup (the steps of k_small_qr); Rh -> Dout (type T,
+  // row-major ldd) and Qh -> Qh_out (f x f, element (i,j) at j*f + i) by
+  // workgroup 0; with Uout, U = Uq Qh (Uq: m_u x f, element (i,c) at
+  // c*ldq_u + i; U likewise with ldu), rows split evenly over the workgroups
+  int close_qr;
+  void* Dout;
+  int64_t ldd;
+  double* Qh_out;
+  const void* Uq;
+  int64_t ldq_u;
+  void* Uout;
+  int64_t ldu, m_u;
+};
+
+template <typename T, int F>
+struct Cqr2Cfg {
+  typedef SmallCfg<F> S;
+  static constexpr int LDX = CQR2_RPW + 16 / (int)sizeof(T);      // panel column stride (T elements)
+  static constexpr int XD = (F * LDX * (int)sizeof(T) + 7) / 8;    // panel, in doubles
+  static constexpr int RED = (F / 16) * (F / 16) * 256;             // wave fold of a partial Gram
+  static constexpr int CH = 2 * S::SIZE + 24 * F + F;               // G/R, R^{-1}, elimination rows, diagonal
+  static constexpr int WORK = RED > CH ? RED : CH;
+  static constexpr int TOTAL = XD + WORK + F + 8 + S::SIZE;         // + R1's diagonal + scalars + R1
+  static_assert(XD >= 3 * S::SIZE, "the closing QR's three work matrices fit the panel area");
+};
+
+// ---------------------------------------------------------------------------
+// CholeskyQR2 of a block (f <= F <= 32 columns, at most CQR2_GMAX panels of
+// CQR2_RPW rows) in one launch, one workgroup per row panel, the panel held
+// in LDS throughout (Alg. 1, "compute QR" of the sketch; Alg. 2, QR(C^T)):
+//   pass 0: partial Gram of the panel; barrier; every workgroup sums all
+//           partials in the same fixed order and runs chol_inv with the
+//           floor rule (R1, R1^{-1}: the same bits in every workgroup);
+//           Z1 = X R1^{-1} (FP64 MFMA, rounded to T) replaces the panel;
+//   pass 1: partial Gram of Z1; barrier; sum, chol_inv with the kill rule
+//           (R2, R2^{-1}); with stop_test the first column c with
+//           |T(c,c)| = R2(c,c) R1(c,c) <= eps ends the kept width (every
+//           workgroup takes the same decision); Q = Z1 R2^{-1} for the
+//           kept columns.
+// The arithmetic is that of the Gram kernel pair (k_gram_rows, modes 0 and
+// 1) and the apply (k_apply) it replaces: the same partial grouping, fold
+// order and MFMA sequences.  Workgroup 0 alone writes R1, R2, their
+// inverses, the dead flags, the floors and the state.
+// ---------------------------------------------------------------------------
+template <typename T, int F>
+__global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
+  typedef Mfma<double> MF;
+  typedef Cqr2Cfg<T, F> Cfg;
+  typedef SmallCfg<F> S;
+  constexpr int TT = F / 16, RPW = CQR2_RPW, LDX = Cfg::LDX, LD = S::LD, PW = RPW / 4, KS = F / 4;
+  static_assert(F <= 32, "register budget of the Gram tiles");
+  static_assert(Cfg::TOTAL * 8 <= 160 * 1024, "LDS budget");
+  // early exits read state written by earlier launches only: the same for every workgroup
+  if (a.stop_block && *a.stop_block < a.block_id) return;
+  if (gate_shut(a.gate)) return;
+  const int f = a.f_dev ? (int)*a.f_dev : a.f;
+  if (f <= 0 || f > F) return;
+  __shared__ __align__(16) double lds[Cfg::TOTAL];
+  T* pan = reinterpret_cast<T*>(lds);            // pan[c*LDX + row]
+  double* Gs = lds + Cfg::XD;                    // G, then R
+  double* Ri = Gs + S::SIZE;                     // R^{-1}
+  double* rowbuf = Ri + S::SIZE;
+  double* dgs = rowbuf + 24 * F;
+  double* red = Gs;                              // wave fold, before the Cholesky takes the area
+  double* r1d = lds + Cfg::XD + Cfg::WORK;       // R1's diagonal
+  int* sx = reinterpret_cast<int*>(r1d + F);
+  double* R1s = r1d + F + 8;                     // R1 (the closing QR needs all of it)
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
+  const T* X = reinterpret_cast<const T*>(a.X);
+  const int64_t rb = (int64_t)blockIdx.x * RPW;
+  const unsigned G = gridDim.x;
+  const int ff = f * f;
+  const bool lead = blockIdx.x == 0;
+  State* st = a.st;
+  const int64_t zoff = (a.stop_test && a.wlog) ? a.wlog[a.block_id] : 0;
+  // everything read from earlier launches is requested now, ahead of the
+  // barriers (after them the caches are invalidated and each read would be
+  // a round trip on the critical path)
+  const int paired = st->paired;
+  const double tol = st->tol;
+  const int lp_mode = st->lp_mode;
+  const double eps_g = st->eps;
+  const int nonf_g = st->nonfinite;
+  const int dead0 = (lane < f && !a.fresh) ? a.dead[lane] : 0;
+  double pv0[8];
+  float mv0[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t i = lane + 64 * q;
+    const bool in = a.norm_parts && wv == 0 && i < a.n_norm;
+    pv0[q] = in ? a.norm_parts[i] : 0.0;
+    mv0[q] = (in && a.max_parts) ? a.max_parts[i] : 0.0f;
+  }
+  {                                              // stage the panel (zero outside rows x f), all loads in flight
+    constexpr int NIT = F * RPW / 256;
+    T xv[NIT];
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int idx = tid + 256 * q;
+      const int c = idx / RPW, rl = idx - c * RPW;
+      const int64_t row = rb + rl;
+      xv[q] = (c < f && row < a.rows) ? X[(int64_t)c * a.ldx + row] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int idx = tid + 256 * q;
+      const int c = idx / RPW, rl = idx - c * RPW;
+      pan[c * LDX + rl] = xv[q];
+    }
+  }
+  uint64_t dmask = 0;
+  double eps_l = 0.0;
+  bool nonf_l = false;
+  for (int pass = 0; pass < 2; ++pass) {
+    __syncthreads();                             // panel (pass 1: Z1) complete
+    typename MF::acc_t acc[TT][TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+#pragma unroll
+      for (int u = 0; u < TT; ++u) acc[t][u] = MF::zero();
+#pragma unroll
+    for (int k0 = 0; k0 < PW; k0 += 16) {        // wave wv: panel rows [wv*PW, (wv+1)*PW)
+      const int kr = wv * PW + k0 + 4 * g;
+      V4<double> av[TT];
+#pragma unroll
+      for (int t = 0; t < TT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) av[t].v[e] = (double)pan[(16 * t + r) * LDX + kr + e];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+#pragma unroll
+          for (int u = t; u < TT; ++u) acc[t][u] = MF::op(av[t].v[v], av[u].v[v], acc[t][u]);
+    }
+    for (int w = 0; w < 4; ++w) {                // fold the 4 waves (fixed order)
+      if (wv == w) {
+#pragma unroll
+        for (int t = 0; t < TT; ++t)
+#pragma unroll
+          for (int u = t; u < TT; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              double* qq = &red[((t * TT + u) * 4 + e) * 64 + lane];
+              *qq = (w == 0) ? acc[t][u][e] : *qq + acc[t][u][e];
+            }
+      }
+      __syncthreads();
+    }
+    double* pp = a.parts + (int64_t)pass * G * ff;
+    double* Pw = pp + (int64_t)blockIdx.x * ff;  // this workgroup's partial, symmetric fill
+    for (int idx = tid; idx < TT * TT * 256; idx += 256) {
+      const int l = idx & 63, e = (idx >> 6) & 3, tu = idx >> 8;
+      const int t = tu / TT, u = tu - t * TT;
+      if (u < t) continue;
+      const int i = 16 * t + MF::row(l >> 4, e), jj = 16 * u + (l & 15);
+      if (i < f && jj < f) {
+        const double v = red[idx];
+        Pw[(int64_t)jj * f + i] = v;
+        Pw[(int64_t)i * f + jj] = v;
+      }
+    }
+    grid_barrier(a.counter, (unsigned)(pass + 1) * G, st);
+    constexpr int EPT = (F * F + 255) / 256;
+    double sum[EPT];                             // G's upper triangle, kept for a second Cholesky
+    {                                            // all partials, upper triangle, order b = 0, 1, ...
+      constexpr int PB = 16;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) sum[e] = 0.0;
+      for (unsigned b = 0; b < G; b += PB) {
+        double v[EPT][PB];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int idx = tid + 256 * e;
+          const int c = idx / f, rr = idx - c * f;
+          const bool ok = idx < ff && rr <= c;
+#pragma unroll
+          for (int q = 0; q < PB; ++q) v[e][q] = (ok && b + q < G) ? pp[(int64_t)(b + q) * ff + idx] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+#pragma unroll
+          for (int q = 0; q < PB; ++q) sum[e] += v[e][q];
+      }
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 256 * e;
+        const int c = idx / f, rr = idx - c * f;
+        if (idx < ff && rr <= c) {
+          Gs[rr * LD + c] = sum[e];
+          Gs[c * LD + rr] = sum[e];
+        }
+      }
+    }
+    if (pass == 0 && a.norm_parts && wv == 0) {  // ||A||_F from the sketch partials (fixed order)
+      double s = 0.0;
+      float mx = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {             // the first 512, prefetched
+        if (lane + 64 * q < a.n_norm) s += pv0[q];
+        mx = fmaxf(mx, mv0[q]);
+      }
+      for (int64_t i0 = 64 * 8; i0 < a.n_norm; i0 += 64 * 8) {
+        double pv[8];
+        float mv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t i = i0 + lane + 64 * q;
+          pv[q] = i < a.n_norm ? a.norm_parts[i] : 0.0;
+          mv[q] = (a.max_parts && i < a.n_norm) ? a.max_parts[i] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (i0 + lane + 64 * q < a.n_norm) s += pv[q];
+          mx = fmaxf(mx, mv[q]);
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+      }
+      nonf_l = !(s < INFINITY);
+      eps_l = nonf_l ? 0.0 : tol * sqrt(s);
+      if (lead && lane == 0) {
+        st->normsq = s;
+        st->nonfinite = nonf_l ? 1 : 0;
+        st->eps = eps_l;
+        st->lp_scale = lp_scale_of(mx, lp_mode);
+      }
+    }
+    uint64_t dmask_in = dmask;
+    if (pass == 0) dmask_in = __ballot(dead0 != 0);
+    __syncthreads();
+    int nfl = 0;
+    // the branch-free elimination first; the full pivot rules only when it
+    // meets a dead column or a pivot at or below the floor
+    const bool fast = dmask_in == 0ull && chol_inv_fast<F>(Gs, Ri, rowbuf, dgs, f);
+    if (!fast) {
+      if (dmask_in == 0ull) {                    // Gs was overwritten: G again from the registers
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int idx = tid + 256 * e;
+          const int c = idx / f, rr = idx - c * f;
+          if (idx < ff && rr <= c) {
+            Gs[rr * LD + c] = sum[e];
+            Gs[c * LD + rr] = sum[e];
+          }
+        }
+        __syncthreads();
+      }
+      [[clang::noinline]] chol_inv<F>(Gs, Ri, rowbuf, dgs, f, dmask_in, pass == 0, &dmask, &nfl);
+    } else {
+      dmask = 0ull;
+    }
+    if (lead) {
+      double* Ro = pass == 0 ? a.R1 : a.R2;
+      double* Rio = pass == 0 ? a.R1inv : a.R2inv;
+      for (int idx = tid; idx < ff; idx += 256) {
+        const int c = idx / f, rr = idx - c * f;  // element (rr, c) at c*f + rr
+        if (Ro) Ro[idx] = Gs[rr * LD + c];
+        if (Rio) Rio[idx] = Ri[rr * LD + c];
+      }
+      if (a.count_floors && tid == 0 && nfl) atomicAdd(&st->floored, nfl);
+      if (pass == 1 && tid < f) a.dead[tid] = (int32_t)((dmask >> tid) & 1ull);
+    }
+    if (pass == 0) {
+      if (tid < F) r1d[tid] = Gs[tid * LD + tid];
+      if (a.close_qr)
+        for (int idx = tid; idx < S::SIZE; idx += 256) R1s[idx] = Gs[idx];
+      // Z1 = X R1^{-1} in place: wave wv takes 16-row tiles wv, wv + 4, ...
+      // (each tile's rows are read whole before they are written)
+      for (int rt = wv; rt < RPW / 16; rt += 4) {
+        double av[KS];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) av[kk] = (double)pan[(4 * kk + g) * LDX + 16 * rt + r];
+        typename MF::acc_t z[TT];
+#pragma unroll
+        for (int u = 0; u < TT; ++u) z[u] = MF::zero();
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+          for (int u = 0; u < TT; ++u) z[u] = MF::op(av[kk], Ri[(4 * kk + g) * LD + 16 * u + r], z[u]);
+#pragma unroll
+        for (int u = 0; u < TT; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pan[(16 * u + r) * LDX + 16 * rt + MF::row(g, e)] = (T)z[u][e];
+      }
+    }
+  }
+  // stop test (Alg. 1) on wave 0 of every workgroup: first column whose
+  // |T(c,c)| <= eps
+  int keep = f;
+  if (a.stop_test) {
+    if (wv == 0) {
+      const int j = lane;
+      const bool mine = j < f;
+      const double eps = a.norm_parts ? eps_l : eps_g;
+      const bool nonf = a.norm_parts ? nonf_l : (nonf_g != 0);
+      double d = 0.0;
+      bool hit = false;
+      if (mine) {
+        d = ((dmask >> j) & 1ull) ? 0.0 : Gs[j * LD + j] * r1d[j];
+        hit = ((d <= eps) && (!paired || ((a.col0 + j) & 1) == 0)) || nonf;
+      }
+      const unsigned long long mask = __ballot(hit);
+      const int kp = mask ? (int)__ffsll((long long)mask) - 1 : f;
+      if (lane == 0) sx[0] = kp;
+      if (lead) {
+        if (mine && j <= kp) a.diag_log[a.col0 + j] = d;
+        const double dk = __shfl(d, kp & 63);
+        if (j == 0) {
+          if (mask != 0ull) st->d_stop = dk;
+          const bool stop = (mask != 0ull) || (a.col0 + f >= a.n);
+          a.acc[a.block_id] = kp;
+          const int64_t wn = zoff + kp;
+          a.wlog[a.block_id + 1] = wn;
+          st->rank = wn;
+          if (stop) st->stop_block = a.block_id;
+        }
+      }
+    }
+    __syncthreads();
+    keep = sx[0];
+  }
+  // Q = Z1 R2^{-1} for the kept columns (the apply's tile order and sums)
+  T* Q = reinterpret_cast<T*>(a.Q);
+  for (int rt = wv; rt < RPW / 16; rt += 4) {
+    double av[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) av[kk] = (double)pan[(4 * kk + g) * LDX + 16 * rt + r];
+    typename MF::acc_t z[TT];
+#pragma unroll
+    for (int u = 0; u < TT; ++u) z[u] = MF::zero();
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+      for (int u = 0; u < TT; ++u) z[u] = MF::op(av[kk], Ri[(4 * kk + g) * LD + 16 * u + r], z[u]);
+#pragma unroll
+    for (int u = 0; u < TT; ++u) {
+      const int col = 16 * u + r;
+      if (col >= keep) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = rb + 16 * rt + MF::row(g, e);
+        if (row < a.rows) Q[(zoff + col) * a.ldq + row] = (T)z[u][e];
+      }
+    }
+  }
+  if (!a.close_qr) return;
+  // closing QR (Alg. 2, QR(R^T)), redundantly on every workgroup
+  __syncthreads();                               // the panel and R2^{-1} are free
+  double* B0 = lds;
+  double* B1 = lds + S::SIZE;
+  double* B2 = lds + 2 * S::SIZE;
+  double* B3 = Ri;
+  double* Qs = Gs;                               // Qh (R2 is dead once M is formed)
+  lds_gemm<F, false, false>(Gs, R1s, [&](int i, int jj, double v) { B0[i * LD + jj] = v; });   // M = R2 R1
+  __syncthreads();
+  lds_gemm<F, false, true>(B0, B0, [&](int i, int jj, double v) { B1[i * LD + jj] = v; });     // M M^T
+  __syncthreads();
+  uint64_t dm1 = 0ull, dm2 = 0ull;
+  int nf1 = 0, nf2 = 0;
+  if (!chol_inv_fast<F>(B1, B2, rowbuf, dgs, f)) {
+    lds_gemm<F, false, true>(B0, B0, [&](int i, int jj, double v) { B1[i * LD + jj] = v; });
+    __syncthreads();
+    [[clang::noinline]] chol_inv<F>(B1, B2, rowbuf, dgs, f, 0ull, 1, &dm1, &nf1);                                 // Rh1, Rh1^{-1}
+  }
+  lds_gemm<F, true, false>(B0, B2, [&](int i, int jj, double v) { B3[i * LD + jj] = v; });     // Z = M^T Rh1^{-1}
+  __syncthreads();
+  lds_gemm<F, true, false>(B3, B3, [&](int i, int jj, double v) { B0[i * LD + jj] = v; });     // Z^T Z
+  __syncthreads();
+  if (!(dm1 == 0ull && chol_inv_fast<F>(B0, B2, rowbuf, dgs, f))) {
+    if (dm1 == 0ull) {
+      lds_gemm<F, true, false>(B3, B3, [&](int i, int jj, double v) { B0[i * LD + jj] = v; });
+      __syncthreads();
+    }
+    [[clang::noinline]] chol_inv<F>(B0, B2, rowbuf, dgs, f, dm1, 0, &dm2, &nf2);                                  // Rh2, Rh2^{-1}
+  }
+  lds_gemm<F, false, false>(B3, B2, [&](int i, int jj, double v) {                            // Qh = Z Rh2^{-1}
+    Qs[i * LD + jj] = v;
+    if (lead && i < f && jj < f) a.Qh_out[(int64_t)jj * f + i] = v;
+  });
+  T* Dout = reinterpret_cast<T*>(a.Dout);
+  if (lead)
+    lds_gemm<F, false, false>(B0, B1, [&](int i, int jj, double v) {                          // Rh = Rh2 Rh1
+      if (i < f && jj < f) Dout[(int64_t)i * a.ldd + jj] = (T)v;
+    });
+  if (lead && a.count_floors && tid == 0 && nf1 + nf2) atomicAdd(&st->floored, nf1 + nf2);
+  if (!a.Uout) return;
+  __syncthreads();                               // Qh complete
+  // U = Uq Qh on this workgroup's rows, 16-row tiles, four per wave in flight
+  // (the apply's operand order and sums)
+  const T* Uq = reinterpret_cast<const T*>(a.Uq);
+  T* U = reinterpret_cast<T*>(a.Uout);
+  const int64_t chunk = (((a.m_u + G - 1) / G + 15) / 16) * 16;
+  const int64_t u0 = (int64_t)blockIdx.x * chunk, u1 = min(a.m_u, u0 + chunk);
+  constexpr int NB = 4;
+  for (int64_t t0 = u0 + 16 * wv; t0 < u1; t0 += 64 * NB) {
+    T xa[NB][KS];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int64_t arow = t0 + 64 * b + r;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        const int k = 4 * kk + g;
+        xa[b][kk] = (arow < u1 && k < f) ? Uq[(int64_t)k * a.ldq_u + arow] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      typename MF::acc_t z[TT];
+#pragma unroll
+      for (int u = 0; u < TT; ++u) z[u] = MF::zero();
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+        for (int u = 0; u < TT; ++u) z[u] = MF::op((double)xa[b][kk], Qs[(4 * kk + g) * LD + 16 * u + r], z[u]);
+#pragma unroll
+      for (int u = 0; u < TT; ++u) {
+        const int col = 16 * u + r;
+        if (col >= f) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = t0 + 64 * b + MF::row(g, e);
+          if (row < u1) U[col * a.ldu + row] = (T)z[u][e];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Z = X W (FP64 MFMA, rounded to T) for one or two jobs (blockIdx.y):
 // X column-major rows x f (ldx), W f x f FP64 (element (i,j) at j*f + i,
 // any shape), Z column-major (ldz), columns zoff .. zoff+ncols-1 written.
@@ -3024,7 +3644,7 @@ __global__ void k_init_state(State* st, double tol, int64_t* wlog, int nwlog, in
     st->eps = 0.0; st->normsq = 0.0; st->tol = tol;
     st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->paired = paired; st->rank = 0;
     for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
-    st->lp_scale = 1.0; st->lp_mode = lp_mode; st->pad2 = 0; st->d_stop = 0.0;
+    st->lp_scale = 1.0; st->lp_mode = lp_mode; st->sync_fail = 0; st->d_stop = 0.0;
   }
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = t; i < nwlog; i += nt) wlog[i] = 0;

@@ -41,8 +41,9 @@ def test_every_declared_symbol_is_exported(E):
 
 
 def test_strerror_and_defaults(E):
-    for code in (0, -1, -2, -3, -4, -5, -6, 1):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 1):
         assert E.strerror(code) and E.strerror(code) != "unknown status"
+    assert "barrier" in E.strerror(E.EODABE_ESYNC)
     o = E.Opts()
     E._lib.eodabe_default_opts(ctypes.byref(o))
     assert o.block == 32 and o.power_iters == 0 and o.a_dtype == E.F32
@@ -169,3 +170,19 @@ def test_predictor_checkpoint_roundtrip(tmp_path):
         head = fh.readline()
     assert b'"format": "eodabe-mlp-1"' in head
     assert PR.init_params(5).size == PR.NPARAM == 149506
+
+
+def test_status_codes_match_header(E):
+    """Every status code the header defines has the same value in the
+    binding and a message of its own."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "eodabe.h")).read()
+    codes = dict((n, int(v)) for n, v in re.findall(r"#define (EODABE_(?:OK|E[A-Z]+|W[A-Z_]+))\s+(-?\d+)", hdr))
+    assert {"EODABE_OK", "EODABE_ESYNC", "EODABE_ESCRATCH", "EODABE_WTOL_FLOOR"} <= set(codes)
+    msgs = set()
+    for name, v in codes.items():
+        assert getattr(E, name) == v, name
+        m = E.strerror(v)
+        assert m != "unknown status", name
+        msgs.add(m)
+    assert len(msgs) == len(codes)

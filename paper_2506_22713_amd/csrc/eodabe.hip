@@ -42,6 +42,7 @@ struct eodabe_ctx {
   int cu_count;
   int last_hip;
   State* host_state;      // pinned host copy of the control block
+  State* host_state_dev;  // its device address (null: copied by hipMemcpyAsync only)
   int64_t* host_wlog;     // pinned host copy of the basis-width log
   int64_t host_wlog_cap;
   bool host_only;
@@ -879,7 +880,8 @@ int copy2d(eodabe_ctx* ctx, hipStream_t st, const T* src, int64_t lds, T* dst, i
 // is in w.q (column-major, ld g.ldy) and *rank holds its width.
 // after_chunk(jend) is called once the blocks [.., jend) are enqueued and
 // before the host reads the stop flag; it returns 1 if it enqueued the
-// (gated) closing steps, 0 if not, < 0 on error.  *spec_ran tells whether
+// (gated) closing steps, 2 if those steps also write the control block to
+// the context's host copy (no copy needed), 0 if not, < 0 on error.  *spec_ran tells whether
 // such closing steps ran to completion for the chunk that ended the loop.
 template <typename T, typename Hook>
 int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, double tol,
@@ -1100,15 +1102,16 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
     }
     const int spec = after_chunk(j);
     if (spec < 0) return spec;
-    // host check of the stop flag (one small D2H copy per chunk)
-    HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
+    // host check of the stop flag (one small D2H copy per chunk, unless the
+    // closing kernel wrote the control block to host memory itself: spec 2)
+    if (spec != 2) HIPCHK(hipMemcpyAsync(ctx->host_state, w.st, sizeof(State), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const State& hs = *ctx->host_state;
     if (hs.sync_fail) return EODABE_ESYNC;
     if (hs.stop_block != 0x7fffffff || j >= g.nblk) finished = true;
     // the gated closing steps ran iff the loop stopped with a finite norm
     // and 0 < rank <= r_cap (the gate of those kernels)
-    const bool ran = spec == 1 && hs.stop_block != 0x7fffffff && !hs.nonfinite && hs.rank > 0 &&
+    const bool ran = spec >= 1 && hs.stop_block != 0x7fffffff && !hs.nonfinite && hs.rank > 0 &&
                      hs.rank <= g.r_cap;
     if (ctx->prof_on)
       prof_collect(ctx, hs.stop_block != 0x7fffffff ? hs.stop_block : (int)g.nblk, ran, hs.rank);
@@ -1231,7 +1234,7 @@ int core_splits(const Geo& g, int64_t r) {
 template <typename T>
 int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const T* Ae, int64_t r,
                 Gate gate, const int64_t* r_dev, T* Uout, int64_t ldu, T* Vout, int64_t ldv, T* Dout,
-                int64_t ldd, int prof_block) {
+                int64_t ldd, int prof_block, bool* state_sent = nullptr) {
   if (r <= 0 || r > 128 || (r > 64 && (gate.st || r_dev))) return EODABE_EINVAL;
   Ops<T> ops{ctx, st};
   T* q = (T*)w.q;
@@ -1288,6 +1291,12 @@ int close_small(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, cons
       a.Uout = Uout;
       a.ldu = ldu;
       a.m_u = g.mm;
+    }
+    // the control block to host memory from the same kernel, once final (no
+    // later launch of the chunk changes it): the host needs no copy
+    if (state_sent && ctx->host_state_dev) {
+      a.state_out = ctx->host_state_dev;
+      *state_sent = true;
     }
     TRY(cqr2<T>(ctx, st, a));
     if (!u_in) {
@@ -1879,6 +1888,7 @@ int eodabe_create_host(eodabe_ctx** out, const eodabe_opts* opts) {
   c->cu_count = 0;
   c->last_hip = 0;
   c->host_state = nullptr;
+  c->host_state_dev = nullptr;
   c->host_wlog = nullptr;
   c->host_wlog_cap = 0;
   c->host_only = true;
@@ -1906,6 +1916,11 @@ int eodabe_create(eodabe_ctx** out, const eodabe_opts* opts) {
   if (hipHostMalloc((void**)&c->host_state, sizeof(State), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return EODABE_EHIP;
+  }
+  // the fused closing kernel can then write the control block there itself
+  if (hipHostGetDevicePointer((void**)&c->host_state_dev, c->host_state, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    c->host_state_dev = nullptr;
   }
   // device address of this GPU's copy of the no-allocation scratch, looked up
   // once per device with the device current
@@ -2053,10 +2068,11 @@ static int factor_impl(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int
     auto after_chunk = [&](int64_t jend) -> int {
       if (!can_spec) return 0;
       const int64_t rb = std::min<int64_t>(g.nn, jend * (int64_t)g.b);
+      bool sent = false;
       if (rb <= 0 || rb > 64) return 0;
       TRY(close_small<T>(ctx, st, g, w, Ae, rb, Gate{w.st, g.r_cap}, &w.st->rank, (T*)Ut, m, (T*)Vt,
-                         n, (T*)core, g.r_cap, SPEC_BLOCK));
-      return 1;
+                         n, (T*)core, g.r_cap, SPEC_BLOCK, &sent));
+      return sent ? 2 : 1;
     };
     bool spec_ran = false;
     TRY(run_basis<T>(ctx, st, g, w, Ae, tol, &rank, &blocks, &norm_a, after_chunk, &spec_ran));

@@ -50,6 +50,7 @@ struct State {
   int32_t sync_fail;     // a barrier across workgroups timed out (outputs void)
   double d_stop;         // |T(l,l)| of the column whose test stopped the loop (0: none)
 };
+static_assert(sizeof(State) % 8 == 0, "the control block is copied in 8-byte words");
 
 // Low-precision copies of A for the sketch: IEEE binary16 or bfloat16,
 // both rounded to nearest even from FP32 and stored as 16-bit patterns.
@@ -3035,7 +3036,20 @@ struct Cqr2Args {
   int64_t ldq_u;
   void* Uout;
   int64_t ldu, m_u;
+  State* state_out;          // non-null (host-mapped): workgroup 0 copies the control block there
+                             // once it is final, whether the gate let the closing run or not
 };
+
+// The control block into host-mapped memory (thread 0 of workgroup 0): an
+// acquire fence first, so the words read are the device's latest (the
+// floor count was just updated by an atomic).
+__device__ __forceinline__ void state_send(const Cqr2Args& a) {
+  if (!a.state_out || blockIdx.x != 0 || threadIdx.x != 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(a.st);
+  uint64_t* dst = reinterpret_cast<uint64_t*>(a.state_out);
+  for (int i = 0; i < (int)(sizeof(State) / 8); ++i) dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <typename T, int F>
 struct Cqr2Cfg {
@@ -3077,9 +3091,11 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
   static_assert(Cfg::TOTAL * 8 <= 160 * 1024, "LDS budget");
   // early exits read state written by earlier launches only: the same for every workgroup
   if (a.stop_block && *a.stop_block < a.block_id) return;
-  if (gate_shut(a.gate)) return;
   const int f = a.f_dev ? (int)*a.f_dev : a.f;
-  if (f <= 0 || f > F) return;
+  if (gate_shut(a.gate) || f <= 0 || f > F) {
+    state_send(a);
+    return;
+  }
   __shared__ __align__(16) double lds[Cfg::TOTAL];
   T* pan = reinterpret_cast<T*>(lds);            // pan[c*LDX + row]
   double* Gs = lds + Cfg::XD;                    // G, then R
@@ -3411,6 +3427,7 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
       if (i < f && jj < f) Dout[(int64_t)i * a.ldd + jj] = (T)v;
     });
   if (lead && a.count_floors && tid == 0 && nf1 + nf2) atomicAdd(&st->floored, nf1 + nf2);
+  state_send(a);                                 // the control block is final here
   if (!a.Uout) return;
   __syncthreads();                               // Qh complete
   // U = Uq Qh on this workgroup's rows, 16-row tiles, four per wave in flight

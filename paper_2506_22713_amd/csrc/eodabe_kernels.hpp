@@ -85,6 +85,18 @@ struct Gate {
   const State* st;       // null: always open
   int64_t r_cap;
 };
+// Handing a workgroup's global stores to other workgroups: every wave
+// waits until its own stores have reached L2 (s_waitcnt vmcnt(0); the
+// immediate keeps expcnt and lgkmcnt at their no-wait maxima), the
+// workgroup meets, and thread 0 alone then takes the device-scope release,
+// one L2 write-back for the workgroup instead of one per wave.  The
+// receiving side mirrors it: thread 0 takes the acquire (one L1/L2
+// invalidate) before the barrier that lets its waves read.
+__device__ __forceinline__ void wg_stores_done() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+}
+
 __device__ __forceinline__ bool gate_shut(const Gate& g) {
   if (!g.st) return false;
   return g.st->stop_block == 0x7fffffff || g.st->nonfinite != 0 || g.st->rank <= 0 ||
@@ -2842,13 +2854,15 @@ __global__ __launch_bounds__(256) void k_gram_rows(
     }
   }
   // the last workgroup to arrive folds all partials in fixed order
-  __threadfence();
+  wg_stores_done();
   __shared__ int s_last;
-  __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  if (tid == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    s_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
   const int ff = f * f;
   double* Gs = ph;                   // G, then R
   double* Ri = Gs + S::SIZE;         // R^{-1}
@@ -2964,10 +2978,11 @@ __global__ __launch_bounds__(256) void k_gram_rows(
 // ---------------------------------------------------------------------------
 // Barrier across the workgroups of one launch, for launches small enough
 // that all their workgroups are resident at once (at most CQR2_GMAX
-// workgroups of 256 threads on a device of 256 CUs).  Every thread makes its
-// global stores visible at device scope (release fence), thread 0 arrives
-// on the counter and waits for `target` arrivals, then every thread takes an
-// acquire fence before it reads what the others wrote.  The wait is bounded by the 100 MHz wall
+// workgroups of 256 threads on a device of 256 CUs).  The workgroup's
+// global stores are handed over as wg_stores_done describes (thread 0 takes
+// the release), thread 0 arrives on the counter, waits for `target`
+// arrivals and takes the acquire before the barrier that lets its waves
+// read what the others wrote.  The wait is bounded by the 100 MHz wall
 // clock: past CQR2_WAIT_TICKS (about 1.3 s; a resident grid arrives within
 // microseconds) the workgroup sets st->sync_fail and goes on, so every wave
 // still ends; the call then reports EODABE_ESYNC and its outputs are void.
@@ -2979,9 +2994,9 @@ constexpr int CQR2_RPW = 256;
 constexpr uint64_t CQR2_WAIT_TICKS = 1ull << 27;
 
 __device__ __forceinline__ void grid_barrier(uint32_t* ctr, uint32_t target, State* st) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
+  wg_stores_done();
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     atomicAdd(ctr, 1u);
     const uint64_t t0 = wall_clock64();
     while (atomicAdd(ctr, 0u) < target) {        // a read-modify-write: the device-coherent value
@@ -2991,9 +3006,9 @@ __device__ __forceinline__ void grid_barrier(uint32_t* ctr, uint32_t target, Sta
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Arguments of k_cqr2.  Matrices R1, R2 and their inverses: f x f FP64,

@@ -995,7 +995,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
                             g.ld_lp, w.st));
         if (g.lp && j == 1) abytes += 2.0 * g.mm * g.nn;
       } else {
-        TRY(ops.sketch(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch, (T*)w.ypart, g.ldy,
+        // one K-split: the sketch writes Y itself (no partial to fold)
+        TRY(ops.sketch(Ae, g.lda_eff, omega, g.ldk, g.mm, g.bn, g.nn, g.s_sketch, nsp == 1 ? y : (T*)w.ypart, g.ldy,
                        ystride, j == 0 ? w.normparts : nullptr, stopb, blk,
                        (j == 0 && g.lp) ? w.maxparts : nullptr, (g.lp && j == 1) ? g.lp : 0, w.alp, g.ld_lp,
                        w.st));
@@ -1005,7 +1006,8 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       prof_end(ctx, st, pid, EODABE_PROF_SKETCH, blk,
                abytes + (double)g.elem * ((double)g.nn * f + (double)g.mm * f));
       // partials to fold unless the sketch wrote Y itself
-      if (j > 0 && !rows_blk) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+      const bool y_direct = rows_blk || (nsp == 1 && !(g.lp && j >= 2));
+      if (j > 0 && !y_direct) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       if (j > 0) TRY(pair_fix<T>(ctx, st, g.paired, y, g.ldy, g.mm, f, stopb, blk));
       }
       // a3 + a4: two rounds of [project against the basis so far (width
@@ -1017,7 +1019,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
       const int64_t wmax = std::min<int64_t>(j * g.b, g.nn);
       const bool small = f <= 64;     // fused Gram + Cholesky-with-inverse kernels
       const bool mid = f <= 128;      // explicit R^{-1} (blocked Cholesky above 64 columns) + apply
-      if (j == 0 && !rows_blk) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
+      if (j == 0 && !(rows_blk || nsp == 1)) TRY(ops.reduce_wide((const T*)w.ypart, nsp, ystride, ystride, y, stopb, blk));
       if (j == 0) TRY(pair_fix<T>(ctx, st, g.paired, y, g.ldy, g.mm, f, stopb, blk));
       if (j == 0 && cqr2_fits(g.mm, f)) {
         // block 0: both CholeskyQR2 passes, the stop test and the append in

@@ -2876,7 +2876,7 @@ __global__ __launch_bounds__(256) void k_gram_rows(
     double sum[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) sum[e] = 0.0;
-    constexpr int PB = EPT <= 4 ? 16 : 4;        // partials per batch (loads in flight)
+    constexpr int PB = EPT == 1 ? 64 : (EPT <= 4 ? 16 : 4);   // partials per batch (loads in flight)
     for (unsigned b = 0; b < nb; b += PB) {
       double v[EPT][PB];
 #pragma unroll
@@ -2905,21 +2905,24 @@ __global__ __launch_bounds__(256) void k_gram_rows(
   }
   if (tid == 0) *counter = 0u;
   State* st = ca.st;
-  if (ca.norm_parts && wv == 0) {    // ||A||_F from the sketch partials (fixed order)
+  if (ca.norm_parts) {               // ||A||_F from the sketch partials (fixed order)
+    // all four waves, 8 loads per thread in flight; the thread sums, the
+    // wave sums and the four wave sums (in wave order) are each formed in a
+    // fixed order
     double a = 0.0;
     float mx = 0.0f;
-    for (int64_t i0 = 0; i0 < ca.n_norm; i0 += 64 * 8) {   // 8 loads per lane in flight
+    for (int64_t i0 = 0; i0 < ca.n_norm; i0 += 256 * 8) {
       double pv[8];
       float mv[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int64_t i = i0 + lane + 64 * q;
+        const int64_t i = i0 + tid + 256 * q;
         pv[q] = i < ca.n_norm ? ca.norm_parts[i] : 0.0;
         mv[q] = (ca.max_parts && i < ca.n_norm) ? ca.max_parts[i] : 0.0f;
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        if (i0 + lane + 64 * q < ca.n_norm) a += pv[q];
+        if (i0 + tid + 256 * q < ca.n_norm) a += pv[q];
         mx = fmaxf(mx, mv[q]);
       }
     }
@@ -2927,7 +2930,16 @@ __global__ __launch_bounds__(256) void k_gram_rows(
       a += __shfl_xor(a, off);
       mx = fmaxf(mx, __shfl_xor(mx, off));
     }
+    __shared__ double s_norm[4];
+    __shared__ float s_max[4];
     if (lane == 0) {
+      s_norm[wv] = a;
+      s_max[wv] = mx;
+    }
+    __syncthreads();
+    a = ((s_norm[0] + s_norm[1]) + s_norm[2]) + s_norm[3];
+    mx = fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
+    if (tid == 0) {
       st->normsq = a;
       const bool bad = !(a < INFINITY);
       st->nonfinite = bad ? 1 : 0;

@@ -628,6 +628,9 @@ struct Ops {
       hipLaunchKernelGGL((k_apply<T, 32>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else if (f <= 64)
       hipLaunchKernelGGL((k_apply<T, 64>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
+    else if (f <= 128 && j0.Z != j0.X && jb.Z != jb.X)   // output columns over four workgroups
+      hipLaunchKernelGGL((k_apply_cols<T, 128>), dim3(grid.x, grid.y, 4), dim3(256), 0, st, j0, jb, stopb, blk,
+                         gate);
     else if (f <= 128)
       hipLaunchKernelGGL((k_apply<T, 128>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else

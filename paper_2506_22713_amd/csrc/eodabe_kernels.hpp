@@ -3551,9 +3551,21 @@ __global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
   if constexpr (F <= 64) {
     stage_small<F>({jb.W}, f, {Wl}, LD);
   } else {
-    for (int idx = tid; idx < F * F; idx += 256) {
-      const int i = idx / F, jj = idx - i * F;
-      Wl[i * LD + jj] = (i < f && jj < f) ? jb.W[(int64_t)jj * f + i] : 0.0;
+    // 16 loads per thread in flight at a time, coalesced down each column of W
+    for (int q0 = 0; q0 < F * F / 256; q0 += 16) {
+      double wq[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int idx = tid + 256 * (q0 + q);
+        const int jj = idx / F, i = idx - jj * F;
+        wq[q] = (i < f && jj < f) ? jb.W[(int64_t)jj * f + i] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int idx = tid + 256 * (q0 + q);
+        const int jj = idx / F, i = idx - jj * F;
+        Wl[i * LD + jj] = wq[q];
+      }
     }
   }
   double a[KS];
@@ -3570,6 +3582,82 @@ __global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
 #pragma unroll
   for (int u = 0; u < TT; ++u) {
     const int col = 16 * u + r;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = rbase + MF::row(g, e);
+      if (row < jb.rows) Z[(zoff + col) * jb.ldz + row] = (T)z[u][e];
+    }
+  }
+}
+
+// k_apply for 64 < f <= 128 with the output columns split over workgroups
+// (blockIdx.z: a slice of 32), each staging only its 32 columns of W (33 KB
+// of LDS instead of 132 KB, so four workgroups fit a CU and the FP64 MFMA
+// work spreads over four times as many CUs).  Each output element is
+// formed by the same MFMA sequence as in k_apply, so the results are bit
+// for bit the same.  Z must not alias X (a slice would overwrite columns
+// another slice still reads).
+template <typename T, int F>
+__global__ __launch_bounds__(256) void k_apply_cols(ApplyJob j0, ApplyJob j1,
+                                                    const int32_t* __restrict__ stop_block, int block_id,
+                                                    Gate gate) {
+  typedef Mfma<double> MF;
+  constexpr int CW = 32, TC = CW / 16, LDC = CW + 1, KS = F / 4;
+  if (stop_block && *stop_block < block_id) return;
+  if (gate_shut(gate)) return;
+  const ApplyJob jb = blockIdx.y == 0 ? j0 : j1;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  if (row0 >= jb.rows) return;
+  const int f = jb.f_dev ? (int)*jb.f_dev : jb.f;
+  if (f > F) return;                    // cannot happen: the launch width bounds the rank
+  const int ncols = jb.f_dev ? f : (jb.ncols_dev ? jb.ncols_dev[block_id] : jb.ncols);
+  const int c0 = (int)blockIdx.z * CW;
+  if (c0 >= ncols) return;
+  const int64_t zoff = jb.zoff_dev ? jb.zoff_dev[block_id] : jb.zoff;
+  __shared__ double Wl[F * LDC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
+  const T* X = reinterpret_cast<const T*>(jb.X);
+  T* Z = reinterpret_cast<T*>(jb.Z);
+  const int64_t rbase = row0 + 16 * wv;
+  const int64_t arow = rbase + r;
+  const bool aok = arow < jb.rows;
+  T xa[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const int k = 4 * kk + g;
+    xa[kk] = (aok && k < f) ? X[(int64_t)k * jb.ldx + arow] : (T)0;
+  }
+  {                                     // W's slice: all loads in flight, coalesced down each column
+    constexpr int NQ = F * CW / 256;
+    double wq[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int idx = tid + 256 * q;
+      const int jj = idx / F, i = idx - jj * F;
+      wq[q] = (i < f && c0 + jj < f) ? jb.W[(int64_t)(c0 + jj) * f + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int idx = tid + 256 * q;
+      const int jj = idx / F, i = idx - jj * F;
+      Wl[i * LDC + jj] = wq[q];
+    }
+  }
+  double a[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) a[kk] = (double)xa[kk];
+  __syncthreads();
+  typename MF::acc_t z[TC];
+#pragma unroll
+  for (int u = 0; u < TC; ++u) z[u] = MF::zero();
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+    for (int u = 0; u < TC; ++u) z[u] = MF::op(a[kk], Wl[(4 * kk + g) * LDC + 16 * u + r], z[u]);
+#pragma unroll
+  for (int u = 0; u < TC; ++u) {
+    const int col = c0 + 16 * u + r;
     if (col >= ncols) continue;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {

@@ -245,6 +245,7 @@ struct WS {
   void* wpart;          // s_proj x ldw x bn
   void* w;              // ldw x bn
   double* gpart;        // Gram partials (max(s_gram,16) x bn x bn)
+  void* wfp;            // W = Q^T Y partials of the one-launch block Gram-Schmidt
   double* gsum;         // summed block Gram (bn x bn)
   double* r1;           // bn x bn
   double* r2;
@@ -296,6 +297,7 @@ WS carve(void* base, const Geo& g) {
   w.wpart = c.take<char>((int64_t)g.s_proj * ldw_of(g) * g.bn * e);
   w.w = c.take<char>(ldw_of(g) * g.bn * e);
   w.gpart = c.take<double>((int64_t)std::max(g.s_gram, 64) * g.bn * g.bn);
+  w.wfp = c.take<char>((int64_t)CQR2_GMAX * CQR2_PROJ_WMAX * 32 * e);   // W partials of the one-launch BCGS2
   w.gsum = c.take<double>((int64_t)g.bn * g.bn);
   w.r1 = c.take<double>(g.bn * g.bn);
   w.r2 = c.take<double>(g.bn * g.bn);
@@ -723,12 +725,17 @@ bool cqr2_fits(int64_t rows, int64_t f) {
 }
 
 template <typename T>
-int cqr2(eodabe_ctx* ctx, hipStream_t st, const Cqr2Args& a) {
+int cqr2(eodabe_ctx* ctx, hipStream_t st, const Cqr2Args& a, bool proj = false) {
   const int64_t fb = a.f;                          // the launch width (the bound of f_dev)
   if (!cqr2_fits(a.rows, fb)) return EODABE_EINVAL;
   const dim3 grid((unsigned)cdiv(a.rows, CQR2_RPW));
-  if (fb <= 16) hipLaunchKernelGGL((k_cqr2<T, 16>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((k_cqr2<T, 32>), grid, dim3(256), 0, st, a);
+  if (proj) {
+    if (fb <= 16) hipLaunchKernelGGL((k_cqr2<T, 16, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_cqr2<T, 32, true>), grid, dim3(256), 0, st, a);
+  } else {
+    if (fb <= 16) hipLaunchKernelGGL((k_cqr2<T, 16, false>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_cqr2<T, 32, false>), grid, dim3(256), 0, st, a);
+  }
   LAUNCHCHK();
   return 0;
 }
@@ -1054,6 +1061,40 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
         a.Q = q;
         a.ldq = g.ldy;
         TRY(cqr2<T>(ctx, st, a));
+        continue;
+      }
+      if (j > 0 && cqr2_fits(g.mm, f) && !g.paired && wmax <= CQR2_PROJ_WMAX) {
+        // later blocks while the basis is narrow: both BCGS2 projections,
+        // both CholeskyQR2 passes, the stop test and the append in one launch
+        Cqr2Args a{};
+        a.X = y;
+        a.ldx = g.ldy;
+        a.rows = g.mm;
+        a.f = f;
+        a.parts = w.gpart;
+        a.counter = &w.st->counter[3];       // shared by these launches, reset by each one's last workgroup
+        a.reuse_counter = 1;
+        a.stop_block = stopb;
+        a.block_id = blk;
+        a.st = w.st;
+        a.R1 = w.r1;
+        a.R1inv = w.r1inv;
+        a.R2 = w.r2;
+        a.R2inv = w.r2inv;
+        a.dead = deadj;
+        a.stop_test = 1;
+        a.col0 = col0;
+        a.n = g.nn;
+        a.wlog = w.wlog;
+        a.acc = w.accv;
+        a.diag_log = w.diag_log;
+        a.Q = q;
+        a.ldq = g.ldy;
+        a.Qb = q;
+        a.ldqb = g.ldy;
+        a.w_dev = w.wlog + j;
+        a.wparts = w.wfp;
+        TRY(cqr2<T>(ctx, st, a, true));
         continue;
       }
       for (int pass = 0; pass < 2; ++pass) {

@@ -44,7 +44,9 @@ struct State {
   int32_t floored;       // a pivot was floored in the closing QRs
   int32_t paired;        // complex input (realified): stops only at pair-leading columns
   int64_t rank;          // basis width after the latest decided block
-  uint32_t counter[8];   // arrival counters (reset by the last arriving workgroup)
+  uint32_t counter[8];   // arrival counters: [0] the Gram kernels' (reset by their last workgroup); [1] block 0's and
+                         // [2] the closing's one-launch CholeskyQR2 (one launch each, zeroed here); [3] the later blocks'
+                         // (shared, reset by the last workgroup out)
   double lp_scale;       // power of two applied to A before rounding it to FP16 (1 for BF16)
   int32_t lp_mode;       // 0: none, 1: FP16, 2: BF16 (low-precision sketch form)
   int32_t sync_fail;     // a barrier across workgroups timed out (outputs void)
@@ -3003,6 +3005,11 @@ __global__ __launch_bounds__(256) void k_gram_rows(
 // ---------------------------------------------------------------------------
 constexpr int CQR2_GMAX = 32;
 constexpr int CQR2_RPW = 256;
+// basis width up to which the projection runs in the launch: beyond it the
+// 16-32 workgroups' MFMA work on W = Q^T Y and Y -= Q W outweighs the
+// launches saved (at widths 160-256 on 4096 rows: 3-5 % slower than the
+// separate K-split kernels on the whole GPU)
+constexpr int CQR2_PROJ_WMAX = 128;
 constexpr uint64_t CQR2_WAIT_TICKS = 1ull << 27;
 
 __device__ __forceinline__ void grid_barrier(uint32_t* ctr, uint32_t target, State* st) {
@@ -3065,6 +3072,14 @@ struct Cqr2Args {
   int64_t ldu, m_u;
   State* state_out;          // non-null (host-mapped): workgroup 0 copies the control block there
                              // once it is final, whether the gate let the closing run or not
+  // block Gram-Schmidt against the basis before each pass (the PROJ form):
+  // W = Qb^T Y, Y -= Qb W with Qb the basis (rows x wb, element (i,c) at
+  // c*ldqb + i) and wb = *w_dev <= CQR2_PROJ_WMAX
+  const void* Qb;
+  int64_t ldqb;
+  const int64_t* w_dev;
+  void* wparts;              // CQR2_GMAX * CQR2_PROJ_WMAX * F elements of T: the partial W per workgroup
+  int reuse_counter;         // the last workgroup out resets the counter (launches that share one)
 };
 
 // The control block into host-mapped memory (thread 0 of workgroup 0): an
@@ -3078,15 +3093,18 @@ __device__ __forceinline__ void state_send(const Cqr2Args& a) {
   for (int i = 0; i < (int)(sizeof(State) / 8); ++i) dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T, int F>
+template <typename T, int F, bool PROJ = false>
 struct Cqr2Cfg {
   typedef SmallCfg<F> S;
+  static constexpr int LDW = F + 1;                                 // folded W, row stride (T elements)
+  static constexpr int WMAX = CQR2_PROJ_WMAX;
+  static constexpr int WD = PROJ ? (WMAX * LDW * (int)sizeof(T) + 7) / 8 : 0;
   static constexpr int LDX = CQR2_RPW + 16 / (int)sizeof(T);      // panel column stride (T elements)
   static constexpr int XD = (F * LDX * (int)sizeof(T) + 7) / 8;    // panel, in doubles
   static constexpr int RED = (F / 16) * (F / 16) * 256;             // wave fold of a partial Gram
   static constexpr int CH = 2 * S::SIZE + 24 * F + F;               // G/R, R^{-1}, elimination rows, diagonal
   static constexpr int WORK = RED > CH ? RED : CH;
-  static constexpr int TOTAL = XD + WORK + F + 8 + S::SIZE;         // + R1's diagonal + scalars + R1
+  static constexpr int TOTAL = XD + WORK + F + 8 + S::SIZE + WD;    // + R1's diagonal + scalars + R1 + W
   static_assert(XD >= 3 * S::SIZE, "the closing QR's three work matrices fit the panel area");
 };
 
@@ -3108,10 +3126,10 @@ struct Cqr2Cfg {
 // order and MFMA sequences.  Workgroup 0 alone writes R1, R2, their
 // inverses, the dead flags, the floors and the state.
 // ---------------------------------------------------------------------------
-template <typename T, int F>
+template <typename T, int F, bool PROJ>
 __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
   typedef Mfma<double> MF;
-  typedef Cqr2Cfg<T, F> Cfg;
+  typedef Cqr2Cfg<T, F, PROJ> Cfg;
   typedef SmallCfg<F> S;
   constexpr int TT = F / 16, RPW = CQR2_RPW, LDX = Cfg::LDX, LD = S::LD, PW = RPW / 4, KS = F / 4;
   static_assert(F <= 32, "register budget of the Gram tiles");
@@ -3133,6 +3151,7 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
   double* r1d = lds + Cfg::XD + Cfg::WORK;       // R1's diagonal
   int* sx = reinterpret_cast<int*>(r1d + F);
   double* R1s = r1d + F + 8;                     // R1 (the closing QR needs all of it)
+  T* Ws = reinterpret_cast<T*>(R1s + S::SIZE);   // PROJ: the folded W, Ws[a*LDW + c]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
   const T* X = reinterpret_cast<const T*>(a.X);
   const int64_t rb = (int64_t)blockIdx.x * RPW;
@@ -3179,8 +3198,117 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
   uint64_t dmask = 0;
   double eps_l = 0.0;
   bool nonf_l = false;
+  unsigned bars = 0;                             // barriers passed (their arrival targets are multiples of G)
+  const int wb = PROJ ? (int)*a.w_dev : 0;       // basis width (uniform; <= Cfg::WMAX by the host's bound)
   for (int pass = 0; pass < 2; ++pass) {
     __syncthreads();                             // panel (pass 1: Z1) complete
+    if constexpr (PROJ) {
+      if (wb > 0 && wb <= Cfg::WMAX) {
+        // block Gram-Schmidt: W = Qb^T Y over all rows, Y -= Qb W
+        typedef Mfma<T> MT;
+        constexpr int LDW = Cfg::LDW, NCH = RPW / 16;
+        const T* Qb = reinterpret_cast<const T*>(a.Qb);
+        T* WP = reinterpret_cast<T*>(a.wparts);
+        T* myWP = WP + (int64_t)blockIdx.x * CQR2_PROJ_WMAX * F;
+        const int TA = (wb + 15) / 16;
+        // (1) this panel's W_g = Q_g^T Y_g (T-precision MFMA), tile (ta, tc)
+        //     per wave in turn; the 16-row chunks' Q loads all in flight
+        for (int tile = wv; tile < TA * TT; tile += 4) {
+          const int ta = tile / TT, tc = tile - ta * TT;
+          const int acol = 16 * ta + r;
+          const bool aok = acol < wb;
+          const T* qc = Qb + (int64_t)(aok ? acol : 0) * a.ldqb + rb;
+          typename MT::acc_t acc = MT::zero();
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            V4<T> q4[NCH / 2];
+#pragma unroll
+            for (int c8 = 0; c8 < NCH / 2; ++c8) {
+              const int ch = h * (NCH / 2) + c8;
+              const int64_t r0 = rb + 16 * ch + 4 * g;       // this lane's four rows
+              if (aok && r0 + 3 < a.rows) {
+                q4[c8] = ld4(qc + 16 * ch + 4 * g);
+              } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) q4[c8].v[t] = (aok && r0 + t < a.rows) ? qc[16 * ch + 4 * g + t] : (T)0;
+              }
+            }
+#pragma unroll
+            for (int c8 = 0; c8 < NCH / 2; ++c8) {
+              const int ch = h * (NCH / 2) + c8;
+#pragma unroll
+              for (int t = 0; t < 4; ++t)
+                acc = MT::op(q4[c8].v[t], pan[(16 * tc + r) * LDX + 16 * ch + 4 * g + t], acc);
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int am = 16 * ta + MT::row(g, e), cn = 16 * tc + r;
+            if (am < wb && cn < f) myWP[am * F + cn] = (T)acc[e];
+          }
+        }
+        grid_barrier(a.counter, (++bars) * G, st);
+        // (2) W = sum of the G partials in order g = 0, 1, ... (every
+        //     workgroup the same), four consecutive columns per load; a
+        //     thread takes its groups of four one after another, sixteen
+        //     partials' loads in flight
+        {
+          const int nq = wb * (F / 4);                 // groups of four elements of W
+          for (int qi = tid; qi < nq; qi += 256) {
+            V4<T> sw;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sw.v[e] = (T)0;
+            for (unsigned g0 = 0; g0 < G; g0 += 16) {
+              V4<T> v[16];
+#pragma unroll
+              for (int i = 0; i < 16; ++i) {
+                if (g0 + i < G) {
+                  v[i] = ld4(WP + (int64_t)(g0 + i) * CQR2_PROJ_WMAX * F + 4 * qi);
+                } else {
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) v[i].v[e] = (T)0;
+                }
+              }
+#pragma unroll
+              for (int i = 0; i < 16; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sw.v[e] += v[i].v[e];
+            }
+            const int am = qi / (F / 4), c4 = 4 * (qi - am * (F / 4));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Ws[am * LDW + c4 + e] = (c4 + e < f) ? sw.v[e] : (T)0;
+          }
+        }
+        __syncthreads();
+        // (3) Y_g -= Q_g W in place: wave wv takes output tiles (row tile,
+        //     column tile) in turn, K = wb in steps of 4, eight steps' loads
+        //     in flight
+        for (int tile = wv; tile < NCH * TT; tile += 4) {
+          const int rt = tile / TT, tc = tile - rt * TT;
+          const int64_t row = rb + 16 * rt + r;
+          const bool rok = row < a.rows;
+          typename MT::acc_t acc = MT::zero();
+          for (int s0 = 0; s0 < wb; s0 += 32) {
+            T qv[8], wv8[8];
+#pragma unroll
+            for (int st8 = 0; st8 < 8; ++st8) {
+              const int ak = s0 + 4 * st8 + g;
+              const bool kok = ak < wb;
+              qv[st8] = (kok && rok) ? Qb[(int64_t)ak * a.ldqb + row] : (T)0;
+              wv8[st8] = kok ? Ws[ak * LDW + 16 * tc + r] : (T)0;
+            }
+#pragma unroll
+            for (int st8 = 0; st8 < 8; ++st8) acc = MT::op(qv[st8], wv8[st8], acc);
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int lr = 16 * rt + MT::row(g, e), cc = 16 * tc + r;
+            pan[cc * LDX + lr] = (T)(pan[cc * LDX + lr] - acc[e]);
+          }
+        }
+        __syncthreads();
+      }
+    }
     typename MF::acc_t acc[TT][TT];
 #pragma unroll
     for (int t = 0; t < TT; ++t)
@@ -3228,7 +3356,7 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
         Pw[(int64_t)i * f + jj] = v;
       }
     }
-    grid_barrier(a.counter, (unsigned)(pass + 1) * G, st);
+    grid_barrier(a.counter, (++bars) * G, st);
     constexpr int EPT = (F * F + 255) / 256;
     double sum[EPT];                             // G's upper triangle, kept for a second Cholesky
     {                                            // all partials, upper triangle, order b = 0, 1, ...
@@ -3413,6 +3541,9 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
         if (row < a.rows) Q[(zoff + col) * a.ldq + row] = (T)z[u][e];
       }
     }
+  }
+  if (a.reuse_counter && tid == 0) {            // every workgroup is past its last barrier: reset for the next launch
+    if (atomicAdd(a.counter, 1u) == (bars + 1) * G - 1) atomicExch(a.counter, 0u);
   }
   if (!a.close_qr) return;
   // closing QR (Alg. 2, QR(R^T)), redundantly on every workgroup

@@ -5,6 +5,7 @@
 // workspace and enqueues.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
+#include <cstdlib>
 
 #include <algorithm>
 #include <chrono>
@@ -43,6 +44,7 @@ struct eodabe_ctx {
   int last_hip;
   State* host_state;      // pinned host copy of the control block
   State* host_state_dev;  // its device address (null: copied by hipMemcpyAsync only)
+  bool barrier_fail = false;  // EODABE_TEST_BARRIER_FAIL set at creation: every grid barrier times out (tests)
   int64_t* host_wlog;     // pinned host copy of the basis-width log
   int64_t host_wlog_cap;
   bool host_only;
@@ -725,9 +727,14 @@ bool cqr2_fits(int64_t rows, int64_t f) {
 }
 
 template <typename T>
-int cqr2(eodabe_ctx* ctx, hipStream_t st, const Cqr2Args& a, bool proj = false) {
-  const int64_t fb = a.f;                          // the launch width (the bound of f_dev)
-  if (!cqr2_fits(a.rows, fb)) return EODABE_EINVAL;
+int cqr2(eodabe_ctx* ctx, hipStream_t st, const Cqr2Args& a_in, bool proj = false) {
+  const int64_t fb = a_in.f;                       // the launch width (the bound of f_dev)
+  if (!cqr2_fits(a_in.rows, fb)) return EODABE_EINVAL;
+  Cqr2Args a = a_in;
+  if (ctx->barrier_fail) {                         // 10 us waits for an arrival that never comes
+    a.wait_extra = 1;
+    a.wait_ticks = 1000;
+  }
   const dim3 grid((unsigned)cdiv(a.rows, CQR2_RPW));
   if (proj) {
     if (fb <= 16) hipLaunchKernelGGL((k_cqr2<T, 16, true>), grid, dim3(256), 0, st, a);
@@ -1962,6 +1969,11 @@ int eodabe_create(eodabe_ctx** out, const eodabe_opts* opts) {
   if (hipHostMalloc((void**)&c->host_state, sizeof(State), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return EODABE_EHIP;
+  }
+  // test of the barrier time-out path (EODABE_ESYNC) without a stuck device
+  {
+    const char* e = std::getenv("EODABE_TEST_BARRIER_FAIL");
+    c->barrier_fail = e && e[0] == '1';
   }
   // the fused closing kernel can then write the control block there itself
   if (hipHostGetDevicePointer((void**)&c->host_state_dev, c->host_state, 0) != hipSuccess) {

@@ -3012,7 +3012,8 @@ constexpr int CQR2_RPW = 256;
 constexpr int CQR2_PROJ_WMAX = 128;
 constexpr uint64_t CQR2_WAIT_TICKS = 1ull << 27;
 
-__device__ __forceinline__ void grid_barrier(uint32_t* ctr, uint32_t target, State* st) {
+__device__ __forceinline__ void grid_barrier(uint32_t* ctr, uint32_t target, State* st,
+                                             uint64_t wait_ticks = CQR2_WAIT_TICKS) {
   wg_stores_done();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -3020,7 +3021,7 @@ __device__ __forceinline__ void grid_barrier(uint32_t* ctr, uint32_t target, Sta
     const uint64_t t0 = wall_clock64();
     while (atomicAdd(ctr, 0u) < target) {        // a read-modify-write: the device-coherent value
       __builtin_amdgcn_s_sleep(1);
-      if (wall_clock64() - t0 > CQR2_WAIT_TICKS) {
+      if (wall_clock64() - t0 > wait_ticks) {
         atomicMax(&st->sync_fail, 1);
         break;
       }
@@ -3080,6 +3081,11 @@ struct Cqr2Args {
   const int64_t* w_dev;
   void* wparts;              // CQR2_GMAX * CQR2_PROJ_WMAX * F elements of T: the partial W per workgroup
   int reuse_counter;         // the last workgroup out resets the counter (launches that share one)
+  // failure injection for the tests of the time-out path: every barrier
+  // waits for one arrival more than the launch makes, for at most
+  // wait_ticks, so each one times out and every wave still ends
+  uint32_t wait_extra;
+  uint64_t wait_ticks;       // 0: CQR2_WAIT_TICKS
 };
 
 // The control block into host-mapped memory (thread 0 of workgroup 0): an
@@ -3199,6 +3205,7 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
   double eps_l = 0.0;
   bool nonf_l = false;
   unsigned bars = 0;                             // barriers passed (their arrival targets are multiples of G)
+  const uint64_t wticks = a.wait_ticks ? a.wait_ticks : CQR2_WAIT_TICKS;
   const int wb = PROJ ? (int)*a.w_dev : 0;       // basis width (uniform; <= Cfg::WMAX by the host's bound)
   for (int pass = 0; pass < 2; ++pass) {
     __syncthreads();                             // panel (pass 1: Z1) complete
@@ -3247,7 +3254,7 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
             if (am < wb && cn < f) myWP[am * F + cn] = (T)acc[e];
           }
         }
-        grid_barrier(a.counter, (++bars) * G, st);
+        grid_barrier(a.counter, (++bars) * G + a.wait_extra, st, wticks);
         // (2) W = sum of the G partials in order g = 0, 1, ... (every
         //     workgroup the same), four consecutive columns per load; a
         //     thread takes its groups of four one after another, sixteen
@@ -3356,7 +3363,7 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
         Pw[(int64_t)i * f + jj] = v;
       }
     }
-    grid_barrier(a.counter, (++bars) * G, st);
+    grid_barrier(a.counter, (++bars) * G + a.wait_extra, st, wticks);
     constexpr int EPT = (F * F + 255) / 256;
     double sum[EPT];                             // G's upper triangle, kept for a second Cholesky
     {                                            // all partials, upper triangle, order b = 0, 1, ...

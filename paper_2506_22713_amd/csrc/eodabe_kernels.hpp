@@ -3127,10 +3127,18 @@ struct Cqr2Cfg {
 //           |T(c,c)| = R2(c,c) R1(c,c) <= eps ends the kept width (every
 //           workgroup takes the same decision); Q = Z1 R2^{-1} for the
 //           kept columns.
-// The arithmetic is that of the Gram kernel pair (k_gram_rows, modes 0 and
-// 1) and the apply (k_apply) it replaces: the same partial grouping, fold
-// order and MFMA sequences.  Workgroup 0 alone writes R1, R2, their
-// inverses, the dead flags, the floors and the state.
+// PROJ (a later block of the basis loop, basis width <= CQR2_PROJ_WMAX):
+// before each pass the panel is projected against the basis (block
+// Gram-Schmidt, BCGS2 over the two passes): W = Qb^T Y from per-workgroup
+// partials summed in a fixed order after a barrier, then Y -= Qb W in place.
+// close_qr (the closing of Alg. 2): after pass 1 every workgroup also runs
+// the QR of R^T = (R2 R1)^T on its own LDS (the steps of k_small_qr) and
+// forms its rows of U = Uq Qh.
+// The arithmetic is that of the kernels it replaces (k_gram_rows modes 0
+// and 1, k_apply, k_small_qr; for PROJ the K-split projection and update up
+// to the grouping of the partial sums): the same fold order and MFMA
+// sequences.  Workgroup 0 alone writes R1, R2, their inverses, the dead
+// flags, the floors and the state.
 // ---------------------------------------------------------------------------
 template <typename T, int F, bool PROJ>
 __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {

@@ -81,6 +81,9 @@ constexpr int BN_MAX = 128;
 
 inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 inline int64_t cdiv(int64_t x, int64_t a) { return (x + a - 1) / a; }
+// Workgroups of a Gram kernel of the basis loop (one row panel each up to
+// this; the partial buffer holds that many)
+constexpr int GRAM_LOOP_WG = 128;
 
 // K-chunk (multiple of 16) and the number of non-empty splits actually
 // launched for a reduction of length K asked to use `want` splits.  Every
@@ -246,7 +249,7 @@ struct WS {
   void* y;              // ldy x bn
   void* wpart;          // s_proj x ldw x bn
   void* w;              // ldw x bn
-  double* gpart;        // Gram partials (max(s_gram,16) x bn x bn)
+  double* gpart;        // Gram partials (max(s_gram, GRAM_LOOP_WG) x bn x bn)
   void* wfp;            // W = Q^T Y partials of the one-launch block Gram-Schmidt
   double* gsum;         // summed block Gram (bn x bn)
   double* r1;           // bn x bn
@@ -298,7 +301,7 @@ WS carve(void* base, const Geo& g) {
   w.y = c.take<char>(g.ldy * g.bn * e);
   w.wpart = c.take<char>((int64_t)g.s_proj * ldw_of(g) * g.bn * e);
   w.w = c.take<char>(ldw_of(g) * g.bn * e);
-  w.gpart = c.take<double>((int64_t)std::max(g.s_gram, 64) * g.bn * g.bn);
+  w.gpart = c.take<double>((int64_t)std::max(g.s_gram, GRAM_LOOP_WG) * g.bn * g.bn);
   w.wfp = c.take<char>((int64_t)CQR2_GMAX * CQR2_PROJ_WMAX * 32 * e);   // W partials of the one-launch BCGS2
   w.gsum = c.take<double>((int64_t)g.bn * g.bn);
   w.r1 = c.take<double>(g.bn * g.bn);
@@ -758,14 +761,15 @@ int cqr2(eodabe_ctx* ctx, hipStream_t st, const Cqr2Args& a_in, bool proj = fals
 template <typename T>
 int gram_chol(eodabe_ctx* ctx, hipStream_t st, const WS& w, T* X, int64_t ld, int64_t rows, int f,
               double* parts, const CholArgs& ca, const int32_t* stopb = nullptr, int blk = 0,
-              const double* W = nullptr) {
+              const double* W = nullptr, int64_t max_wg = 64) {
   if (f <= 0) return 0;
   if (f <= 64) {
     uint32_t* counter = &w.st->counter[0];
+    const int64_t cap = max_wg;
 #define GRAM_CASE(FF, MM)                                                                            \
   do {                                                                                               \
     const int64_t npan = cdiv(rows, GramCfg<T, FF, MM>::RPW);                                        \
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(npan, 64));               \
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(npan, cap));              \
     hipLaunchKernelGGL((k_gram_rows<T, FF, MM>), dim3(grid), dim3(256), 0, st, X, ld, rows, f, W,    \
                        parts, counter, stopb, blk, ca);                                              \
   } while (0)
@@ -1138,7 +1142,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
         // normalised block (re-orthogonalisation needs that order).
         const bool fuse = small && j == 0;
         TRY(gram_chol<T>(ctx, st, w, y, g.ldy, g.mm, f, w.gpart, ca, stopb, blk,
-                         (fuse && pass == 1) ? w.r1inv : nullptr));
+                         (fuse && pass == 1) ? w.r1inv : nullptr, GRAM_LOOP_WG));
         if (pass == 0 && mid && !fuse) {
           const ApplyJob a{y, g.ldy, y, g.ldy, w.r1inv, g.mm, 0, f, f, nullptr, nullptr, nullptr};
           TRY(ops.apply(a, nullptr, f, stopb, blk));

@@ -83,7 +83,7 @@ inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 inline int64_t cdiv(int64_t x, int64_t a) { return (x + a - 1) / a; }
 // Workgroups of a Gram kernel of the basis loop (one row panel each up to
 // this; the partial buffer holds that many)
-constexpr int GRAM_LOOP_WG = 128;
+constexpr int GRAM_LOOP_WG = 192;
 
 // K-chunk (multiple of 16) and the number of non-empty splits actually
 // launched for a reduction of length K asked to use `want` splits.  Every

@@ -249,18 +249,48 @@ class Context:
         return torch.empty(nb, dtype=torch.uint8, device="cuda")
 
 
-@dataclass
 class Factorization:
-    U: torch.Tensor       # m x r view (columns orthonormal)
-    D: torch.Tensor       # r x r upper triangular
-    Vt: torch.Tensor      # r x n
-    rank: int
-    blocks: int
-    eps: float
-    norm_a: float
-    status: int
-    flags: int
-    relres_est: float = 0.0   # |T(l,l)| / ||A||_F at the stopping column (0: no stop)
+    """Result of factor(): A ~= U D Vt with U m x r (columns orthonormal), D
+    r x r upper triangular and Vt r x n, views into the output buffers
+    (Ut r_cap x m, core, Vt r_cap x n).  The views are made on first access:
+    each costs the host microseconds, and back-to-back calls that only read
+    the rank would otherwise keep the GPU waiting for them."""
+    __slots__ = ("_bufs", "_views", "rank", "blocks", "eps", "norm_a", "status", "flags", "relres_est")
+
+    def __init__(self, bufs, rank: int, blocks: int, eps: float, norm_a: float, status: int, flags: int,
+                 relres_est: float = 0.0):
+        self._bufs = bufs                  # (Ut, core, Vt) output buffers
+        self._views = None
+        self.rank = rank
+        self.blocks = blocks
+        self.eps = eps
+        self.norm_a = norm_a
+        self.status = status
+        self.flags = flags
+        self.relres_est = relres_est       # |T(l,l)| / ||A||_F at the stopping column (0: no stop)
+
+    def _view(self, k: int) -> torch.Tensor:
+        if self._views is None:
+            Ut, core, Vt = self._bufs
+            r = self.rank
+            self._views = (Ut[:r].T, core[:r, :r], Vt[:r])
+        return self._views[k]
+
+    @property
+    def U(self) -> torch.Tensor:
+        return self._view(0)
+
+    @property
+    def D(self) -> torch.Tensor:
+        return self._view(1)
+
+    @property
+    def Vt(self) -> torch.Tensor:
+        return self._view(2)
+
+    def __repr__(self) -> str:
+        return (f"Factorization(rank={self.rank}, blocks={self.blocks}, eps={self.eps:g}, "
+                f"norm_a={self.norm_a:g}, status={self.status}, flags={self.flags})")
 
 
 def _check_matrix(A: torch.Tensor, dtype: torch.dtype):
@@ -297,8 +327,8 @@ def factor(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int =
                             Ut.data_ptr(), core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
     ctx._check(st, "eodabe_factor")
     r = int(info.rank)
-    return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
-                         float(info.norm_a), st, int(info.status_flags), float(info.relres_est))
+    return Factorization((Ut, core, Vt), r, int(info.blocks), float(info.eps), float(info.norm_a), st,
+                         int(info.status_flags), float(info.relres_est))
 
 
 def factor_complex(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int = 0,
@@ -328,8 +358,8 @@ def factor_complex(A: torch.Tensor, tol: float, ctx: Context | None = None, r_ca
                                     Ut.data_ptr(), core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
     ctx._check(st, "eodabe_factor_complex")
     r = int(info.rank)
-    return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
-                         float(info.norm_a), st, int(info.status_flags), float(info.relres_est))
+    return Factorization((Ut, core, Vt), r, int(info.blocks), float(info.eps), float(info.norm_a), st,
+                         int(info.status_flags), float(info.relres_est))
 
 
 def factor_noalloc(A: torch.Tensor, tol: float, ctx: Context, out, r_cap: int = 0) -> Factorization:
@@ -346,8 +376,8 @@ def factor_noalloc(A: torch.Tensor, tol: float, ctx: Context, out, r_cap: int = 
                                     core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
     ctx._check(st, "eodabe_factor_noalloc")
     r = int(info.rank)
-    return Factorization(Ut[:r].T, core[:r, :r], Vt[:r], r, int(info.blocks), float(info.eps),
-                         float(info.norm_a), st, int(info.status_flags), float(info.relres_est))
+    return Factorization((Ut, core, Vt), r, int(info.blocks), float(info.eps), float(info.norm_a), st,
+                         int(info.status_flags), float(info.relres_est))
 
 
 @dataclass

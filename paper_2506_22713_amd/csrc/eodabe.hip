@@ -911,9 +911,17 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   Ops<T> ops{ctx, st};
   const uint32_t k0 = (uint32_t)(ctx->o.seed & 0xffffffffu), k1 = (uint32_t)(ctx->o.seed >> 32);
   const int nwlog = (int)(g.nblk + 2);
-  hipLaunchKernelGGL(k_init_state, dim3(64), dim3(256), 0, st, w.st, tol, w.wlog, nwlog, w.dead,
-                     (int64_t)(g.nblk + 1) * BN_MAX, w.accv, (int)(g.nblk + 1), g.lp, g.paired ? 1 : 0);
-  LAUNCHCHK();
+  const bool learned = g.wide && ctx->pred_params != nullptr;
+  // The reset of the control block rides on block 0's tiled Omega launch when
+  // that is the first launch (ungated), else it is a launch of its own.
+  StateInit init{w.st, tol, w.wlog, nwlog, w.dead, (int64_t)(g.nblk + 1) * BN_MAX, w.accv, (int)(g.nblk + 1),
+                 g.lp, g.paired ? 1 : 0};
+  if (!(g.sk_rows && !learned && g.nn > 0)) {
+    hipLaunchKernelGGL(k_init_state, dim3(64), dim3(256), 0, st, init.st, init.tol, init.wlog, init.nwlog,
+                       init.dead, init.ndead, init.acc, init.nacc, init.lp_mode, init.paired);
+    LAUNCHCHK();
+    init.st = nullptr;
+  }
   T* omega = (T*)w.omega;
   T* y = (T*)w.y;
   T* q = (T*)w.q;
@@ -931,7 +939,6 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
   // values (device) and returns a width d0; the blocks up to column d0 then
   // take their sketches from one wide pass over A (WIDE_COLS columns at a
   // time) and are orthogonalised as usual; past d0 the plain loop resumes.
-  const bool learned = g.wide && ctx->pred_params != nullptr;
   ctx->pred_last = {};
   bool probed = !learned;
   int64_t pred_end = 0;                 // warm-start end column (exclusive)
@@ -980,7 +987,7 @@ int run_basis(eodabe_ctx* ctx, hipStream_t st, const Geo& g, const WS& w, const 
         if (rows_blk) {
           dim3 grid((unsigned)cdiv(cdiv(rup(g.nn, 16), 4), 256), g.bn);
           hipLaunchKernelGGL((k_omega_tiled<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.bn / 16,
-                             omega, stopb, blk);
+                             omega, stopb, blk, j == 0 ? init : StateInit{});
         } else if (g.paired) {
           dim3 grid((unsigned)cdiv(g.ldk, 256), f);
           hipLaunchKernelGGL((k_omega_paired<T>), grid, dim3(256), 0, st, k0, k1, g.nn, col0, f, g.ldk, omega,
@@ -2436,7 +2443,7 @@ int eodabe_sketch(eodabe_ctx* ctx, const void* A, int64_t m, int64_t n, int64_t 
     if (rows) {
       dim3 grid((unsigned)cdiv(cdiv(rup(n, 16), 4), 256), (unsigned)bn);
       hipLaunchKernelGGL((k_omega_tiled<T>), grid, dim3(256), 0, st, k0, k1, n, col0, (int)ncols, (int)(bn / 16),
-                         om, nullptr, 0);
+                         om, nullptr, 0, StateInit{});
     } else {
       dim3 grid((unsigned)cdiv(cdiv(ldk, 4), 256), (unsigned)bn);
       hipLaunchKernelGGL((k_omega<T>), grid, dim3(256), 0, st, k0, k1, n, col0, (int)ncols, ldk, om,

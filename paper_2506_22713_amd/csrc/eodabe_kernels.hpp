@@ -54,6 +54,34 @@ struct State {
 };
 static_assert(sizeof(State) % 8 == 0, "the control block is copied in 8-byte words");
 
+// The reset of the control block and the per-block logs at the start of a
+// factorization; thread t of nt threads in all clears its share.
+struct StateInit {
+  State* st;                 // null: nothing to reset
+  double tol;
+  int64_t* wlog;
+  int nwlog;
+  int32_t* dead;
+  int64_t ndead;
+  int32_t* acc;
+  int nacc;
+  int lp_mode;
+  int paired;
+};
+
+__device__ __forceinline__ void init_state_part(const StateInit& a, int64_t t, int64_t nt) {
+  if (t == 0) {
+    State* st = a.st;
+    st->eps = 0.0; st->normsq = 0.0; st->tol = a.tol;
+    st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->paired = a.paired; st->rank = 0;
+    for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
+    st->lp_scale = 1.0; st->lp_mode = a.lp_mode; st->sync_fail = 0; st->d_stop = 0.0;
+  }
+  for (int64_t i = t; i < a.nwlog; i += nt) a.wlog[i] = 0;
+  for (int64_t i = t; i < a.ndead; i += nt) a.dead[i] = 0;
+  for (int64_t i = t; i < a.nacc; i += nt) a.acc[i] = 0;
+}
+
 // Low-precision copies of A for the sketch: IEEE binary16 or bfloat16,
 // both rounded to nearest even from FP32 and stored as 16-bit patterns.
 __device__ __forceinline__ uint16_t to_f16_bits(float x) {
@@ -176,12 +204,21 @@ __global__ void k_omega(uint32_t k0, uint32_t k1, int64_t n, int64_t col0, int n
 // contiguous.  Entries past n (up to the next multiple of 16) are zero.
 // Same values as k_omega (each entry a pure function of (seed, row, column)).
 // Grid: (ceil(rup(n, 16) / 4 / 256), 16 ct).
+// With init.st set (the first launch of a factorization, block 0, which no
+// stop can gate) the grid also resets the control block and the logs, as
+// k_init_state does, and reads no stop flag.
 template <typename T>
 __global__ void k_omega_tiled(uint32_t k0, uint32_t k1, int64_t n, int64_t col0, int ncols, int ct,
-                              T* __restrict__ out, const int32_t* __restrict__ stop_block, int block_id) {
-  if (stop_block && *stop_block < block_id) return;
+                              T* __restrict__ out, const int32_t* __restrict__ stop_block, int block_id,
+                              StateInit init) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
+  if (init.st) {
+    const int64_t nx = (int64_t)gridDim.x * blockDim.x;
+    init_state_part(init, j * nx + q, nx * gridDim.y);
+  } else if (stop_block && *stop_block < block_id) {
+    return;
+  }
   const int64_t n16 = (n + 15) / 16 * 16;
   if (4 * q >= n16 || j >= 16 * ct) return;
   float z[4] = {0.f, 0.f, 0.f, 0.f};
@@ -3918,16 +3955,8 @@ __global__ void k_finish_norm(const double* __restrict__ parts, const float* __r
 
 __global__ void k_init_state(State* st, double tol, int64_t* wlog, int nwlog, int32_t* dead,
                              int64_t ndead, int32_t* acc, int nacc, int lp_mode, int paired) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->eps = 0.0; st->normsq = 0.0; st->tol = tol;
-    st->stop_block = 0x7fffffff; st->nonfinite = 0; st->floored = 0; st->paired = paired; st->rank = 0;
-    for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
-    st->lp_scale = 1.0; st->lp_mode = lp_mode; st->sync_fail = 0; st->d_stop = 0.0;
-  }
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = t; i < nwlog; i += nt) wlog[i] = 0;
-  for (int64_t i = t; i < ndead; i += nt) dead[i] = 0;
-  for (int64_t i = t; i < nacc; i += nt) acc[i] = 0;
+  const StateInit a{st, tol, wlog, nwlog, dead, ndead, acc, nacc, lp_mode, paired};
+  init_state_part(a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 // Fill with zeros (graph-safe replacement for memset).

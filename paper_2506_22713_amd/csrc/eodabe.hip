@@ -329,7 +329,7 @@ WS carve(void* base, const Geo& g) {
   w.dg = c.take<double>(std::max<int64_t>(rc, g.bn) + 64);
   w.tbig = c.take<char>(std::max(g.ldy, g.ldk) * rc * std::max<size_t>(e, 8));
   w.sq128 = rb > 64 ? c.take<double>(7 * 128 * 128) : nullptr;
-  w.cbmask = c.take<uint64_t>(cdiv(rb, 64) + 1);
+  w.cbmask = c.take<uint64_t>(2 * (cdiv(rb, 64) + 1));   // per panel: nolive, then the dead masks
   if (g.wide) {
     w.omega_w = c.take<char>((int64_t)WIDE_COLS * g.ldk * e);
     w.ypart_w = c.take<char>((int64_t)g.s_sketch * g.ldy * WIDE_COLS * e);
@@ -689,7 +689,7 @@ CholArgs chol_args(const WS& w, double* R, int32_t* dead, int first, int fresh, 
 // R, R^{-1} column-major, leading dimension f; G overwritten by the Schur
 // complements): one workgroup on each diagonal block, the independent 64 x 64
 // block products of a step on separate workgroups, R^{-1} by recursive
-// doubling.  dg: f doubles; cbmask: one word per 64-column panel.
+// doubling.  dg: f doubles; cbmask: two words per 64-column panel.
 void cb_chol(hipStream_t st, double* G, int f, double* R, double* Rinv, double* dg, int32_t* dead,
              uint64_t* cbmask, int first_pass, int fresh, State* state, int count_floors,
              const int32_t* stopb = nullptr, int blk = 0) {
@@ -704,21 +704,20 @@ void cb_chol(hipStream_t st, double* G, int f, double* R, double* Rinv, double* 
                      R, Rinv, dg, dead, fresh, stopb, blk);
   hipLaunchKernelGGL(k_cb_diag, dim3(1), dim3(256), 0, st, G, f, f, 0, R, Rinv, dg, dead, cbmask, first_pass,
                      state, count_floors, stopb, blk);
+  uint64_t* deadmask = cbmask + P;        // dead flags found by the steps p >= 1
   for (int p = 0; p + 1 < P; ++p) {
-    hipLaunchKernelGGL(k_cb_row, dim3(P - p - 1), dim3(256), 0, st, G, f, f, p, R, Rinv, dead, cbmask, stopb,
-                       blk);
-    // trailing update of step p with the diagonal step p+1 on its workgroup 0
+    // R_p. and the trailing update of step p, the diagonal step p+1 on its workgroup 0
     hipLaunchKernelGGL(k_cb_look, dim3((P - p - 1) * (P - p) / 2), dim3(256), 0, st, G, f, f, p, R, Rinv, dg,
-                       dead, cbmask, first_pass, state, count_floors, stopb, blk);
+                       dead, cbmask, deadmask, first_pass, state, count_floors, stopb, blk);
   }
   for (int L = 1; L < P; L *= 2) {                       // R^{-1} by recursive doubling
     int nb = 0;
     for (int a = 0; a + L < P; a += 2 * L) nb += L * (std::min(a + 2 * L, P) - (a + L));
     if (L == 1) {
-      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 2, stopb, blk);
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 2, deadmask, dead, stopb, blk);
     } else {
-      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 0, stopb, blk);
-      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 1, stopb, blk);
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 0, deadmask, dead, stopb, blk);
+      hipLaunchKernelGGL(k_cb_inv, dim3(nb), dim3(256), 0, st, R, Rinv, G, f, f, L, 1, deadmask, dead, stopb, blk);
     }
   }
 }

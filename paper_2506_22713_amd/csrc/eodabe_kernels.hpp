@@ -2430,12 +2430,20 @@ __global__ __launch_bounds__(256) void k_small_qr128(const double* __restrict__ 
 //   k_cb_diag(p)    one workgroup: R_pp and R_pp^{-1} of the current Schur
 //                   block (floor rule against dg), dead flags of the panel,
 //                   mask of the pivots that did not eliminate -> nolive[p];
-//   k_cb_row(p)     workgroup q - p - 1: R_pq = R_pp^{-T} S_pq, masked;
-//   k_cb_look(p)    one workgroup per pair p < q <= r: S_qr -= R_pq^T R_pr;
-//                   workgroup 0 takes (p+1, p+1) in LDS and goes on with
-//                   the diagonal step p+1 while the others update the rest
-//                   (the next diagonal factorization overlaps this step's
-//                   trailing update);
+//   k_cb_look(p)    one workgroup per pair p < q <= r: it forms R_pq =
+//                   R_pp^{-T} S_pq and R_pr (rows of pivots that did not
+//                   eliminate and columns already dead zeroed) in LDS, and
+//                   S_qr -= R_pq^T R_pr; the pair (q, q) also writes R_pq
+//                   (every workgroup forms a block from the same operands
+//                   in the same order, so the copies agree bit for bit);
+//                   workgroup 0 takes (p+1, p+1) in LDS, writes R_{p,p+1}
+//                   and goes on with the diagonal step p+1 while the others
+//                   update the rest (the next diagonal factorization
+//                   overlaps this step's trailing update).  The dead flags
+//                   that step p+1 finds go to deadmask[p+1]: the other
+//                   workgroups of the launch still read the flags panel
+//                   p+1 had before, and no later step reads the new ones;
+//                   the first k_cb_inv launch writes them to dead;
 //   k_cb_inv(L, s)  R^{-1} by recursive doubling over groups of L = 1, 2,
 //                   4, ... blocks: for adjacent groups A = [a, a+L) and
 //                   C = [a+L, a+2L) (a = 0, 2L, ...) the block of rows A,
@@ -2444,7 +2452,8 @@ __global__ __launch_bounds__(256) void k_small_qr128(const double* __restrict__ 
 //                   C^{-1} into G (free after the factorization), stage 1
 //                   the blocks -A^{-1} T, stage 2 both for L = 1; one
 //                   workgroup per output block, log2(P) levels instead of
-//                   P - 1 dependent diagonals.
+//                   P - 1 dependent diagonals; stage 2 also writes the dead
+//                   flags of panels 1 .. P-1 from deadmask.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int cb_width(int f, int p) { return (f - 64 * p) < 64 ? f - 64 * p : 64; }
 
@@ -2494,34 +2503,32 @@ __global__ __launch_bounds__(256) void k_cb_diag(const double* __restrict__ G, i
   }
 }
 
-__global__ __launch_bounds__(256) void k_cb_row(const double* __restrict__ G, int ld, int f, int p,
-                                                double* __restrict__ R, const double* __restrict__ Rinv,
-                                                const int32_t* __restrict__ dead, const uint64_t* __restrict__ nolive,
-                                                const int32_t* __restrict__ stopb, int blk) {
-  if (stopb && *stopb < blk) return;       // a speculative block after the stop
-  const int q = p + 1 + blockIdx.x, k0 = 64 * p, c0 = 64 * q;
-  const int pw = cb_width(f, p), qw = cb_width(f, q);
-  const uint64_t nl = nolive[p];
-  __shared__ double sm[GMM64S_LDS];
-  // op(A)(i,k) = (R_pp^{-1})(k,i): column-major at (k0+i)*ld + k0+k
-  gmm64s<false, true>(Rinv + (int64_t)k0 * ld + k0, ld, G + (int64_t)c0 * ld + k0, ld, pw, qw, pw, sm,
-                      [&](int i, int j, double v) {
-                        const bool z = ((nl >> i) & 1ull) || dead[c0 + j] != 0;
-                        R[(int64_t)(c0 + j) * ld + k0 + i] = z ? 0.0 : v;
-                      });
-}
-
 __global__ __launch_bounds__(256) void k_cb_look(double* __restrict__ G, int ld, int f, int p,
                                                  double* __restrict__ R, double* __restrict__ Rinv,
-                                                 const double* __restrict__ dg, int32_t* __restrict__ dead,
-                                                 uint64_t* __restrict__ nolive, int first_pass, State* st,
-                                                 int count_floors, const int32_t* __restrict__ stopb, int blk) {
+                                                 const double* __restrict__ dg, const int32_t* __restrict__ dead,
+                                                 uint64_t* __restrict__ nolive, uint64_t* __restrict__ deadmask,
+                                                 int first_pass, State* st, int count_floors,
+                                                 const int32_t* __restrict__ stopb, int blk) {
   if (stopb && *stopb < blk) return;       // a speculative block after the stop
   typedef SmallCfg<64> S;
   constexpr int LD = S::LD;
+  static_assert(S::SIZE >= 64 * LD, "a 64 x 64 block per buffer");
   __shared__ double sm[GMM64S_LDS];
   __shared__ double Gs[S::SIZE], Ri[S::SIZE], work[24 * 64], dgs[64];
   const int k0 = 64 * p, pw = cb_width(f, p);
+  const uint64_t nl = nolive[p];
+  // R_pq = R_pp^{-T} S_pq with the masked entries zeroed, into dst (column j
+  // at dst + j*LD) and, if store, into R
+  auto rblock = [&](int q, double* dst, bool store) {
+    const int c0 = 64 * q, qw = cb_width(f, q);
+    gmm64s<false, true>(Rinv + (int64_t)k0 * ld + k0, ld, G + (int64_t)c0 * ld + k0, ld, pw, qw, pw, sm,
+                        [&](int i, int j, double v) {
+                          const bool z = ((nl >> i) & 1ull) || dead[c0 + j] != 0;
+                          const double x = z ? 0.0 : v;
+                          dst[j * LD + i] = x;
+                          if (store) R[(int64_t)(c0 + j) * ld + k0 + i] = x;
+                        });
+  };
   if (blockIdx.x != 0) {
     // trailing block pair (q, r), p < q <= r < P, enumerated row by row;
     // pair 0 = (p+1, p+1) belongs to workgroup 0
@@ -2533,36 +2540,41 @@ __global__ __launch_bounds__(256) void k_cb_look(double* __restrict__ G, int ld,
     }
     const int r = q + idx;
     const int cq = 64 * q, cr = 64 * r, qw = cb_width(f, q), rw = cb_width(f, r);
-    gmm64s<false, true>(R + (int64_t)cq * ld + k0, ld, R + (int64_t)cr * ld + k0, ld, qw, rw, pw, sm,
+    rblock(q, Gs, q == r);
+    if (r != q) rblock(r, Ri, false);
+    gmm64s<false, true>(Gs, LD, r != q ? Ri : Gs, LD, qw, rw, pw, sm,
                         [&](int i, int j, double v) { G[(int64_t)(cr + j) * ld + cq + i] -= v; });
     return;
   }
-  // workgroup 0: S_{p+1,p+1} -= R_{p,p+1}^T R_{p,p+1} in LDS, then the
-  // diagonal step p+1 on it (as k_cb_diag)
+  // workgroup 0: R_{p,p+1}, S_{p+1,p+1} -= R_{p,p+1}^T R_{p,p+1} in LDS,
+  // then the diagonal step p+1 on it (as k_cb_diag)
   const int tid = threadIdx.x, p1 = p + 1, c1 = 64 * p1, w1 = cb_width(f, p1);
-  uint64_t dm = 0, dmo = 0, nl = 0;
+  uint64_t dm = 0, dmo = 0, nl1 = 0;
   for (int c = 0; c < w1; ++c) dm |= (uint64_t)(dead[c1 + c] != 0) << c;
+  rblock(p1, Ri, true);
   stage_small<64>({G + (int64_t)c1 * ld + c1}, w1, {Gs}, LD, ld);
-  gmm64s<false, true>(R + (int64_t)c1 * ld + k0, ld, R + (int64_t)c1 * ld + k0, ld, w1, w1, pw, sm,
-                      [&](int i, int j, double v) { Gs[i * LD + j] -= v; });
+  gmm64s<false, true>(Ri, LD, Ri, LD, w1, w1, pw, sm, [&](int i, int j, double v) { Gs[i * LD + j] -= v; });
   int nf = 0;
-  chol_inv<64>(Gs, Ri, work, dgs, w1, dm, first_pass, &dmo, &nf, dg + c1, &nl);
+  chol_inv<64>(Gs, Ri, work, dgs, w1, dm, first_pass, &dmo, &nf, dg + c1, &nl1);
   for (int idx = tid; idx < w1 * w1; idx += 256) {
     const int i = idx / w1, j = idx - i * w1;
     R[(int64_t)(c1 + j) * ld + c1 + i] = Gs[i * LD + j];
     Rinv[(int64_t)(c1 + j) * ld + c1 + i] = Ri[i * LD + j];
   }
-  for (int c = tid; c < w1; c += 256) dead[c1 + c] = (int32_t)((dmo >> c) & 1ull);
   if (tid == 0) {
-    nolive[p1] = nl;
+    nolive[p1] = nl1;
+    deadmask[p1] = dmo;
     if (count_floors && nf && st) atomicAdd(&st->floored, nf);
   }
 }
 
 __global__ __launch_bounds__(256) void k_cb_inv(const double* __restrict__ R, double* __restrict__ Rinv,
                                                 double* __restrict__ G, int ld, int f, int L, int stage,
+                                                const uint64_t* __restrict__ deadmask, int32_t* __restrict__ dead,
                                                 const int32_t* __restrict__ stopb, int blk) {
   if (stopb && *stopb < blk) return;       // a speculative block after the stop
+  if (stage == 2 && blockIdx.x == 0)
+    for (int c = 64 + threadIdx.x; c < f; c += 256) dead[c] = (int32_t)((deadmask[c >> 6] >> (c & 63)) & 1ull);
   constexpr int LD = SmallCfg<64>::LD;
   __shared__ double Acc[64 * LD];
   __shared__ double sm[GMM64S_LDS];

@@ -3610,6 +3610,26 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
     if (atomicAdd(a.counter, 1u) == (bars + 1) * G - 1) atomicExch(a.counter, 0u);
   }
   if (!a.close_qr) return;
+  // U = Uq Qh at the end runs over this workgroup's rows in 16-row tiles,
+  // four per wave at a time; Uq (the basis, final before this launch) is
+  // read now for the first four, so their loads overlap the QR of R^T
+  const T* Uq = reinterpret_cast<const T*>(a.Uq);
+  const int64_t chunk = (((a.m_u + G - 1) / G + 15) / 16) * 16;
+  const int64_t u0 = (int64_t)blockIdx.x * chunk, u1 = min(a.m_u, u0 + chunk);
+  constexpr int NB = 4;
+  T xa[NB][KS];
+  auto load_u = [&](int64_t t0) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int64_t arow = t0 + 64 * b + r;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        const int k = 4 * kk + g;
+        xa[b][kk] = (arow < u1 && k < f) ? Uq[(int64_t)k * a.ldq_u + arow] : (T)0;
+      }
+    }
+  };
+  if (a.Uout) load_u(u0 + 16 * wv);
   // closing QR (Alg. 2, QR(R^T)), redundantly on every workgroup
   __syncthreads();                               // the panel and R2^{-1} are free
   double* B0 = lds;
@@ -3652,24 +3672,10 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
   state_send(a);                                 // the control block is final here
   if (!a.Uout) return;
   __syncthreads();                               // Qh complete
-  // U = Uq Qh on this workgroup's rows, 16-row tiles, four per wave in flight
-  // (the apply's operand order and sums)
-  const T* Uq = reinterpret_cast<const T*>(a.Uq);
+  // U = Uq Qh (the apply's operand order and sums)
   T* U = reinterpret_cast<T*>(a.Uout);
-  const int64_t chunk = (((a.m_u + G - 1) / G + 15) / 16) * 16;
-  const int64_t u0 = (int64_t)blockIdx.x * chunk, u1 = min(a.m_u, u0 + chunk);
-  constexpr int NB = 4;
   for (int64_t t0 = u0 + 16 * wv; t0 < u1; t0 += 64 * NB) {
-    T xa[NB][KS];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int64_t arow = t0 + 64 * b + r;
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        const int k = 4 * kk + g;
-        xa[b][kk] = (arow < u1 && k < f) ? Uq[(int64_t)k * a.ldq_u + arow] : (T)0;
-      }
-    }
+    if (t0 != u0 + 16 * wv) load_u(t0);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       typename MF::acc_t z[TT];

@@ -443,8 +443,9 @@ def subresults(args, E, torch):
     hs = {}
     for name, code in (("fp32", E.SKETCH_NATIVE), ("fp16_form", E.SKETCH_F16)):
         ctx = E.Context(block=16, seed=0, sketch=code)
-        ctx.profile(True)
-        st = solve_stats(E, torch, Ht, 1e-2, ctx, steps=10)
+        st = solve_stats(E, torch, Ht, 1e-2, ctx, steps=50)
+        ctx.profile(True)                     # the sketch rate, from its own short run:
+        solve_stats(E, torch, Ht, 1e-2, ctx, steps=5, warmup=0)   # events between kernels slow the solve
         tot, n_l, by = ctx.profile_read(E.PROF_SKETCH)
         ctx.profile(False)
         if n_l:

@@ -3258,6 +3258,20 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
       pan[c * LDX + rl] = xv[q];
     }
   }
+  // this thread's elements of the packed upper triangle of G: p = tid + 256 e
+  // is (prr, pcc) with p = pcc (pcc + 1) / 2 + prr, prr <= pcc
+  constexpr int EPT = (F * (F + 1) / 2 + 255) / 256;
+  const int np = f * (f + 1) / 2;
+  int prr[EPT], pcc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int p = tid + 256 * e;
+    int c = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+    while (c > 0 && c * (c + 1) / 2 > p) --c;
+    while ((c + 1) * (c + 2) / 2 <= p) ++c;
+    pcc[e] = c;
+    prr[e] = p - c * (c + 1) / 2;
+  }
   uint64_t dmask = 0;
   double eps_l = 0.0;
   bool nonf_l = false;
@@ -3407,23 +3421,19 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
       }
       __syncthreads();
     }
+    // partials hold G's upper triangle packed column by column: (i, j), i <= j, at j(j+1)/2 + i
     double* pp = a.parts + (int64_t)pass * G * ff;
-    double* Pw = pp + (int64_t)blockIdx.x * ff;  // this workgroup's partial, symmetric fill
+    double* Pw = pp + (int64_t)blockIdx.x * np;  // this workgroup's partial
     for (int idx = tid; idx < TT * TT * 256; idx += 256) {
       const int l = idx & 63, e = (idx >> 6) & 3, tu = idx >> 8;
       const int t = tu / TT, u = tu - t * TT;
       if (u < t) continue;
       const int i = 16 * t + MF::row(l >> 4, e), jj = 16 * u + (l & 15);
-      if (i < f && jj < f) {
-        const double v = red[idx];
-        Pw[(int64_t)jj * f + i] = v;
-        Pw[(int64_t)i * f + jj] = v;
-      }
+      if (i <= jj && jj < f) Pw[jj * (jj + 1) / 2 + i] = red[idx];
     }
     grid_barrier(a.counter, (++bars) * G + a.wait_extra, st, wticks);
-    constexpr int EPT = (F * F + 255) / 256;
     double sum[EPT];                             // G's upper triangle, kept for a second Cholesky
-    {                                            // all partials, upper triangle, order b = 0, 1, ...
+    {                                            // all partials, order b = 0, 1, ...
       constexpr int PB = 16;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) sum[e] = 0.0;
@@ -3432,10 +3442,9 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           const int idx = tid + 256 * e;
-          const int c = idx / f, rr = idx - c * f;
-          const bool ok = idx < ff && rr <= c;
+          const bool ok = idx < np;
 #pragma unroll
-          for (int q = 0; q < PB; ++q) v[e][q] = (ok && b + q < G) ? pp[(int64_t)(b + q) * ff + idx] : 0.0;
+          for (int q = 0; q < PB; ++q) v[e][q] = (ok && b + q < G) ? pp[(int64_t)(b + q) * np + idx] : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e)
@@ -3444,11 +3453,9 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
       }
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const int idx = tid + 256 * e;
-        const int c = idx / f, rr = idx - c * f;
-        if (idx < ff && rr <= c) {
-          Gs[rr * LD + c] = sum[e];
-          Gs[c * LD + rr] = sum[e];
+        if (tid + 256 * e < np) {
+          Gs[prr[e] * LD + pcc[e]] = sum[e];
+          Gs[pcc[e] * LD + prr[e]] = sum[e];
         }
       }
     }
@@ -3499,11 +3506,9 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
       if (dmask_in == 0ull) {                    // Gs was overwritten: G again from the registers
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-          const int idx = tid + 256 * e;
-          const int c = idx / f, rr = idx - c * f;
-          if (idx < ff && rr <= c) {
-            Gs[rr * LD + c] = sum[e];
-            Gs[c * LD + rr] = sum[e];
+          if (tid + 256 * e < np) {
+            Gs[prr[e] * LD + pcc[e]] = sum[e];
+            Gs[pcc[e] * LD + prr[e]] = sum[e];
           }
         }
         __syncthreads();

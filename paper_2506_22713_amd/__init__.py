@@ -80,6 +80,13 @@ _lib.eodabe_workspace_size.restype = _sz
 _lib.eodabe_factor.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_double, _vp, _sz,
                                _vp, _vp, _vp, _i64, ctypes.POINTER(Info)]
 _lib.eodabe_factor.restype = ctypes.c_int
+# eodabe_factor through a CPython entry that converts its arguments in C
+# (the same C-ABI call; ctypes' conversion costs microseconds per call)
+try:
+    from . import _fastcall
+    _fastcall.bind(ctypes.cast(_lib.eodabe_factor, ctypes.c_void_p).value)
+except ImportError:
+    _fastcall = None
 class ImageInfo(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int64 * 4), ("channels", ctypes.c_int), ("relerr", ctypes.c_double),
                 ("psnr", ctypes.c_double), ("ssim", ctypes.c_double), ("stored", ctypes.c_double),
@@ -321,8 +328,14 @@ def factor(A: torch.Tensor, tol: float, ctx: Context | None = None, r_cap: int =
     if ws is None:
         ws = ctx.workspace(m, n, rc)
     Ut, core, Vt = out if out is not None else alloc_outputs(A, rc)
-    info = Info()
     lda = A.stride(0) if m > 1 else max(n, 1)
+    if _fastcall is not None:
+        st, r, blocks, flags, norm_a, eps, relres = _fastcall.factor(
+            ctx.h.value if ctx.h is not None else 0, A.data_ptr(), m, n, lda, float(tol), ws.data_ptr(),
+            ws.numel(), Ut.data_ptr(), core.data_ptr(), Vt.data_ptr(), rc)
+        ctx._check(st, "eodabe_factor")
+        return Factorization((Ut, core, Vt), r, blocks, eps, norm_a, st, flags, relres)
+    info = Info()
     st = _lib.eodabe_factor(ctx.h, A.data_ptr(), m, n, lda, float(tol), ws.data_ptr(), ws.numel(),
                             Ut.data_ptr(), core.data_ptr(), Vt.data_ptr(), rc, ctypes.byref(info))
     ctx._check(st, "eodabe_factor")

@@ -3,6 +3,7 @@ import os
 import shutil
 import subprocess
 import sys
+import sysconfig
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -28,8 +29,32 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm toolchain required to build the EOD-ABE library)")
 
 
+FAST_SRC = os.path.join(HERE, "csrc", "fastcall.c")
+FAST_OUT = os.path.join(HERE, "_fastcall" + (sysconfig.get_config_var("EXT_SUFFIX") or ".so"))
+
+
+def build_fastcall(verbose: bool = False) -> str:
+    """Compile csrc/fastcall.c, the CPython entry for eodabe_factor (host C;
+    it reaches the library through the address ctypes resolved)."""
+    cc = os.environ.get("CC") or shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        raise RuntimeError("no C compiler for the CPython entry (gcc)")
+    tmp = FAST_OUT + ".tmp"
+    cmd = [cc, "-O2", "-shared", "-fPIC", "-I", sysconfig.get_paths()["include"], "-I", os.path.join(ROOT, "include"),
+           FAST_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"C compiler failed ({res.returncode}):\n{res.stdout}{res.stderr}")
+    os.replace(tmp, FAST_OUT)
+    return FAST_OUT
+
+
 def build(verbose: bool = False) -> str:
-    """Compile csrc/eodabe.hip into libeodabe.so (always recompiles)."""
+    """Compile csrc/eodabe.hip into libeodabe.so and the CPython entry
+    (always recompiles)."""
+    build_fastcall(verbose)
     tmp = OUT + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), SRC, "-o", tmp]
     if verbose:

@@ -101,6 +101,37 @@ def test_factor_argument_errors_without_device(E):
     assert f(c.h, ws, 4, 4, 4, 1e-3, big, need, ws, ws, ws, 0, ctypes.byref(info)) == E.EODABE_ENODEVICE
 
 
+def test_fast_entry_matches_ctypes_call(E):
+    """The CPython entry of eodabe_factor (argument conversion in C) is built,
+    bound to the library ctypes loaded, and returns what the ctypes call
+    returns on the same arguments (status, then the info fields)."""
+    assert E._fastcall is not None
+    fc = E._fastcall.factor
+    c = E.Context(host_only=True)
+    ws = ctypes.create_string_buffer(16)
+    a = ctypes.addressof(ws)
+    need = c.workspace_size(4, 4)
+    big = ctypes.create_string_buffer(need)
+    b = ctypes.addressof(big)
+    cases = [
+        (0, 0, 4, 4, 4, 1e-3, 0, 0, 0, 0, 0, 0),                  # NULL context
+        (c.h.value, 0, -1, 4, 4, 1e-3, 0, 0, 0, 0, 0, 0),        # bad size
+        (c.h.value, a, 4, 4, 3, 1e-3, 0, 0, a, a, a, 0),          # lda < n
+        (c.h.value, a, 4, 4, 4, float("nan"), 0, 0, a, a, a, 0),  # bad tol
+        (c.h.value, a, 4, 4, 4, 1e-3, a, 16, a, a, a, 0),         # workspace too small
+        (c.h.value, a, 4, 4, 4, 1e-3, b, need, a, a, a, 0),       # no device
+    ]
+    for args in cases:
+        info = E.Info()
+        ref = E._lib.eodabe_factor(*(x if not isinstance(x, int) or i in (2, 3, 4, 7, 11) else (x or None)
+                                     for i, x in enumerate(args)), ctypes.byref(info))
+        got = fc(*args)
+        assert got == (ref, info.rank, info.blocks, info.status_flags, info.norm_a, info.eps, info.relres_est), args
+    assert got[0] == E.EODABE_ENODEVICE
+    with pytest.raises(TypeError):
+        fc(0, 0, 4)
+
+
 def test_batched_argument_errors_without_device(E):
     """Host checks of eodabe_factor_batched: sizes, tol, dtype, output pool
     extent and workspace, all before any device use."""

@@ -573,8 +573,10 @@ def cpu_baseline_one_thread(A64, tol, block, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 300 for one matrix per step, 50 for tiles1024 and learned4096)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 20 for one matrix per step, 5 for tiles1024 and learned4096)")
     ap.add_argument("--workload", default="image4096")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -589,6 +591,11 @@ def main():
     ap.add_argument("--skip-sequential", action="store_true",
                     help="tiles1024 under a counter profiler: time the batched launches only, print no JSON line")
     args = ap.parse_args()
+    many = args.workload in ("tiles1024", "learned4096")      # steps of many matrices each
+    if args.steps is None:
+        args.steps = 50 if many else 300
+    if args.warmup is None:
+        args.warmup = 5 if many else 20
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "the EOD-ABE library here runs on a single GPU", file=sys.stderr)

@@ -84,6 +84,8 @@ inline int64_t cdiv(int64_t x, int64_t a) { return (x + a - 1) / a; }
 // Workgroups of a Gram kernel of the basis loop (one row panel each up to
 // this; the partial buffer holds that many)
 constexpr int GRAM_LOOP_WG = 192;
+// Workgroups of a k_apply launch (its 64-row blocks taken grid-stride)
+constexpr int64_t APPLY_WG = 1024;
 
 // K-chunk (multiple of 16) and the number of non-empty splits actually
 // launched for a reduction of length K asked to use `want` splits.  Every
@@ -628,18 +630,21 @@ struct Ops {
     const int64_t rows = std::max<int64_t>(j0.rows, j1 ? j1->rows : 0);
     if (rows <= 0) return 0;
     dim3 grid((unsigned)cdiv(rows, 64), j1 ? 2 : 1);
+    // k_apply takes its 64-row blocks grid-stride: up to 32 columns at most
+    // APPLY_WG workgroups, each staging W once; wider, one block each
+    const dim3 gs((unsigned)(f <= 32 ? std::min<int64_t>(grid.x, APPLY_WG) : grid.x), grid.y);
     const ApplyJob jb = j1 ? *j1 : j0;
     if (f <= 16)
-      hipLaunchKernelGGL((k_apply<T, 16>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
+      hipLaunchKernelGGL((k_apply<T, 16>), gs, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else if (f <= 32)
-      hipLaunchKernelGGL((k_apply<T, 32>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
+      hipLaunchKernelGGL((k_apply<T, 32>), gs, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else if (f <= 64)
-      hipLaunchKernelGGL((k_apply<T, 64>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
+      hipLaunchKernelGGL((k_apply<T, 64>), gs, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else if (f <= 128 && j0.Z != j0.X && jb.Z != jb.X)   // output columns over four workgroups
       hipLaunchKernelGGL((k_apply_cols<T, 128>), dim3(grid.x, grid.y, 4), dim3(256), 0, st, j0, jb, stopb, blk,
                          gate);
     else if (f <= 128)
-      hipLaunchKernelGGL((k_apply<T, 128>), grid, dim3(256), 0, st, j0, jb, stopb, blk, gate);
+      hipLaunchKernelGGL((k_apply<T, 128>), gs, dim3(256), 0, st, j0, jb, stopb, blk, gate);
     else
       return EODABE_EINVAL;
     LAUNCHCHK();

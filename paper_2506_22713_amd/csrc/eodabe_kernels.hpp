@@ -3709,8 +3709,12 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
 // X column-major rows x f (ldx), W f x f FP64 (element (i,j) at j*f + i,
 // any shape), Z column-major (ldz), columns zoff .. zoff+ncols-1 written.
 // With zoff_dev / ncols_dev the offset and count are read on the device
-// (the basis append: zoff = wlog[block], ncols = acc[block]).  Each wave
-// computes 16 complete rows, so Z may alias X when zoff = 0 and ldz = ldx.
+// (the basis append: zoff = wlog[block], ncols = acc[block]).  Up to 32
+// columns a workgroup stages W once and takes 64-row blocks grid-stride, the
+// next block's rows of X loading while the current block is multiplied;
+// wider, it takes one block (the launch covers every block).  Each wave computes 16
+// complete rows and reads a block's rows before it writes them (no other
+// workgroup touches the block), so Z may alias X when zoff = 0 and ldz = ldx.
 // ---------------------------------------------------------------------------
 struct ApplyJob {
   const void* X;
@@ -3734,8 +3738,9 @@ __global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
   if (stop_block && *stop_block < block_id) return;
   if (gate_shut(gate)) return;
   const ApplyJob jb = blockIdx.y == 0 ? j0 : j1;
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
-  if (row0 >= jb.rows) return;
+  const int64_t nrb = (jb.rows + 63) / 64;      // 64-row blocks, taken grid-stride
+  int64_t rb = blockIdx.x;
+  if (rb >= nrb) return;
   __shared__ double Wl[F * LD];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r = lane & 15, g = lane >> 4;
   const int f = jb.f_dev ? (int)*jb.f_dev : jb.f;
@@ -3744,16 +3749,19 @@ __global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
   const int64_t zoff = jb.zoff_dev ? jb.zoff_dev[block_id] : jb.zoff;
   const T* X = reinterpret_cast<const T*>(jb.X);
   T* Z = reinterpret_cast<T*>(jb.Z);
-  const int64_t rbase = row0 + 16 * wv;
-  const int64_t arow = rbase + r;
-  const bool aok = arow < jb.rows;
-  // X rows requested first, then W: both round trips overlap
+  // this wave's 16 rows of block rbk (lane r holds row 16*wv + r)
   T xa[KS];
+  auto load_x = [&](int64_t rbk) {
+    const int64_t arow = rbk * 64 + 16 * wv + r;
+    const bool aok = arow < jb.rows;
 #pragma unroll
-  for (int kk = 0; kk < KS; ++kk) {
-    const int k = 4 * kk + g;
-    xa[kk] = (aok && k < f) ? X[(int64_t)k * jb.ldx + arow] : (T)0;
-  }
+    for (int kk = 0; kk < KS; ++kk) {
+      const int k = 4 * kk + g;
+      xa[kk] = (aok && k < f) ? X[(int64_t)k * jb.ldx + arow] : (T)0;
+    }
+  };
+  // the first block's X rows requested first, then W: both round trips overlap
+  load_x(rb);
   if constexpr (F <= 64) {
     stage_small<F>({jb.W}, f, {Wl}, LD);
   } else {
@@ -3774,26 +3782,38 @@ __global__ __launch_bounds__(256) void k_apply(ApplyJob j0, ApplyJob j1,
       }
     }
   }
-  double a[KS];
-#pragma unroll
-  for (int kk = 0; kk < KS; ++kk) a[kk] = (double)xa[kk];
   __syncthreads();
-  typename MF::acc_t z[TT];
+  auto block = [&](int64_t rbk) {                // Z rows of block rbk from xa
+    double a[KS];
 #pragma unroll
-  for (int u = 0; u < TT; ++u) z[u] = MF::zero();
+    for (int kk = 0; kk < KS; ++kk) a[kk] = (double)xa[kk];
+    if constexpr (F <= 32)                       // the next block's rows in flight
+      if (rbk + gridDim.x < nrb) load_x(rbk + gridDim.x);
+    const int64_t rbase = rbk * 64 + 16 * wv;
+    typename MF::acc_t z[TT];
 #pragma unroll
-  for (int kk = 0; kk < KS; ++kk)
+    for (int u = 0; u < TT; ++u) z[u] = MF::zero();
 #pragma unroll
-    for (int u = 0; u < TT; ++u) z[u] = MF::op(a[kk], Wl[(4 * kk + g) * LD + 16 * u + r], z[u]);
+    for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
-  for (int u = 0; u < TT; ++u) {
-    const int col = 16 * u + r;
-    if (col >= ncols) continue;
+      for (int u = 0; u < TT; ++u) z[u] = MF::op(a[kk], Wl[(4 * kk + g) * LD + 16 * u + r], z[u]);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t row = rbase + MF::row(g, e);
-      if (row < jb.rows) Z[(zoff + col) * jb.ldz + row] = (T)z[u][e];
+    for (int u = 0; u < TT; ++u) {
+      const int col = 16 * u + r;
+      if (col >= ncols) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = rbase + MF::row(g, e);
+        if (row < jb.rows) Z[(zoff + col) * jb.ldz + row] = (T)z[u][e];
+      }
     }
+  };
+  if constexpr (F <= 32) {
+    for (; rb < nrb; rb += gridDim.x) block(rb);
+  } else {
+    // wider: one block per workgroup (in a loop the compiler would keep the
+    // loop-invariant W operands in registers, more than there are)
+    block(rb);
   }
 }
 

@@ -7,6 +7,7 @@ import re
 import subprocess
 
 import pytest
+import torch
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HDR = os.path.join(ROOT, "include", "eodabe.h")
@@ -130,6 +131,24 @@ def test_fast_entry_matches_ctypes_call(E):
     assert got[0] == E.EODABE_ENODEVICE
     with pytest.raises(TypeError):
         fc(0, 0, 4)
+
+
+def test_factorization_views_alias_the_outputs(E):
+    """factor()'s result makes U = Ut[:r]^T, D = core[:r, :r] and Vt[:r] on
+    first access: views of the caller's buffers, nothing copied."""
+    m, n, rc, r = 7, 5, 5, 3
+    Ut = torch.arange(rc * m, dtype=torch.float32).reshape(rc, m)
+    core = torch.arange(rc * rc, dtype=torch.float32).reshape(rc, rc)
+    Vt = torch.arange(rc * n, dtype=torch.float32).reshape(rc, n)
+    f = E.Factorization((Ut, core, Vt), r, 1, 0.5, 2.0, 0, 0, 0.1)
+    assert f.rank == r and f.blocks == 1 and f.eps == 0.5 and f.norm_a == 2.0 and f.relres_est == 0.1
+    assert f.U.shape == (m, r) and f.D.shape == (r, r) and f.Vt.shape == (r, n)
+    assert torch.equal(f.U, Ut[:r].T) and torch.equal(f.D, core[:r, :r]) and torch.equal(f.Vt, Vt[:r])
+    assert f.U.data_ptr() == Ut.data_ptr() and f.D.data_ptr() == core.data_ptr() and f.Vt.data_ptr() == Vt.data_ptr()
+    assert f.U is f.U                              # made once
+    core[0, 0] = -1.0                              # a view: later writes show through
+    assert f.D[0, 0].item() == -1.0
+    assert "rank=3" in repr(f)
 
 
 def test_batched_argument_errors_without_device(E):

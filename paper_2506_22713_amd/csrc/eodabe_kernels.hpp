@@ -3421,41 +3421,66 @@ __global__ __launch_bounds__(256) void k_cqr2(Cqr2Args a) {
       }
       __syncthreads();
     }
-    // partials hold G's upper triangle packed column by column: (i, j), i <= j, at j(j+1)/2 + i
-    double* pp = a.parts + (int64_t)pass * G * ff;
-    double* Pw = pp + (int64_t)blockIdx.x * np;  // this workgroup's partial
-    for (int idx = tid; idx < TT * TT * 256; idx += 256) {
-      const int l = idx & 63, e = (idx >> 6) & 3, tu = idx >> 8;
-      const int t = tu / TT, u = tu - t * TT;
-      if (u < t) continue;
-      const int i = 16 * t + MF::row(l >> 4, e), jj = 16 * u + (l & 15);
-      if (i <= jj && jj < f) Pw[jj * (jj + 1) / 2 + i] = red[idx];
-    }
-    grid_barrier(a.counter, (++bars) * G + a.wait_extra, st, wticks);
     double sum[EPT];                             // G's upper triangle, kept for a second Cholesky
-    {                                            // all partials, order b = 0, 1, ...
-      constexpr int PB = 16;
+    // one workgroup: its wave fold is the Gram (the same sums as the fold of
+    // a single partial), no partial and no barrier.  Compiled into the
+    // 16-column form only: the 32-column form's code sits near the size of
+    // the instruction cache, and the branch alone slowed it measurably.
+    bool one = false;
+    if constexpr (!PROJ && F <= 16) one = G == 1;
+    if (one) {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) sum[e] = 0.0;
-      for (unsigned b = 0; b < G; b += PB) {
-        double v[EPT][PB];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const int idx = tid + 256 * e;
-          const bool ok = idx < np;
-#pragma unroll
-          for (int q = 0; q < PB; ++q) v[e][q] = (ok && b + q < G) ? pp[(int64_t)(b + q) * np + idx] : 0.0;
+      for (int e = 0; e < EPT; ++e) {
+        sum[e] = 0.0;
+        if (tid + 256 * e < np) {
+          const int i = prr[e], jj = pcc[e], il = i & 15;
+          sum[e] += red[(((i >> 4) * TT + (jj >> 4)) * 4 + (il >> 2)) * 64 + (il & 3) * 16 + (jj & 15)];
         }
-#pragma unroll
-        for (int e = 0; e < EPT; ++e)
-#pragma unroll
-          for (int q = 0; q < PB; ++q) sum[e] += v[e][q];
       }
+      __syncthreads();                           // the fold area (Gs) read before Gs is written
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         if (tid + 256 * e < np) {
           Gs[prr[e] * LD + pcc[e]] = sum[e];
           Gs[pcc[e] * LD + prr[e]] = sum[e];
+        }
+      }
+    } else {
+      // partials hold G's upper triangle packed column by column: (i, j), i <= j, at j(j+1)/2 + i
+      double* pp = a.parts + (int64_t)pass * G * ff;
+      double* Pw = pp + (int64_t)blockIdx.x * np;  // this workgroup's partial
+      for (int idx = tid; idx < TT * TT * 256; idx += 256) {
+        const int l = idx & 63, e = (idx >> 6) & 3, tu = idx >> 8;
+        const int t = tu / TT, u = tu - t * TT;
+        if (u < t) continue;
+        const int i = 16 * t + MF::row(l >> 4, e), jj = 16 * u + (l & 15);
+        if (i <= jj && jj < f) Pw[jj * (jj + 1) / 2 + i] = red[idx];
+      }
+      grid_barrier(a.counter, (++bars) * G + a.wait_extra, st, wticks);
+      {                                            // all partials, order b = 0, 1, ...
+        constexpr int PB = 16;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) sum[e] = 0.0;
+        for (unsigned b = 0; b < G; b += PB) {
+          double v[EPT][PB];
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int idx = tid + 256 * e;
+            const bool ok = idx < np;
+#pragma unroll
+            for (int q = 0; q < PB; ++q) v[e][q] = (ok && b + q < G) ? pp[(int64_t)(b + q) * np + idx] : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < EPT; ++e)
+#pragma unroll
+            for (int q = 0; q < PB; ++q) sum[e] += v[e][q];
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          if (tid + 256 * e < np) {
+            Gs[prr[e] * LD + pcc[e]] = sum[e];
+            Gs[pcc[e] * LD + prr[e]] = sum[e];
+          }
         }
       }
     }

@@ -2927,7 +2927,7 @@ __global__ __launch_bounds__(256) void k_gram_rows(
     double sum[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) sum[e] = 0.0;
-    constexpr int PB = EPT == 1 ? 64 : (EPT <= 4 ? 16 : 4);   // partials per batch (loads in flight)
+    constexpr int PB = EPT == 1 ? 96 : (EPT <= 4 ? 16 : 4);   // partials per batch (loads in flight)
     for (unsigned b = 0; b < nb; b += PB) {
       double v[EPT][PB];
 #pragma unroll
